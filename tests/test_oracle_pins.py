@@ -1,0 +1,419 @@
+"""Pins of the CPU oracle against closed forms, textbook identities, an
+independent integrator and brute force (no GPU).
+
+Each test names the part of the oracle it pins and what it is pinned to;
+none of them re-derives the oracle's own formula.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from inputs import square_mesh, gauss7, paper7, centroid1, collapsed
+from inputs.workloads import small_constant
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def cfg(kernel="constant", c=1.0, delta=0.1, approach="bary", rule=None,
+        singular_n=0, polygon_n=32):
+    rule = rule or gauss7()
+    return dict(kernel=kernel, c=c, delta=delta, approach=approach, outer=rule,
+                inner=rule, singular_n=singular_n, polygon_n=polygon_n,
+                ncomp=2 if kernel == "peridynamic" else 1)
+
+
+def dense(P, rp, col, val):
+    M = P.V.shape[0] * P.n
+    return sp.csr_matrix((val, col, rp), shape=(M, M)).toarray()
+
+
+def mass_matrix(mesh):
+    """Textbook P1 mass matrix: |T|/12 (1 + delta_ij) per element."""
+    M = mesh.n_vertices
+    A = np.zeros((M, M))
+    m = np.zeros(M)
+    for e in mesh.elements:
+        v = mesh.vertices[e]
+        area = 0.5 * abs((v[1, 0] - v[0, 0]) * (v[2, 1] - v[0, 1]) -
+                         (v[2, 0] - v[0, 0]) * (v[1, 1] - v[0, 1]))
+        for a in range(3):
+            m[e[a]] += area / 3.0
+            for b in range(3):
+                A[e[a], e[b]] += area / 12.0 * (2.0 if a == b else 1.0)
+    return A, m
+
+
+# ----------------------------------------------------------------------
+# pair lists: brute force == breadth-first traversal (Alg. 2)
+
+@pytest.mark.parametrize("case", ["const_bary", "invdist_duffy", "poly", "peri"])
+def test_pairs_bruteforce_equals_bfs(oracle_lib, case):
+    if case == "const_bary":
+        w = small_constant()
+        mesh, c = w["mesh"], w
+    elif case == "invdist_duffy":
+        mesh = square_mesh(14, delta=0.2, jitter=0.2, seed=1)
+        c = cfg("inv_dist", delta=0.2, singular_n=5)
+    elif case == "poly":
+        mesh = square_mesh(12, delta=0.15, jitter=0.1, seed=2)
+        c = cfg("constant", delta=0.15, approach="poly")
+    else:
+        mesh = square_mesh(12, delta=0.25, jitter=0.15, seed=3)
+        c = cfg("peridynamic", delta=0.25, singular_n=5)
+    P = oracle_lib.Problem(mesh, c)
+    k, l, cls = P.pairs()
+    kb, lb, cb = P.pairs_bfs()
+    assert len(k) > 0
+    assert np.array_equal(k, kb) and np.array_equal(l, lb) and np.array_equal(cls, cb)
+    # sorted by (k, l), labels admissible
+    key = k.astype(np.int64) * mesh.n_elements + l
+    assert np.all(np.diff(key) > 0)
+    lab = mesh.labels
+    assert np.all((lab[k] == 1) | (lab[l] == 1))
+
+
+def test_pair_count_small_constant(oracle_lib):
+    """Counts of the 800-triangle constant-kernel case: 12,906 ordered
+    pairs, 6,975 nonzeros over 225 degrees of freedom."""
+    w = small_constant()
+    P = oracle_lib.Problem(w["mesh"], w)
+    k, l, c = P.pairs()
+    assert len(k) == 12906
+    rp, col = P.pattern(k, l)
+    assert len(col) == 6975
+    assert int(P.isdof().sum()) == 225
+
+
+def test_table1_dispatch(oracle_lib):
+    """Table 1: touching pairs get the regularising transform when the kernel
+    is treated as singular; disjoint pairs always the standard rule."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_dispatch.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert rows[0] == ["s<=-1", "std", "std"]
+    assert all(r[2] == "std" for r in rows)
+    mesh = square_mesh(8, delta=0.3)
+    E = mesh.elements
+    for ns, kern in ((0, "constant"), (5, "inv_dist")):
+        P = oracle_lib.Problem(mesh, cfg(kern, delta=0.3, singular_n=ns))
+        k, l, cls = P.pairs()
+        shared = np.array([len(set(E[a]) & set(E[b])) for a, b in zip(k, l)])
+        if ns == 0:
+            assert np.all(cls == 0)
+        else:
+            assert np.array_equal(cls, shared)
+
+
+# ----------------------------------------------------------------------
+# hand-computed asymmetric inclusion (barycentre ball, Sec. 2.2)
+
+def test_two_triangles_by_hand(oracle_lib):
+    """T0 = (0,0),(1,0),(0,1), T1 = (3,0),(4,0),(3,1), delta = 2.5, c = 1,
+    paper's 7-point rule on both sides.  Distances from the rule points of
+    T0 to bary(T1) = (10/3, 1/3): only the vertex (1,0) is within 2.5
+    (|.|^2 = 50/9 < 6.25); from T1's points to bary(T0) = (1/3, 1/3) the
+    nearest is (3, 1/2) with |.|^2 = 257/36 > 6.25.  So (0,1) is a pair,
+    (1,0) is not, and with d_p = 1/40 for that vertex
+      A1 = d_p * 1/2 e1 e1^T, A2 = -d_p e1 (1/6, 1/6, 1/6),
+      A3 = d_p * (1 + delta_ij)/24.
+    Self pairs see the whole element: c (2|T| M - 2 m m^T) with
+    M = (1 + delta_ij)/24, m = 1/6."""
+    from inputs.meshes import Mesh
+    V = np.array([[0, 0], [1, 0], [0, 1], [3, 0], [4, 0], [3, 1]], float)
+    E = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    mesh = Mesh(V, E, np.array([1, 1], np.int32), 1.0, 1, 0)
+    P = oracle_lib.Problem(mesh, cfg("constant", c=1.0, delta=2.5, rule=paper7()))
+    k, l, cls = P.pairs()
+    assert list(zip(k, l)) == [(0, 0), (0, 1), (1, 1)]
+    F = Fraction
+    L01 = [[F(0)] * 6 for _ in range(6)]
+    dp = F(1, 40)
+    L01[1][1] = dp * F(1, 2)
+    for j in range(3):
+        L01[1][3 + j] = -dp * F(1, 6)
+        L01[3 + j][1] = -dp * F(1, 6)
+        for i in range(3):
+            L01[3 + i][3 + j] = dp * F(2 if i == j else 1, 24)
+    nodes, L = P.local(0, 1, 0)
+    assert list(nodes) == [0, 1, 2, 3, 4, 5]
+    assert np.max(np.abs(L - np.array(L01, dtype=float))) < 1e-16
+    self_blk = np.array([[float(F(2 if i == j else 1, 24) - F(1, 18)) for j in range(3)]
+                         for i in range(3)])
+    A = dense(P, *P.assemble())
+    expect = np.array(L01, dtype=float)
+    expect[:3, :3] += self_blk
+    expect[3:, 3:] += self_blk
+    assert np.max(np.abs(A - expect)) < 1e-15
+
+
+# ----------------------------------------------------------------------
+# constant kernel, every pair fully interacting: closed form
+
+@pytest.mark.parametrize("singular_n", [0, 5])
+@pytest.mark.parametrize("rule", ["gauss7", "paper7"])
+def test_constant_kernel_full_ball_closed_form(oracle_lib, singular_n, rule):
+    """With the ball covering the whole mesh, A(phi_j, phi_i) =
+    c int int (phi_i(x)-phi_i(y))(phi_j(x)-phi_j(y)) = c (2|D| M_ij - 2 m_i m_j)
+    (M the P1 mass matrix, m_i = int phi_i) for every degree of freedom i;
+    both the product rule and the touching-pair transforms are exact here."""
+    mesh = square_mesh(5, m=1, jitter=0.2, seed=4)
+    r = gauss7() if rule == "gauss7" else paper7()
+    c = 3.7
+    P = oracle_lib.Problem(mesh, cfg("constant", c=c, delta=100.0, rule=r, singular_n=singular_n))
+    A = dense(P, *P.assemble())
+    M, m = mass_matrix(mesh)
+    D = m.sum()
+    expect = c * (2 * D * M - 2 * np.outer(m, m))
+    dof = P.isdof()
+    assert np.max(np.abs(A[dof] - expect[dof])) < 1e-13 * np.abs(expect).max()
+    assert np.all(A[~dof] == 0)
+
+
+def test_constant_kernel_touching_transform_equals_product_rule(oracle_lib):
+    """For the constant kernel the integrand is a polynomial of degree 2, so
+    the transforms to (0,1)^4 and the 7x7 product rule must agree."""
+    mesh = square_mesh(4, m=1, jitter=0.2, seed=5)
+    Pd = oracle_lib.Problem(mesh, cfg("constant", delta=100.0, singular_n=5))
+    Ps = oracle_lib.Problem(mesh, cfg("constant", delta=100.0, singular_n=0))
+    k, l, cls = Pd.pairs()
+    seen = set()
+    for a, b, c in zip(k, l, cls):
+        if c == 0 or c in seen and len(seen) == 3:
+            continue
+        seen.add(int(c))
+        n1, L1 = Pd.local(a, b, c)
+        n2, L2 = Ps.local(a, b, 0)
+        assert list(n1) == sorted(n1, key=list(n2).index) or set(n1) == set(n2)
+        perm = [list(n2).index(x) for x in n1]
+        L2p = L2[np.ix_(perm, perm)]
+        assert np.max(np.abs(L1 - L2p)) < 1e-14 * np.abs(L2).max()
+    assert seen == {1, 2, 3}
+
+
+# ----------------------------------------------------------------------
+# regularising transforms (Sec. 2.4.2): cubature on T x T
+
+def _tri_int(a, b):
+    return math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+
+
+@pytest.mark.parametrize("cls", [1, 2, 3])
+def test_touching_transforms_are_cubatures(oracle_lib, cls):
+    """Every transform maps (0,1)^4 onto T^ x T^ with the right Jacobian:
+    weights sum to |T^|^2 = 1/4, samples lie in T^ x T^ and all monomials of
+    total degree <= 3 in (xi, eta) integrate exactly."""
+    xi, eta, w = oracle_lib.duffy_samples(cls, 5)
+    assert abs(w.sum() - 0.25) < 1e-15
+    for p in (xi, eta):
+        assert p.min() >= -1e-15 and (p.sum(axis=1)).max() <= 1 + 1e-15
+    worst = 0.0
+    for a in range(4):
+        for b in range(4 - a):
+            for c in range(4 - a - b):
+                for d in range(4 - a - b - c):
+                    q = np.sum(w * xi[:, 0] ** a * xi[:, 1] ** b * eta[:, 0] ** c * eta[:, 1] ** d)
+                    ex = _tri_int(a, b) * _tri_int(c, d)
+                    worst = max(worst, abs(q - ex))
+    assert worst < 2e-16
+
+
+def _touching_examples(mesh, E, k0):
+    pick = {}
+    for l in range(len(E)):
+        s = len(set(E[k0]) & set(E[l]))
+        if s and s not in pick:
+            pick[s] = l
+        if s == 0 and 0 not in pick:
+            v = mesh.vertices
+            if np.linalg.norm(v[E[l]].mean(0) - v[E[k0]].mean(0)) > 2.5 * mesh.h:
+                pick[0] = l
+    return pick
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kernel", ["inv_dist", "peridynamic"])
+def test_singular_quadrature_vs_independent_integral(oracle_lib, kernel):
+    """Touching pairs: the oracle's transforms converge (n = 16) to an
+    independent polar/sinh-transformed integral to 1e-10, and the paper's
+    n = 5 rule stays within the quadrature error of that integral."""
+    from _refint import PairIntegral
+    mesh = square_mesh(4, m=1, jitter=0.2, seed=3)
+    E, V = mesh.elements, mesh.vertices
+    k0 = 14
+    pick = _touching_examples(mesh, E, k0)
+    n = 2 if kernel == "peridynamic" else 1
+    bound5 = {1: 1e-5, 2: 2e-4, 3: 2e-3}
+    for cls in (1, 2, 3):
+        l = pick[cls]
+        un, Lr = PairIntegral(V[E[k0]], V[E[l]], list(E[k0]), list(E[l]), kernel, 1.0).local(epsrel=1e-12)
+        for ns, tol in ((16, 1e-10), (5, bound5[cls])):
+            P = oracle_lib.Problem(mesh, cfg(kernel, delta=10.0, singular_n=ns))
+            nodes, Lo = P.local(k0, l, cls)
+            perm = [un.index(a) for a in nodes]
+            idx = np.array([n * p + c for p in perm for c in range(n)])
+            R = Lr[np.ix_(idx, idx)]
+            err = np.linalg.norm(Lo - R) / np.linalg.norm(R)
+            assert err < tol, (cls, ns, err)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kernel", ["inv_dist", "peridynamic"])
+def test_far_pair_integrand_vs_independent_integral(oracle_lib, kernel):
+    """Disjoint pair, ball covering both: with a degree-11 product rule the
+    oracle's truncation quadrature converges to the exact integral."""
+    from _refint import PairIntegral
+    mesh = square_mesh(4, m=1, jitter=0.2, seed=3)
+    E, V = mesh.elements, mesh.vertices
+    k0 = 14
+    l = _touching_examples(mesh, E, k0)[0]
+    n = 2 if kernel == "peridynamic" else 1
+    un, Lr = PairIntegral(V[E[k0]], V[E[l]], list(E[k0]), list(E[l]), kernel, 1.0).local(epsrel=1e-12)
+    P = oracle_lib.Problem(mesh, cfg(kernel, delta=10.0, rule=collapsed(6)))
+    nodes, Lo = P.local(k0, l, 0)
+    perm = [un.index(a) for a in nodes]
+    idx = np.array([n * p + c for p in perm for c in range(n)])
+    R = Lr[np.ix_(idx, idx)]
+    assert np.linalg.norm(Lo - R) / np.linalg.norm(R) < 1e-9
+
+
+# ----------------------------------------------------------------------
+# global invariants (Remark on symmetry; null space of the Neumann case)
+
+def _problem(oracle_lib, which):
+    if which == "const":
+        w = small_constant()
+        return oracle_lib.Problem(w["mesh"], w), w["mesh"]
+    if which == "invdist":
+        mesh = square_mesh(16, delta=0.15, jitter=0.2, seed=0)
+        return oracle_lib.Problem(mesh, cfg("inv_dist", c=2.0, delta=0.15, singular_n=5)), mesh
+    if which == "poly":
+        mesh = square_mesh(12, delta=0.15, jitter=0.15, seed=0)
+        return oracle_lib.Problem(mesh, cfg("constant", c=2.0, delta=0.15, approach="poly")), mesh
+    mesh = square_mesh(12, delta=0.2, jitter=0.15, seed=0)
+    return oracle_lib.Problem(mesh, cfg("peridynamic", c=2.0, delta=0.2, singular_n=5)), mesh
+
+
+@pytest.mark.parametrize("which", ["const", "invdist", "poly", "peri"])
+def test_symmetry_and_null_space(oracle_lib, which):
+    P, mesh = _problem(oracle_lib, which)
+    rp, col, val = P.assemble()
+    A = sp.csr_matrix((val, col, rp), shape=(P.n * mesh.n_vertices,) * 2)
+    dofm = np.repeat(P.isdof(), P.n)
+    B = A[dofm][:, dofm]
+    asym = abs(B - B.T).max() / abs(B).max()
+    assert asym < 1e-14
+    absrow = np.asarray(abs(A).sum(axis=1)).ravel()
+    X, Y = mesh.vertices[:, 0], mesh.vertices[:, 1]
+    if P.n == 1:
+        modes = [np.ones(mesh.n_vertices)]
+    else:
+        ones, zeros = np.ones_like(X), np.zeros_like(X)
+        modes = [np.stack([ones, zeros], 1).ravel(), np.stack([zeros, ones], 1).ravel(),
+                 np.stack([-Y, X], 1).ravel()]
+    for U in modes:
+        r = A @ U
+        scale = np.asarray(abs(A) @ abs(U)).ravel()
+        ok = dofm
+        assert np.all(np.abs(r[ok]) <= 1e-13 * scale[ok] + 1e-300)
+
+
+def test_translation_invariance_uniform_mesh(oracle_lib):
+    """On the uniform mesh every interior degree of freedom sees a translated
+    copy of the same neighbourhood, and the mesh and the symmetric 7-point
+    rule are invariant under point reflection through a node: A u = 0 for
+    linear u, and A u is the same in every interior row for quadratic u."""
+    P, mesh = _problem(oracle_lib, "const")
+    rp, col, val = P.assemble()
+    A = sp.csr_matrix((val, col, rp), shape=(mesh.n_vertices,) * 2)
+    X, Y = mesh.vertices[:, 0], mesh.vertices[:, 1]
+    h = mesh.h
+    interior = P.isdof() & (X > 3 * h - 1e-12) & (X < 1 - 3 * h + 1e-12) & \
+        (Y > 3 * h - 1e-12) & (Y < 1 - 3 * h + 1e-12)
+    assert interior.sum() >= 25
+    scale = abs(A).max()
+    for U in (X, Y, 2 * X - 3 * Y):
+        assert np.abs((A @ U)[interior]).max() < 1e-12 * scale
+    q = (A @ (X ** 2 + Y ** 2))[interior]
+    assert np.ptp(q) < 1e-12 * scale
+    q2 = (A @ (X * Y))[interior]
+    assert np.ptp(q2) < 1e-12 * scale
+
+
+# ----------------------------------------------------------------------
+# 32-gon ball (Def. 2.4 reading): clipping and sub-triangle quadrature
+
+def test_polygon_inner_moments(oracle_lib):
+    """Summed over all inner elements, the clipped-and-retriangulated inner
+    quadrature reproduces the moments of the regular N-gon P around x:
+    |P| = N/2 delta^2 sin(2pi/N), int y = |P| x, and
+    int (y-x)(y-x)^T = N delta^4 sin(2pi/N)(2 + cos(2pi/N))/24 * I.
+    The trace ratio to the disc is kappa_32 = 0.98722302."""
+    N, delta = 32, 0.12
+    mesh = square_mesh(10, delta=delta, jitter=0.2, seed=6)
+    P = oracle_lib.Problem(mesh, cfg("constant", delta=delta, approach="poly", polygon_n=N))
+    th = 2 * math.pi / N
+    area = 0.5 * N * delta ** 2 * math.sin(th)
+    I2 = N * delta ** 4 * math.sin(th) * (2 + math.cos(th)) / 24.0
+    kappa = I2 / (math.pi * delta ** 4 / 4)
+    assert abs(kappa - 0.98722302) < 1e-8
+    rng = np.random.default_rng(7)
+    V, E = mesh.vertices, mesh.elements
+    for x in rng.uniform(0.05, 0.95, size=(12, 2)):
+        tot0, tot1, tot2 = 0.0, np.zeros(2), np.zeros((2, 2))
+        nclipped = 0
+        for l in range(mesh.n_elements):
+            a0, a1, a2 = P.inner_moments(x, l)
+            if a0 == 0.0:
+                continue
+            v = V[E[l]]
+            tot0 += a0
+            tot1 += a1 @ v
+            tot2 += v.T @ a2 @ v
+            if abs(a0 - 0.5 * abs(np.linalg.det(np.array([v[1] - v[0], v[2] - v[0]])))) > 1e-15:
+                nclipped += 1
+        assert nclipped > 5
+        assert abs(tot0 - area) < 1e-14
+        assert np.abs(tot1 - area * x).max() < 1e-14
+        cen = tot2 - area * np.outer(x, x)
+        assert np.abs(cen - I2 * np.eye(2)).max() < 1e-15
+
+
+def test_polygon_clip_area_matches_shoelace_sum(oracle_lib):
+    """Clip areas of all inner elements add up to the polygon area."""
+    N, delta = 32, 0.1
+    mesh = square_mesh(8, delta=delta, seed=0)
+    P = oracle_lib.Problem(mesh, cfg("constant", delta=delta, approach="poly", polygon_n=N))
+    x = np.array([0.43, 0.57])
+    s = sum(P.clip_area(x, l)[0] for l in range(mesh.n_elements))
+    assert abs(s - 0.5 * N * delta ** 2 * math.sin(2 * math.pi / N)) < 1e-15
+
+
+# ----------------------------------------------------------------------
+# load vector
+
+def test_rhs_closed_forms(oracle_lib):
+    """Both rules integrate linear forcing times P1 exactly:
+    b_i = sum_{T in Omega, T ni i} sum_j f(v_j) |T|/12 (1 + delta_ij)."""
+    mesh = square_mesh(8, delta=0.2, jitter=0.2, seed=8)
+    for r in (gauss7(), paper7()):
+        P = oracle_lib.Problem(mesh, cfg("constant", delta=0.2, rule=r))
+        b = P.rhs(f_const=[-4.0])
+        Mfull, _ = mass_matrix(mesh)
+        from inputs.meshes import Mesh
+        om = Mesh(mesh.vertices, mesh.elements[mesh.labels == 1], mesh.labels[mesh.labels == 1],
+                  mesh.h, mesh.n, mesh.m)
+        Mo, mo = mass_matrix(om)
+        assert np.abs(b - (-4.0) * mo).max() < 1e-15
+        f = 0.5 - 2.0 * mesh.vertices[:, 0] + 3.0 * mesh.vertices[:, 1]
+        b2 = P.rhs(f_affine=[(0.5, -2.0, 3.0)])
+        assert np.abs(b2 - Mo @ f).max() < 1e-15
+    # vector case: components independent
+    P = oracle_lib.Problem(mesh, cfg("peridynamic", delta=0.2, singular_n=5))
+    b = P.rhs(f_affine=[(-1.0, -2.0, 0.0), (0.0, 0.0, -1.0)])
+    f0 = -1.0 - 2.0 * mesh.vertices[:, 0]
+    f1 = -mesh.vertices[:, 1]
+    assert np.abs(b[0::2] - Mo @ f0).max() < 1e-15
+    assert np.abs(b[1::2] - Mo @ f1).max() < 1e-15
