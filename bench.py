@@ -1,0 +1,164 @@
+"""Benchmark: nonlocal P1 stiffness assembly on one MI355X.
+
+One step = the whole hot path on one synthetic workload: element geometry,
+pair search, CSR pattern (nlfem_build_pairs, reusing the handle's device
+memory), the stiffness values (nlfem_assemble) and the load vector
+(nlfem_rhs).  The metric is element-pair interactions assembled per second:
+ordered interacting pairs of the workload x steps / wall time of the timed
+steps, inputs resident in HBM.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOADS = ("invdist_h64", "const_h16", "peri_h128", "poly32_h256")
+
+
+def _workload(name, precision):
+    from inputs import workloads as W
+    if name == "invdist_h64":
+        return W.inv_dist_jittered(precision=precision)
+    if name == "const_h16":
+        w = W.small_constant()
+        w["precision"] = precision
+        return w
+    if name == "peri_h128":
+        return W.peridynamic(precision=precision)
+    if name == "poly32_h256":
+        return W.constant_polygon(precision=precision)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _config(w, precision):
+    import paper_2207_03921_amd as nl
+    from inputs.rules import polygon_dirs
+    return nl.Config(kernel=w["kernel"], c=float(w["c"]), delta=float(w["delta"]),
+                     outer_xi=w["outer"].xi, outer_w=w["outer"].w, inner_xi=w["inner"].xi,
+                     inner_w=w["inner"].w, approach=w.get("approach", "bary"),
+                     polygon_dirs=polygon_dirs(32) if w.get("approach") == "poly" else None,
+                     singular_n=int(w.get("singular_n", 0)), precision=precision)
+
+
+def _f_affine(w):
+    if w.get("f_affine") is not None:
+        return w["f_affine"]
+    return [(float(v), 0.0, 0.0) for v in w["f"]]
+
+
+def cpu_baseline(w):
+    """The oracle as it stands on the host cores: the whole workload once
+    (brute-force pair search, assembly, load vector)."""
+    import oracle
+    oracle.build(force=False)
+    P = oracle.Problem(w["mesh"], w)
+    t0 = time.perf_counter()
+    k, l, c = P.pairs()
+    P.assemble((k, l, c))
+    P.rhs(f_affine=_f_affine(w))
+    dt = time.perf_counter() - t0
+    return {"value": len(k) / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"whole workload once ({len(k)} ordered pairs, {dt:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="invdist_h64", choices=WORKLOADS)
+    ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2207_03921_amd as nl
+
+    torch.cuda.set_device(0)
+    w = _workload(args.workload, args.precision)
+    mesh = w["mesh"]
+    dm = nl.DeviceMesh.from_numpy(mesh)
+    cfg = _config(w, args.precision)
+    cfg64 = _config(w, "fp64")
+    aff = _f_affine(w)
+    stream = torch.cuda.current_stream()
+    pairs = nl.nlfem_build_pairs(dm, cfg)
+    info = nl.nlfem_pairs_info(pairs)
+    val = torch.empty(max(info["nnz"], 1), dtype=torch.float64, device="cuda")
+    b = torch.empty(cfg.ncomp * mesh.n_vertices, dtype=torch.float64, device="cuda")
+
+    def step(c):
+        nl.nlfem_build_pairs(dm, c, pairs=pairs)
+        nl.nlfem_assemble(dm, c, pairs, val=val)
+        nl.nlfem_rhs(dm, c, f_affine=aff, b=b)
+
+    def timed(c, steps, warmup):
+        for _ in range(warmup):
+            step(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(c)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_step = timed(cfg, args.steps, args.warmup)
+
+    # assemble alone (HIP events on the library's stream)
+    def assemble_ms(c, reps=20):
+        for _ in range(3):
+            nl.nlfem_assemble(dm, c, pairs, val=val)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            nl.nlfem_assemble(dm, c, pairs, val=val)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_asm = assemble_ms(cfg)
+    t_asm64 = assemble_ms(cfg64)
+    t_step64 = timed(cfg64, max(3, args.steps // 2), 1)
+    n_pairs = info["n_pairs"]
+    out = {
+        "metric": "element-pair interactions assembled/sec",
+        "value": n_pairs / t_step,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} ({w['name']})", "triangles": mesh.n_elements,
+                   "vertices": mesh.n_vertices, "ordered_pairs": n_pairs,
+                   "touching_pairs": info["n_vertex"] + info["n_edge"] + info["n_ident"],
+                   "nnz": info["nnz"], "precision": args.precision},
+        "assemble_ms": t_asm,
+        "assemble_pairs_per_s": n_pairs / (t_asm * 1e-3),
+        "fp64_plain": {"ms_per_step": t_step64 * 1e3, "value": n_pairs / t_step64,
+                       "assemble_ms": t_asm64},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * nlfem.h - C ABI of the MI355X (gfx950) nonlocal P1 finite-element
+ * assembler.
+ *
+ * The library assembles the stiffness matrix of the approximate bilinear
+ * form (Klar, Vollmann, Schulz, "nlfem", arXiv 2207.03921, Sec. 2.2,
+ * eq. biFormApprox)
+ *
+ *   A_h(phi_j, phi_i) = sum_k sum_l int_{T_k} int_{T_l}
+ *                       1_{B(x)}(y) Phi_ij(x, y) dy dx,
+ *   Phi_ij(x, y) = (phi_i(x) - phi_i(y))^T (Psi(x,y) phi_j(x) - Psi(y,x) phi_j(y))
+ *
+ * for continuous P1 ansatz functions on a triangulation labelled into the
+ * domain Omega (label 1) and the interaction domain Omega_D (label 2)
+ * (Sec. 2.2, Assumption 2), together with the load vector (f, phi_i).
+ *
+ * Conventions shared by all entry points
+ *  - All mesh, matrix and vector arrays are DEVICE pointers owned by the
+ *    caller; they must stay valid until the work enqueued on `stream`
+ *    has completed.  Quadrature tables and polygon directions are HOST
+ *    pointers, read during the call.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Every call enqueues its work on that stream and returns without
+ *    waiting, except where a call is documented as synchronising.
+ *  - Return value: NLFEM_OK (0) or a negative NLFEM_E_* code; the message of
+ *    the last failure on the calling thread is returned by
+ *    nlfem_last_error().  No call aborts or throws.
+ *  - Element vertex order may be clockwise or counter-clockwise.
+ *  - A node is a degree of freedom iff it is a vertex of some Omega element
+ *    and of no Omega_D element (Sec. 2.2, Fig. 2.1).  Elements with other
+ *    labels are ignored (Sec. 2.5 allows marking elements that are not part
+ *    of the discretisation).
+ *  - The matrix is returned in CSR form (Sec. 1: the Python front end returns
+ *    CSR) over n*M rows and n*M columns, n = 1 (scalar) or 2
+ *    (peridynamics); row/column n*node + component.  Rows of nodes that are
+ *    not degrees of freedom are empty.  Column indices ascend within a row;
+ *    the pattern holds every entry touched by some interacting element pair,
+ *    including numerically zero ones.  Splitting the columns into degrees of
+ *    freedom and Omega_D nodes yields the Dirichlet splitting of Sec. 3
+ *    (eq. inhomogeneousDirichletData).
+ */
+#ifndef NLFEM_H
+#define NLFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NLFEM_ABI_VERSION 1
+
+/* return codes */
+enum {
+    NLFEM_OK = 0,
+    NLFEM_E_INVALID = -1,   /* bad argument: NULL pointer, size <= 0, delta <= 0,
+                               weights not summing to 1/2, unsupported option */
+    NLFEM_E_MESH = -2,      /* vertex index out of range or zero-area element */
+    NLFEM_E_NOMEM = -3,     /* device allocation failed */
+    NLFEM_E_HIP = -4,       /* HIP runtime error (message has the HIP text) */
+    NLFEM_E_OVERFLOW = -5,  /* a count exceeds 32-bit column indices or an
+                               internal capacity */
+    NLFEM_E_MISMATCH = -6,  /* handle built for another mesh or configuration */
+    NLFEM_E_NODEVICE = -7   /* no HIP device available */
+};
+
+/* kernel functions Psi (Sec. 3.1 and 3.2) */
+enum {
+    NLFEM_K_CONSTANT = 0,    /* Psi = c                       (s = -1)    */
+    NLFEM_K_INV_DIST = 1,    /* Psi = c / |x - y|             (s = -1/2)  */
+    NLFEM_K_PERIDYNAMIC = 2  /* Psi = c (x-y)(x-y)^T / |x-y|^3, 2 components */
+};
+
+/* ball approximations 1_{B(x)}(y) for the Euclidean ball of radius delta */
+enum {
+    NLFEM_A_NOCAPS_BARY = 0,     /* T_l counts for x iff |x - bary(T_l)| <= delta */
+    NLFEM_A_APPROXCAPS_POLY = 1  /* regular polygon inscribed in the circle,
+                                    T_l n polygon retriangulated (Sec. 2.4.1) */
+};
+
+/* arithmetic of the quadrature of non-touching pairs */
+enum {
+    NLFEM_P_FP64 = 0,   /* everything in FP64 */
+    NLFEM_P_MIXED = 1   /* non-touching pairs in FP32 with FP32 accumulation per
+                           pair; inclusion tests, polygon clipping, touching pairs
+                           and the global sums stay FP64 */
+};
+
+/* pair classes (Sec. 2.3: intersecting pairs are vertex touching, edge
+   touching or identical) */
+enum { NLFEM_C_FAR = 0, NLFEM_C_VERTEX = 1, NLFEM_C_EDGE = 2, NLFEM_C_IDENT = 3 };
+
+typedef struct {
+    int64_t n_vertices;        /* M >= 1 */
+    int64_t n_elements;        /* K >= 1 */
+    const double *vertices;    /* device, [M][2] */
+    const int32_t *elements;   /* device, [K][3] vertex indices in [0, M) */
+    const int32_t *labels;     /* device, [K]: 1 Omega, 2 Omega_D, other = ignored */
+} nlfem_mesh;
+
+/* quadrature rule on the reference triangle {xi >= 0, xi_1 + xi_2 <= 1}
+   (Sec. 2.4.1); weights sum to 1/2.  1 <= n <= 16. */
+typedef struct {
+    int32_t n;
+    const double *xi;          /* host, [n][2] */
+    const double *w;           /* host, [n] */
+} nlfem_rule;
+
+typedef struct {
+    int32_t kernel;            /* NLFEM_K_* */
+    double c;                  /* kernel constant */
+    double delta;              /* horizon > 0 */
+    int32_t approach;          /* NLFEM_A_* */
+    int32_t polygon_n;         /* polygon vertices (approach POLY), 3..64 */
+    const double *polygon_dirs;/* host, [polygon_n][2] unit directions, CCW;
+                                  vertex j = x + delta * dir_j */
+    nlfem_rule outer;          /* rule for the outer element T_k */
+    nlfem_rule inner;          /* rule for the inner element T_l */
+    int32_t singular_n;        /* Gauss-Legendre points per direction of the
+                                  regularising transforms on touching pairs
+                                  (Sec. 2.4.2); 0 = touching pairs use the
+                                  product rule like all others.  Required > 0
+                                  for INV_DIST and PERIDYNAMIC.  0..32. */
+    int32_t precision;         /* NLFEM_P_* */
+} nlfem_config;
+
+typedef struct nlfem_pairs nlfem_pairs;   /* opaque, library-owned */
+
+typedef struct {
+    int64_t n_pairs;      /* interacting ordered pairs (k, l), labels in {1,2},
+                             at least one of them 1 */
+    int64_t n_far;        /* ... of class NLFEM_C_FAR */
+    int64_t n_vertex, n_edge, n_ident;   /* ... touching classes */
+    int64_t n_dof;        /* degree-of-freedom nodes */
+    int64_t n_rows;       /* n * n_dof non-empty matrix rows */
+    int64_t nnz;          /* stored entries of the CSR matrix */
+    int64_t n_upper_far;  /* unordered non-touching pairs processed by assemble */
+    int64_t n_upper_touch;/* unordered touching pairs processed by assemble */
+} nlfem_pairs_info_t;
+
+/* ABI version (NLFEM_ABI_VERSION of the built library). */
+int32_t nlfem_version(void);
+
+/* Message of the last failing call on this thread; valid until the next
+   call on this thread.  Never NULL. */
+const char *nlfem_last_error(void);
+
+/* Interaction traversal (Sec. 2.5): finds all interacting element pairs of
+   the mesh for `cfg` and the CSR pattern of the matrix.
+   Pair (k, l) interacts iff both labels are in {1, 2}, at least one is 1, and
+   either (singular_n > 0 and T_k, T_l share a vertex) - class = number of
+   shared vertices - or some outer quadrature point x_p of T_k sees T_l
+   through the ball approximation (class FAR).  All inclusion decisions are
+   taken in FP64 with the same operation order as the plain definition
+   (no fused multiply-add), so the pattern does not depend on `precision`.
+   *pairs: if NULL a new handle is created; otherwise the given handle is
+   rebuilt in place, reusing its device memory when large enough.
+   Synchronises with `stream` (sizes are needed to allocate).
+   Errors: E_INVALID, E_MESH, E_NOMEM, E_HIP, E_OVERFLOW, E_NODEVICE. */
+int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg,
+                      nlfem_pairs **pairs, void *stream);
+
+/* Counts of a built handle.  Synchronous.  Errors: E_INVALID. */
+int nlfem_pairs_info(const nlfem_pairs *pairs, nlfem_pairs_info_t *info);
+
+/* Ordered pair list sorted by (k, l): k[n_pairs], l[n_pairs] (int32) and
+   cls[n_pairs] (NLFEM_C_*) device arrays owned by the caller.
+   Errors: E_INVALID, E_HIP. */
+int nlfem_pairs_export(const nlfem_pairs *pairs, int32_t *k, int32_t *l,
+                       int8_t *cls, void *stream);
+
+/* CSR pattern: row_ptr[n*M + 1] (int64) and col[nnz] (int32), device arrays
+   owned by the caller.  Errors: E_INVALID, E_HIP. */
+int nlfem_csr_pattern(const nlfem_pairs *pairs, int64_t *row_ptr, int32_t *col,
+                      void *stream);
+
+/* Stiffness matrix values val[nnz] (device, FP64) in the pattern of `pairs`
+   (eq. biFormApprox with the local contributions of eq. def:localStiffness):
+   non-touching pairs by the product rule with the ball approximation
+   (Sec. 2.4.1, eq. discrete-inner), touching pairs of a singular
+   configuration by the regularising transforms (Sec. 2.4.2, Alg. 1).
+   `mesh` must be the mesh the handle was built from; `cfg` may differ from
+   the build configuration only in `c`, `precision` and `singular_n` when
+   the latter keeps its zero/non-zero status (E_MISMATCH otherwise).
+   Allocates nothing and never synchronises; uses workspace held by the
+   handle, so two assemblies with the same handle must not overlap in time.
+   Errors: E_INVALID, E_MISMATCH, E_HIP. */
+int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg,
+                   const nlfem_pairs *pairs, double *val, void *stream);
+
+/* Load vector b[n*M] (device, FP64):
+     b_(n i + c) = sum over Omega elements T containing node i of
+                   |J_T| sum_p d_p f_c(x_p) phi^_(i)(xi_p)
+   with the outer rule of `cfg` (Sec. 3, right-hand side (f, v)).  Entries
+   of nodes that are not degrees of freedom are returned too.
+   f_qp:     device [K][outer.n][n] values at the outer quadrature points, or
+   f_affine: host [n][3], f_c(x) = f_affine[c][0] + f_affine[c][1] x_1
+             + f_affine[c][2] x_2 (used when f_qp is NULL).
+   Allocates nothing and never synchronises.
+   Errors: E_INVALID, E_HIP. */
+int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_qp,
+              const double *f_affine, double *b, void *stream);
+
+/* Releases a handle and its device memory (synchronises the device). */
+void nlfem_pairs_free(nlfem_pairs *pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLFEM_H */

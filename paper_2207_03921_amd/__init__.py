@@ -1,0 +1,278 @@
+"""Python binding of libnlfem (gfx950 nonlocal P1 stiffness assembly).
+
+Thin ctypes layer over the C ABI declared in ``include/nlfem.h``: every
+function here has the name of the C entry point it marshals arguments for.
+PyTorch supplies device memory and the current HIP stream; all arithmetic
+runs in the library's kernels.  There is no fallback: if ``libnlfem.so`` is
+missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlfem.so")
+
+NLFEM_OK = 0
+ERRORS = {-1: "E_INVALID", -2: "E_MESH", -3: "E_NOMEM", -4: "E_HIP", -5: "E_OVERFLOW",
+          -6: "E_MISMATCH", -7: "E_NODEVICE"}
+K_CONSTANT, K_INV_DIST, K_PERIDYNAMIC = 0, 1, 2
+A_NOCAPS_BARY, A_APPROXCAPS_POLY = 0, 1
+P_FP64, P_MIXED = 0, 1
+C_FAR, C_VERTEX, C_EDGE, C_IDENT = 0, 1, 2, 3
+
+KERNELS = {"constant": K_CONSTANT, "inv_dist": K_INV_DIST, "peridynamic": K_PERIDYNAMIC}
+APPROACHES = {"bary": A_NOCAPS_BARY, "poly": A_APPROXCAPS_POLY}
+PRECISIONS = {"fp64": P_FP64, "mixed": P_MIXED}
+
+
+class NlfemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("n_elements", C.c_int64),
+                ("vertices", C.c_void_p), ("elements", C.c_void_p), ("labels", C.c_void_p)]
+
+
+class _Rule(C.Structure):
+    _fields_ = [("n", C.c_int32), ("xi", C.c_void_p), ("w", C.c_void_p)]
+
+
+class _Config(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("c", C.c_double), ("delta", C.c_double),
+                ("approach", C.c_int32), ("polygon_n", C.c_int32), ("polygon_dirs", C.c_void_p),
+                ("outer", _Rule), ("inner", _Rule), ("singular_n", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_pairs", "n_far", "n_vertex", "n_edge", "n_ident",
+                                         "n_dof", "n_rows", "nnz", "n_upper_far", "n_upper_touch")]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libnlfem.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NlfemError(-4, f"{LIB_PATH} not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int
+        L.nlfem_version.restype = C.c_int32
+        L.nlfem_last_error.restype = C.c_char_p
+        L.nlfem_build_pairs.argtypes = [vp, vp, C.POINTER(vp), vp]
+        L.nlfem_build_pairs.restype = i32
+        L.nlfem_pairs_info.argtypes = [vp, vp]
+        L.nlfem_pairs_info.restype = i32
+        L.nlfem_pairs_export.argtypes = [vp, vp, vp, vp, vp]
+        L.nlfem_pairs_export.restype = i32
+        L.nlfem_csr_pattern.argtypes = [vp, vp, vp, vp]
+        L.nlfem_csr_pattern.restype = i32
+        L.nlfem_assemble.argtypes = [vp, vp, vp, vp, vp]
+        L.nlfem_assemble.restype = i32
+        L.nlfem_rhs.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.nlfem_rhs.restype = i32
+        L.nlfem_pairs_free.argtypes = [vp]
+        L.nlfem_pairs_free.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != NLFEM_OK:
+        raise NlfemError(rc, lib().nlfem_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+@dataclass
+class DeviceMesh:
+    """Device copies of a mesh (vertices float64 [M,2], elements int32 [K,3],
+    labels int32 [K])."""
+    vertices: object
+    elements: object
+    labels: object
+
+    @classmethod
+    def from_numpy(cls, mesh, device="cuda"):
+        import torch
+        return cls(torch.as_tensor(np.ascontiguousarray(mesh.vertices, np.float64), device=device),
+                   torch.as_tensor(np.ascontiguousarray(mesh.elements, np.int32), device=device),
+                   torch.as_tensor(np.ascontiguousarray(mesh.labels, np.int32), device=device))
+
+    def c_struct(self):
+        import torch
+        return _Mesh(self.vertices.shape[0], self.elements.shape[0],
+                     _dev_ptr(self.vertices, torch.float64, "vertices"),
+                     _dev_ptr(self.elements, torch.int32, "elements"),
+                     _dev_ptr(self.labels, torch.int32, "labels"))
+
+
+@dataclass
+class Config:
+    """Mirror of nlfem_config; host tables are kept alive by this object."""
+    kernel: str
+    c: float
+    delta: float
+    outer_xi: np.ndarray
+    outer_w: np.ndarray
+    inner_xi: np.ndarray
+    inner_w: np.ndarray
+    approach: str = "bary"
+    polygon_dirs: np.ndarray | None = None
+    singular_n: int = 0
+    precision: str = "fp64"
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def ncomp(self) -> int:
+        return 2 if self.kernel == "peridynamic" else 1
+
+    def c_struct(self):
+        arrs = [np.ascontiguousarray(a, np.float64) for a in
+                (self.outer_xi, self.outer_w, self.inner_xi, self.inner_w)]
+        dirs = None if self.polygon_dirs is None else np.ascontiguousarray(self.polygon_dirs, np.float64)
+        self._keep = arrs + [dirs]
+        oxi, ow, ixi, iw = arrs
+        return _Config(KERNELS[self.kernel], float(self.c), float(self.delta),
+                       APPROACHES[self.approach], 0 if dirs is None else dirs.shape[0],
+                       None if dirs is None else dirs.ctypes.data,
+                       _Rule(ow.shape[0], oxi.ctypes.data, ow.ctypes.data),
+                       _Rule(iw.shape[0], ixi.ctypes.data, iw.ctypes.data),
+                       int(self.singular_n), PRECISIONS[self.precision])
+
+
+class Pairs:
+    """Owner of an nlfem_pairs handle."""
+
+    def __init__(self, ptr: C.c_void_p, ncomp: int, n_vertices: int):
+        self.ptr = ptr
+        self.ncomp = ncomp
+        self.n_vertices = n_vertices
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and self.ptr.value and _lib is not None:
+            _lib.nlfem_pairs_free(self.ptr)
+            self.ptr = C.c_void_p(None)
+
+
+def nlfem_version() -> int:
+    return int(lib().nlfem_version())
+
+
+def nlfem_last_error() -> str:
+    return lib().nlfem_last_error().decode()
+
+
+def nlfem_build_pairs(mesh: DeviceMesh, cfg: Config, pairs: Pairs | None = None, stream=None) -> Pairs:
+    cm, cc = mesh.c_struct(), cfg.c_struct()
+    h = C.c_void_p(None if pairs is None else pairs.ptr.value)
+    _check(lib().nlfem_build_pairs(C.byref(cm), C.byref(cc), C.byref(h), _stream(stream)))
+    if pairs is not None:
+        pairs.ptr = h
+        pairs.ncomp = cfg.ncomp
+        pairs.n_vertices = int(mesh.vertices.shape[0])
+        return pairs
+    return Pairs(h, cfg.ncomp, int(mesh.vertices.shape[0]))
+
+
+def nlfem_pairs_info(pairs: Pairs) -> dict:
+    info = _Info()
+    _check(lib().nlfem_pairs_info(pairs.ptr, C.byref(info)))
+    return {n: int(getattr(info, n)) for n, _ in _Info._fields_}
+
+
+def nlfem_pairs_export(pairs: Pairs, stream=None):
+    import torch
+    n = nlfem_pairs_info(pairs)["n_pairs"]
+    k = torch.empty(n, dtype=torch.int32, device="cuda")
+    l = torch.empty(n, dtype=torch.int32, device="cuda")
+    c = torch.empty(n, dtype=torch.int8, device="cuda")
+    _check(lib().nlfem_pairs_export(pairs.ptr, C.c_void_p(k.data_ptr()), C.c_void_p(l.data_ptr()),
+                                    C.c_void_p(c.data_ptr()), _stream(stream)))
+    return k, l, c
+
+
+def nlfem_csr_pattern(pairs: Pairs, stream=None):
+    import torch
+    info = nlfem_pairs_info(pairs)
+    rp = torch.empty(pairs.ncomp * pairs.n_vertices + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(max(info["nnz"], 1), dtype=torch.int32, device="cuda")
+    _check(lib().nlfem_csr_pattern(pairs.ptr, C.c_void_p(rp.data_ptr()), C.c_void_p(col.data_ptr()),
+                                   _stream(stream)))
+    return rp, col[:info["nnz"]]
+
+
+def nlfem_assemble(mesh: DeviceMesh, cfg: Config, pairs: Pairs, val=None, stream=None):
+    import torch
+    if val is None:
+        nnz = nlfem_pairs_info(pairs)["nnz"]
+        val = torch.empty(max(nnz, 1), dtype=torch.float64, device="cuda")
+    cm, cc = mesh.c_struct(), cfg.c_struct()
+    _check(lib().nlfem_assemble(C.byref(cm), C.byref(cc), pairs.ptr,
+                                C.c_void_p(_dev_ptr(val, torch.float64, "val")), _stream(stream)))
+    return val
+
+
+def nlfem_rhs(mesh: DeviceMesh, cfg: Config, f_qp=None, f_affine=None, b=None, stream=None):
+    import torch
+    n = cfg.ncomp
+    if b is None:
+        b = torch.empty(n * mesh.vertices.shape[0], dtype=torch.float64, device="cuda")
+    cm, cc = mesh.c_struct(), cfg.c_struct()
+    fq = None if f_qp is None else C.c_void_p(_dev_ptr(f_qp, torch.float64, "f_qp"))
+    aff = None
+    if f_affine is not None:
+        aff = np.ascontiguousarray(np.asarray(f_affine, np.float64).reshape(-1))
+    _check(lib().nlfem_rhs(C.byref(cm), C.byref(cc), fq, None if aff is None else aff.ctypes.data,
+                           C.c_void_p(_dev_ptr(b, torch.float64, "b")), _stream(stream)))
+    return b
+
+
+def nlfem_pairs_free(pairs: Pairs):
+    if pairs.ptr.value:
+        lib().nlfem_pairs_free(pairs.ptr)
+        pairs.ptr = C.c_void_p(None)
+
+
+def assemble(mesh: DeviceMesh, cfg: Config, f_affine=None, stream=None):
+    """Builds the pairs, assembles and returns (torch sparse CSR matrix, b)."""
+    import torch
+    pairs = nlfem_build_pairs(mesh, cfg, stream=stream)
+    rp, col = nlfem_csr_pattern(pairs, stream=stream)
+    val = nlfem_assemble(mesh, cfg, pairs, stream=stream)
+    nnz = col.shape[0]
+    N = cfg.ncomp * mesh.vertices.shape[0]
+    A = torch.sparse_csr_tensor(rp, col, val[:nnz], size=(N, N))
+    if f_affine is None:
+        f_affine = [(0.0, 0.0, 0.0)] * cfg.ncomp
+    b = nlfem_rhs(mesh, cfg, f_affine=f_affine, stream=stream)
+    return A, b

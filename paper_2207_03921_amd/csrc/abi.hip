@@ -1,0 +1,495 @@
+// Exported C ABI: argument validation, handle life cycle, device buffers and
+// the order of the build steps.  All arithmetic happens in the kernels of the
+// other translation units.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "nlfem_internal.h"
+
+namespace nlfem {
+
+namespace {
+thread_local std::string g_err = "no error";
+
+enum Buf {
+    B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
+    B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
+    B_SNBR, B_SFLAG, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF, B_NLEN, B_NPTR, B_NCOL, B_DACC, B_LAST
+};
+
+int ensure(nlfem_pairs *h, int id, size_t bytes)
+{
+    auto &b = h->bufs[id];
+    if (bytes == 0) bytes = 16;
+    if (b.p && b.cap >= bytes) return NLFEM_OK;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    const size_t want = bytes + bytes / 8;   // headroom for rebuilds that grow a little
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return set_error(NLFEM_E_NOMEM, std::string("device allocation of ") + std::to_string(want) +
+                                            " bytes failed: " + hipGetErrorString(e));
+    }
+    b.cap = want;
+    return NLFEM_OK;
+}
+
+template <typename T>
+int ensure_typed(nlfem_pairs *h, int id, int64_t n, T *&ptr)
+{
+    int rc = ensure(h, id, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    if (rc) return rc;
+    ptr = (T *)h->bufs[id].p;
+    return NLFEM_OK;
+}
+
+#define NLFEM_TRY(x)                 \
+    do {                             \
+        int _rc = (x);               \
+        if (_rc != NLFEM_OK) return _rc; \
+    } while (0)
+
+// Gauss-Legendre nodes and weights on [0, 1]: Newton's method on P_n, with P_n
+// from the three-term recurrence (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}.
+void gauss_legendre01(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;   // P_0, P_1
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);   // P_n'(z)
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = 0.5 * (1.0 - z);   // z descends with i, so x ascends on [0, 1]
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int check_rule(const nlfem_rule &r, const char *which)
+{
+    if (r.n < 1 || r.n > kMaxRule)
+        return set_error(NLFEM_E_INVALID, std::string(which) + " rule: n must be in [1, 16]");
+    if (!r.xi || !r.w) return set_error(NLFEM_E_INVALID, std::string(which) + " rule: NULL table");
+    double s = 0.0;
+    for (int p = 0; p < r.n; ++p) {
+        if (!is_finite(r.xi[2 * p]) || !is_finite(r.xi[2 * p + 1]) || !is_finite(r.w[p]))
+            return set_error(NLFEM_E_INVALID, std::string(which) + " rule: non-finite entry");
+        s += r.w[p];
+    }
+    if (std::fabs(s - 0.5) > 1e-12)
+        return set_error(NLFEM_E_INVALID, std::string(which) + " rule: weights must sum to 1/2");
+    return NLFEM_OK;
+}
+
+int check_mesh(const nlfem_mesh *m)
+{
+    if (!m) return set_error(NLFEM_E_INVALID, "mesh is NULL");
+    if (m->n_vertices < 1 || m->n_elements < 1)
+        return set_error(NLFEM_E_INVALID, "mesh needs at least one vertex and one element");
+    if (m->n_vertices > (int64_t)INT32_MAX / 2 || m->n_elements > (int64_t)INT32_MAX / 4)
+        return set_error(NLFEM_E_OVERFLOW, "mesh too large for 32-bit indices");
+    if (!m->vertices || !m->elements || !m->labels) return set_error(NLFEM_E_INVALID, "mesh array is NULL");
+    return NLFEM_OK;
+}
+
+int check_cfg(const nlfem_config *c)
+{
+    if (!c) return set_error(NLFEM_E_INVALID, "config is NULL");
+    if (c->kernel < NLFEM_K_CONSTANT || c->kernel > NLFEM_K_PERIDYNAMIC)
+        return set_error(NLFEM_E_INVALID, "unknown kernel");
+    if (!is_finite(c->c)) return set_error(NLFEM_E_INVALID, "kernel constant must be finite");
+    if (!(c->delta > 0.0) || !is_finite(c->delta)) return set_error(NLFEM_E_INVALID, "delta must be positive");
+    if (c->approach != NLFEM_A_NOCAPS_BARY && c->approach != NLFEM_A_APPROXCAPS_POLY)
+        return set_error(NLFEM_E_INVALID, "unknown ball approach");
+    if (c->precision != NLFEM_P_FP64 && c->precision != NLFEM_P_MIXED)
+        return set_error(NLFEM_E_INVALID, "unknown precision");
+    if (c->singular_n < 0 || c->singular_n > kMaxGauss)
+        return set_error(NLFEM_E_INVALID, "singular_n must be in [0, 32]");
+    if (c->kernel != NLFEM_K_CONSTANT && c->singular_n == 0)
+        return set_error(NLFEM_E_INVALID, "singular kernels need singular_n > 0 on touching pairs");
+    NLFEM_TRY(check_rule(c->outer, "outer"));
+    NLFEM_TRY(check_rule(c->inner, "inner"));
+    if (c->approach == NLFEM_A_APPROXCAPS_POLY) {
+        if (c->polygon_n < 3 || c->polygon_n > kMaxPoly)
+            return set_error(NLFEM_E_INVALID, "polygon_n must be in [3, 64]");
+        if (!c->polygon_dirs) return set_error(NLFEM_E_INVALID, "polygon_dirs is NULL");
+        const int N = c->polygon_n;
+        for (int j = 0; j < N; ++j) {
+            const double *a = c->polygon_dirs + 2 * j, *b = c->polygon_dirs + 2 * ((j + 1) % N);
+            const double *d = c->polygon_dirs + 2 * ((j + 2) % N);
+            if (!is_finite(a[0]) || !is_finite(a[1])) return set_error(NLFEM_E_INVALID, "polygon_dirs not finite");
+            // convex, counter-clockwise and containing the centre
+            if ((b[0] - a[0]) * (d[1] - b[1]) - (b[1] - a[1]) * (d[0] - b[0]) <= 0.0 ||
+                a[0] * b[1] - a[1] * b[0] <= 0.0)
+                return set_error(NLFEM_E_INVALID, "polygon must be convex, counter-clockwise, around 0");
+        }
+    }
+    return NLFEM_OK;
+}
+
+RuleArgs make_rules(const nlfem_config *c)
+{
+    RuleArgs r{};
+    r.P = c->outer.n;
+    r.Q = c->inner.n;
+    for (int p = 0; p < r.P; ++p) {
+        r.pxi[p][0] = c->outer.xi[2 * p];
+        r.pxi[p][1] = c->outer.xi[2 * p + 1];
+        r.pw[p] = c->outer.w[p];
+        r.pphi[p][0] = 1.0 - r.pxi[p][0] - r.pxi[p][1];
+        r.pphi[p][1] = r.pxi[p][0];
+        r.pphi[p][2] = r.pxi[p][1];
+    }
+    for (int q = 0; q < r.Q; ++q) {
+        r.qxi[q][0] = c->inner.xi[2 * q];
+        r.qxi[q][1] = c->inner.xi[2 * q + 1];
+        r.qw[q] = c->inner.w[q];
+        r.qphi[q][0] = 1.0 - r.qxi[q][0] - r.qxi[q][1];
+        r.qphi[q][1] = r.qxi[q][0];
+        r.qphi[q][2] = r.qxi[q][1];
+    }
+    r.same = r.P == r.Q && std::memcmp(r.pxi, r.qxi, sizeof(double) * 2 * r.P) == 0 &&
+             std::memcmp(r.pw, r.qw, sizeof(double) * r.P) == 0;
+    return r;
+}
+
+PolyArgs make_poly(const nlfem_config *c)
+{
+    PolyArgs p{};
+    if (c->approach != NLFEM_A_APPROXCAPS_POLY) return p;
+    p.N = c->polygon_n;
+    double rmin = 1e300;
+    for (int j = 0; j < p.N; ++j) {
+        p.dir[j][0] = c->polygon_dirs[2 * j];
+        p.dir[j][1] = c->polygon_dirs[2 * j + 1];
+    }
+    for (int j = 0; j < p.N; ++j) {
+        const int j1 = (j + 1) % p.N;
+        const double ex = p.dir[j1][0] - p.dir[j][0], ey = p.dir[j1][1] - p.dir[j][1];
+        const double cr = p.dir[j][0] * p.dir[j1][1] - p.dir[j][1] * p.dir[j1][0];
+        rmin = std::min(rmin, cr / std::sqrt(ex * ex + ey * ey));
+    }
+    p.r_in = c->delta * rmin;
+    return p;
+}
+
+int ncomp_of(int kernel) { return kernel == NLFEM_K_PERIDYNAMIC ? 2 : 1; }
+
+int check_device()
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        return set_error(NLFEM_E_NODEVICE, "no HIP device available");
+    }
+    return NLFEM_OK;
+}
+
+int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStream_t s)
+{
+    NLFEM_HIP(hipGetDevice(&h->device));
+    h->mesh_vertices = m->vertices;
+    h->mesh_elements = m->elements;
+    h->mesh_labels = m->labels;
+    h->M = m->n_vertices;
+    h->K = m->n_elements;
+    h->kernel = cfg->kernel;
+    h->ncomp = ncomp_of(cfg->kernel);
+    h->approach = cfg->approach;
+    h->singular = cfg->singular_n > 0;
+    h->delta = cfg->delta;
+    h->rules = make_rules(cfg);
+    h->poly = make_poly(cfg);
+    const int64_t K = h->K, M = h->M, K1 = K + 1, P = h->rules.P;
+
+    // geometry ---------------------------------------------------------
+    NLFEM_TRY(ensure_typed(h, B_V0, K, h->v0));
+    NLFEM_TRY(ensure_typed(h, B_J, K, h->J));
+    NLFEM_TRY(ensure_typed(h, B_DET, K, h->det));
+    NLFEM_TRY(ensure_typed(h, B_BARY, K, h->bary));
+    NLFEM_TRY(ensure_typed(h, B_XP, K * P, h->xp));
+    NLFEM_TRY(ensure_typed(h, B_FLAGS, M, h->node_flags));
+    NLFEM_TRY(ensure_typed(h, B_ERR, 1, h->err));
+    NLFEM_TRY(ensure_typed(h, B_RED, 16, h->red));
+    NLFEM_TRY(launch_geometry(h, m, s));
+    unsigned long long red[16];
+    int32_t err = 0;
+    NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof red, hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipStreamSynchronize(s));
+    if (err & kErrIndex) return set_error(NLFEM_E_MESH, "element vertex index out of range");
+    if (err & kErrArea) return set_error(NLFEM_E_MESH, "element with zero area");
+    const double x0 = key_to_double(red[0]), y0 = key_to_double(red[1]);
+    const double x1 = key_to_double(red[2]), y1 = key_to_double(red[3]);
+    const double rq = key_to_double(red[4]), rv = key_to_double(red[5]);
+    const bool any = x1 >= x0 && y1 >= y0;
+
+    // uniform grid over the barycentres -----------------------------------
+    double far = h->delta + rq + (h->approach == NLFEM_A_APPROXCAPS_POLY ? rv : 0.0);
+    far = far * (1.0 + 1e-9) + 1e-300;
+    h->far_reach = far;
+    double reach = std::max(far, h->singular ? 2.0 * rv * (1.0 + 1e-9) : 0.0);
+    h->gr = 2;
+    h->gh = reach / h->gr;
+    h->gx0 = any ? x0 : 0.0;
+    h->gy0 = any ? y0 : 0.0;
+    const double wx = any ? x1 - x0 : 0.0, wy = any ? y1 - y0 : 0.0;
+    // keep the number of cells in the order of the number of elements
+    for (;;) {
+        const double nx = std::floor(wx / h->gh) + 1.0, ny = std::floor(wy / h->gh) + 1.0;
+        if (nx * ny <= 2.0 * (double)K + 64.0) {
+            h->gnx = (int32_t)nx;
+            h->gny = (int32_t)ny;
+            break;
+        }
+        h->gh *= 1.5;
+    }
+    const int64_t ncell = (int64_t)h->gnx * h->gny;
+    NLFEM_TRY(ensure_typed(h, B_CELLCNT, ncell + 1, h->cell_cnt));
+    NLFEM_TRY(ensure_typed(h, B_CELLSTART, ncell + 1, h->cell_start));
+    NLFEM_TRY(ensure_typed(h, B_CELLFILL, ncell, h->cell_fill));
+    NLFEM_TRY(ensure_typed(h, B_CELLELEMS, K, h->cell_elems));
+    NLFEM_TRY(ensure_typed(h, B_CELLOF, K, h->cell_of));
+    const int64_t scan_need = scan_tmp_size(std::max<int64_t>({K1, M + 1, ncell + 1})) + 1;
+    NLFEM_TRY(ensure_typed(h, B_SCAN, scan_need, h->scan_tmp));
+    h->scan_cap = (int64_t)(h->bufs[B_SCAN].cap / sizeof(int64_t));
+    NLFEM_TRY(launch_cell_count(h, s));
+    NLFEM_TRY(exclusive_scan(h->cell_cnt, h->cell_start, ncell, h->scan_tmp, h->scan_cap, s));
+    NLFEM_TRY(launch_cell_fill(h, s));
+    NLFEM_HIP(hipMemcpyAsync(red + 6, h->red + 6, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipStreamSynchronize(s));
+    h->max_cell = (int32_t)red[6];
+
+    // pair search: count, scan, fill ---------------------------------------
+    NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
+    NLFEM_TRY(ensure_typed(h, B_LOFF, kLsLast * K1, h->loff));
+    NLFEM_HIP(hipMemsetAsync(h->lcnt, 0, sizeof(int64_t) * kLsLast * K1, s));
+    NLFEM_HIP(hipMemsetAsync(h->red + 7, 0, sizeof(unsigned long long), s));
+    NLFEM_TRY(launch_pairs(h, m, false, s));
+    for (int k = 0; k < kLsLast; ++k)
+        NLFEM_TRY(exclusive_scan(h->lcnt + k * K1, h->loff + k * K1, K, h->scan_tmp, h->scan_cap, s));
+    int64_t tot[kLsLast];
+    for (int k = 0; k < kLsLast; ++k)
+        NLFEM_HIP(hipMemcpyAsync(&tot[k], h->loff + k * K1 + K, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipMemcpyAsync(red + 7, h->red + 7, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipStreamSynchronize(s));
+    h->nS = tot[kLsS];
+    h->nP = tot[kLsP];
+    h->nUF = tot[kLsUF];
+    h->nUTc[0] = tot[kLsUI];
+    h->nUTc[1] = tot[kLsUE];
+    h->nUTc[2] = tot[kLsUV];
+    h->nUT = h->nUTc[0] + h->nUTc[1] + h->nUTc[2];
+    h->max_S = (int64_t)red[7];
+    h->n_pairs = h->nP;
+    h->n_ident = h->nUTc[0];
+    h->n_edge = 2 * h->nUTc[1];
+    h->n_vertex = 2 * h->nUTc[2];
+    h->n_far = h->n_pairs - h->n_ident - h->n_edge - h->n_vertex;
+    NLFEM_TRY(ensure_typed(h, B_SNBR, h->nS, h->snbr));
+    NLFEM_TRY(ensure_typed(h, B_SFLAG, h->nS, h->sflag));
+    NLFEM_TRY(ensure_typed(h, B_UE, h->nUF, h->ue));
+    NLFEM_TRY(ensure_typed(h, B_UF, h->nUF, h->uf));
+    NLFEM_TRY(ensure_typed(h, B_UMEF, h->nUF, h->um_ef));
+    NLFEM_TRY(ensure_typed(h, B_UMFE, h->nUF, h->um_fe));
+    NLFEM_TRY(ensure_typed(h, B_TE, h->nUT, h->te));
+    NLFEM_TRY(ensure_typed(h, B_TF, h->nUT, h->tf));
+    NLFEM_TRY(launch_pairs(h, m, true, s));
+
+    // node -> element incidence --------------------------------------------
+    NLFEM_TRY(ensure_typed(h, B_NLEN, M + 1, h->nlen));
+    NLFEM_TRY(ensure_typed(h, B_NPTR, M + 1, h->nptr));
+    NLFEM_TRY(ensure_typed(h, B_NEPTR, M + 1, h->ne_ptr));
+    NLFEM_TRY(ensure_typed(h, B_NELIST, 3 * K, h->ne_list));
+    NLFEM_TRY(ensure_typed(h, B_NEFILL, M, h->ne_fill));
+    NLFEM_TRY(launch_incidence_count(h, m, s));
+    NLFEM_TRY(exclusive_scan(h->nlen, h->ne_ptr, M, h->scan_tmp, h->scan_cap, s));
+    NLFEM_TRY(launch_incidence(h, m, s));
+    NLFEM_TRY(launch_count_dofs(h, s));
+
+    // CSR pattern -------------------------------------------------------------
+    int hcap = 64;
+    while (hcap < 4 * (h->max_S + 8) && hcap < 16384) hcap <<= 1;
+    for (;;) {
+        h->hcap = hcap;
+        NLFEM_HIP(hipMemsetAsync(h->err, 0, sizeof(int32_t), s));
+        NLFEM_TRY(launch_csr(h, m, false, s));
+        NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
+        NLFEM_HIP(hipStreamSynchronize(s));
+        if (!(err & kErrRowCap)) break;
+        if (hcap >= 16384) return set_error(NLFEM_E_OVERFLOW, "matrix row longer than the symbolic capacity");
+        hcap <<= 1;
+    }
+    NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s));
+    NLFEM_HIP(hipMemcpyAsync(&h->nnz_node, h->nptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipMemcpyAsync(red + 8, h->red + 8, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipStreamSynchronize(s));
+    h->n_dof = (int64_t)red[8];
+    NLFEM_TRY(ensure_typed(h, B_NCOL, h->nnz_node, h->ncol));
+    NLFEM_TRY(launch_csr(h, m, true, s));
+
+    // workspace of the assembly ----------------------------------------------
+    const int NN = h->ncomp * h->ncomp;
+    h->dacc_stride = (int64_t)(h->rules.same ? h->rules.P : h->rules.P + h->rules.Q) * NN;
+    NLFEM_TRY(ensure_typed(h, B_DACC, K * h->dacc_stride, h->dacc));
+    NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipStreamSynchronize(s));
+    if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");
+    return NLFEM_OK;
+}
+
+bool same_build(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c)
+{
+    if (h->mesh_vertices != m->vertices || h->mesh_elements != m->elements || h->mesh_labels != m->labels)
+        return false;
+    if (h->M != m->n_vertices || h->K != m->n_elements) return false;
+    if (h->kernel != c->kernel || h->approach != c->approach || h->delta != c->delta) return false;
+    if (h->singular != (c->singular_n > 0)) return false;
+    const RuleArgs r = make_rules(c);
+    if (r.P != h->rules.P || r.Q != h->rules.Q) return false;
+    if (std::memcmp(r.pxi, h->rules.pxi, sizeof r.pxi) || std::memcmp(r.pw, h->rules.pw, sizeof r.pw) ||
+        std::memcmp(r.qxi, h->rules.qxi, sizeof r.qxi) || std::memcmp(r.qw, h->rules.qw, sizeof r.qw))
+        return false;
+    if (c->approach == NLFEM_A_APPROXCAPS_POLY) {
+        const PolyArgs p = make_poly(c);
+        if (p.N != h->poly.N || std::memcmp(p.dir, h->poly.dir, sizeof p.dir)) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+int set_error(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? NLFEM_E_NOMEM : NLFEM_E_HIP;
+}
+
+}  // namespace nlfem
+
+using namespace nlfem;
+
+extern "C" {
+
+int32_t nlfem_version(void) { return NLFEM_ABI_VERSION; }
+
+const char *nlfem_last_error(void) { return g_err.c_str(); }
+
+int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pairs **pairs, void *stream)
+{
+    if (!pairs) return set_error(NLFEM_E_INVALID, "pairs is NULL");
+    NLFEM_TRY(check_mesh(mesh));
+    NLFEM_TRY(check_cfg(cfg));
+    NLFEM_TRY(check_device());
+    const bool fresh = *pairs == nullptr;
+    nlfem_pairs *h = fresh ? new (std::nothrow) nlfem_pairs() : *pairs;
+    if (!h) return set_error(NLFEM_E_NOMEM, "host allocation failed");
+    int rc = build(mesh, cfg, h, (hipStream_t)stream);
+    if (rc != NLFEM_OK) {
+        if (fresh) nlfem_pairs_free(h);
+        else h->K = 0;   // leave a reused handle unusable rather than half built
+        return rc;
+    }
+    *pairs = h;
+    return NLFEM_OK;
+}
+
+int nlfem_pairs_info(const nlfem_pairs *h, nlfem_pairs_info_t *info)
+{
+    if (!h || !info) return set_error(NLFEM_E_INVALID, "NULL argument");
+    info->n_pairs = h->n_pairs;
+    info->n_far = h->n_far;
+    info->n_vertex = h->n_vertex;
+    info->n_edge = h->n_edge;
+    info->n_ident = h->n_ident;
+    info->n_dof = h->n_dof;
+    info->n_rows = h->n_dof * h->ncomp;
+    info->nnz = h->nnz_node * h->ncomp * h->ncomp;
+    info->n_upper_far = h->nUF;
+    info->n_upper_touch = h->nUT;
+    return NLFEM_OK;
+}
+
+int nlfem_pairs_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls, void *stream)
+{
+    if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle is NULL or not built");
+    if (h->n_pairs > 0 && (!k || !l || !cls)) return set_error(NLFEM_E_INVALID, "NULL output array");
+    return launch_export(h, k, l, cls, (hipStream_t)stream);
+}
+
+int nlfem_csr_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, void *stream)
+{
+    if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle is NULL or not built");
+    if (!row_ptr || (h->nnz_node > 0 && !col)) return set_error(NLFEM_E_INVALID, "NULL output array");
+    return launch_pattern(h, row_ptr, col, (hipStream_t)stream);
+}
+
+int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg, const nlfem_pairs *h, double *val,
+                   void *stream)
+{
+    if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle is NULL or not built");
+    NLFEM_TRY(check_mesh(mesh));
+    NLFEM_TRY(check_cfg(cfg));
+    if (h->nnz_node > 0 && !val) return set_error(NLFEM_E_INVALID, "val is NULL");
+    if (!same_build(h, mesh, cfg))
+        return set_error(NLFEM_E_MISMATCH, "mesh or configuration differs from the one the pairs were built for");
+    int dev = -1;
+    NLFEM_HIP(hipGetDevice(&dev));
+    if (dev != h->device) return set_error(NLFEM_E_MISMATCH, "current device differs from the build device");
+    GaussArgs g{};
+    g.n = cfg->singular_n;
+    if (g.n > 0) gauss_legendre01(g.n, g.x, g.w);
+    return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
+}
+
+int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_qp, const double *f_affine,
+              double *b, void *stream)
+{
+    NLFEM_TRY(check_mesh(mesh));
+    if (!cfg) return set_error(NLFEM_E_INVALID, "config is NULL");
+    if (cfg->kernel < NLFEM_K_CONSTANT || cfg->kernel > NLFEM_K_PERIDYNAMIC)
+        return set_error(NLFEM_E_INVALID, "unknown kernel");
+    NLFEM_TRY(check_rule(cfg->outer, "outer"));
+    if (!b) return set_error(NLFEM_E_INVALID, "b is NULL");
+    if (!f_qp && !f_affine) return set_error(NLFEM_E_INVALID, "give f_qp or f_affine");
+    const int nc = ncomp_of(cfg->kernel);
+    if (!f_qp)
+        for (int t = 0; t < 3 * nc; ++t)
+            if (!is_finite(f_affine[t])) return set_error(NLFEM_E_INVALID, "f_affine not finite");
+    NLFEM_TRY(check_device());
+    return launch_rhs(mesh, make_rules(cfg), nc, f_qp, f_affine, b, (hipStream_t)stream);
+}
+
+void nlfem_pairs_free(nlfem_pairs *h)
+{
+    if (!h) return;
+    for (auto &b : h->bufs)
+        if (b.p) (void)hipFree(b.p);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+// Internal declarations of the gfx950 nonlocal assembler (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/nlfem.h"
+
+namespace nlfem {
+
+constexpr int kMaxRule = 16;      // outer/inner rule points (2 status bits each in a u32)
+constexpr int kMaxGauss = 32;     // 1-D Gauss points of the touching-pair rules
+constexpr int kMaxPoly = 64;      // polygon vertices
+constexpr int kWave = 64;
+
+// status of one outer point with respect to an inner element
+enum : uint32_t { kOut = 0u, kWhole = 1u, kStraddle = 2u };
+
+// error bits raised by kernels, read back at synchronising calls
+enum : int32_t {
+    kErrIndex = 1,       // vertex index out of range
+    kErrArea = 2,        // zero-area element
+    kErrRowCap = 4,      // CSR row exceeded the symbolic capacity
+    kErrSlot = 8,        // scatter target not in the pattern (internal bug)
+    kErrCell = 16,       // cell occupancy above the pair-search tile size
+};
+
+// Quadrature tables passed by value (kernel arguments live in scalar registers).
+struct RuleArgs {
+    int32_t P, Q;
+    int32_t same;                  // outer and inner rule identical
+    double pxi[kMaxRule][2], pw[kMaxRule];
+    double qxi[kMaxRule][2], qw[kMaxRule];
+    double pphi[kMaxRule][3], qphi[kMaxRule][3];   // phi^ at the points
+};
+
+struct PolyArgs {
+    int32_t N;
+    double r_in;                   // inscribed radius delta cos(pi/N)
+    double dir[kMaxPoly][2];
+};
+
+struct GaussArgs {
+    int32_t n;
+    double x[kMaxGauss], w[kMaxGauss];   // on [0, 1]
+};
+
+// counters filled by the pair search (ordered pairs per class)
+enum { kCntPairs = 0, kCntFar, kCntVertex, kCntEdge, kCntIdent, kCntLast };
+
+// per-element count arrays of the pair search, each [K + 1]
+enum { kLsS = 0, kLsP, kLsUF, kLsUI, kLsUE, kLsUV, kLsLast };
+
+}  // namespace nlfem
+
+struct nlfem_pairs {
+    int device = 0;
+    // what the handle was built from
+    const double *mesh_vertices = nullptr;
+    const int32_t *mesh_elements = nullptr;
+    const int32_t *mesh_labels = nullptr;
+    int64_t M = 0, K = 0;
+    int32_t ncomp = 1;
+    int32_t kernel = 0, approach = 0, singular = 0;
+    double delta = 0.0;
+    nlfem::RuleArgs rules{};
+    nlfem::PolyArgs poly{};
+    // counts
+    int64_t nS = 0, nP = 0, nUF = 0, nUT = 0, nUTc[3] = {0, 0, 0};   // ident, edge, vertex
+    int64_t n_pairs = 0, n_far = 0, n_vertex = 0, n_edge = 0, n_ident = 0;
+    int64_t n_dof = 0, nnz_node = 0;
+    int32_t hcap = 0;
+    // grid
+    double gx0 = 0, gy0 = 0, gh = 0, far_reach = 0;
+    int64_t max_S = 0;
+    int32_t gnx = 0, gny = 0, gr = 2, max_cell = 0;   // gr: neighbour-cell radius
+    // ---- device memory (grow-only buffers, sized by cap_*) ----
+    // element geometry (SoA)
+    double2 *v0 = nullptr;       // [K]
+    double4 *J = nullptr;        // [K]  (J00, J01, J10, J11), J = [v1 - v0, v2 - v0]
+    double *det = nullptr;       // [K]  |det J|
+    double2 *bary = nullptr;     // [K]
+    double2 *xp = nullptr;       // [K * P] outer quadrature points (FP64)
+    uint32_t *node_flags = nullptr;  // [M] bit0 vertex of an Omega element, bit1 of an Omega_D one
+    int32_t *err = nullptr;      // [1] error bits
+    unsigned long long *red = nullptr;   // [16] bbox keys 0-3, radii 4-5, max cell 6, max |S| 7, dofs 8
+    unsigned long long *counters = nullptr;  // [kCntLast]
+    // node -> element incidence
+    int64_t *ne_ptr = nullptr;   // [M + 1]
+    int32_t *ne_list = nullptr;  // [3K]
+    int32_t *ne_fill = nullptr;  // [M]
+    // grid
+    int64_t *cell_cnt = nullptr;    // [ncell + 1]
+    int64_t *cell_start = nullptr;  // [ncell + 1]
+    int32_t *cell_fill = nullptr;   // [ncell]
+    int32_t *cell_elems = nullptr;  // [K]
+    int32_t *cell_of = nullptr;     // [K]
+    // per-element counts and offsets [kLsLast][K + 1]
+    int64_t *lcnt = nullptr;
+    int64_t *loff = nullptr;
+    int64_t *scan_tmp = nullptr;
+    // symmetric neighbour list S(e)
+    int32_t *snbr = nullptr;     // [nS]
+    uint8_t *sflag = nullptr;    // [nS] bit0 (e,f) in P, bit1 (f,e) in P, bits 2-3 class
+    // unordered non-touching pairs e <= f with 2-bit point status per direction
+    int32_t *ue = nullptr, *uf = nullptr;     // [nUF]
+    uint32_t *um_ef = nullptr, *um_fe = nullptr;
+    // unordered touching pairs e <= f: [ident | edge | vertex]
+    int32_t *te = nullptr, *tf = nullptr;     // [nUT]
+    // node-level CSR of degree-of-freedom rows
+    int64_t *nlen = nullptr;     // [M + 1]
+    int64_t *nptr = nullptr;     // [M + 1]
+    int32_t *ncol = nullptr;     // [nnz_node]
+    // per-element accumulators of the diagonal blocks: [K][P][n*n] (+ inner rule part)
+    double *dacc = nullptr;
+    int64_t dacc_stride = 0;     // doubles per element
+    // grow-only device buffers behind the typed pointers above
+    struct DevBuf {
+        void *p = nullptr;
+        size_t cap = 0;
+    };
+    DevBuf bufs[40];
+    int64_t scan_cap = 0;
+};
+
+namespace nlfem {
+
+// error reporting (abi.hip) --------------------------------------------
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+
+#define NLFEM_HIP(call)                                               \
+    do {                                                              \
+        hipError_t _e = (call);                                       \
+        if (_e != hipSuccess) return ::nlfem::hip_error(_e, #call);   \
+    } while (0)
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// scan.hip: out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total.
+int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap,
+                   hipStream_t s);
+int64_t scan_tmp_size(int64_t n);
+double key_to_double(unsigned long long key);
+
+// geometry.hip
+int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
+int launch_incidence(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);   // needs ne_ptr scanned
+int launch_incidence_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
+int launch_count_dofs(nlfem_pairs *h, hipStream_t s);   // -> red[8]
+// grid + pairs (pairs.hip)
+int launch_cell_count(nlfem_pairs *h, hipStream_t s);
+int launch_cell_fill(nlfem_pairs *h, hipStream_t s);   // also sorts cells, max occupancy -> red[6]
+int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
+// csr.hip
+int launch_csr(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
+int launch_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
+int launch_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls, hipStream_t s);
+// assemble.hip
+int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg,
+                    const GaussArgs &g, double *val, hipStream_t s);
+// rhs.hip
+int launch_rhs(const nlfem_mesh *m, const RuleArgs &r, int ncomp, const double *f_qp,
+               const double *f_affine, double *b, hipStream_t s);
+
+}  // namespace nlfem

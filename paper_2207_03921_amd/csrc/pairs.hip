@@ -1,0 +1,490 @@
+// Interaction search (Sec. 2.5): all element pairs (e, f) that interact,
+// found with a uniform bucket grid over the barycentres instead of the
+// breadth-first traversal of Alg. 2.
+//
+// A block owns a tile of up to kTE elements of one grid cell and streams the
+// elements of the (2 gr + 1)^2 neighbouring cells through LDS in chunks of
+// kCH candidates.  Each wave takes one element e of the tile at a time and
+// tests 64 candidates per step, one per lane; ballots give every lane its
+// output position, so the lists come out in a fixed order (cell order, then
+// element id) without sorting.
+//
+// For every unordered pair both directions are tested at once:
+//   status_p(e -> f) for the outer points x_p of e against T_f, and
+//   status_q(f -> e) for the outer points of f against T_e,
+// so the symmetric neighbour list S(e) = {f : (e,f) or (f,e) interacts}
+// and the unordered lists used by the assembly are built in one pass.
+//
+// All decisions are FP64 without contraction and follow the operation
+// order of the plain definition:
+//   barycentre ball: (x - b).(x - b) <= delta^2,
+//   polygon ball: Sutherland-Hodgman clip of T_f by the regular N-gon around
+//   x (vertex j = x + delta dir_j), nonzero shoelace area; the clip is only
+//   run when cheap bounds cannot decide (vertices well inside the inscribed
+//   circle: whole; triangle well outside the circumscribed circle: empty).
+#include "nlfem_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace nlfem {
+namespace {
+
+constexpr int kTE = 64;      // elements of a cell per block
+constexpr int kCH = 128;     // candidates staged per chunk
+constexpr int kBlock = 256;  // four waves
+constexpr int kMaxNbr = 49;  // neighbour cells for gr <= 3
+
+struct PairArgs {
+    int64_t K, K1;
+    const int32_t *E;
+    const int32_t *lab;
+    const double *V;
+    const double2 *bary;
+    const double2 *xp;
+    const int64_t *cell_start;
+    const int32_t *cell_elems;
+    int32_t gnx, gny, gr, P;
+    int32_t singular, poly;
+    double delta, delta2, reach2, rin2, out2;
+    int64_t *lcnt;          // count pass: [kLsLast][K1]
+    unsigned long long *maxS;   // count pass: max |S(e)|
+    const int64_t *loff;    // fill pass:  [kLsLast][K1]
+    int64_t baseE, baseV;   // offsets of the edge / vertex classes in te, tf
+    int32_t *snbr;
+    uint8_t *sflag;
+    int32_t *ue, *uf;
+    uint32_t *um_ef, *um_fe;
+    int32_t *te, *tf;
+};
+
+// ---- polygon ball -------------------------------------------------------
+
+__device__ double point_segment_dist2(double px, double py, double ax, double ay, double bx, double by)
+{
+    double ex = bx - ax, ey = by - ay;
+    double l2 = ex * ex + ey * ey;
+    double t = l2 > 0.0 ? ((px - ax) * ex + (py - ay) * ey) / l2 : 0.0;
+    t = fmin(1.0, fmax(0.0, t));
+    double dx = px - (ax + t * ex), dy = py - (ay + t * ey);
+    return dx * dx + dy * dy;
+}
+
+__device__ double point_triangle_dist2(double px, double py, const double2 v[3])
+{
+    double s0 = (v[1].x - v[0].x) * (py - v[0].y) - (v[1].y - v[0].y) * (px - v[0].x);
+    double s1 = (v[2].x - v[1].x) * (py - v[1].y) - (v[2].y - v[1].y) * (px - v[1].x);
+    double s2 = (v[0].x - v[2].x) * (py - v[2].y) - (v[0].y - v[2].y) * (px - v[2].x);
+    if ((s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0)) return 0.0;
+    double d = point_segment_dist2(px, py, v[0].x, v[0].y, v[1].x, v[1].y);
+    d = fmin(d, point_segment_dist2(px, py, v[1].x, v[1].y, v[2].x, v[2].y));
+    d = fmin(d, point_segment_dist2(px, py, v[2].x, v[2].y, v[0].x, v[0].y));
+    return d;
+}
+
+// Exact replica of the clip of the plain definition; returns the status.
+__device__ __noinline__ uint32_t clip_status(double x, double y, const double2 v[3], const PolyArgs &pg,
+                                             double delta)
+{
+    double bx[2][kMaxPoly + 4], by[2][kMaxPoly + 4];
+    for (int a = 0; a < 3; ++a) {
+        bx[0][a] = v[a].x;
+        by[0][a] = v[a].y;
+    }
+    int cnt = 3, cur = 0;
+    const int N = pg.N;
+    for (int j = 0; j < N && cnt > 0; ++j) {
+        int j1 = (j + 1) % N;
+        double qa0 = x + delta * pg.dir[j][0];
+        double qa1 = y + delta * pg.dir[j][1];
+        double qb0 = x + delta * pg.dir[j1][0];
+        double qb1 = y + delta * pg.dir[j1][1];
+        double e0 = qb0 - qa0, e1 = qb1 - qa1;
+        int nxt = 1 - cur, m = 0;
+        for (int i = 0; i < cnt; ++i) {
+            int i1 = (i + 1) % cnt;
+            double p0 = bx[cur][i], p1 = by[cur][i];
+            double q0 = bx[cur][i1], q1 = by[cur][i1];
+            double dp = e0 * (p1 - qa1) - e1 * (p0 - qa0);
+            double dq = e0 * (q1 - qa1) - e1 * (q0 - qa0);
+            bool pin = dp >= 0.0, qin = dq >= 0.0;
+            if (pin) {
+                bx[nxt][m] = p0;
+                by[nxt][m] = p1;
+                m++;
+            }
+            if (pin != qin) {
+                double t = dp / (dp - dq);
+                bx[nxt][m] = p0 + t * (q0 - p0);
+                by[nxt][m] = p1 + t * (q1 - p1);
+                m++;
+            }
+        }
+        cnt = m;
+        cur = nxt;
+    }
+    if (cnt < 3) return kOut;
+    double s = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+        int i1 = (i + 1) % cnt;
+        s += bx[cur][i] * by[cur][i1] - bx[cur][i1] * by[cur][i];
+    }
+    double area = 0.5 * s;
+    if (!(fabs(area) > 0.0)) return kOut;
+    if (cnt == 3 && bx[cur][0] == v[0].x && by[cur][0] == v[0].y && bx[cur][1] == v[1].x &&
+        by[cur][1] == v[1].y && bx[cur][2] == v[2].x && by[cur][2] == v[2].y)
+        return kWhole;
+    return kStraddle;
+}
+
+__device__ inline uint32_t poly_status(double x, double y, const double2 v[3], const PolyArgs &pg,
+                                       const PairArgs &a)
+{
+    double d0 = (v[0].x - x) * (v[0].x - x) + (v[0].y - y) * (v[0].y - y);
+    double d1 = (v[1].x - x) * (v[1].x - x) + (v[1].y - y) * (v[1].y - y);
+    double d2 = (v[2].x - x) * (v[2].x - x) + (v[2].y - y) * (v[2].y - y);
+    if (d0 < a.rin2 && d1 < a.rin2 && d2 < a.rin2) return kWhole;
+    if (point_triangle_dist2(x, y, v) > a.out2) return kOut;
+    return clip_status(x, y, v, pg, a.delta);
+}
+
+// ---- the tile kernel --------------------------------------------------------
+
+template <bool FILL, bool POLY>
+__global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int cell = blockIdx.x;
+    const int64_t cs = a.cell_start[cell], ce = a.cell_start[cell + 1];
+    const int64_t t0 = cs + (int64_t)blockIdx.y * kTE;
+    if (t0 >= ce) return;
+    const int ne = (int)min((int64_t)kTE, ce - t0);
+    const int cx = cell % a.gnx, cy = cell / a.gnx;
+
+    double2 *c_b = (double2 *)smem;                       // [kCH]
+    double2 *c_xp = c_b + kCH;                            // [P][kCH]
+    double2 *c_v = c_xp + a.P * kCH;                      // [3][kCH] (polygon ball)
+    int64_t *e_off = (int64_t *)(c_v + (POLY ? 3 * kCH : 0));   // [kTE][kLsLast]
+    int32_t *c_id = (int32_t *)(e_off + kTE * kLsLast);   // [kCH]
+    int32_t *c_lab = c_id + kCH;                          // [kCH]
+    int32_t *c_nd = c_lab + kCH;                          // [3][kCH]
+    __shared__ int64_t nb_start[kMaxNbr], nb_pre[kMaxNbr + 1];
+    __shared__ int nb_n;
+
+    if (threadIdx.x == 0) {
+        int n = 0;
+        int64_t pre = 0;
+        for (int yy = max(0, cy - a.gr); yy <= min(a.gny - 1, cy + a.gr); ++yy)
+            for (int xx = max(0, cx - a.gr); xx <= min(a.gnx - 1, cx + a.gr); ++xx) {
+                int c = yy * a.gnx + xx;
+                nb_start[n] = a.cell_start[c];
+                nb_pre[n] = pre;
+                pre += a.cell_start[c + 1] - a.cell_start[c];
+                n++;
+            }
+        nb_pre[n] = pre;
+        nb_n = n;
+    }
+    for (int t = threadIdx.x; t < kTE * kLsLast; t += kBlock) {
+        int i = t / kLsLast, kind = t % kLsLast;
+        int64_t v = 0;
+        if (FILL && i < ne) v = a.loff[kind * a.K1 + a.cell_elems[t0 + i]];
+        e_off[t] = v;
+    }
+    __syncthreads();
+    const int64_t total = nb_pre[nb_n];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+
+    for (int64_t c0 = 0; c0 < total; c0 += kCH) {
+        const int nch = (int)min((int64_t)kCH, total - c0);
+        if (threadIdx.x < nch) {
+            const int64_t g = c0 + threadIdx.x;
+            int j = 0;
+            while (nb_pre[j + 1] <= g) ++j;
+            const int32_t f = a.cell_elems[nb_start[j] + (g - nb_pre[j])];
+            const int t = threadIdx.x;
+            c_id[t] = f;
+            c_lab[t] = a.lab[f];
+            c_nd[t] = a.E[3 * (int64_t)f];
+            c_nd[kCH + t] = a.E[3 * (int64_t)f + 1];
+            c_nd[2 * kCH + t] = a.E[3 * (int64_t)f + 2];
+            c_b[t] = a.bary[f];
+            for (int p = 0; p < a.P; ++p) c_xp[p * kCH + t] = a.xp[(int64_t)f * a.P + p];
+            if (POLY)
+                for (int v = 0; v < 3; ++v) {
+                    int32_t n = c_nd[v * kCH + t];
+                    c_v[v * kCH + t] = make_double2(a.V[2 * (int64_t)n], a.V[2 * (int64_t)n + 1]);
+                }
+        }
+        __syncthreads();
+        for (int i = wv; i < ne; i += 4) {
+            const int32_t e = a.cell_elems[t0 + i];
+            const int32_t lab_e = a.lab[e];
+            const int32_t ne0 = a.E[3 * (int64_t)e], ne1 = a.E[3 * (int64_t)e + 1],
+                          ne2 = a.E[3 * (int64_t)e + 2];
+            const double2 be = a.bary[e];
+            double2 ve[3];
+            if (POLY) {
+                ve[0] = make_double2(a.V[2 * (int64_t)ne0], a.V[2 * (int64_t)ne0 + 1]);
+                ve[1] = make_double2(a.V[2 * (int64_t)ne1], a.V[2 * (int64_t)ne1 + 1]);
+                ve[2] = make_double2(a.V[2 * (int64_t)ne2], a.V[2 * (int64_t)ne2 + 1]);
+            }
+            int64_t off[kLsLast];
+            for (int k = 0; k < kLsLast; ++k) off[k] = e_off[i * kLsLast + k];
+            for (int jj = 0; jj < nch; jj += 64) {
+                const int j = jj + lane;
+                const bool valid = j < nch;
+                bool inS = false, inP = false, isUF = false;
+                int cls = 0;
+                uint32_t mef = 0, mfe = 0;
+                int32_t f = -1;
+                uint8_t flags = 0;
+                if (valid) {
+                    f = c_id[j];
+                    const int32_t lab_f = c_lab[j];
+                    const bool act = (lab_f == 1 || lab_f == 2) && (lab_e == 1 || lab_f == 1);
+                    const int32_t f0 = c_nd[j], f1 = c_nd[kCH + j], f2 = c_nd[2 * kCH + j];
+                    const int shared = (ne0 == f0) + (ne0 == f1) + (ne0 == f2) + (ne1 == f0) +
+                                       (ne1 == f1) + (ne1 == f2) + (ne2 == f0) + (ne2 == f1) +
+                                       (ne2 == f2);
+                    const bool touch = a.singular && shared > 0;
+                    if (act && !touch) {
+                        const double2 bf = c_b[j];
+                        const double dbx = be.x - bf.x, dby = be.y - bf.y;
+                        if (dbx * dbx + dby * dby <= a.reach2) {
+                            if (!POLY) {
+                                for (int p = 0; p < a.P; ++p) {
+                                    const double2 x = a.xp[(int64_t)e * a.P + p];
+                                    const double dx = x.x - bf.x, dy = x.y - bf.y;
+                                    if (dx * dx + dy * dy <= a.delta2) mef |= kWhole << (2 * p);
+                                }
+                                for (int q = 0; q < a.P; ++q) {
+                                    const double2 x = c_xp[q * kCH + j];
+                                    const double dx = x.x - be.x, dy = x.y - be.y;
+                                    if (dx * dx + dy * dy <= a.delta2) mfe |= kWhole << (2 * q);
+                                }
+                            } else {
+                                double2 vf[3] = {c_v[j], c_v[kCH + j], c_v[2 * kCH + j]};
+                                for (int p = 0; p < a.P; ++p) {
+                                    const double2 x = a.xp[(int64_t)e * a.P + p];
+                                    mef |= poly_status(x.x, x.y, vf, pg, a) << (2 * p);
+                                }
+                                for (int q = 0; q < a.P; ++q) {
+                                    const double2 x = c_xp[q * kCH + j];
+                                    mfe |= poly_status(x.x, x.y, ve, pg, a) << (2 * q);
+                                }
+                            }
+                        }
+                    }
+                    if (touch) cls = shared;
+                    inS = act && (touch || (mef | mfe) != 0u);
+                    inP = act && (touch || mef != 0u);
+                    flags = (uint8_t)((touch ? 3 : ((mef != 0u) | ((mfe != 0u) << 1))) | (cls << 2));
+                    isUF = inS && !touch && f >= e;
+                }
+                const unsigned long long bS = __ballot(inS);
+                const unsigned long long bP = __ballot(inP);
+                const unsigned long long bF = __ballot(isUF);
+                const unsigned long long bI = __ballot(inS && cls == 3);
+                const unsigned long long bE = __ballot(inS && cls == 2 && f > e);
+                const unsigned long long bV = __ballot(inS && cls == 1 && f > e);
+                if (FILL) {
+                    if (inS) {
+                        const int64_t o = off[kLsS] + __popcll(bS & lt);
+                        a.snbr[o] = f;
+                        a.sflag[o] = flags;
+                    }
+                    if (isUF) {
+                        const int64_t o = off[kLsUF] + __popcll(bF & lt);
+                        a.ue[o] = e;
+                        a.uf[o] = f;
+                        a.um_ef[o] = mef;
+                        a.um_fe[o] = f == e ? 0u : mfe;
+                    }
+                    if (inS && cls == 3) {
+                        const int64_t o = off[kLsUI] + __popcll(bI & lt);
+                        a.te[o] = e;
+                        a.tf[o] = f;
+                    }
+                    if (inS && cls == 2 && f > e) {
+                        const int64_t o = a.baseE + off[kLsUE] + __popcll(bE & lt);
+                        a.te[o] = e;
+                        a.tf[o] = f;
+                    }
+                    if (inS && cls == 1 && f > e) {
+                        const int64_t o = a.baseV + off[kLsUV] + __popcll(bV & lt);
+                        a.te[o] = e;
+                        a.tf[o] = f;
+                    }
+                }
+                off[kLsS] += __popcll(bS);
+                off[kLsP] += __popcll(bP);
+                off[kLsUF] += __popcll(bF);
+                off[kLsUI] += __popcll(bI);
+                off[kLsUE] += __popcll(bE);
+                off[kLsUV] += __popcll(bV);
+            }
+            if (lane == 0)
+                for (int k = 0; k < kLsLast; ++k) e_off[i * kLsLast + k] = off[k];
+        }
+        __syncthreads();
+    }
+    if (!FILL) {
+        for (int t = threadIdx.x; t < ne * kLsLast; t += kBlock) {
+            int i = t / kLsLast, kind = t % kLsLast;
+            a.lcnt[kind * a.K1 + a.cell_elems[t0 + i]] = e_off[t];
+            if (kind == kLsS) atomicMax(a.maxS, (unsigned long long)e_off[t]);
+        }
+    }
+}
+
+// ---- grid build ---------------------------------------------------------------
+
+struct CellArgs {
+    int64_t K;
+    const int32_t *lab;
+    const double2 *bary;
+    double x0, y0, h;
+    int32_t nx, ny;
+    int64_t *cnt;
+    const int64_t *start;
+    int32_t *fill;
+    int32_t *elems;
+    int32_t *cell_of;
+};
+
+__global__ void __launch_bounds__(256) k_cell_count(CellArgs a)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.K) return;
+    const int32_t l = a.lab[k];
+    if (l != 1 && l != 2) {
+        a.cell_of[k] = -1;
+        return;
+    }
+    const double2 b = a.bary[k];
+    int cx = (int)floor((b.x - a.x0) / a.h), cy = (int)floor((b.y - a.y0) / a.h);
+    cx = min(max(cx, 0), a.nx - 1);
+    cy = min(max(cy, 0), a.ny - 1);
+    const int c = cy * a.nx + cx;
+    a.cell_of[k] = c;
+    atomicAdd((unsigned long long *)&a.cnt[c], 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_cell_fill(CellArgs a)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.K) return;
+    const int c = a.cell_of[k];
+    if (c < 0) return;
+    const int32_t pos = atomicAdd(&a.fill[c], 1);
+    a.elems[a.start[c] + pos] = (int32_t)k;
+}
+
+// per-cell insertion sort (cells hold tens of elements) and max occupancy
+__global__ void __launch_bounds__(256) k_cell_sort(int64_t ncell, const int64_t *start, int32_t *elems,
+                                                   unsigned long long *maxcnt)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int64_t s = start[c], e = start[c + 1];
+    for (int64_t i = s + 1; i < e; ++i) {
+        int32_t v = elems[i];
+        int64_t j = i - 1;
+        while (j >= s && elems[j] > v) {
+            elems[j + 1] = elems[j];
+            --j;
+        }
+        elems[j + 1] = v;
+    }
+    atomicMax(maxcnt, (unsigned long long)(e - s));
+}
+
+CellArgs cell_args(nlfem_pairs *h)
+{
+    return CellArgs{h->K, h->mesh_labels, h->bary, h->gx0, h->gy0, h->gh, h->gnx, h->gny,
+                    h->cell_cnt, h->cell_start, h->cell_fill, h->cell_elems, h->cell_of};
+}
+
+}  // namespace
+
+int launch_cell_count(nlfem_pairs *h, hipStream_t s)
+{
+    const int64_t ncell = (int64_t)h->gnx * h->gny;
+    NLFEM_HIP(hipMemsetAsync(h->cell_cnt, 0, sizeof(int64_t) * (ncell + 1), s));
+    hipLaunchKernelGGL(k_cell_count, dim3(grid_for(h->K, 256)), dim3(256), 0, s, cell_args(h));
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
+
+int launch_cell_fill(nlfem_pairs *h, hipStream_t s)
+{
+    const int64_t ncell = (int64_t)h->gnx * h->gny;
+    NLFEM_HIP(hipMemsetAsync(h->cell_fill, 0, sizeof(int32_t) * ncell, s));
+    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(h->K, 256)), dim3(256), 0, s, cell_args(h));
+    NLFEM_HIP(hipMemsetAsync(h->red + 6, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, 256)), dim3(256), 0, s, ncell, h->cell_start,
+                       h->cell_elems, h->red + 6);
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
+
+int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
+{
+    const int64_t ncell = (int64_t)h->gnx * h->gny;
+    if ((2 * h->gr + 1) * (2 * h->gr + 1) > kMaxNbr)
+        return set_error(NLFEM_E_INVALID, "grid neighbour radius too large");
+    PairArgs a{};
+    a.K = h->K;
+    a.K1 = h->K + 1;
+    a.E = m->elements;
+    a.lab = m->labels;
+    a.V = m->vertices;
+    a.bary = h->bary;
+    a.xp = h->xp;
+    a.cell_start = h->cell_start;
+    a.cell_elems = h->cell_elems;
+    a.gnx = h->gnx;
+    a.gny = h->gny;
+    a.gr = h->gr;
+    a.P = h->rules.P;
+    a.singular = h->singular;
+    a.poly = h->approach == NLFEM_A_APPROXCAPS_POLY;
+    a.delta = h->delta;
+    a.delta2 = h->delta * h->delta;
+    // conservative reach of a non-touching interaction between barycentres
+    a.reach2 = h->far_reach * h->far_reach;
+    const double rin = h->poly.r_in * (1.0 - 1e-12);
+    a.rin2 = rin * rin;
+    const double out = h->delta * (1.0 + 1e-12);
+    a.out2 = out * out;
+    a.lcnt = h->lcnt;
+    a.maxS = h->red + 7;
+    a.loff = h->loff;
+    a.baseE = h->nUTc[0];
+    a.baseV = h->nUTc[0] + h->nUTc[1];
+    a.snbr = h->snbr;
+    a.sflag = h->sflag;
+    a.ue = h->ue;
+    a.uf = h->uf;
+    a.um_ef = h->um_ef;
+    a.um_fe = h->um_fe;
+    a.te = h->te;
+    a.tf = h->tf;
+    const int slices = (h->max_cell + kTE - 1) / kTE;
+    if (slices <= 0) return NLFEM_OK;
+    const size_t lds = sizeof(double2) * (size_t)kCH * (1 + a.P + (a.poly ? 3 : 0)) +
+                       sizeof(int64_t) * kTE * kLsLast + sizeof(int32_t) * kCH * 5;
+    dim3 grid((unsigned)ncell, (unsigned)slices);
+    if (a.poly) {
+        if (fill) hipLaunchKernelGGL((k_pairs<true, true>), grid, dim3(kBlock), lds, s, a, h->poly);
+        else hipLaunchKernelGGL((k_pairs<false, true>), grid, dim3(kBlock), lds, s, a, h->poly);
+    } else {
+        if (fill) hipLaunchKernelGGL((k_pairs<true, false>), grid, dim3(kBlock), lds, s, a, h->poly);
+        else hipLaunchKernelGGL((k_pairs<false, false>), grid, dim3(kBlock), lds, s, a, h->poly);
+    }
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
+
+}  // namespace nlfem
