@@ -16,7 +16,8 @@ thread_local std::string g_err = "no error";
 enum Buf {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
-    B_SNBR, B_SFLAG, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF, B_NLEN, B_NPTR, B_NCOL, B_DACC, B_LAST
+    B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
+    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_LAST
 };
 
 int ensure(nlfem_pairs *h, int id, size_t bytes)
@@ -304,8 +305,15 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->n_edge = 2 * h->nUTc[1];
     h->n_vertex = 2 * h->nUTc[2];
     h->n_far = h->n_pairs - h->n_ident - h->n_edge - h->n_vertex;
+    if (h->nS >= (int64_t)INT32_MAX || h->nUF >= (int64_t)INT32_MAX || h->nUT >= (int64_t)INT32_MAX)
+        return set_error(NLFEM_E_OVERFLOW, "more than 2^31 neighbour entries");
+    NLFEM_TRY(ensure_typed(h, B_SNBRT, h->nS, h->snbr_tmp));
+    NLFEM_TRY(ensure_typed(h, B_SFLAGT, h->nS, h->sflag_tmp));
+    NLFEM_TRY(ensure_typed(h, B_SMASKT, h->nS, h->smask_tmp));
     NLFEM_TRY(ensure_typed(h, B_SNBR, h->nS, h->snbr));
     NLFEM_TRY(ensure_typed(h, B_SFLAG, h->nS, h->sflag));
+    NLFEM_TRY(ensure_typed(h, B_SMASK, h->nS, h->smask));
+    NLFEM_TRY(ensure_typed(h, B_SREC, h->nS, h->srec));
     NLFEM_TRY(ensure_typed(h, B_UE, h->nUF, h->ue));
     NLFEM_TRY(ensure_typed(h, B_UF, h->nUF, h->uf));
     NLFEM_TRY(ensure_typed(h, B_UMEF, h->nUF, h->um_ef));
@@ -313,6 +321,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_TE, h->nUT, h->te));
     NLFEM_TRY(ensure_typed(h, B_TF, h->nUT, h->tf));
     NLFEM_TRY(launch_pairs(h, m, true, s));
+    NLFEM_TRY(launch_sort_lists(h, s));
+    NLFEM_HIP(hipMemsetAsync(h->srec, 0xff, sizeof(int32_t) * (size_t)std::max<int64_t>(h->nS, 1), s));
+    NLFEM_TRY(launch_worklists(h, m, s));
 
     // node -> element incidence --------------------------------------------
     NLFEM_TRY(ensure_typed(h, B_NLEN, M + 1, h->nlen));
@@ -331,6 +342,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     for (;;) {
         h->hcap = hcap;
         NLFEM_HIP(hipMemsetAsync(h->err, 0, sizeof(int32_t), s));
+        NLFEM_HIP(hipMemsetAsync(h->red + 9, 0, sizeof(unsigned long long), s));
         NLFEM_TRY(launch_csr(h, m, false, s));
         NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
@@ -340,16 +352,20 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     }
     NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s));
     NLFEM_HIP(hipMemcpyAsync(&h->nnz_node, h->nptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipMemcpyAsync(red + 8, h->red + 8, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipMemcpyAsync(red + 8, h->red + 8, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
     h->n_dof = (int64_t)red[8];
+    h->max_row = (int64_t)red[9];
     NLFEM_TRY(ensure_typed(h, B_NCOL, h->nnz_node, h->ncol));
     NLFEM_TRY(launch_csr(h, m, true, s));
 
-    // workspace of the assembly ----------------------------------------------
-    const int NN = h->ncomp * h->ncomp;
-    h->dacc_stride = (int64_t)(h->rules.same ? h->rules.P : h->rules.P + h->rules.Q) * NN;
-    NLFEM_TRY(ensure_typed(h, B_DACC, K * h->dacc_stride, h->dacc));
+    // workspace of the assembly: one result record per unordered pair
+    h->far_stride = far_record_stride(h->ncomp);
+    h->touch_stride = touch_record_stride(h->ncomp);
+    double *far_rec = nullptr;
+    NLFEM_TRY(ensure_typed(h, B_FARREC, h->nUF * h->far_stride, far_rec));
+    h->far_rec = far_rec;
+    NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
     NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
     if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");

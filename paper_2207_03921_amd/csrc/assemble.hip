@@ -1,62 +1,42 @@
-// Stiffness-matrix values: local contributions (eq. def:localStiffness) of all
-// interacting pairs, summed into the CSR pattern (eq. biFormApprox).
+// Stiffness-matrix values: the local contributions (eq. def:localStiffness) of
+// all interacting pairs, summed into the CSR pattern (eq. biFormApprox).
 //
-// Non-touching pairs (truncation quadrature, Sec. 2.4.1).  An unordered pair
-// {e, f} is processed once for both ordered pairs (e,f) and (f,e).  With the
-// same outer and inner rule both directions share the kernel values
+// Phase 1 computes one result per unordered pair; phase 2 owns the matrix
+// rows and gathers.  No global atomics, no zero fill: every stored entry is
+// written exactly once by the wave that owns its row.
+//
+// Non-touching pairs (truncation quadrature, Sec. 2.4.1).  For {e, f} both
+// ordered pairs (e,f) and (f,e) are evaluated together.  With the same rule
+// on both sides they share the kernel values
 //   G_pq = w_p |J_e| w_q |J_f| Psi(x_p(e) - x_q(f)),
-// and with the inclusion indicators s_p (x_p(e) sees T_f) and t_q (x_q(f)
-// sees T_e) the four terms of eq. case-one-factoredOut of both directions add
-// up to
-//   rows e, cols e:  sum_p alpha_p phi_p phi_p^T,   alpha_p = sum_q H_pq
-//   rows f, cols f:  sum_q beta_q  phi_q phi_q^T,   beta_q  = sum_p H_pq
-//   rows e, cols f:  X = -Phi_e^T H Phi_f,  rows f, cols e: X^T
-// with H_pq = G_pq (s_p + t_q).  alpha and beta are summed per element in a
-// small accumulator (7 values per element instead of 9 matrix entries per
-// pair); a last pass turns them into the element-diagonal blocks.  The self
-// pair (e, e) is the single ordered pair with t = 0.
+// and with the point indicators s_p (x_p(e) sees T_f) and t_q (x_q(f) sees
+// T_e) the four terms of eq. case-one-factoredOut of both directions become
+//   rows e, cols f:  X  = -Phi_e^T H Phi_f,        H_pq = G_pq (s_p + t_q)
+//   rows e, cols e:  De = sum_p (sum_q H_pq) phi_p phi_p^T
+//   rows f, cols f:  Df = sum_q (sum_p H_pq) phi_q phi_q^T
+//   rows f, cols e:  X^T.
+// The record of the pair holds X, De and Df (FP32 in the mixed form: FP32
+// quadrature with FP32 accumulation per pair).  The self pair (e, e) is the
+// single ordered pair with t = 0 and stores X + X^T and De + Df.
 //
-// Touching pairs of a singular configuration (Sec. 2.4.2, Alg. 1) use the
+// Touching pairs of a singular configuration (Sec. 2.4.2, Alg. 1): the
 // regularising transforms to (0,1)^4 with the radial direction integrated in
-// closed form: the integrand is homogeneous of degree d = 2 + deg(Psi) in
-// the radial variable, so the Gauss rule in that direction (exact for the
-// polynomial it meets) can be replaced by its exact value.  What remains:
+// closed form.  The integrand is homogeneous of degree d = 2 + deg(Psi) in
+// the radial variable and the Gauss rule integrates that direction exactly,
+// so it is replaced by its exact value.  What remains:
 //   identical: 6 hexagon sectors x n points,   factor 1/((d+2)(d+3)(d+4))
 //   edge:      4 faces x n^2 points,           factor 1/((d+3)(d+4))
 //   vertex:    2 regions x n^3 points,          factor 1/(d+4)
-// For a symmetric kernel the rules give L_fe = L_ef, so each unordered
-// touching pair adds 2 L_ef (L_ee for the identical pair).
+// A group of lanes shares one pair and reduces through cross-lane shuffles.
+// For a symmetric kernel the rules give L_fe = L_ef, so a row that meets the
+// pair only through one of its elements adds 2 L, a row of a shared vertex
+// meets it twice and adds L each time.
 #include "nlfem_internal.h"
 
 namespace nlfem {
 namespace {
 
-struct FarArgs {
-    int64_t n;
-    const int32_t *ue, *uf;
-    const uint32_t *m_ef, *m_fe;
-    const int32_t *E;
-    const double2 *v0;
-    const double4 *J;
-    const double *det;
-    const uint32_t *node_flags;
-    const int64_t *nptr;
-    const int32_t *ncol;
-    double *val;
-    double *daccA;     // accumulator of the A-role points (on e)
-    double *daccB;     // accumulator of the B-role points (on f)
-    int64_t dstride;   // doubles per element
-    double c;
-    int32_t use_s, use_t;
-    int32_t *err;
-};
-
-// rule points of the two roles (A on e, B on f)
-struct RoleArgs {
-    int32_t PA, PB;
-    double xa[kMaxRule][2], wa[kMaxRule], pa[kMaxRule][3];
-    double xb[kMaxRule][2], wb[kMaxRule], pb[kMaxRule][3];
-};
+// ------------------------------------------------------------------ helpers
 
 __device__ inline double rsqrt64(double x)
 {
@@ -68,46 +48,17 @@ __device__ inline double rsqrt64(double x)
     }
     return y;
 }
-__device__ inline float rsqrt32(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsq(double x) { return rsqrt64(x); }
-__device__ inline float rsq(float x) { return rsqrt32(x); }
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// position of column j in node row i, -1 if absent
-__device__ inline int64_t find_col(const int64_t *nptr, const int32_t *ncol, int32_t i, int32_t j)
-{
-    int64_t lo = nptr[i], hi = nptr[i + 1];
-    const int64_t base = lo;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (ncol[mid] < j) lo = mid + 1;
-        else hi = mid;
-    }
-    if (lo < nptr[i + 1] && ncol[lo] == j) return lo - base;
-    return -1;
-}
+template <int KER>
+struct Ker {
+    static constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
+    static constexpr int NK = NC == 1 ? 1 : 3;   // stored values of a symmetric NC x NC block
+    static constexpr int D = KER == NLFEM_K_CONSTANT ? 2 : 1;   // homogeneity degree of the integrand
+};
 
-// add an n x n block v[c][d] at node row i, node column j
-template <int NC>
-__device__ inline void add_block(const int64_t *nptr, const int32_t *ncol, double *val, int32_t *err,
-                                 int32_t i, int32_t j, const double *v)
-{
-    const int64_t pos = find_col(nptr, ncol, i, j);
-    if (pos < 0) {
-        atomicOr(err, kErrSlot);
-        return;
-    }
-    if (NC == 1) {
-        atomicAdd(&val[nptr[i] + pos], v[0]);
-    } else {
-        const int64_t len = nptr[i + 1] - nptr[i];
-        const int64_t b = (int64_t)NC * NC * nptr[i];
-        for (int c = 0; c < NC; ++c)
-            for (int d = 0; d < NC; ++d)
-                atomicAdd(&val[b + (int64_t)c * NC * len + (int64_t)NC * pos + d], v[c * NC + d]);
-    }
-}
-
-// kernel values; for NC == 2 the symmetric 2x2 block (k00, k01, k11)
+// kernel values; for two components the symmetric block (k00, k01, k11)
 template <int KER, typename T>
 __device__ inline void kernel_eval(T zx, T zy, T c, T *k)
 {
@@ -124,221 +75,246 @@ __device__ inline void kernel_eval(T zx, T zy, T c, T *k)
     }
 }
 
-// ---------------------------------------------------------------------------
-// non-touching pairs, barycentre ball (every point status is out or whole)
+__device__ inline int sym_index(int r, int s, int D)
+{
+    if (r > s) {
+        const int t = r;
+        r = s;
+        s = t;
+    }
+    return r * D - r * (r - 1) / 2 + (s - r);
+}
+
+// Vertex order of the transforms.  identical: the stored order; edge:
+// (P0, P1, A, B) with P0 < P1 the shared nodes, A and B the third vertices
+// of the first and second element; vertex: (P0, A1, A2, B1, B2) with P0 the
+// shared node and each element's other vertices in cyclic order after P0.
+__device__ inline int touch_frame(int cls, const int32_t *ek, const int32_t *el, int32_t *n)
+{
+    if (cls == 3) {
+        n[0] = ek[0];
+        n[1] = ek[1];
+        n[2] = ek[2];
+        return 3;
+    }
+    if (cls == 2) {
+        int32_t sh0 = -1, sh1 = -1, A = -1, B = -1;
+        for (int i = 0; i < 3; ++i) {
+            const bool in = ek[i] == el[0] || ek[i] == el[1] || ek[i] == el[2];
+            if (in) {
+                if (sh0 < 0) sh0 = ek[i];
+                else sh1 = ek[i];
+            } else {
+                A = ek[i];
+            }
+            const bool inl = el[i] == ek[0] || el[i] == ek[1] || el[i] == ek[2];
+            if (!inl) B = el[i];
+        }
+        n[0] = min(sh0, sh1);
+        n[1] = max(sh0, sh1);
+        n[2] = A;
+        n[3] = B;
+        return 4;
+    }
+    int ia = 0, ib = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (ek[i] == el[j]) {
+                ia = i;
+                ib = j;
+            }
+    n[0] = ek[ia];
+    n[1] = ek[(ia + 1) % 3];
+    n[2] = ek[(ia + 2) % 3];
+    n[3] = el[(ib + 1) % 3];
+    n[4] = el[(ib + 2) % 3];
+    return 5;
+}
+
+__device__ inline double2 vtx(const double *V, int32_t n) { return make_double2(V[2 * (int64_t)n], V[2 * (int64_t)n + 1]); }
+
+// ------------------------------------------------------ phase 1: far pairs
+
+struct FarArgs {
+    int64_t n;
+    const int32_t *ue, *uf;
+    const uint32_t *m_ef, *m_fe;
+    const double2 *v0;
+    const double4 *J;
+    const double *det;
+    void *rec;
+    int32_t stride;
+    double c;
+    int32_t same;
+};
+
+// rule points of the two roles (A on e, B on f)
+struct RoleArgs {
+    int32_t PA, PB;
+    double xa[kMaxRule][2], wa[kMaxRule], pa[kMaxRule][3];
+    double xb[kMaxRule][2], wb[kMaxRule], pb[kMaxRule][3];
+};
 
 template <int KER, typename T, int PM>
-__global__ void __launch_bounds__(256) k_far_bary(FarArgs a, RoleArgs r)
+__device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double4 &Je, const double4 &Jf,
+                                     double dete, double detf, uint32_t ms, uint32_t mt, T cc,
+                                     T (&X)[3][3][Ker<KER>::NK], T (&De)[6][Ker<KER>::NK],
+                                     T (&Df)[6][Ker<KER>::NK])
 {
-    constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
-    constexpr int NK = NC == 1 ? 1 : 3;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.n) return;
+    constexpr int NK = Ker<KER>::NK;
+    constexpr int PMAX = PM > 0 ? PM : kMaxRule;
     const int PA = PM > 0 ? PM : r.PA;
     const int PB = PM > 0 ? PM : r.PB;
-    const int32_t e = a.ue[idx], f = a.uf[idx];
-    const uint32_t ms = a.use_s ? a.m_ef[idx] : 0u;
-    const uint32_t mt = a.use_t ? a.m_fe[idx] : 0u;
-    const double2 v0e = a.v0[e], v0f = a.v0[f];
-    const double4 Je = a.J[e], Jf = a.J[f];
-    const T dx = (T)(v0e.x - v0f.x), dy = (T)(v0e.y - v0f.y);
-    const T cc = (T)a.c;
-    constexpr int PMAX = PM > 0 ? PM : kMaxRule;
-    T ox[PMAX], oy[PMAX], we0[PMAX], we[PMAX];
-    T fx[PMAX], fy[PMAX], wf[PMAX];
-    const double dete = a.det[e], detf = a.det[f];
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-        if (p < PA) {
-            ox[p] = (T)(Je.x * r.xa[p][0] + Je.y * r.xa[p][1]) + dx;
-            oy[p] = (T)(Je.z * r.xa[p][0] + Je.w * r.xa[p][1]) + dy;
-            we0[p] = (T)(r.wa[p] * dete);
-            we[p] = we0[p] * (T)((ms >> (2 * p)) & 1u);
-        }
-        if (p < PB) {
-            fx[p] = (T)(Jf.x * r.xb[p][0] + Jf.y * r.xb[p][1]);
-            fy[p] = (T)(Jf.z * r.xb[p][0] + Jf.w * r.xb[p][1]);
-            wf[p] = (T)(r.wb[p] * detf);
-        }
-    }
-    T alpha[PMAX][NK], beta[PMAX][NK], tm[PMAX][3][NK];
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p)
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            alpha[p][k] = 0;
-            beta[p][k] = 0;
-            tm[p][0][k] = tm[p][1][k] = tm[p][2][k] = 0;
-        }
+    T fx[PMAX], fy[PMAX], wf[PMAX], tf[PMAX];
+    T beta[PMAX][NK];
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) {
-        if (q >= PB) continue;
-        const T tq = (T)((mt >> (2 * q)) & 1u) * wf[q];
-        const T wq = wf[q];
+        if (q < PB) {
+            fx[q] = (T)(Jf.x * r.xb[q][0] + Jf.y * r.xb[q][1]);
+            fy[q] = (T)(Jf.z * r.xb[q][0] + Jf.w * r.xb[q][1]);
+            wf[q] = (T)(r.wb[q] * detf);
+            tf[q] = wf[q] * (T)((mt >> (2 * q)) & 1u);
+        }
 #pragma unroll
-        for (int p = 0; p < PMAX; ++p) {
-            if (p >= PA) continue;
-            const T zx = ox[p] - fx[q], zy = oy[p] - fy[q];
+        for (int k = 0; k < NK; ++k) beta[q][k] = 0;
+    }
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+        if (p >= PA) continue;
+        const T ox = (T)(Je.x * r.xa[p][0] + Je.y * r.xa[p][1]) + dx;
+        const T oy = (T)(Je.z * r.xa[p][0] + Je.w * r.xa[p][1]) + dy;
+        const T we0 = (T)(r.wa[p] * dete);
+        const T we = we0 * (T)((ms >> (2 * p)) & 1u);
+        T alpha[NK], tm[3][NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) alpha[k] = tm[0][k] = tm[1][k] = tm[2][k] = 0;
+#pragma unroll
+        for (int q = 0; q < PMAX; ++q) {
+            if (q >= PB) continue;
+            const T zx = ox - fx[q], zy = oy - fy[q];
             T kv[NK];
             kernel_eval<KER, T>(zx, zy, cc, kv);
-            // H = G (s_p + t_q), G = w_p|J_e| w_q|J_f| Psi
-            const T wgt = we[p] * wq + we0[p] * tq;
+            const T wgt = we * wf[q] + we0 * tf[q];   // w_p|J_e| w_q|J_f| (s_p + t_q)
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
                 const T hv = wgt * kv[k];
-                alpha[p][k] += hv;
+                alpha[k] += hv;
                 beta[q][k] += hv;
-                tm[p][0][k] += hv * (T)r.pb[q][0];
-                tm[p][1][k] += hv * (T)r.pb[q][1];
-                tm[p][2][k] += hv * (T)r.pb[q][2];
+                tm[0][k] += hv * (T)r.pb[q][0];
+                tm[1][k] += hv * (T)r.pb[q][1];
+                tm[2][k] += hv * (T)r.pb[q][2];
             }
         }
-    }
-    // X_ab = -sum_p phi_pa tm[p][b]
-    double X[3][3][NK];
+        const T pp[3] = {(T)r.pa[p][0], (T)r.pa[p][1], (T)r.pa[p][2]};
 #pragma unroll
-    for (int ia = 0; ia < 3; ++ia)
-#pragma unroll
-        for (int ib = 0; ib < 3; ++ib)
-#pragma unroll
-            for (int k = 0; k < NK; ++k) {
-                T s = 0;
-#pragma unroll
-                for (int p = 0; p < PMAX; ++p)
-                    if (p < PA) s += (T)r.pa[p][ia] * tm[p][ib][k];
-                X[ia][ib][k] = -(double)s;
-            }
-    const int32_t ne[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
-    const int32_t nf[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
-    bool dof_e[3], dof_f[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        dof_e[i] = a.node_flags[ne[i]] == 1u;
-        dof_f[i] = a.node_flags[nf[i]] == 1u;
-    }
-#pragma unroll
-    for (int ia = 0; ia < 3; ++ia)
-#pragma unroll
-        for (int ib = 0; ib < 3; ++ib) {
-            double blk[NC * NC], blkT[NC * NC];
-            if (NC == 1) {
-                blk[0] = blkT[0] = X[ia][ib][0];
-            } else {
-                blk[0] = X[ia][ib][0];
-                blk[1] = X[ia][ib][1];
-                blk[2] = X[ia][ib][1];
-                blk[3] = X[ia][ib][2];
-                for (int t = 0; t < 4; ++t) blkT[t] = blk[t];   // symmetric 2x2
-            }
-            if (dof_e[ia]) add_block<NC>(a.nptr, a.ncol, a.val, a.err, ne[ia], nf[ib], blk);
-            if (dof_f[ib]) add_block<NC>(a.nptr, a.ncol, a.val, a.err, nf[ib], ne[ia], blkT);
-        }
-    const bool any_e = dof_e[0] || dof_e[1] || dof_e[2];
-    const bool any_f = dof_f[0] || dof_f[1] || dof_f[2];
-    constexpr int NN = NC * NC;
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-        if (any_e && p < PA)
-#pragma unroll
-            for (int k = 0; k < NK; ++k) atomicAdd(&a.daccA[(int64_t)e * a.dstride + p * NN + k], (double)alpha[p][k]);
-        if (any_f && p < PB)
-#pragma unroll
-            for (int k = 0; k < NK; ++k) atomicAdd(&a.daccB[(int64_t)f * a.dstride + p * NN + k], (double)beta[p][k]);
-    }
-}
-
-// element-diagonal blocks from the per-element accumulators
-struct DiagArgs {
-    int64_t K;
-    const int64_t *sptr;     // [K + 1] offsets of the neighbour lists
-    const int32_t *E;
-    const uint32_t *node_flags;
-    const int64_t *nptr;
-    const int32_t *ncol;
-    double *val;
-    const double *dacc;
-    int64_t dstride;
-    int32_t P, Q, same;
-    int32_t *err;
-};
-
-template <int NC>
-__global__ void __launch_bounds__(256) k_diag(DiagArgs a, RuleArgs r)
-{
-    constexpr int NK = NC == 1 ? 1 : 3;
-    constexpr int NN = NC * NC;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.K) return;
-    if (a.sptr[e + 1] == a.sptr[e]) return;   // no interacting pair: nothing to add
-    const int32_t nd[3] = {a.E[3 * e], a.E[3 * e + 1], a.E[3 * e + 2]};
-    bool dof[3];
-    for (int i = 0; i < 3; ++i) dof[i] = a.node_flags[nd[i]] == 1u;
-    if (!(dof[0] || dof[1] || dof[2])) return;
-    double D[3][3][NK];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < NK; ++k) D[i][j][k] = 0.0;
-    const double *acc = a.dacc + e * a.dstride;
-    for (int p = 0; p < a.P; ++p)
         for (int k = 0; k < NK; ++k) {
-            const double v = acc[p * NN + k];
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) D[i][j][k] += v * r.pphi[p][i] * r.pphi[p][j];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) X[a][b][k] -= pp[a] * tm[b][k];
+            De[0][k] += alpha[k] * pp[0] * pp[0];
+            De[1][k] += alpha[k] * pp[0] * pp[1];
+            De[2][k] += alpha[k] * pp[0] * pp[2];
+            De[3][k] += alpha[k] * pp[1] * pp[1];
+            De[4][k] += alpha[k] * pp[1] * pp[2];
+            De[5][k] += alpha[k] * pp[2] * pp[2];
         }
-    if (!a.same) {
-        const double *acc2 = acc + (int64_t)a.P * NN;
-        for (int q = 0; q < a.Q; ++q)
-            for (int k = 0; k < NK; ++k) {
-                const double v = acc2[q * NN + k];
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j) D[i][j][k] += v * r.qphi[q][i] * r.qphi[q][j];
-            }
     }
-    for (int i = 0; i < 3; ++i) {
-        if (!dof[i]) continue;
-        for (int j = 0; j < 3; ++j) {
-            double blk[NN];
-            if (NC == 1) {
-                blk[0] = D[i][j][0];
-            } else {
-                blk[0] = D[i][j][0];
-                blk[1] = blk[2] = D[i][j][1];
-                blk[3] = D[i][j][2];
-            }
-            add_block<NC>(a.nptr, a.ncol, a.val, a.err, nd[i], nd[j], blk);
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+        if (q >= PB) continue;
+        const T b0 = (T)r.pb[q][0], b1 = (T)r.pb[q][1], b2 = (T)r.pb[q][2];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            Df[0][k] += beta[q][k] * b0 * b0;
+            Df[1][k] += beta[q][k] * b0 * b1;
+            Df[2][k] += beta[q][k] * b0 * b2;
+            Df[3][k] += beta[q][k] * b1 * b1;
+            Df[4][k] += beta[q][k] * b1 * b2;
+            Df[5][k] += beta[q][k] * b2 * b2;
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// touching pairs
+template <int KER, typename T, int PM>
+__global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArgs r2)
+{
+    constexpr int NK = Ker<KER>::NK;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n) return;
+    const int32_t e = a.ue[idx], f = a.uf[idx];
+    const uint32_t ms = a.m_ef[idx], mt = a.m_fe[idx];   // mt == 0 for the self pair
+    const bool self = e == f;
+    const double2 v0e = a.v0[e], v0f = a.v0[f];
+    const double4 Je = a.J[e], Jf = a.J[f];
+    const double dete = a.det[e], detf = a.det[f];
+    const T dx = (T)(v0e.x - v0f.x), dy = (T)(v0e.y - v0f.y);
+    const T cc = (T)a.c;
+    T X[3][3][NK], De[6][NK], Df[6][NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) X[i / 3][i % 3][k] = 0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) De[i][k] = Df[i][k] = 0;
+    }
+    if (a.same) {
+        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, mt, cc, X, De, Df);
+    } else {
+        // (e, f): outer rule on e, inner rule on f
+        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, 0u, cc, X, De, Df);
+        // (f, e): inner rule on e, outer rule on f
+        if (!self) far_direction<KER, T, PM>(r2, dx, dy, Je, Jf, dete, detf, 0u, mt, cc, X, De, Df);
+    }
+    T *out = (T *)a.rec + idx * a.stride;
+    if (self) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) out[(3 * i + j) * NK + k] = X[i][j][k] + X[j][i][k];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                out[(9 + i) * NK + k] = De[i][k] + Df[i][k];
+                out[(15 + i) * NK + k] = 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) out[i * NK + k] = X[i / 3][i % 3][k];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                out[(9 + i) * NK + k] = De[i][k];
+                out[(15 + i) * NK + k] = Df[i][k];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- phase 1: touching pairs
 
 struct TouchArgs {
     int64_t n;
     const int32_t *te, *tf;
     const int32_t *E;
     const double *V;
-    const uint32_t *node_flags;
-    const int64_t *nptr;
-    const int32_t *ncol;
-    double *val;
+    double *rec;
+    int32_t stride;
     double c;
-    int32_t *err;
 };
 
-__device__ inline double2 vtx(const double *V, int32_t n) { return make_double2(V[2 * (int64_t)n], V[2 * (int64_t)n + 1]); }
-
-// accumulate w * Psi(z) (g g^T) into the packed upper triangle of L (nu nodes)
+// accumulate w * Psi(z) (g g^T) into the packed upper triangle of L
 template <int KER, int NU>
-__device__ inline void acc_sample(double (&L)[(NU * (KER == NLFEM_K_PERIDYNAMIC ? 2 : 1)) *
-                                              (NU * (KER == NLFEM_K_PERIDYNAMIC ? 2 : 1) + 1) / 2],
-                                  double w, double zx, double zy, const double (&g)[NU], double c)
+__device__ inline void acc_sample(double *L, double w, double zx, double zy, const double *g, double c)
 {
-    constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
+    constexpr int NC = Ker<KER>::NC;
     constexpr int D = NU * NC;
     double k[3];
     kernel_eval<KER, double>(zx, zy, c, k);
-    double kk[NC][NC];
+    double kk[2][2];
     if (NC == 1) {
         kk[0][0] = k[0];
     } else {
@@ -348,186 +324,305 @@ __device__ inline void acc_sample(double (&L)[(NU * (KER == NLFEM_K_PERIDYNAMIC 
     }
     int idx = 0;
 #pragma unroll
-    for (int r = 0; r < D; ++r)
+    for (int r = 0; r < D; ++r) {
+        const double wr = w * g[r / NC];
 #pragma unroll
-        for (int s = r; s < D; ++s) {
-            L[idx++] += w * kk[r % NC][s % NC] * g[r / NC] * g[s / NC];
-        }
+        for (int s = r; s < D; ++s) L[idx++] += wr * kk[r % NC][s % NC] * g[s / NC];
+    }
 }
 
-template <int KER, int NU>
-__device__ inline void scatter_touch(const TouchArgs &a, const int32_t (&nodes)[NU],
-                                     const double (&L)[(NU * (KER == NLFEM_K_PERIDYNAMIC ? 2 : 1)) *
-                                                       (NU * (KER == NLFEM_K_PERIDYNAMIC ? 2 : 1) + 1) / 2],
-                                     double scale)
+template <int KER, int CLS, int G>
+__global__ void __launch_bounds__(256) k_touch_rec(TouchArgs a, GaussArgs g)
 {
-    constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
+    constexpr int NC = Ker<KER>::NC;
+    constexpr int NU = CLS == 3 ? 3 : CLS == 2 ? 4 : 5;
     constexpr int D = NU * NC;
-    for (int i = 0; i < NU; ++i) {
-        if (a.node_flags[nodes[i]] != 1u) continue;
-        for (int j = 0; j < NU; ++j) {
-            double blk[NC * NC];
-            for (int c = 0; c < NC; ++c)
-                for (int d = 0; d < NC; ++d) {
-                    int r = i * NC + c, s = j * NC + d;
-                    if (r > s) {
-                        int t = r;
-                        r = s;
-                        s = t;
-                    }
-                    // packed upper index of (r, s)
-                    const int idx = r * D - r * (r - 1) / 2 + (s - r);
-                    blk[c * NC + d] = scale * L[idx];
-                }
-            add_block<NC>(a.nptr, a.ncol, a.val, a.err, nodes[i], nodes[j], blk);
-        }
-    }
-}
-
-template <int KER>
-constexpr int homog_degree() { return KER == NLFEM_K_CONSTANT ? 2 : 1; }
-
-template <int KER>
-__global__ void __launch_bounds__(256) k_touch_ident(TouchArgs a, GaussArgs g)
-{
-    constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
-    constexpr int D = 3 * NC;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.n) return;
-    const int32_t e = a.te[idx];
-    const int32_t nodes[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
-    const double2 p0 = vtx(a.V, nodes[0]), p1 = vtx(a.V, nodes[1]), p2 = vtx(a.V, nodes[2]);
-    const double J00 = p1.x - p0.x, J01 = p2.x - p0.x, J10 = p1.y - p0.y, J11 = p2.y - p0.y;
-    const double det = fabs(J00 * J11 - J01 * J10);
-    double L[D * (D + 1) / 2];
-    for (int t = 0; t < D * (D + 1) / 2; ++t) L[t] = 0.0;
-    const double hx[6] = {1, 0, -1, -1, 0, 1}, hy[6] = {0, 1, 1, 0, -1, -1};
-    for (int j = 0; j < 6; ++j) {
-        const int j1 = j == 5 ? 0 : j + 1;
-        for (int iu = 0; iu < g.n; ++iu) {
+    constexpr int NP = D * (D + 1) / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pair = gid / G;
+    const int sub = (int)(gid % G);
+    if (pair >= a.n) return;   // whole groups leave together
+    const int32_t e = a.te[pair], f = a.tf[pair];
+    const int32_t ek[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
+    const int32_t el[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
+    int32_t nd[5];
+    touch_frame(CLS, ek, el, nd);
+    double L[NP];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) L[t] = 0.0;
+    const int n = g.n;
+    double scale;
+    if (CLS == 3) {
+        const double2 p0 = vtx(a.V, nd[0]), p1 = vtx(a.V, nd[1]), p2 = vtx(a.V, nd[2]);
+        const double J00 = p1.x - p0.x, J01 = p2.x - p0.x, J10 = p1.y - p0.y, J11 = p2.y - p0.y;
+        const double det = fabs(J00 * J11 - J01 * J10);
+        for (int ev = sub; ev < 6 * n; ev += G) {
+            const int j = ev / n, iu = ev - j * n;
+            // hexagon corners (1,0),(0,1),(-1,1),(-1,0),(0,-1),(1,-1)
+            const int j1 = j == 5 ? 0 : j + 1;
+            const double cx0 = j == 0 || j == 5 ? 1.0 : (j == 2 || j == 3 ? -1.0 : 0.0);
+            const double cy0 = j == 1 || j == 2 ? 1.0 : (j == 4 || j == 5 ? -1.0 : 0.0);
+            const double cx1 = j1 == 0 || j1 == 5 ? 1.0 : (j1 == 2 || j1 == 3 ? -1.0 : 0.0);
+            const double cy1 = j1 == 1 || j1 == 2 ? 1.0 : (j1 == 4 || j1 == 5 ? -1.0 : 0.0);
             const double u = g.x[iu];
-            const double wx = (1.0 - u) * hx[j] + u * hx[j1];
-            const double wy = (1.0 - u) * hy[j] + u * hy[j1];
-            // a = phi(x^) - phi(x^ + z) = -grad phi . z ; z = rho w
+            const double wx = (1.0 - u) * cx0 + u * cx1;
+            const double wy = (1.0 - u) * cy0 + u * cy1;
+            // phi(x^) - phi(x^ + z) = -grad phi . z, z = rho w
             const double gg[3] = {wx + wy, -wx, -wy};
-            const double zx = J00 * wx + J01 * wy, zy = J10 * wx + J11 * wy;
-            acc_sample<KER, 3>(L, g.w[iu], zx, zy, gg, a.c);
+            acc_sample<KER, 3>(L, g.w[iu], J00 * wx + J01 * wy, J10 * wx + J11 * wy, gg, a.c);
         }
-    }
-    constexpr int d = homog_degree<KER>();
-    const double scale = det * det / (double)((d + 2) * (d + 3) * (d + 4));
-    scatter_touch<KER, 3>(a, nodes, L, scale);
-}
-
-template <int KER>
-__global__ void __launch_bounds__(256) k_touch_edge(TouchArgs a, GaussArgs g)
-{
-    constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
-    constexpr int D = 4 * NC;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.n) return;
-    const int32_t e = a.te[idx], f = a.tf[idx];
-    const int32_t ek[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
-    const int32_t el[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
-    // frames (P0, P1, A) and (P0, P1, B), P0 the smaller shared node id
-    int32_t sh0 = -1, sh1 = -1, A = -1, B = -1;
-    for (int i = 0; i < 3; ++i) {
-        const bool in = ek[i] == el[0] || ek[i] == el[1] || ek[i] == el[2];
-        if (in) {
-            if (sh0 < 0) sh0 = ek[i];
-            else sh1 = ek[i];
-        } else {
-            A = ek[i];
-        }
-        const bool inl = el[i] == ek[0] || el[i] == ek[1] || el[i] == ek[2];
-        if (!inl) B = el[i];
-    }
-    const int32_t P0 = min(sh0, sh1), P1 = max(sh0, sh1);
-    const int32_t nodes[4] = {P0, P1, A, B};
-    const double2 q0 = vtx(a.V, P0), q1 = vtx(a.V, P1), qa = vtx(a.V, A), qb = vtx(a.V, B);
-    // x - y = E v, E = [P1 - P0, A - P0, -(B - P0)]
-    const double E0x = q1.x - q0.x, E0y = q1.y - q0.y;
-    const double E1x = qa.x - q0.x, E1y = qa.y - q0.y;
-    const double E2x = -(qb.x - q0.x), E2y = -(qb.y - q0.y);
-    const double detk = fabs(E0x * E1y - E1x * E0y);
-    const double detl = fabs(E0x * E2y - E2x * E0y);
-    double L[D * (D + 1) / 2];
-    for (int t = 0; t < D * (D + 1) / 2; ++t) L[t] = 0.0;
-    for (int face = 0; face < 4; ++face)
-        for (int ip = 0; ip < g.n; ++ip)
-            for (int iq = 0; iq < g.n; ++iq) {
+        constexpr int d = Ker<KER>::D;
+        scale = det * det / (double)((d + 2) * (d + 3) * (d + 4));
+    } else if (CLS == 2) {
+        const double2 q0 = vtx(a.V, nd[0]), q1 = vtx(a.V, nd[1]), qa = vtx(a.V, nd[2]), qb = vtx(a.V, nd[3]);
+        // x - y = E v,  E = [P1 - P0, A - P0, -(B - P0)]
+        const double E0x = q1.x - q0.x, E0y = q1.y - q0.y;
+        const double E1x = qa.x - q0.x, E1y = qa.y - q0.y;
+        const double E2x = -(qb.x - q0.x), E2y = -(qb.y - q0.y);
+        // faces of the cone {max(v2 + v1+, v3 + v1-) <= 1} are unrolled at
+        // compile time; the lanes of the group share the n^2 points of each
+        // face (a data-dependent face index miscompiled here once: keep it
+        // out of divergent control flow)
+#pragma unroll
+        for (int face = 0; face < 4; ++face) {
+            for (int ev = sub; ev < n * n; ev += G) {
+                const int ip = ev / n, iq = ev - ip * n;
                 const double p = g.x[ip], q = g.x[iq];
-                double w0, w1, w2, jf;
-                if (face == 0) { w0 = p; w1 = 1.0 - p; w2 = q; jf = 1.0; }
-                else if (face == 1) { w0 = p; w1 = (1.0 - p) * q; w2 = 1.0; jf = 1.0 - p; }
-                else if (face == 2) { w0 = -p; w1 = 1.0; w2 = (1.0 - p) * q; jf = 1.0 - p; }
-                else { w0 = -p; w1 = q; w2 = 1.0 - p; jf = 1.0; }
+                const double u = 1.0 - p, t = u * q;
+                const double w0 = face < 2 ? p : -p;
+                const double w1 = face == 0 ? u : face == 1 ? t : face == 2 ? 1.0 : q;
+                const double w2 = face == 0 ? q : face == 1 ? 1.0 : face == 2 ? t : u;
+                const double jf = (face == 1 || face == 2) ? u : 1.0;
                 const double gg[4] = {-w0 - w1 + w2, w0, w1, -w2};
-                const double zx = E0x * w0 + E1x * w1 + E2x * w2;
-                const double zy = E0y * w0 + E1y * w1 + E2y * w2;
-                acc_sample<KER, 4>(L, g.w[ip] * g.w[iq] * jf, zx, zy, gg, a.c);
-            }
-    constexpr int d = homog_degree<KER>();
-    const double scale = 2.0 * detk * detl / (double)((d + 3) * (d + 4));
-    scatter_touch<KER, 4>(a, nodes, L, scale);
-}
-
-template <int KER>
-__global__ void __launch_bounds__(256) k_touch_vertex(TouchArgs a, GaussArgs g)
-{
-    constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
-    constexpr int D = 5 * NC;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.n) return;
-    const int32_t e = a.te[idx], f = a.tf[idx];
-    const int32_t ek[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
-    const int32_t el[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
-    int ia = 0, ib = 0;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            if (ek[i] == el[j]) {
-                ia = i;
-                ib = j;
-            }
-    const int32_t nodes[5] = {ek[ia], ek[(ia + 1) % 3], ek[(ia + 2) % 3], el[(ib + 1) % 3], el[(ib + 2) % 3]};
-    const double2 q0 = vtx(a.V, nodes[0]), a1 = vtx(a.V, nodes[1]), a2 = vtx(a.V, nodes[2]);
-    const double2 b1 = vtx(a.V, nodes[3]), b2 = vtx(a.V, nodes[4]);
-    const double A1x = a1.x - q0.x, A1y = a1.y - q0.y, A2x = a2.x - q0.x, A2y = a2.y - q0.y;
-    const double B1x = b1.x - q0.x, B1y = b1.y - q0.y, B2x = b2.x - q0.x, B2y = b2.y - q0.y;
-    const double detk = fabs(A1x * A2y - A2x * A1y);
-    const double detl = fabs(B1x * B2y - B2x * B1y);
-    double L[D * (D + 1) / 2];
-    for (int t = 0; t < D * (D + 1) / 2; ++t) L[t] = 0.0;
-    for (int iw = 0; iw < g.n; ++iw) {
-        const double w = g.x[iw];
-        for (int iaa = 0; iaa < g.n; ++iaa) {
-            const double al = g.x[iaa];
-            const double ex = (1.0 - al) * A1x + al * A2x, ey = (1.0 - al) * A1y + al * A2y;
-            for (int ibb = 0; ibb < g.n; ++ibb) {
-                const double be = g.x[ibb];
-                const double fx = (1.0 - be) * B1x + be * B2x, fy = (1.0 - be) * B1y + be * B2y;
-                const double wt = g.w[iw] * g.w[iaa] * g.w[ibb] * w;
-                {   // region t <= s: t = s w
-                    const double gg[5] = {w - 1.0, 1.0 - al, al, -w * (1.0 - be), -w * be};
-                    acc_sample<KER, 5>(L, wt, ex - w * fx, ey - w * fy, gg, a.c);
-                }
-                {   // region s <= t: s = t w
-                    const double gg[5] = {1.0 - w, w * (1.0 - al), w * al, -(1.0 - be), -be};
-                    acc_sample<KER, 5>(L, wt, w * ex - fx, w * ey - fy, gg, a.c);
-                }
+                acc_sample<KER, 4>(L, g.w[ip] * g.w[iq] * jf, E0x * w0 + E1x * w1 + E2x * w2,
+                                   E0y * w0 + E1y * w1 + E2y * w2, gg, a.c);
             }
         }
+        const double detk = fabs(E0x * E1y - E1x * E0y), detl = fabs(E0x * E2y - E2x * E0y);
+        constexpr int d = Ker<KER>::D;
+        scale = detk * detl / (double)((d + 3) * (d + 4));
+    } else {
+        const double2 q0 = vtx(a.V, nd[0]), a1 = vtx(a.V, nd[1]), a2 = vtx(a.V, nd[2]);
+        const double2 b1 = vtx(a.V, nd[3]), b2 = vtx(a.V, nd[4]);
+        const double A1x = a1.x - q0.x, A1y = a1.y - q0.y, A2x = a2.x - q0.x, A2y = a2.y - q0.y;
+        const double B1x = b1.x - q0.x, B1y = b1.y - q0.y, B2x = b2.x - q0.x, B2y = b2.y - q0.y;
+        for (int ev = sub; ev < n * n * n; ev += G) {
+            const int iw = ev / (n * n), rem = ev - iw * n * n;
+            const int ia = rem / n, ib = rem - ia * n;
+            const double w = g.x[iw], al = g.x[ia], be = g.x[ib];
+            const double ex = (1.0 - al) * A1x + al * A2x, ey = (1.0 - al) * A1y + al * A2y;
+            const double fx = (1.0 - be) * B1x + be * B2x, fy = (1.0 - be) * B1y + be * B2y;
+            const double wt = g.w[iw] * g.w[ia] * g.w[ib] * w;
+            {   // region t <= s: t = s w
+                const double gg[5] = {w - 1.0, 1.0 - al, al, -w * (1.0 - be), -w * be};
+                acc_sample<KER, 5>(L, wt, ex - w * fx, ey - w * fy, gg, a.c);
+            }
+            {   // region s <= t: s = t w
+                const double gg[5] = {1.0 - w, w * (1.0 - al), w * al, -(1.0 - be), -be};
+                acc_sample<KER, 5>(L, wt, w * ex - fx, w * ey - fy, gg, a.c);
+            }
+        }
+        const double detk = fabs(A1x * A2y - A2x * A1y), detl = fabs(B1x * B2y - B2x * B1y);
+        constexpr int d = Ker<KER>::D;
+        scale = detk * detl / (double)(d + 4);
     }
-    constexpr int d = homog_degree<KER>();
-    const double scale = 2.0 * detk * detl / (double)(d + 4);
-    scatter_touch<KER, 5>(a, nodes, L, scale);
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int t = 0; t < NP; ++t) L[t] += __shfl_xor(L[t], off, G);
+    double *out = a.rec + pair * a.stride;
+#pragma unroll
+    for (int t = 0; t < NP; ++t)
+        if (t % G == sub) out[t] = scale * L[t];
 }
 
-__global__ void __launch_bounds__(256) k_zero(double *p, int64_t n)
+// ------------------------------------------------- phase 2: row gather
+
+struct RowArgs {
+    int64_t M;
+    const uint32_t *node_flags;
+    const int64_t *nptr;
+    const int32_t *ncol;
+    const int64_t *ne_ptr;
+    const int32_t *ne_list;
+    const int32_t *E;
+    const int64_t *sptr;
+    const int32_t *snbr;
+    const uint8_t *sflag;
+    const int32_t *srec;
+    const void *far_rec;
+    int32_t far_stride;
+    int64_t n_far;
+    const double *touch_rec;
+    int32_t touch_stride;
+    int64_t n_touch;
+    int32_t hcap;        // power of two, >= 2 * longest row
+    int32_t maxlen;
+    double *val;
+    int32_t *err;
+};
+
+constexpr int kRowQ = 32;   // elements around a node handled per batch
+
+__device__ inline int hpos(const int32_t *hk, const int32_t *hv, int32_t mask, int32_t key)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
+    uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
+    for (int probe = 0; probe <= mask; ++probe) {
+        const int32_t k = hk[h];
+        if (k == key) return hv[h];
+        if (k < 0) return -1;
+        h = (h + 1) & (uint32_t)mask;
+    }
+    return -1;
 }
+
+template <int NC>
+__device__ inline void add_sym_block(double *acc, int pos, const double *v)
+{
+    if (NC == 1) {
+        atomicAdd(&acc[pos], v[0]);
+    } else {
+        atomicAdd(&acc[pos * 4 + 0], v[0]);
+        atomicAdd(&acc[pos * 4 + 1], v[1]);
+        atomicAdd(&acc[pos * 4 + 2], v[1]);
+        atomicAdd(&acc[pos * 4 + 3], v[2]);
+    }
+}
+
+template <int NC, typename TR>
+__global__ void __launch_bounds__(64) k_rows(RowArgs a)
+{
+    constexpr int NN = NC * NC;
+    constexpr int NK = NC == 1 ? 1 : 3;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *acc = (double *)smem;                              // [maxlen * NN]
+    int32_t *hk = (int32_t *)(acc + (size_t)a.maxlen * NN);    // [hcap]
+    int32_t *hv = hk + a.hcap;                                 // [hcap]
+    __shared__ int64_t pre[kRowQ + 1];
+    __shared__ int32_t qe[kRowQ], qloc[kRowQ];
+    const int lane = threadIdx.x;
+    const int32_t mask = a.hcap - 1;
+    for (int64_t i = blockIdx.x; i < a.M; i += gridDim.x) {
+        if (a.node_flags[i] != 1u) continue;
+        const int64_t s = a.nptr[i];
+        const int len = (int)(a.nptr[i + 1] - s);
+        if (len == 0) continue;
+        for (int t = lane; t < a.hcap; t += 64) hk[t] = -1;
+        for (int t = lane; t < len * NN; t += 64) acc[t] = 0.0;
+        __syncthreads();
+        for (int t = lane; t < len; t += 64) {
+            const int32_t key = a.ncol[s + t];
+            uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
+            for (int probe = 0; probe <= mask; ++probe) {
+                if (atomicCAS(&hk[h], -1, key) == -1) {
+                    hv[h] = t;
+                    break;
+                }
+                h = (h + 1) & (uint32_t)mask;
+            }
+        }
+        __syncthreads();
+        bool bad = false;
+        const int64_t q0 = a.ne_ptr[i], q1 = a.ne_ptr[i + 1];
+        for (int64_t qb = q0; qb < q1; qb += kRowQ) {
+            const int nq = (int)min((int64_t)kRowQ, q1 - qb);
+            if (lane == 0) {
+                int64_t p = 0;
+                for (int q = 0; q < nq; ++q) {
+                    const int32_t e = a.ne_list[qb + q];
+                    qe[q] = e;
+                    pre[q] = p;
+                    p += a.sptr[e + 1] - a.sptr[e];
+                    const int32_t *En = a.E + 3 * (int64_t)e;
+                    qloc[q] = En[0] == (int32_t)i ? 0 : En[1] == (int32_t)i ? 1 : 2;
+                }
+                pre[nq] = p;
+            }
+            __syncthreads();
+            const int64_t total = pre[nq];
+            for (int64_t flat = lane; flat < total; flat += 64) {
+                int q = 0;
+                while (pre[q + 1] <= flat) ++q;
+                const int32_t e = qe[q];
+                const int loc = qloc[q];
+                const int64_t t = a.sptr[e] + (flat - pre[q]);
+                const int32_t f = a.snbr[t];
+                const int cls = (a.sflag[t] >> 2) & 3;
+                const int32_t u = a.srec[t];
+                const int32_t ne[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
+                const int32_t nf[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
+                if (u < 0 || u >= (cls == 0 ? a.n_far : a.n_touch)) {
+                    bad = true;
+                    continue;
+                }
+                if (cls == 0) {
+                    const TR *r = (const TR *)a.far_rec + (int64_t)u * a.far_stride;
+                    for (int b = 0; b < 3; ++b) {
+                        // cross block: row loc of X (e first) or column loc (e second)
+                        const int xi = f >= e ? 3 * loc + b : 3 * b + loc;
+                        const int di = 9 + sym_index(loc, b, 3) + (f >= e ? 0 : 6);
+                        const int px = hpos(hk, hv, mask, nf[b]);
+                        const int pd = hpos(hk, hv, mask, ne[b]);
+                        if (px < 0 || pd < 0) {
+                            bad = true;
+                            continue;
+                        }
+                        double xs[NK], ds[NK];
+                        for (int k = 0; k < NK; ++k) {
+                            xs[k] = (double)r[xi * NK + k];
+                            ds[k] = (double)r[di * NK + k];
+                        }
+                        if (f == e) {   // self pair: X + X^T and both diagonal parts, all in cols of e
+                            for (int k = 0; k < NK; ++k) ds[k] += xs[k];
+                            add_sym_block<NC>(acc, pd, ds);
+                        } else {
+                            add_sym_block<NC>(acc, px, xs);
+                            add_sym_block<NC>(acc, pd, ds);
+                        }
+                    }
+                } else {
+                    const bool first = e <= f;
+                    const int32_t *k1 = first ? ne : nf;
+                    const int32_t *k2 = first ? nf : ne;
+                    int32_t fr[5];
+                    const int nu = touch_frame(cls, k1, k2, fr);
+                    int rr = 0;
+                    for (int c = 0; c < nu; ++c)
+                        if (fr[c] == (int32_t)i) rr = c;
+                    const bool in1 = k1[0] == (int32_t)i || k1[1] == (int32_t)i || k1[2] == (int32_t)i;
+                    const bool in2 = k2[0] == (int32_t)i || k2[1] == (int32_t)i || k2[2] == (int32_t)i;
+                    const double factor = (cls == 3 || (in1 && in2)) ? 1.0 : 2.0;
+                    const double *L = a.touch_rec + (int64_t)u * a.touch_stride;
+                    const int D = nu * NC;
+                    for (int c = 0; c < nu; ++c) {
+                        const int pc = hpos(hk, hv, mask, fr[c]);
+                        if (pc < 0) {
+                            bad = true;
+                            continue;
+                        }
+                        for (int cc = 0; cc < NC; ++cc)
+                            for (int dd = 0; dd < NC; ++dd)
+                                atomicAdd(&acc[pc * NN + cc * NC + dd],
+                                          factor * L[sym_index(rr * NC + cc, c * NC + dd, D)]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (bad) atomicOr(a.err, kErrSlot);
+        if (NC == 1) {
+            for (int t = lane; t < len; t += 64) a.val[s + t] = acc[t];
+        } else {
+            for (int t = lane; t < len * 4; t += 64) {
+                const int pos = t >> 2, c = (t >> 1) & 1, d = t & 1;
+                a.val[4 * s + (int64_t)c * 2 * len + 2 * pos + d] = acc[t];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ launching
 
 RoleArgs roles(const RuleArgs &r, bool a_outer, bool b_outer)
 {
@@ -550,18 +645,19 @@ RoleArgs roles(const RuleArgs &r, bool a_outer, bool b_outer)
 }
 
 template <int KER, typename T>
-void far_launch(const FarArgs &a, const RoleArgs &r, hipStream_t s)
+void far_launch(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, hipStream_t s)
 {
     const unsigned grid = grid_for(a.n, 256);
-    if (r.PA == 7 && r.PB == 7) hipLaunchKernelGGL((k_far_bary<KER, T, 7>), dim3(grid), dim3(256), 0, s, a, r);
-    else hipLaunchKernelGGL((k_far_bary<KER, T, 0>), dim3(grid), dim3(256), 0, s, a, r);
+    const bool seven = r1.PA == 7 && r1.PB == 7 && (a.same || (r2.PA == 7 && r2.PB == 7));
+    if (seven) hipLaunchKernelGGL((k_far_rec<KER, T, 7>), dim3(grid), dim3(256), 0, s, a, r1, r2);
+    else hipLaunchKernelGGL((k_far_rec<KER, T, 0>), dim3(grid), dim3(256), 0, s, a, r1, r2);
 }
 
 template <int KER>
-void far_dispatch(const FarArgs &a, const RoleArgs &r, bool fp32, hipStream_t s)
+void far_dispatch(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, bool fp32, hipStream_t s)
 {
-    if (fp32) far_launch<KER, float>(a, r, s);
-    else far_launch<KER, double>(a, r, s);
+    if (fp32) far_launch<KER, float>(a, r1, r2, s);
+    else far_launch<KER, double>(a, r1, r2, s);
 }
 
 template <int KER>
@@ -572,35 +668,34 @@ void touch_launch(const nlfem_pairs *h, TouchArgs t, const GaussArgs &g, hipStre
         t.n = nI;
         t.te = h->te;
         t.tf = h->tf;
-        hipLaunchKernelGGL(k_touch_ident<KER>, dim3(grid_for(nI, 256)), dim3(256), 0, s, t, g);
+        t.rec = h->touch_rec;
+        hipLaunchKernelGGL((k_touch_rec<KER, 3, 16>), dim3(grid_for(nI * 16, 256)), dim3(256), 0, s, t, g);
     }
     if (nE > 0) {
         t.n = nE;
         t.te = h->te + nI;
         t.tf = h->tf + nI;
-        hipLaunchKernelGGL(k_touch_edge<KER>, dim3(grid_for(nE, 256)), dim3(256), 0, s, t, g);
+        t.rec = h->touch_rec + nI * h->touch_stride;
+        hipLaunchKernelGGL((k_touch_rec<KER, 2, 16>), dim3(grid_for(nE * 16, 256)), dim3(256), 0, s, t, g);
     }
     if (nV > 0) {
         t.n = nV;
         t.te = h->te + nI + nE;
         t.tf = h->tf + nI + nE;
-        hipLaunchKernelGGL(k_touch_vertex<KER>, dim3(grid_for(nV, 256)), dim3(256), 0, s, t, g);
+        t.rec = h->touch_rec + (nI + nE) * h->touch_stride;
+        hipLaunchKernelGGL((k_touch_rec<KER, 1, 16>), dim3(grid_for(nV * 16, 256)), dim3(256), 0, s, t, g);
     }
 }
 
 }  // namespace
 
+int far_record_stride(int ncomp) { return ncomp == 1 ? 21 : 63; }
+int touch_record_stride(int ncomp) { return (5 * ncomp) * (5 * ncomp + 1) / 2; }
+
 int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
                     double *val, hipStream_t s)
 {
     const int nc = h->ncomp;
-    const int64_t nnz = h->nnz_node * nc * nc;
-    const int64_t ndacc = h->K * h->dacc_stride;
-    if (nnz > 0)
-        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(grid_for(nnz, 256), 8192)), dim3(256), 0, s, val, nnz);
-    if (ndacc > 0)
-        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(grid_for(ndacc, 256), 8192)), dim3(256), 0, s,
-                           h->dacc, ndacc);
     const bool fp32 = cfg->precision == NLFEM_P_MIXED;
     if (h->nUF > 0) {
         FarArgs a{};
@@ -609,65 +704,69 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         a.uf = h->uf;
         a.m_ef = h->um_ef;
         a.m_fe = h->um_fe;
-        a.E = m->elements;
         a.v0 = h->v0;
         a.J = h->J;
         a.det = h->det;
-        a.node_flags = h->node_flags;
-        a.nptr = h->nptr;
-        a.ncol = h->ncol;
-        a.val = val;
-        a.dstride = h->dacc_stride;
+        a.rec = h->far_rec;
+        a.stride = h->far_stride;
         a.c = cfg->c;
-        a.err = h->err;
-        const int NN = nc * nc;
-        auto run = [&](const RoleArgs &r) {
-            switch (h->kernel) {
-            case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(a, r, fp32, s); break;
-            case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(a, r, fp32, s); break;
-            default: far_dispatch<NLFEM_K_PERIDYNAMIC>(a, r, fp32, s); break;
-            }
-        };
-        if (h->rules.same) {
-            a.use_s = a.use_t = 1;
-            a.daccA = a.daccB = h->dacc;
-            run(roles(h->rules, true, true));
-        } else {
-            // direction e -> f: outer points on e, inner points on f
-            a.use_s = 1;
-            a.use_t = 0;
-            a.daccA = h->dacc;
-            a.daccB = h->dacc + (int64_t)h->rules.P * NN;
-            run(roles(h->rules, true, false));
-            // direction f -> e: outer points on f, inner points on e
-            a.use_s = 0;
-            a.use_t = 1;
-            a.daccA = h->dacc + (int64_t)h->rules.P * NN;
-            a.daccB = h->dacc;
-            run(roles(h->rules, false, true));
+        a.same = h->rules.same;
+        // same rules: one pass, A and B both the outer rule.  Otherwise pass 1
+        // (outer on e, inner on f) and pass 2 (inner on e, outer on f).
+        const RoleArgs r1 = roles(h->rules, true, h->rules.same ? true : false);
+        const RoleArgs r2 = roles(h->rules, false, true);
+        switch (h->kernel) {
+        case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(a, r1, r2, fp32, s); break;
+        case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(a, r1, r2, fp32, s); break;
+        default: far_dispatch<NLFEM_K_PERIDYNAMIC>(a, r1, r2, fp32, s); break;
         }
     }
     if (h->nUT > 0) {
         TouchArgs t{};
         t.E = m->elements;
         t.V = m->vertices;
-        t.node_flags = h->node_flags;
-        t.nptr = h->nptr;
-        t.ncol = h->ncol;
-        t.val = val;
+        t.stride = h->touch_stride;
         t.c = cfg->c;
-        t.err = h->err;
         switch (h->kernel) {
         case NLFEM_K_CONSTANT: touch_launch<NLFEM_K_CONSTANT>(h, t, g, s); break;
         case NLFEM_K_INV_DIST: touch_launch<NLFEM_K_INV_DIST>(h, t, g, s); break;
         default: touch_launch<NLFEM_K_PERIDYNAMIC>(h, t, g, s); break;
         }
     }
-    if (h->K > 0) {
-        DiagArgs d{h->K, h->loff + (int64_t)kLsS * (h->K + 1), m->elements, h->node_flags, h->nptr, h->ncol, val, h->dacc, h->dacc_stride,
-                   h->rules.P, h->rules.Q, h->rules.same, h->err};
-        if (nc == 1) hipLaunchKernelGGL(k_diag<1>, dim3(grid_for(h->K, 256)), dim3(256), 0, s, d, h->rules);
-        else hipLaunchKernelGGL(k_diag<2>, dim3(grid_for(h->K, 256)), dim3(256), 0, s, d, h->rules);
+    if (h->nnz_node > 0) {
+        RowArgs r{};
+        r.M = h->M;
+        r.node_flags = h->node_flags;
+        r.nptr = h->nptr;
+        r.ncol = h->ncol;
+        r.ne_ptr = h->ne_ptr;
+        r.ne_list = h->ne_list;
+        r.E = m->elements;
+        r.sptr = h->loff + (int64_t)kLsS * (h->K + 1);
+        r.snbr = h->snbr;
+        r.sflag = h->sflag;
+        r.srec = h->srec;
+        r.far_rec = h->far_rec;
+        r.far_stride = h->far_stride;
+        r.n_far = h->nUF;
+        r.touch_rec = h->touch_rec;
+        r.touch_stride = h->touch_stride;
+        r.n_touch = h->nUT;
+        int hc = 64;
+        while (hc < 2 * h->max_row) hc <<= 1;
+        r.hcap = hc;
+        r.maxlen = (int32_t)h->max_row;
+        r.val = val;
+        r.err = h->err;
+        const size_t lds = sizeof(double) * (size_t)h->max_row * nc * nc + sizeof(int32_t) * 2 * (size_t)hc;
+        const unsigned grid = (unsigned)std::min<int64_t>(h->M, 1 << 20);
+        if (nc == 1) {
+            if (fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(64), lds, s, r);
+            else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(64), lds, s, r);
+        } else {
+            if (fp32) hipLaunchKernelGGL((k_rows<2, float>), dim3(grid), dim3(64), lds, s, r);
+            else hipLaunchKernelGGL((k_rows<2, double>), dim3(grid), dim3(64), lds, s, r);
+        }
     }
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;

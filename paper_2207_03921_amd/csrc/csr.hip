@@ -23,6 +23,7 @@ struct CsrArgs {
     const int32_t *snbr;
     int32_t hcap;            // power of two
     int64_t *nlen;           // count pass
+    unsigned long long *max_row;
     const int64_t *nptr;     // fill pass
     int32_t *ncol;
     int32_t *err;
@@ -84,7 +85,10 @@ __global__ void __launch_bounds__(64) k_csr(CsrArgs a)
             continue;
         }
         if (!FILL) {
-            if (lane == 0) a.nlen[i] = n;
+            if (lane == 0) {
+                a.nlen[i] = n;
+                atomicMax(a.max_row, (unsigned long long)n);
+            }
             __syncthreads();
             continue;
         }
@@ -210,7 +214,8 @@ __global__ void __launch_bounds__(64) k_export(int64_t K, const int64_t *sptr, c
 int launch_csr(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
 {
     CsrArgs a{h->K + 1, h->M, m->elements, h->node_flags, h->ne_ptr, h->ne_list,
-              h->loff + (int64_t)kLsS * (h->K + 1), h->snbr, h->hcap, h->nlen, h->nptr, h->ncol, h->err};
+              h->loff + (int64_t)kLsS * (h->K + 1), h->snbr, h->hcap, h->nlen, h->red + 9, h->nptr, h->ncol,
+              h->err};
     const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap;
     const unsigned grid = (unsigned)std::min<int64_t>(h->M, 1 << 20);
     if (fill) hipLaunchKernelGGL(k_csr<true>, dim3(grid), dim3(64), lds, s, a);

@@ -1,0 +1,201 @@
+// Post-processing of the interaction lists.
+//
+// 1. Every segment S(e) is sorted by neighbour id (bitonic sort in LDS, one
+//    wave per element), so that the pair (f, e) can be found in S(f) by
+//    binary search.
+// 2. The entries with f >= e are the unordered pairs.  They are compacted
+//    into work lists: non-touching pairs with their point status, touching
+//    pairs grouped by class (identical, edge, vertex).  Each upper entry
+//    records the index of its work item; each lower entry (f < e) takes the
+//    index of its mirror (f, e).  The assembly computes one result per work
+//    item and every matrix row finds the results of all its pairs through
+//    these indices.
+#include "nlfem_internal.h"
+
+namespace nlfem {
+namespace {
+
+struct ListArgs {
+    int64_t K, K1;
+    const int64_t *sptr;
+    const int64_t *loff;       // [kLsLast][K1] per-element offsets of the upper classes
+    int32_t cap;               // power of two >= longest segment
+    int32_t singular;
+    int64_t baseE, baseV;
+    const int32_t *snbr_tmp;
+    const uint8_t *sflag_tmp;
+    const uint2 *smask_tmp;
+    int32_t *snbr;
+    uint8_t *sflag;
+    uint2 *smask;
+    int32_t *srec;
+    int32_t *ue, *uf;
+    uint32_t *um_ef, *um_fe;
+    int32_t *te, *tf;
+    int32_t *err;
+};
+
+__global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
+{
+    extern __shared__ unsigned long long key[];
+    const int lane = threadIdx.x;
+    for (int64_t e = blockIdx.x; e < a.K; e += gridDim.x) {
+        const int64_t s0 = a.sptr[e];
+        const int n = (int)(a.sptr[e + 1] - s0);
+        if (n == 0) continue;
+        int n2 = 1;
+        while (n2 < n) n2 <<= 1;
+        for (int t = lane; t < n2; t += 64)
+            key[t] = t < n ? (((unsigned long long)(uint32_t)a.snbr_tmp[s0 + t]) << 32) | (uint32_t)t : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= n2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < n2; t += 64) {
+                    const int ixj = t ^ j;
+                    if (ixj > t) {
+                        const unsigned long long x = key[t], y = key[ixj];
+                        if ((x > y) == ((t & k) == 0)) {
+                            key[t] = y;
+                            key[ixj] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int t = lane; t < n; t += 64) {
+            const unsigned long long kk = key[t];
+            const int src = (int)(kk & 0xffffffffull);
+            a.snbr[s0 + t] = (int32_t)(kk >> 32);
+            a.sflag[s0 + t] = a.sflag_tmp[s0 + src];
+            a.smask[s0 + t] = a.smask_tmp[s0 + src];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(64) k_worklists(ListArgs a)
+{
+    const int lane = threadIdx.x;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int64_t e = blockIdx.x; e < a.K; e += gridDim.x) {
+        const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
+        int64_t oF = a.loff[kLsUF * a.K1 + e];
+        int64_t oI = a.loff[kLsUI * a.K1 + e];
+        int64_t oE = a.baseE + a.loff[kLsUE * a.K1 + e];
+        int64_t oV = a.baseV + a.loff[kLsUV * a.K1 + e];
+        for (int64_t t0 = s0; t0 < s1; t0 += 64) {
+            const int64_t t = t0 + lane;
+            bool isF = false, isI = false, isE = false, isV = false;
+            int32_t f = 0;
+            uint2 m = make_uint2(0u, 0u);
+            if (t < s1) {
+                f = a.snbr[t];
+                const int cls = (a.sflag[t] >> 2) & 3;
+                const bool upper = f >= e;
+                isF = upper && cls == 0;
+                isI = upper && cls == 3;
+                isE = upper && cls == 2;
+                isV = upper && cls == 1;
+                if (isF) m = a.smask[t];
+            }
+            const unsigned long long bF = __ballot(isF), bI = __ballot(isI);
+            const unsigned long long bE = __ballot(isE), bV = __ballot(isV);
+            if (isF) {
+                const int64_t u = oF + __popcll(bF & lt);
+                a.ue[u] = (int32_t)e;
+                a.uf[u] = f;
+                a.um_ef[u] = m.x;
+                a.um_fe[u] = f == e ? 0u : m.y;
+                a.srec[t] = (int32_t)u;
+            }
+            if (isI || isE || isV) {
+                const int64_t u = isI ? oI + __popcll(bI & lt) : isE ? oE + __popcll(bE & lt)
+                                                                      : oV + __popcll(bV & lt);
+                a.te[u] = (int32_t)e;
+                a.tf[u] = f;
+                a.srec[t] = (int32_t)u;
+            }
+            oF += __popcll(bF);
+            oI += __popcll(bI);
+            oE += __popcll(bE);
+            oV += __popcll(bV);
+        }
+    }
+}
+
+// lower entries (f < e) point at the record of their mirror (f, e) in S(f)
+__global__ void __launch_bounds__(64) k_link(ListArgs a)
+{
+    const int lane = threadIdx.x;
+    for (int64_t e = blockIdx.x; e < a.K; e += gridDim.x) {
+        const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
+        for (int64_t t = s0 + lane; t < s1; t += 64) {
+            const int32_t f = a.snbr[t];
+            if (f >= e) continue;
+            int64_t lo = a.sptr[f], hi = a.sptr[f + 1];
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (a.snbr[mid] < e) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < a.sptr[f + 1] && a.snbr[lo] == (int32_t)e) a.srec[t] = a.srec[lo];
+            else atomicOr(a.err, kErrSlot);
+        }
+    }
+}
+
+ListArgs list_args(nlfem_pairs *h)
+{
+    ListArgs a{};
+    a.K = h->K;
+    a.K1 = h->K + 1;
+    a.sptr = h->loff + (int64_t)kLsS * (h->K + 1);
+    a.loff = h->loff;
+    int cap = 64;
+    while (cap < h->max_S) cap <<= 1;
+    a.cap = cap;
+    a.singular = h->singular;
+    a.baseE = h->nUTc[0];
+    a.baseV = h->nUTc[0] + h->nUTc[1];
+    a.snbr_tmp = h->snbr_tmp;
+    a.sflag_tmp = h->sflag_tmp;
+    a.smask_tmp = h->smask_tmp;
+    a.snbr = h->snbr;
+    a.sflag = h->sflag;
+    a.smask = h->smask;
+    a.srec = h->srec;
+    a.ue = h->ue;
+    a.uf = h->uf;
+    a.um_ef = h->um_ef;
+    a.um_fe = h->um_fe;
+    a.te = h->te;
+    a.tf = h->tf;
+    a.err = h->err;
+    return a;
+}
+
+}  // namespace
+
+int launch_sort_lists(nlfem_pairs *h, hipStream_t s)
+{
+    if (h->nS == 0) return NLFEM_OK;
+    ListArgs a = list_args(h);
+    if (a.cap > 8192) return set_error(NLFEM_E_OVERFLOW, "neighbour list longer than 8192 entries");
+    const unsigned grid = (unsigned)std::min<int64_t>(h->K, 1 << 20);
+    hipLaunchKernelGGL(k_sort_lists, dim3(grid), dim3(64), sizeof(unsigned long long) * a.cap, s, a);
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
+
+int launch_worklists(nlfem_pairs *h, const nlfem_mesh *, hipStream_t s)
+{
+    if (h->nS == 0) return NLFEM_OK;
+    ListArgs a = list_args(h);
+    const unsigned grid = (unsigned)std::min<int64_t>(h->K, 1 << 20);
+    hipLaunchKernelGGL(k_worklists, dim3(grid), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_link, dim3(grid), dim3(64), 0, s, a);
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
+
+}  // namespace nlfem

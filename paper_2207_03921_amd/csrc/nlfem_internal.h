@@ -85,7 +85,7 @@ struct nlfem_pairs {
     double2 *xp = nullptr;       // [K * P] outer quadrature points (FP64)
     uint32_t *node_flags = nullptr;  // [M] bit0 vertex of an Omega element, bit1 of an Omega_D one
     int32_t *err = nullptr;      // [1] error bits
-    unsigned long long *red = nullptr;   // [16] bbox keys 0-3, radii 4-5, max cell 6, max |S| 7, dofs 8
+    unsigned long long *red = nullptr;   // [16] bbox keys 0-3, radii 4-5, max cell 6, max |S| 7, dofs 8, max row 9
     unsigned long long *counters = nullptr;  // [kCntLast]
     // node -> element incidence
     int64_t *ne_ptr = nullptr;   // [M + 1]
@@ -101,10 +101,16 @@ struct nlfem_pairs {
     int64_t *lcnt = nullptr;
     int64_t *loff = nullptr;
     int64_t *scan_tmp = nullptr;
-    // symmetric neighbour list S(e)
+    // symmetric neighbour list S(e) = {f : (e,f) or (f,e) interacts}, each
+    // segment sorted by neighbour id
     int32_t *snbr = nullptr;     // [nS]
     uint8_t *sflag = nullptr;    // [nS] bit0 (e,f) in P, bit1 (f,e) in P, bits 2-3 class
-    // unordered non-touching pairs e <= f with 2-bit point status per direction
+    uint2 *smask = nullptr;      // [nS] 2-bit point status: x = e's points vs f, y = f's points vs e
+    int32_t *srec = nullptr;     // [nS] record of the unordered pair (far or touching list)
+    int32_t *snbr_tmp = nullptr; // unsorted lists written by the pair search
+    uint8_t *sflag_tmp = nullptr;
+    uint2 *smask_tmp = nullptr;
+    // unordered non-touching pairs e <= f (far work list)
     int32_t *ue = nullptr, *uf = nullptr;     // [nUF]
     uint32_t *um_ef = nullptr, *um_fe = nullptr;
     // unordered touching pairs e <= f: [ident | edge | vertex]
@@ -113,9 +119,11 @@ struct nlfem_pairs {
     int64_t *nlen = nullptr;     // [M + 1]
     int64_t *nptr = nullptr;     // [M + 1]
     int32_t *ncol = nullptr;     // [nnz_node]
-    // per-element accumulators of the diagonal blocks: [K][P][n*n] (+ inner rule part)
-    double *dacc = nullptr;
-    int64_t dacc_stride = 0;     // doubles per element
+    int64_t max_row = 0;         // longest node row
+    // per-pair results of the assembly (workspace held by the handle)
+    void *far_rec = nullptr;     // [nUF][far_stride] FP32 (mixed) or FP64
+    double *touch_rec = nullptr; // [nUT][touch_stride]
+    int32_t far_stride = 0, touch_stride = 0;
     // grow-only device buffers behind the typed pointers above
     struct DevBuf {
         void *p = nullptr;
@@ -154,11 +162,16 @@ int launch_count_dofs(nlfem_pairs *h, hipStream_t s);   // -> red[8]
 int launch_cell_count(nlfem_pairs *h, hipStream_t s);
 int launch_cell_fill(nlfem_pairs *h, hipStream_t s);   // also sorts cells, max occupancy -> red[6]
 int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
+// lists.hip: sorted neighbour lists, work lists and record links
+int launch_sort_lists(nlfem_pairs *h, hipStream_t s);
+int launch_worklists(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 // csr.hip
 int launch_csr(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
 int launch_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
 int launch_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls, hipStream_t s);
 // assemble.hip
+int far_record_stride(int ncomp);     // values per non-touching pair record
+int touch_record_stride(int ncomp);   // values per touching pair record
 int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg,
                     const GaussArgs &g, double *val, hipStream_t s);
 // rhs.hip

@@ -49,12 +49,9 @@ struct PairArgs {
     int64_t *lcnt;          // count pass: [kLsLast][K1]
     unsigned long long *maxS;   // count pass: max |S(e)|
     const int64_t *loff;    // fill pass:  [kLsLast][K1]
-    int64_t baseE, baseV;   // offsets of the edge / vertex classes in te, tf
     int32_t *snbr;
     uint8_t *sflag;
-    int32_t *ue, *uf;
-    uint32_t *um_ef, *um_fe;
-    int32_t *te, *tf;
+    uint2 *smask;           // (status of e's points seeing f, status of f's points seeing e)
 };
 
 // ---- polygon ball -------------------------------------------------------
@@ -288,34 +285,11 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                 const unsigned long long bI = __ballot(inS && cls == 3);
                 const unsigned long long bE = __ballot(inS && cls == 2 && f > e);
                 const unsigned long long bV = __ballot(inS && cls == 1 && f > e);
-                if (FILL) {
-                    if (inS) {
-                        const int64_t o = off[kLsS] + __popcll(bS & lt);
-                        a.snbr[o] = f;
-                        a.sflag[o] = flags;
-                    }
-                    if (isUF) {
-                        const int64_t o = off[kLsUF] + __popcll(bF & lt);
-                        a.ue[o] = e;
-                        a.uf[o] = f;
-                        a.um_ef[o] = mef;
-                        a.um_fe[o] = f == e ? 0u : mfe;
-                    }
-                    if (inS && cls == 3) {
-                        const int64_t o = off[kLsUI] + __popcll(bI & lt);
-                        a.te[o] = e;
-                        a.tf[o] = f;
-                    }
-                    if (inS && cls == 2 && f > e) {
-                        const int64_t o = a.baseE + off[kLsUE] + __popcll(bE & lt);
-                        a.te[o] = e;
-                        a.tf[o] = f;
-                    }
-                    if (inS && cls == 1 && f > e) {
-                        const int64_t o = a.baseV + off[kLsUV] + __popcll(bV & lt);
-                        a.te[o] = e;
-                        a.tf[o] = f;
-                    }
+                if (FILL && inS) {
+                    const int64_t o = off[kLsS] + __popcll(bS & lt);
+                    a.snbr[o] = f;
+                    a.sflag[o] = flags;
+                    a.smask[o] = make_uint2(mef, mfe);
                 }
                 off[kLsS] += __popcll(bS);
                 off[kLsP] += __popcll(bP);
@@ -461,16 +435,9 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     a.lcnt = h->lcnt;
     a.maxS = h->red + 7;
     a.loff = h->loff;
-    a.baseE = h->nUTc[0];
-    a.baseV = h->nUTc[0] + h->nUTc[1];
-    a.snbr = h->snbr;
-    a.sflag = h->sflag;
-    a.ue = h->ue;
-    a.uf = h->uf;
-    a.um_ef = h->um_ef;
-    a.um_fe = h->um_fe;
-    a.te = h->te;
-    a.tf = h->tf;
+    a.snbr = h->snbr_tmp;
+    a.sflag = h->sflag_tmp;
+    a.smask = h->smask_tmp;
     const int slices = (h->max_cell + kTE - 1) / kTE;
     if (slices <= 0) return NLFEM_OK;
     const size_t lds = sizeof(double2) * (size_t)kCH * (1 + a.P + (a.poly ? 3 : 0)) +
