@@ -129,6 +129,16 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    # per-phase times from the library's HIP events on the same stream
+    nl.nlfem_timing_enable(True)
+    nl.nlfem_timing_read(reset=True)
+    for _ in range(args.steps):
+        step(cfg)
+    torch.cuda.synchronize()
+    phases = nl.nlfem_timing_read(reset=True)
+    nl.nlfem_timing_enable(False)
+    phase_ms = {k: (v[0] / max(v[1], 1)) for k, v in phases.items()}
+
     t_asm = assemble_ms(cfg)
     t_asm64 = assemble_ms(cfg64)
     t_step64 = timed(cfg64, max(3, args.steps // 2), 1)
@@ -151,6 +161,7 @@ def main():
                    "touching_pairs": info["n_vertex"] + info["n_edge"] + info["n_ident"],
                    "nnz": info["nnz"], "precision": args.precision},
         "assemble_ms": t_asm,
+        "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "assemble_pairs_per_s": n_pairs / (t_asm * 1e-3),
         "fp64_plain": {"ms_per_step": t_step64 * 1e3, "value": n_pairs / t_step64,
                        "assemble_ms": t_asm64},

@@ -201,6 +201,19 @@ int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg,
 int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_qp,
               const double *f_affine, double *b, void *stream);
 
+/* Per-phase timing (diagnostic).  While enabled, every call records a pair of
+   HIP events on its stream around each phase; nlfem_timing_read waits for
+   them and returns the accumulated milliseconds and the number of timed
+   launches per phase since the last reset.  Phases:
+     0 geometry and grid     1 pair search        2 list sorting/linking
+     3 CSR pattern           4 non-touching pairs 5 touching pairs
+     6 row gather            7 load vector
+   Enabling creates events (host allocation); nlfem_assemble then still
+   allocates no device memory.  Not thread-safe.  Errors: E_INVALID, E_HIP. */
+#define NLFEM_TIMING_PHASES 8
+int nlfem_timing_enable(int on);
+int nlfem_timing_read(double *ms, int64_t *launches, int reset);
+
 /* Releases a handle and its device memory (synchronises the device). */
 void nlfem_pairs_free(nlfem_pairs *pairs);
 

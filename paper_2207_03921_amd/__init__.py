@@ -84,6 +84,10 @@ def lib():
         L.nlfem_rhs.restype = i32
         L.nlfem_pairs_free.argtypes = [vp]
         L.nlfem_pairs_free.restype = None
+        L.nlfem_timing_enable.argtypes = [C.c_int]
+        L.nlfem_timing_enable.restype = i32
+        L.nlfem_timing_read.argtypes = [vp, vp, C.c_int]
+        L.nlfem_timing_read.restype = i32
         _lib = L
     return _lib
 
@@ -255,6 +259,20 @@ def nlfem_rhs(mesh: DeviceMesh, cfg: Config, f_qp=None, f_affine=None, b=None, s
     _check(lib().nlfem_rhs(C.byref(cm), C.byref(cc), fq, None if aff is None else aff.ctypes.data,
                            C.c_void_p(_dev_ptr(b, torch.float64, "b")), _stream(stream)))
     return b
+
+
+TIMING_PHASES = ("geometry", "pairs", "lists", "csr", "far", "touch", "rows", "rhs")
+
+
+def nlfem_timing_enable(on: bool = True):
+    _check(lib().nlfem_timing_enable(1 if on else 0))
+
+
+def nlfem_timing_read(reset: bool = True) -> dict:
+    ms = np.zeros(len(TIMING_PHASES), np.float64)
+    n = np.zeros(len(TIMING_PHASES), np.int64)
+    _check(lib().nlfem_timing_read(ms.ctypes.data, n.ctypes.data, 1 if reset else 0))
+    return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(TIMING_PHASES)}
 
 
 def nlfem_pairs_free(pairs: Pairs):

@@ -17,7 +17,7 @@ enum Buf {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
-    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_LAST
+    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_LAST
 };
 
 int ensure(nlfem_pairs *h, int id, size_t bytes)
@@ -230,7 +230,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_FLAGS, M, h->node_flags));
     NLFEM_TRY(ensure_typed(h, B_ERR, 1, h->err));
     NLFEM_TRY(ensure_typed(h, B_RED, 16, h->red));
+    timing_begin(kPhGeometry, s);
     NLFEM_TRY(launch_geometry(h, m, s));
+    timing_end(kPhGeometry, s);
     unsigned long long red[16];
     int32_t err = 0;
     NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof red, hipMemcpyDeviceToHost, s));
@@ -284,7 +286,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_LOFF, kLsLast * K1, h->loff));
     NLFEM_HIP(hipMemsetAsync(h->lcnt, 0, sizeof(int64_t) * kLsLast * K1, s));
     NLFEM_HIP(hipMemsetAsync(h->red + 7, 0, sizeof(unsigned long long), s));
+    timing_begin(kPhPairs, s);
     NLFEM_TRY(launch_pairs(h, m, false, s));
+    timing_end(kPhPairs, s);
     for (int k = 0; k < kLsLast; ++k)
         NLFEM_TRY(exclusive_scan(h->lcnt + k * K1, h->loff + k * K1, K, h->scan_tmp, h->scan_cap, s));
     int64_t tot[kLsLast];
@@ -320,10 +324,14 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_UMFE, h->nUF, h->um_fe));
     NLFEM_TRY(ensure_typed(h, B_TE, h->nUT, h->te));
     NLFEM_TRY(ensure_typed(h, B_TF, h->nUT, h->tf));
+    timing_begin(kPhPairs, s);
     NLFEM_TRY(launch_pairs(h, m, true, s));
+    timing_end(kPhPairs, s);
+    timing_begin(kPhLists, s);
     NLFEM_TRY(launch_sort_lists(h, s));
     NLFEM_HIP(hipMemsetAsync(h->srec, 0xff, sizeof(int32_t) * (size_t)std::max<int64_t>(h->nS, 1), s));
     NLFEM_TRY(launch_worklists(h, m, s));
+    timing_end(kPhLists, s);
 
     // node -> element incidence --------------------------------------------
     NLFEM_TRY(ensure_typed(h, B_NLEN, M + 1, h->nlen));
@@ -343,7 +351,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         h->hcap = hcap;
         NLFEM_HIP(hipMemsetAsync(h->err, 0, sizeof(int32_t), s));
         NLFEM_HIP(hipMemsetAsync(h->red + 9, 0, sizeof(unsigned long long), s));
+        timing_begin(kPhCsr, s);
         NLFEM_TRY(launch_csr(h, m, false, s));
+        timing_end(kPhCsr, s);
         NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
         if (!(err & kErrRowCap)) break;
@@ -357,7 +367,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->n_dof = (int64_t)red[8];
     h->max_row = (int64_t)red[9];
     NLFEM_TRY(ensure_typed(h, B_NCOL, h->nnz_node, h->ncol));
+    timing_begin(kPhCsr, s);
     NLFEM_TRY(launch_csr(h, m, true, s));
+    timing_end(kPhCsr, s);
 
     // workspace of the assembly: one result record per unordered pair
     h->far_stride = far_record_stride(h->ncomp);
@@ -366,6 +378,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_FARREC, h->nUF * h->far_stride, far_rec));
     h->far_rec = far_rec;
     NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
+    NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
     NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
     if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");
@@ -392,6 +405,57 @@ bool same_build(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c
 }
 
 }  // namespace
+
+// ---- timing
+namespace {
+struct Timing {
+    bool on = false;
+    static constexpr int kPool = 4096;
+    hipEvent_t ev[kPool];
+    int used = 0;
+    int open_slot[kPhLast];
+    struct Pair {
+        int phase, a, b;
+    };
+    Pair pairs[kPool / 2];
+    int npairs = 0;
+    double ms[kPhLast] = {};
+    int64_t launches[kPhLast] = {};
+};
+Timing g_timing;
+
+int timing_collect()
+{
+    for (int k = 0; k < g_timing.npairs; ++k) {
+        const auto &p = g_timing.pairs[k];
+        float ms = 0.f;
+        NLFEM_HIP(hipEventSynchronize(g_timing.ev[p.b]));
+        NLFEM_HIP(hipEventElapsedTime(&ms, g_timing.ev[p.a], g_timing.ev[p.b]));
+        g_timing.ms[p.phase] += ms;
+        g_timing.launches[p.phase] += 1;
+    }
+    g_timing.npairs = 0;
+    g_timing.used = 0;
+    return NLFEM_OK;
+}
+}  // namespace
+
+void timing_begin(int phase, hipStream_t s)
+{
+    if (!g_timing.on) return;
+    if (g_timing.used + 2 > Timing::kPool) timing_collect();
+    const int a = g_timing.used++;
+    g_timing.open_slot[phase] = a;
+    (void)hipEventRecord(g_timing.ev[a], s);
+}
+
+void timing_end(int phase, hipStream_t s)
+{
+    if (!g_timing.on) return;
+    const int b = g_timing.used++;
+    (void)hipEventRecord(g_timing.ev[b], s);
+    g_timing.pairs[g_timing.npairs++] = {phase, g_timing.open_slot[phase], b};
+}
 
 int set_error(int code, const std::string &msg)
 {
@@ -497,7 +561,44 @@ int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_q
         for (int t = 0; t < 3 * nc; ++t)
             if (!is_finite(f_affine[t])) return set_error(NLFEM_E_INVALID, "f_affine not finite");
     NLFEM_TRY(check_device());
-    return launch_rhs(mesh, make_rules(cfg), nc, f_qp, f_affine, b, (hipStream_t)stream);
+    timing_begin(kPhRhs, (hipStream_t)stream);
+    const int rc = launch_rhs(mesh, make_rules(cfg), nc, f_qp, f_affine, b, (hipStream_t)stream);
+    timing_end(kPhRhs, (hipStream_t)stream);
+    return rc;
+}
+
+int nlfem_timing_enable(int on)
+{
+    if (on && !g_timing.on) {
+        NLFEM_TRY(check_device());
+        for (int k = 0; k < Timing::kPool; ++k) NLFEM_HIP(hipEventCreate(&g_timing.ev[k]));
+        g_timing.used = g_timing.npairs = 0;
+        for (int k = 0; k < kPhLast; ++k) {
+            g_timing.ms[k] = 0.0;
+            g_timing.launches[k] = 0;
+        }
+        g_timing.on = true;
+    } else if (!on && g_timing.on) {
+        NLFEM_TRY(timing_collect());
+        for (int k = 0; k < Timing::kPool; ++k) (void)hipEventDestroy(g_timing.ev[k]);
+        g_timing.on = false;
+    }
+    return NLFEM_OK;
+}
+
+int nlfem_timing_read(double *ms, int64_t *launches, int reset)
+{
+    if (!ms || !launches) return set_error(NLFEM_E_INVALID, "NULL output array");
+    if (g_timing.on) NLFEM_TRY(timing_collect());
+    for (int k = 0; k < kPhLast; ++k) {
+        ms[k] = g_timing.ms[k];
+        launches[k] = g_timing.launches[k];
+        if (reset) {
+            g_timing.ms[k] = 0.0;
+            g_timing.launches[k] = 0;
+        }
+    }
+    return NLFEM_OK;
 }
 
 void nlfem_pairs_free(nlfem_pairs *h)

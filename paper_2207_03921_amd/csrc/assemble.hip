@@ -436,6 +436,55 @@ __global__ void __launch_bounds__(256) k_touch_rec(TouchArgs a, GaussArgs g)
         if (t % G == sub) out[t] = scale * L[t];
 }
 
+// ------------------------------------------ phase 1b: element diagonals
+// D_e = sum over the non-touching pairs of e of the element-diagonal part of
+// their records (De when e is the first element, Df when it is the second).
+// One wave per element; the rows then add D_e once per element.
+
+struct DiagArgs {
+    int64_t K;
+    const int64_t *sptr;
+    const int32_t *snbr;
+    const uint8_t *sflag;
+    const int32_t *srec;
+    const void *far_rec;
+    int32_t far_stride;
+    int64_t n_far;
+    double *dsum;
+    int32_t *err;
+};
+
+template <int NK, typename TR>
+__global__ void __launch_bounds__(256) k_elem_diag(DiagArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= a.K) return;
+    double acc[6 * NK];
+    for (int i = 0; i < 6 * NK; ++i) acc[i] = 0.0;
+    bool bad = false;
+    for (int64_t t = a.sptr[e] + lane; t < a.sptr[e + 1]; t += 64) {
+        if (((a.sflag[t] >> 2) & 3) != 0) continue;
+        const int32_t u = a.srec[t];
+        if (u < 0 || u >= a.n_far) {
+            bad = true;
+            continue;
+        }
+        const int32_t f = a.snbr[t];
+        const TR *r = (const TR *)a.far_rec + (int64_t)u * a.far_stride + (f >= e ? 9 : 15) * NK;
+        for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
+    }
+    for (int i = 0; i < 6 * NK; ++i)
+        for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_xor(acc[i], o);
+    if (bad) atomicOr(a.err, kErrSlot);
+    if (lane < 6 * NK) {
+        double v = 0.0;
+        for (int i = 0; i < 6 * NK; ++i)
+            if (i == lane) v = acc[i];
+        a.dsum[e * 6 * NK + lane] = v;
+    }
+}
+
 // ------------------------------------------------- phase 2: row gather
 
 struct RowArgs {
@@ -453,6 +502,7 @@ struct RowArgs {
     const void *far_rec;
     int32_t far_stride;
     int64_t n_far;
+    const double *dsum;
     const double *touch_rec;
     int32_t touch_stride;
     int64_t n_touch;
@@ -489,8 +539,10 @@ __device__ inline void add_sym_block(double *acc, int pos, const double *v)
     }
 }
 
+constexpr int kRowThreads = 256;
+
 template <int NC, typename TR>
-__global__ void __launch_bounds__(64) k_rows(RowArgs a)
+__global__ void __launch_bounds__(kRowThreads) k_rows(RowArgs a)
 {
     constexpr int NN = NC * NC;
     constexpr int NK = NC == 1 ? 1 : 3;
@@ -498,19 +550,19 @@ __global__ void __launch_bounds__(64) k_rows(RowArgs a)
     double *acc = (double *)smem;                              // [maxlen * NN]
     int32_t *hk = (int32_t *)(acc + (size_t)a.maxlen * NN);    // [hcap]
     int32_t *hv = hk + a.hcap;                                 // [hcap]
-    __shared__ int64_t pre[kRowQ + 1];
-    __shared__ int32_t qe[kRowQ], qloc[kRowQ];
-    const int lane = threadIdx.x;
+    __shared__ int64_t pre[kRowQ + 1], qs[kRowQ];
+    __shared__ int32_t qe[kRowQ], qloc[kRowQ], qn[kRowQ][3], qp[kRowQ][3];
+    const int tid = threadIdx.x;
     const int32_t mask = a.hcap - 1;
     for (int64_t i = blockIdx.x; i < a.M; i += gridDim.x) {
         if (a.node_flags[i] != 1u) continue;
         const int64_t s = a.nptr[i];
         const int len = (int)(a.nptr[i + 1] - s);
         if (len == 0) continue;
-        for (int t = lane; t < a.hcap; t += 64) hk[t] = -1;
-        for (int t = lane; t < len * NN; t += 64) acc[t] = 0.0;
+        for (int t = tid; t < a.hcap; t += kRowThreads) hk[t] = -1;
+        for (int t = tid; t < len * NN; t += kRowThreads) acc[t] = 0.0;
         __syncthreads();
-        for (int t = lane; t < len; t += 64) {
+        for (int t = tid; t < len; t += kRowThreads) {
             const int32_t key = a.ncol[s + t];
             uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
             for (int probe = 0; probe <= mask; ++probe) {
@@ -526,61 +578,70 @@ __global__ void __launch_bounds__(64) k_rows(RowArgs a)
         const int64_t q0 = a.ne_ptr[i], q1 = a.ne_ptr[i + 1];
         for (int64_t qb = q0; qb < q1; qb += kRowQ) {
             const int nq = (int)min((int64_t)kRowQ, q1 - qb);
-            if (lane == 0) {
-                int64_t p = 0;
-                for (int q = 0; q < nq; ++q) {
-                    const int32_t e = a.ne_list[qb + q];
-                    qe[q] = e;
-                    pre[q] = p;
-                    p += a.sptr[e + 1] - a.sptr[e];
-                    const int32_t *En = a.E + 3 * (int64_t)e;
-                    qloc[q] = En[0] == (int32_t)i ? 0 : En[1] == (int32_t)i ? 1 : 2;
+            if (tid < nq) {
+                // the elements around the node: id, local index of the node,
+                // vertex ids and their column positions
+                const int32_t e = a.ne_list[qb + tid];
+                const int32_t *En = a.E + 3 * (int64_t)e;
+                qe[tid] = e;
+                qs[tid] = a.sptr[e];
+                for (int b = 0; b < 3; ++b) {
+                    qn[tid][b] = En[b];
+                    qp[tid][b] = hpos(hk, hv, mask, En[b]);
                 }
-                pre[nq] = p;
+                const int loc = En[0] == (int32_t)i ? 0 : En[1] == (int32_t)i ? 1 : 2;
+                qloc[tid] = loc;
+                pre[tid + 1] = a.sptr[e + 1] - a.sptr[e];
+                // summed element-diagonal block of e's non-touching pairs, row loc
+                const double *dv = a.dsum + (int64_t)e * 6 * NK;
+                for (int b = 0; b < 3 && a.sptr[e + 1] > a.sptr[e]; ++b) {
+                    if (qp[tid][b] < 0) {
+                        bad = true;
+                        continue;
+                    }
+                    double ds[NK];
+                    for (int k = 0; k < NK; ++k) ds[k] = dv[sym_index(loc, b, 3) * NK + k];
+                    add_sym_block<NC>(acc, qp[tid][b], ds);
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                pre[0] = 0;
+                for (int q = 0; q < nq; ++q) pre[q + 1] += pre[q];
             }
             __syncthreads();
             const int64_t total = pre[nq];
-            for (int64_t flat = lane; flat < total; flat += 64) {
+            for (int64_t flat = tid; flat < total; flat += kRowThreads) {
                 int q = 0;
                 while (pre[q + 1] <= flat) ++q;
                 const int32_t e = qe[q];
                 const int loc = qloc[q];
-                const int64_t t = a.sptr[e] + (flat - pre[q]);
+                const int64_t t = qs[q] + (flat - pre[q]);
                 const int32_t f = a.snbr[t];
                 const int cls = (a.sflag[t] >> 2) & 3;
                 const int32_t u = a.srec[t];
-                const int32_t ne[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
-                const int32_t nf[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
                 if (u < 0 || u >= (cls == 0 ? a.n_far : a.n_touch)) {
                     bad = true;
                     continue;
                 }
+                const int32_t nf[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
                 if (cls == 0) {
+                    // cross block: row loc of X (e first), column loc (e second);
+                    // the self pair stores X + X^T, columns are e's own nodes
                     const TR *r = (const TR *)a.far_rec + (int64_t)u * a.far_stride;
                     for (int b = 0; b < 3; ++b) {
-                        // cross block: row loc of X (e first) or column loc (e second)
                         const int xi = f >= e ? 3 * loc + b : 3 * b + loc;
-                        const int di = 9 + sym_index(loc, b, 3) + (f >= e ? 0 : 6);
-                        const int px = hpos(hk, hv, mask, nf[b]);
-                        const int pd = hpos(hk, hv, mask, ne[b]);
-                        if (px < 0 || pd < 0) {
+                        const int px = f == e ? qp[q][b] : hpos(hk, hv, mask, nf[b]);
+                        if (px < 0) {
                             bad = true;
                             continue;
                         }
-                        double xs[NK], ds[NK];
-                        for (int k = 0; k < NK; ++k) {
-                            xs[k] = (double)r[xi * NK + k];
-                            ds[k] = (double)r[di * NK + k];
-                        }
-                        if (f == e) {   // self pair: X + X^T and both diagonal parts, all in cols of e
-                            for (int k = 0; k < NK; ++k) ds[k] += xs[k];
-                            add_sym_block<NC>(acc, pd, ds);
-                        } else {
-                            add_sym_block<NC>(acc, px, xs);
-                            add_sym_block<NC>(acc, pd, ds);
-                        }
+                        double xs[NK];
+                        for (int k = 0; k < NK; ++k) xs[k] = (double)r[xi * NK + k];
+                        add_sym_block<NC>(acc, px, xs);
                     }
                 } else {
+                    const int32_t ne[3] = {qn[q][0], qn[q][1], qn[q][2]};
                     const bool first = e <= f;
                     const int32_t *k1 = first ? ne : nf;
                     const int32_t *k2 = first ? nf : ne;
@@ -611,9 +672,9 @@ __global__ void __launch_bounds__(64) k_rows(RowArgs a)
         }
         if (bad) atomicOr(a.err, kErrSlot);
         if (NC == 1) {
-            for (int t = lane; t < len; t += 64) a.val[s + t] = acc[t];
+            for (int t = tid; t < len; t += kRowThreads) a.val[s + t] = acc[t];
         } else {
-            for (int t = lane; t < len * 4; t += 64) {
+            for (int t = tid; t < len * 4; t += kRowThreads) {
                 const int pos = t >> 2, c = (t >> 1) & 1, d = t & 1;
                 a.val[4 * s + (int64_t)c * 2 * len + 2 * pos + d] = acc[t];
             }
@@ -715,11 +776,13 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         // (outer on e, inner on f) and pass 2 (inner on e, outer on f).
         const RoleArgs r1 = roles(h->rules, true, h->rules.same ? true : false);
         const RoleArgs r2 = roles(h->rules, false, true);
+        timing_begin(kPhFar, s);
         switch (h->kernel) {
         case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(a, r1, r2, fp32, s); break;
         case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(a, r1, r2, fp32, s); break;
         default: far_dispatch<NLFEM_K_PERIDYNAMIC>(a, r1, r2, fp32, s); break;
         }
+        timing_end(kPhFar, s);
     }
     if (h->nUT > 0) {
         TouchArgs t{};
@@ -727,11 +790,13 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         t.V = m->vertices;
         t.stride = h->touch_stride;
         t.c = cfg->c;
+        timing_begin(kPhTouch, s);
         switch (h->kernel) {
         case NLFEM_K_CONSTANT: touch_launch<NLFEM_K_CONSTANT>(h, t, g, s); break;
         case NLFEM_K_INV_DIST: touch_launch<NLFEM_K_INV_DIST>(h, t, g, s); break;
         default: touch_launch<NLFEM_K_PERIDYNAMIC>(h, t, g, s); break;
         }
+        timing_end(kPhTouch, s);
     }
     if (h->nnz_node > 0) {
         RowArgs r{};
@@ -749,6 +814,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         r.far_rec = h->far_rec;
         r.far_stride = h->far_stride;
         r.n_far = h->nUF;
+        r.dsum = h->dsum;
         r.touch_rec = h->touch_rec;
         r.touch_stride = h->touch_stride;
         r.n_touch = h->nUT;
@@ -760,13 +826,26 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         r.err = h->err;
         const size_t lds = sizeof(double) * (size_t)h->max_row * nc * nc + sizeof(int32_t) * 2 * (size_t)hc;
         const unsigned grid = (unsigned)std::min<int64_t>(h->M, 1 << 20);
-        if (nc == 1) {
-            if (fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(64), lds, s, r);
-            else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(64), lds, s, r);
-        } else {
-            if (fp32) hipLaunchKernelGGL((k_rows<2, float>), dim3(grid), dim3(64), lds, s, r);
-            else hipLaunchKernelGGL((k_rows<2, double>), dim3(grid), dim3(64), lds, s, r);
+        timing_begin(kPhRows, s);
+        {
+            DiagArgs d{h->K, r.sptr, h->snbr, h->sflag, h->srec, h->far_rec, h->far_stride, h->nUF, h->dsum, h->err};
+            const unsigned dg = grid_for(h->K, 4);
+            if (nc == 1) {
+                if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float>), dim3(dg), dim3(256), 0, s, d);
+                else hipLaunchKernelGGL((k_elem_diag<1, double>), dim3(dg), dim3(256), 0, s, d);
+            } else {
+                if (fp32) hipLaunchKernelGGL((k_elem_diag<3, float>), dim3(dg), dim3(256), 0, s, d);
+                else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, d);
+            }
         }
+        if (nc == 1) {
+            if (fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(kRowThreads), lds, s, r);
+            else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(kRowThreads), lds, s, r);
+        } else {
+            if (fp32) hipLaunchKernelGGL((k_rows<2, float>), dim3(grid), dim3(kRowThreads), lds, s, r);
+            else hipLaunchKernelGGL((k_rows<2, double>), dim3(grid), dim3(kRowThreads), lds, s, r);
+        }
+        timing_end(kPhRows, s);
     }
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;

@@ -123,6 +123,7 @@ struct nlfem_pairs {
     // per-pair results of the assembly (workspace held by the handle)
     void *far_rec = nullptr;     // [nUF][far_stride] FP32 (mixed) or FP64
     double *touch_rec = nullptr; // [nUT][touch_stride]
+    double *dsum = nullptr;      // [K][6 * NK] summed element-diagonal blocks of the far pairs
     int32_t far_stride = 0, touch_stride = 0;
     // grow-only device buffers behind the typed pointers above
     struct DevBuf {
@@ -134,6 +135,11 @@ struct nlfem_pairs {
 };
 
 namespace nlfem {
+
+// per-phase timing (abi.hip): no-ops unless enabled ------------------------
+enum { kPhGeometry = 0, kPhPairs, kPhLists, kPhCsr, kPhFar, kPhTouch, kPhRows, kPhRhs, kPhLast };
+void timing_begin(int phase, hipStream_t s);
+void timing_end(int phase, hipStream_t s);
 
 // error reporting (abi.hip) --------------------------------------------
 int set_error(int code, const std::string &msg);
