@@ -55,19 +55,77 @@ def _f_affine(w):
     return [(float(v), 0.0, 0.0) for v in w["f"]]
 
 
-def cpu_baseline(w):
-    """The oracle as it stands on the host cores: the whole workload once
-    (brute-force pair search, assembly, load vector)."""
+def cpu_baseline(w, runs=3):
+    """The oracle as it stands on the host cores: the whole workload
+    (brute-force pair search, assembly, load vector), median of `runs`."""
     import oracle
     oracle.build(force=False)
     P = oracle.Problem(w["mesh"], w)
-    t0 = time.perf_counter()
-    k, l, c = P.pairs()
-    P.assemble((k, l, c))
-    P.rhs(f_affine=_f_affine(w))
-    dt = time.perf_counter() - t0
-    return {"value": len(k) / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"whole workload once ({len(k)} ordered pairs, {dt:.2f} s)"}
+    times, n = [], 0
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        k, l, c = P.pairs()
+        P.assemble((k, l, c))
+        P.rhs(f_affine=_f_affine(w))
+        times.append(time.perf_counter() - t0)
+        n = len(k)
+    dt = sorted(times)[len(times) // 2]
+    return {"value": n / dt, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"whole workload ({n} ordered pairs), median of {runs} runs of {dt:.2f} s"}
+
+
+# ---------------------------------------------------------------- roofline
+#
+# Dominant kernel of the step: the row gather (phase "rows", one launch per
+# assembly).  Its algorithmic bytes are what the row-owner gather must move
+# at least once: every pair record and neighbour-list entry read once, the
+# pattern read once and every value written once.
+HBM_PEAK_GBS = 8000.0
+
+
+def rows_algorithmic_bytes(info, n_vertices, n_elements, ncomp, precision):
+    tr = 4 if precision == "mixed" else 8        # far records are FP32 in the mixed form
+    nk = 1 if ncomp == 1 else 3
+    far_stride = 21 * nk                         # X (9 blocks), De and Df (6 blocks each)
+    touch_stride = (5 * ncomp) * (5 * ncomp + 1) // 2
+    K, M = n_elements, n_vertices
+    nnz_node = info["nnz"] // (ncomp * ncomp)
+    return (info["n_upper_far"] * far_stride * tr       # non-touching records
+            + info["n_upper_touch"] * touch_stride * 8  # touching records
+            + K * 6 * nk * 8                            # per-element diagonal sums
+            + info["n_nbr"] * (4 + 1 + 4)               # neighbour lists: id, flags, record index
+            + K * 3 * 4 + 3 * K * 4                     # element vertices, node->element incidence
+            + 2 * (M + 1) * 8 + M * 4                   # row and incidence pointers, node flags
+            + nnz_node * 4                              # column ids
+            + info["nnz"] * 8)                          # values, written once
+
+
+def _source_digest(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the row gather from the committed counter
+    summary, or None when it is missing or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_rows_{workload}_{precision}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2207_03921_amd", "csrc", "assemble.hip")
+    if kv.get("source_sha256_16") != _source_digest(src):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -78,6 +136,8 @@ def main():
     ap.add_argument("--workload", default="invdist_h64", choices=WORKLOADS)
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this size once (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
@@ -109,13 +169,20 @@ def main():
         for _ in range(warmup):
             step(c)
         torch.cuda.synchronize()
+        # the row gather is timed by the library's HIP events on the stream
+        # it is launched on, over exactly the timed steps
+        nl.nlfem_timing_enable(["rows"])
+        nl.nlfem_timing_read(reset=True)
         t0 = time.perf_counter()
         for _ in range(steps):
             step(c)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        dt = (time.perf_counter() - t0) / steps
+        rows = nl.nlfem_timing_read(reset=True)["rows"]
+        nl.nlfem_timing_enable(False)
+        return dt, rows[0] / max(rows[1], 1)
 
-    t_step = timed(cfg, args.steps, args.warmup)
+    t_step, t_rows = timed(cfg, args.steps, args.warmup)
 
     # assemble alone (HIP events on the library's stream)
     def assemble_ms(c, reps=20):
@@ -129,7 +196,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    # per-phase times from the library's HIP events on the same stream
+    # per-phase times per step, all phases timed (separate, untimed loop)
     nl.nlfem_timing_enable(True)
     nl.nlfem_timing_read(reset=True)
     for _ in range(args.steps):
@@ -137,12 +204,18 @@ def main():
     torch.cuda.synchronize()
     phases = nl.nlfem_timing_read(reset=True)
     nl.nlfem_timing_enable(False)
-    phase_ms = {k: (v[0] / max(v[1], 1)) for k, v in phases.items()}
+    phase_ms = {k: v[0] / args.steps for k, v in phases.items()}
 
     t_asm = assemble_ms(cfg)
     t_asm64 = assemble_ms(cfg64)
-    t_step64 = timed(cfg64, max(3, args.steps // 2), 1)
+    t_step64, _ = timed(cfg64, max(3, args.steps // 2), 1)
     n_pairs = info["n_pairs"]
+    alg = rows_algorithmic_bytes(info, mesh.n_vertices, mesh.n_elements, cfg.ncomp, args.precision)
+    achieved = alg / (t_rows * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(args.workload, args.precision),
+                "kernel": "k_rows (row gather)", "algorithmic_bytes": alg, "launch_ms": t_rows}
     out = {
         "metric": "element-pair interactions assembled/sec",
         "value": n_pairs / t_step,
@@ -160,12 +233,20 @@ def main():
                    "vertices": mesh.n_vertices, "ordered_pairs": n_pairs,
                    "touching_pairs": info["n_vertex"] + info["n_edge"] + info["n_ident"],
                    "nnz": info["nnz"], "precision": args.precision},
+        "roofline": roofline,
         "assemble_ms": t_asm,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "assemble_pairs_per_s": n_pairs / (t_asm * 1e-3),
         "fp64_plain": {"ms_per_step": t_step64 * 1e3, "value": n_pairs / t_step64,
                        "assemble_ms": t_asm64},
     }
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = n
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

@@ -136,6 +136,8 @@ typedef struct {
     int64_t nnz;          /* stored entries of the CSR matrix */
     int64_t n_upper_far;  /* unordered non-touching pairs processed by assemble */
     int64_t n_upper_touch;/* unordered touching pairs processed by assemble */
+    int64_t n_nbr;        /* entries of the symmetric neighbour lists
+                             S(k) = {l : (k,l) or (l,k) interacts}, summed over k */
 } nlfem_pairs_info_t;
 
 /* ABI version (NLFEM_ABI_VERSION of the built library). */
@@ -201,17 +203,20 @@ int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg,
 int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_qp,
               const double *f_affine, double *b, void *stream);
 
-/* Per-phase timing (diagnostic).  While enabled, every call records a pair of
-   HIP events on its stream around each phase; nlfem_timing_read waits for
-   them and returns the accumulated milliseconds and the number of timed
-   launches per phase since the last reset.  Phases:
+/* Per-phase timing (diagnostic).  Bit p of `mask` enables phase p; 0 turns
+   timing off.  While phase p is enabled, every call records a pair of HIP
+   events on its stream around each launch group of that phase;
+   nlfem_timing_read waits for them and returns the accumulated milliseconds
+   and the number of timed groups per phase since the last reset.  Phases:
      0 geometry and grid     1 pair search        2 list sorting/linking
-     3 CSR pattern           4 non-touching pairs 5 touching pairs
-     6 row gather            7 load vector
+     3 CSR pattern           4 non-touching pairs (records, then the
+                               per-element sums of their diagonal blocks)
+     5 touching pairs        6 row gather (one kernel)   7 load vector
    Enabling creates events (host allocation); nlfem_assemble then still
-   allocates no device memory.  Not thread-safe.  Errors: E_INVALID, E_HIP. */
+   allocates no device memory.  Not thread-safe.
+   Errors: E_INVALID (mask outside [0, 2^NLFEM_TIMING_PHASES)), E_HIP. */
 #define NLFEM_TIMING_PHASES 8
-int nlfem_timing_enable(int on);
+int nlfem_timing_enable(int mask);
 int nlfem_timing_read(double *ms, int64_t *launches, int reset);
 
 /* Releases a handle and its device memory (synchronises the device). */

@@ -54,7 +54,7 @@ class _Config(C.Structure):
 
 class _Info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_pairs", "n_far", "n_vertex", "n_edge", "n_ident",
-                                         "n_dof", "n_rows", "nnz", "n_upper_far", "n_upper_touch")]
+                                         "n_dof", "n_rows", "nnz", "n_upper_far", "n_upper_touch", "n_nbr")]
 
 
 _lib = None
@@ -264,8 +264,18 @@ def nlfem_rhs(mesh: DeviceMesh, cfg: Config, f_qp=None, f_affine=None, b=None, s
 TIMING_PHASES = ("geometry", "pairs", "lists", "csr", "far", "touch", "rows", "rhs")
 
 
-def nlfem_timing_enable(on: bool = True):
-    _check(lib().nlfem_timing_enable(1 if on else 0))
+def nlfem_timing_enable(phases=True):
+    """True: time every phase; False/None: off; an iterable of phase names:
+    time only those."""
+    if phases is True:
+        mask = (1 << len(TIMING_PHASES)) - 1
+    elif not phases:
+        mask = 0
+    else:
+        mask = 0
+        for p in phases:
+            mask |= 1 << TIMING_PHASES.index(p)
+    _check(lib().nlfem_timing_enable(mask))
 
 
 def nlfem_timing_read(reset: bool = True) -> dict:

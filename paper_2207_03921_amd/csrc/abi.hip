@@ -17,7 +17,7 @@ enum Buf {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
-    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_LAST
+    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_LAST
 };
 
 int ensure(nlfem_pairs *h, int id, size_t bytes)
@@ -339,6 +339,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_NEPTR, M + 1, h->ne_ptr));
     NLFEM_TRY(ensure_typed(h, B_NELIST, 3 * K, h->ne_list));
     NLFEM_TRY(ensure_typed(h, B_NEFILL, M, h->ne_fill));
+    NLFEM_TRY(ensure_typed(h, B_DOFL, M, h->dof_list));
     NLFEM_TRY(launch_incidence_count(h, m, s));
     NLFEM_TRY(exclusive_scan(h->nlen, h->ne_ptr, M, h->scan_tmp, h->scan_cap, s));
     NLFEM_TRY(launch_incidence(h, m, s));
@@ -410,6 +411,7 @@ bool same_build(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c
 namespace {
 struct Timing {
     bool on = false;
+    int mask = 0;                 // bit p: phase p is timed
     static constexpr int kPool = 4096;
     hipEvent_t ev[kPool];
     int used = 0;
@@ -442,7 +444,7 @@ int timing_collect()
 
 void timing_begin(int phase, hipStream_t s)
 {
-    if (!g_timing.on) return;
+    if (!g_timing.on || !((g_timing.mask >> phase) & 1)) return;
     if (g_timing.used + 2 > Timing::kPool) timing_collect();
     const int a = g_timing.used++;
     g_timing.open_slot[phase] = a;
@@ -451,7 +453,7 @@ void timing_begin(int phase, hipStream_t s)
 
 void timing_end(int phase, hipStream_t s)
 {
-    if (!g_timing.on) return;
+    if (!g_timing.on || !((g_timing.mask >> phase) & 1)) return;
     const int b = g_timing.used++;
     (void)hipEventRecord(g_timing.ev[b], s);
     g_timing.pairs[g_timing.npairs++] = {phase, g_timing.open_slot[phase], b};
@@ -511,6 +513,7 @@ int nlfem_pairs_info(const nlfem_pairs *h, nlfem_pairs_info_t *info)
     info->nnz = h->nnz_node * h->ncomp * h->ncomp;
     info->n_upper_far = h->nUF;
     info->n_upper_touch = h->nUT;
+    info->n_nbr = h->nS;
     return NLFEM_OK;
 }
 
@@ -567,8 +570,13 @@ int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_q
     return rc;
 }
 
-int nlfem_timing_enable(int on)
+int nlfem_timing_enable(int mask)
 {
+    if (mask < 0 || mask >= (1 << NLFEM_TIMING_PHASES))
+        return set_error(NLFEM_E_INVALID, "timing mask has bits outside the phases");
+    const bool on = mask != 0;
+    if (on && g_timing.on) NLFEM_TRY(timing_collect());   // close the pairs of the old mask
+    g_timing.mask = mask;
     if (on && !g_timing.on) {
         NLFEM_TRY(check_device());
         for (int k = 0; k < Timing::kPool; ++k) NLFEM_HIP(hipEventCreate(&g_timing.ev[k]));

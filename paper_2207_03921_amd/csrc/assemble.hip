@@ -458,7 +458,7 @@ template <int NK, typename TR>
 __global__ void __launch_bounds__(256) k_elem_diag(DiagArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t e = xcd_item(blockIdx.x, (a.K + 3) / 4) * 4 + (threadIdx.x >> 6);
     if (e >= a.K) return;
     double acc[6 * NK];
     for (int i = 0; i < 6 * NK; ++i) acc[i] = 0.0;
@@ -486,10 +486,18 @@ __global__ void __launch_bounds__(256) k_elem_diag(DiagArgs a)
 }
 
 // ------------------------------------------------- phase 2: row gather
+//
+// One wave per degree-of-freedom node.  The wave maps the row's column ids to
+// positions through an LDS hash table, accumulates the row in LDS and writes
+// it once.  The work items are the entries (e, f) of the neighbour lists S(e)
+// of the elements e around the node.  Each lane takes kRowU entries per step
+// and issues all their loads (list entry, then vertices of f and record
+// values) before it adds any of them, so the dependent global loads of a
+// step overlap instead of forming one chain per entry.
 
 struct RowArgs {
-    int64_t M;
-    const uint32_t *node_flags;
+    int64_t nrows;
+    const int32_t *rows;     // dof nodes
     const int64_t *nptr;
     const int32_t *ncol;
     const int64_t *ne_ptr;
@@ -512,7 +520,8 @@ struct RowArgs {
     int32_t *err;
 };
 
-constexpr int kRowQ = 32;   // elements around a node handled per batch
+constexpr int kRowQ = 64;   // elements around a node per batch (one per lane)
+constexpr int kRowU = 4;    // neighbour-list entries per lane per step
 
 __device__ inline int hpos(const int32_t *hk, const int32_t *hv, int32_t mask, int32_t key)
 {
@@ -539,10 +548,88 @@ __device__ inline void add_sym_block(double *acc, int pos, const double *v)
     }
 }
 
-constexpr int kRowThreads = 256;
+__device__ inline int32_t pick3(int i, int32_t x0, int32_t x1, int32_t x2)
+{
+    return i == 0 ? x0 : (i == 1 ? x1 : x2);
+}
+
+// The vertex order of touch_frame, on scalars (a: first element of the
+// ordered pair, b: second); unused slots are -1.
+struct Frame {
+    int32_t n0, n1, n2, n3, n4;
+    int nu;
+};
+
+__device__ inline Frame frame_of(int cls, int32_t a0, int32_t a1, int32_t a2, int32_t b0, int32_t b1,
+                                 int32_t b2)
+{
+    if (cls == 3) return Frame{a0, a1, a2, -1, -1, 3};
+    if (cls == 2) {
+        const bool i0 = a0 == b0 || a0 == b1 || a0 == b2;
+        const bool i1 = a1 == b0 || a1 == b1 || a1 == b2;
+        const int32_t s0 = !i0 ? a1 : a0;
+        const int32_t s1 = (!i0 || !i1) ? a2 : a1;
+        const int32_t A = !i0 ? a0 : (!i1 ? a1 : a2);
+        const bool j0 = b0 == a0 || b0 == a1 || b0 == a2;
+        const bool j1 = b1 == a0 || b1 == a1 || b1 == a2;
+        const int32_t B = !j0 ? b0 : (!j1 ? b1 : b2);
+        return Frame{min(s0, s1), max(s0, s1), A, B, -1, 4};
+    }
+    const int32_t av[3] = {a0, a1, a2}, bv[3] = {b0, b1, b2};
+    int ia = 0, ib = 0;
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+            if (av[x] == bv[y]) {
+                ia = x;
+                ib = y;
+            }
+    const int ia1 = ia == 2 ? 0 : ia + 1, ia2 = ia == 0 ? 2 : ia - 1;
+    const int ib1 = ib == 2 ? 0 : ib + 1, ib2 = ib == 0 ? 2 : ib - 1;
+    return Frame{pick3(ia, a0, a1, a2), pick3(ia1, a0, a1, a2), pick3(ia2, a0, a1, a2),
+                 pick3(ib1, b0, b1, b2), pick3(ib2, b0, b1, b2), 5};
+}
+
+// Row i's share of a touching pair: factor * (row rr of L) over the frame
+// nodes, rr the frame slot of i.
+template <int NC>
+__device__ inline bool add_touch(double *acc, const int32_t *hk, const int32_t *hv, int32_t mask, int32_t i,
+                                 int cls, int32_t e, int32_t f, int32_t e0, int32_t e1, int32_t e2,
+                                 int32_t f0, int32_t f1, int32_t f2, const double *L)
+{
+    constexpr int NN = NC * NC;
+    const bool first = e <= f;
+    const Frame fr = first ? frame_of(cls, e0, e1, e2, f0, f1, f2) : frame_of(cls, f0, f1, f2, e0, e1, e2);
+    const int32_t nodes[5] = {fr.n0, fr.n1, fr.n2, fr.n3, fr.n4};
+    int rr = 0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        if (nodes[c] == i) rr = c;
+    const bool ine = e0 == i || e1 == i || e2 == i;
+    const bool inf = f0 == i || f1 == i || f2 == i;
+    const double factor = (cls == 3 || (ine && inf)) ? 1.0 : 2.0;
+    const int D = fr.nu * NC;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        if (c >= fr.nu) break;
+        const int pc = hpos(hk, hv, mask, nodes[c]);
+        if (pc < 0) {
+            ok = false;
+            continue;
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+            for (int dd = 0; dd < NC; ++dd)
+                atomicAdd(&acc[pc * NN + cc * NC + dd], factor * L[sym_index(rr * NC + cc, c * NC + dd, D)]);
+    }
+    return ok;
+}
 
 template <int NC, typename TR>
-__global__ void __launch_bounds__(kRowThreads) k_rows(RowArgs a)
+__global__ void __launch_bounds__(64) k_rows(RowArgs a)
 {
     constexpr int NN = NC * NC;
     constexpr int NK = NC == 1 ? 1 : 3;
@@ -550,19 +637,21 @@ __global__ void __launch_bounds__(kRowThreads) k_rows(RowArgs a)
     double *acc = (double *)smem;                              // [maxlen * NN]
     int32_t *hk = (int32_t *)(acc + (size_t)a.maxlen * NN);    // [hcap]
     int32_t *hv = hk + a.hcap;                                 // [hcap]
-    __shared__ int64_t pre[kRowQ + 1], qs[kRowQ];
-    __shared__ int32_t qe[kRowQ], qloc[kRowQ], qn[kRowQ][3], qp[kRowQ][3];
-    const int tid = threadIdx.x;
+    __shared__ int64_t qs[kRowQ];
+    __shared__ int32_t pre[kRowQ + 1], qe[kRowQ], qloc[kRowQ], qn[kRowQ][3], qp[kRowQ][3];
+    const int lane = threadIdx.x;
     const int32_t mask = a.hcap - 1;
-    for (int64_t i = blockIdx.x; i < a.M; i += gridDim.x) {
-        if (a.node_flags[i] != 1u) continue;
+    for (int64_t b = blockIdx.x; b < xcd_span(a.nrows); b += gridDim.x) {
+        const int64_t item = xcd_item(b, a.nrows);
+        if (item >= a.nrows) continue;
+        const int64_t i = a.rows[item];
         const int64_t s = a.nptr[i];
         const int len = (int)(a.nptr[i + 1] - s);
         if (len == 0) continue;
-        for (int t = tid; t < a.hcap; t += kRowThreads) hk[t] = -1;
-        for (int t = tid; t < len * NN; t += kRowThreads) acc[t] = 0.0;
+        for (int t = lane; t < a.hcap; t += 64) hk[t] = -1;
+        for (int t = lane; t < len * NN; t += 64) acc[t] = 0.0;
         __syncthreads();
-        for (int t = tid; t < len; t += kRowThreads) {
+        for (int t = lane; t < len; t += 64) {
             const int32_t key = a.ncol[s + t];
             uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
             for (int probe = 0; probe <= mask; ++probe) {
@@ -578,93 +667,130 @@ __global__ void __launch_bounds__(kRowThreads) k_rows(RowArgs a)
         const int64_t q0 = a.ne_ptr[i], q1 = a.ne_ptr[i + 1];
         for (int64_t qb = q0; qb < q1; qb += kRowQ) {
             const int nq = (int)min((int64_t)kRowQ, q1 - qb);
-            if (tid < nq) {
+            int cnt = 0;
+            if (lane < nq) {
                 // the elements around the node: id, local index of the node,
                 // vertex ids and their column positions
-                const int32_t e = a.ne_list[qb + tid];
-                const int32_t *En = a.E + 3 * (int64_t)e;
-                qe[tid] = e;
-                qs[tid] = a.sptr[e];
-                for (int b = 0; b < 3; ++b) {
-                    qn[tid][b] = En[b];
-                    qp[tid][b] = hpos(hk, hv, mask, En[b]);
+                const int32_t e = a.ne_list[qb + lane];
+                const int32_t v0 = a.E[3 * (int64_t)e], v1 = a.E[3 * (int64_t)e + 1], v2 = a.E[3 * (int64_t)e + 2];
+                const int64_t se0 = a.sptr[e], se1 = a.sptr[e + 1];
+                qe[lane] = e;
+                qs[lane] = se0;
+                qn[lane][0] = v0;
+                qn[lane][1] = v1;
+                qn[lane][2] = v2;
+                const int p0 = hpos(hk, hv, mask, v0), p1 = hpos(hk, hv, mask, v1), p2 = hpos(hk, hv, mask, v2);
+                qp[lane][0] = p0;
+                qp[lane][1] = p1;
+                qp[lane][2] = p2;
+                const int loc = v0 == (int32_t)i ? 0 : v1 == (int32_t)i ? 1 : 2;
+                qloc[lane] = loc;
+                cnt = (int)(se1 - se0);
+                if (cnt > 0) {
+                    // summed element-diagonal block of e's non-touching pairs, row loc
+                    const double *dv = a.dsum + (int64_t)e * 6 * NK;
+                    const int pb[3] = {p0, p1, p2};
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (pb[b] < 0) {
+                            bad = true;
+                            continue;
+                        }
+                        double ds[NK];
+#pragma unroll
+                        for (int k = 0; k < NK; ++k) ds[k] = dv[sym_index(loc, b, 3) * NK + k];
+                        add_sym_block<NC>(acc, pb[b], ds);
+                    }
                 }
-                const int loc = En[0] == (int32_t)i ? 0 : En[1] == (int32_t)i ? 1 : 2;
-                qloc[tid] = loc;
-                pre[tid + 1] = a.sptr[e + 1] - a.sptr[e];
-                // summed element-diagonal block of e's non-touching pairs, row loc
-                const double *dv = a.dsum + (int64_t)e * 6 * NK;
-                for (int b = 0; b < 3 && a.sptr[e + 1] > a.sptr[e]; ++b) {
-                    if (qp[tid][b] < 0) {
+            }
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            if (lane < nq) pre[lane + 1] = incl;
+            if (lane == 0) pre[0] = 0;
+            const int total = __shfl(incl, nq - 1);
+            __syncthreads();
+            for (int base = 0; base < total; base += 64 * kRowU) {
+                int32_t fe[kRowU], uu[kRowU], qq[kRowU], cl[kRowU], nf0[kRowU], nf1[kRowU], nf2[kRowU];
+                bool act[kRowU];
+                TR xv[kRowU][3][NK];
+#pragma unroll
+                for (int k = 0; k < kRowU; ++k) {
+                    const int flat = base + k * 64 + lane;
+                    act[k] = flat < total;
+                    fe[k] = 0;
+                    uu[k] = -1;
+                    cl[k] = 0;
+                    qq[k] = 0;
+                    if (act[k]) {
+                        // the element q with pre[q] <= flat < pre[q + 1]
+                        int lo = 0, hi = nq;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (pre[mid] <= flat) lo = mid;
+                            else hi = mid;
+                        }
+                        qq[k] = lo;
+                        const int64_t t = qs[lo] + (flat - pre[lo]);
+                        fe[k] = a.snbr[t];
+                        cl[k] = (a.sflag[t] >> 2) & 3;
+                        uu[k] = a.srec[t];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kRowU; ++k) {
+                    nf0[k] = nf1[k] = nf2[k] = -1;
+                    if (!act[k]) continue;
+                    if (uu[k] < 0 || uu[k] >= (cl[k] == 0 ? a.n_far : a.n_touch)) {
                         bad = true;
+                        act[k] = false;
                         continue;
                     }
-                    double ds[NK];
-                    for (int k = 0; k < NK; ++k) ds[k] = dv[sym_index(loc, b, 3) * NK + k];
-                    add_sym_block<NC>(acc, qp[tid][b], ds);
-                }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                pre[0] = 0;
-                for (int q = 0; q < nq; ++q) pre[q + 1] += pre[q];
-            }
-            __syncthreads();
-            const int64_t total = pre[nq];
-            for (int64_t flat = tid; flat < total; flat += kRowThreads) {
-                int q = 0;
-                while (pre[q + 1] <= flat) ++q;
-                const int32_t e = qe[q];
-                const int loc = qloc[q];
-                const int64_t t = qs[q] + (flat - pre[q]);
-                const int32_t f = a.snbr[t];
-                const int cls = (a.sflag[t] >> 2) & 3;
-                const int32_t u = a.srec[t];
-                if (u < 0 || u >= (cls == 0 ? a.n_far : a.n_touch)) {
-                    bad = true;
-                    continue;
-                }
-                const int32_t nf[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
-                if (cls == 0) {
-                    // cross block: row loc of X (e first), column loc (e second);
-                    // the self pair stores X + X^T, columns are e's own nodes
-                    const TR *r = (const TR *)a.far_rec + (int64_t)u * a.far_stride;
-                    for (int b = 0; b < 3; ++b) {
-                        const int xi = f >= e ? 3 * loc + b : 3 * b + loc;
-                        const int px = f == e ? qp[q][b] : hpos(hk, hv, mask, nf[b]);
-                        if (px < 0) {
-                            bad = true;
-                            continue;
+                    const int32_t f = fe[k];
+                    nf0[k] = a.E[3 * (int64_t)f];
+                    nf1[k] = a.E[3 * (int64_t)f + 1];
+                    nf2[k] = a.E[3 * (int64_t)f + 2];
+                    if (cl[k] == 0) {
+                        // row loc of X (e first) or column loc (e second); the
+                        // self pair stores X + X^T
+                        const int32_t e = qe[qq[k]];
+                        const int loc = qloc[qq[k]];
+                        const TR *r = (const TR *)a.far_rec + (int64_t)uu[k] * a.far_stride;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const int xi = f >= e ? 3 * loc + b : 3 * b + loc;
+#pragma unroll
+                            for (int kk = 0; kk < NK; ++kk) xv[k][b][kk] = r[xi * NK + kk];
                         }
-                        double xs[NK];
-                        for (int k = 0; k < NK; ++k) xs[k] = (double)r[xi * NK + k];
-                        add_sym_block<NC>(acc, px, xs);
                     }
-                } else {
-                    const int32_t ne[3] = {qn[q][0], qn[q][1], qn[q][2]};
-                    const bool first = e <= f;
-                    const int32_t *k1 = first ? ne : nf;
-                    const int32_t *k2 = first ? nf : ne;
-                    int32_t fr[5];
-                    const int nu = touch_frame(cls, k1, k2, fr);
-                    int rr = 0;
-                    for (int c = 0; c < nu; ++c)
-                        if (fr[c] == (int32_t)i) rr = c;
-                    const bool in1 = k1[0] == (int32_t)i || k1[1] == (int32_t)i || k1[2] == (int32_t)i;
-                    const bool in2 = k2[0] == (int32_t)i || k2[1] == (int32_t)i || k2[2] == (int32_t)i;
-                    const double factor = (cls == 3 || (in1 && in2)) ? 1.0 : 2.0;
-                    const double *L = a.touch_rec + (int64_t)u * a.touch_stride;
-                    const int D = nu * NC;
-                    for (int c = 0; c < nu; ++c) {
-                        const int pc = hpos(hk, hv, mask, fr[c]);
-                        if (pc < 0) {
-                            bad = true;
-                            continue;
+                }
+#pragma unroll
+                for (int k = 0; k < kRowU; ++k) {
+                    if (!act[k]) continue;
+                    const int q = qq[k];
+                    const int32_t e = qe[q], f = fe[k];
+                    if (cl[k] == 0) {
+                        const int32_t nb[3] = {nf0[k], nf1[k], nf2[k]};
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const int px = f == e ? qp[q][b] : hpos(hk, hv, mask, nb[b]);
+                            if (px < 0) {
+                                bad = true;
+                                continue;
+                            }
+                            double xs[NK];
+#pragma unroll
+                            for (int kk = 0; kk < NK; ++kk) xs[kk] = (double)xv[k][b][kk];
+                            add_sym_block<NC>(acc, px, xs);
                         }
-                        for (int cc = 0; cc < NC; ++cc)
-                            for (int dd = 0; dd < NC; ++dd)
-                                atomicAdd(&acc[pc * NN + cc * NC + dd],
-                                          factor * L[sym_index(rr * NC + cc, c * NC + dd, D)]);
+                    } else {
+                        const double *L = a.touch_rec + (int64_t)uu[k] * a.touch_stride;
+                        if (!add_touch<NC>(acc, hk, hv, mask, (int32_t)i, cl[k], e, f, qn[q][0], qn[q][1], qn[q][2],
+                                           nf0[k], nf1[k], nf2[k], L))
+                            bad = true;
                     }
                 }
             }
@@ -672,9 +798,9 @@ __global__ void __launch_bounds__(kRowThreads) k_rows(RowArgs a)
         }
         if (bad) atomicOr(a.err, kErrSlot);
         if (NC == 1) {
-            for (int t = tid; t < len; t += kRowThreads) a.val[s + t] = acc[t];
+            for (int t = lane; t < len; t += 64) a.val[s + t] = acc[t];
         } else {
-            for (int t = tid; t < len * 4; t += kRowThreads) {
+            for (int t = lane; t < len * 4; t += 64) {
                 const int pos = t >> 2, c = (t >> 1) & 1, d = t & 1;
                 a.val[4 * s + (int64_t)c * 2 * len + 2 * pos + d] = acc[t];
             }
@@ -800,8 +926,8 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
     }
     if (h->nnz_node > 0) {
         RowArgs r{};
-        r.M = h->M;
-        r.node_flags = h->node_flags;
+        r.nrows = h->n_dof;
+        r.rows = h->dof_list;
         r.nptr = h->nptr;
         r.ncol = h->ncol;
         r.ne_ptr = h->ne_ptr;
@@ -825,11 +951,11 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         r.val = val;
         r.err = h->err;
         const size_t lds = sizeof(double) * (size_t)h->max_row * nc * nc + sizeof(int32_t) * 2 * (size_t)hc;
-        const unsigned grid = (unsigned)std::min<int64_t>(h->M, 1 << 20);
-        timing_begin(kPhRows, s);
+        const unsigned grid = xcd_grid(h->n_dof);
+        timing_begin(kPhFar, s);
         {
             DiagArgs d{h->K, r.sptr, h->snbr, h->sflag, h->srec, h->far_rec, h->far_stride, h->nUF, h->dsum, h->err};
-            const unsigned dg = grid_for(h->K, 4);
+            const unsigned dg = xcd_grid((h->K + 3) / 4, INT32_MAX);
             if (nc == 1) {
                 if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float>), dim3(dg), dim3(256), 0, s, d);
                 else hipLaunchKernelGGL((k_elem_diag<1, double>), dim3(dg), dim3(256), 0, s, d);
@@ -838,12 +964,14 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
                 else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, d);
             }
         }
+        timing_end(kPhFar, s);
+        timing_begin(kPhRows, s);
         if (nc == 1) {
-            if (fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(kRowThreads), lds, s, r);
-            else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(kRowThreads), lds, s, r);
+            if (fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(64), lds, s, r);
+            else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(64), lds, s, r);
         } else {
-            if (fp32) hipLaunchKernelGGL((k_rows<2, float>), dim3(grid), dim3(kRowThreads), lds, s, r);
-            else hipLaunchKernelGGL((k_rows<2, double>), dim3(grid), dim3(kRowThreads), lds, s, r);
+            if (fp32) hipLaunchKernelGGL((k_rows<2, float>), dim3(grid), dim3(64), lds, s, r);
+            else hipLaunchKernelGGL((k_rows<2, double>), dim3(grid), dim3(64), lds, s, r);
         }
         timing_end(kPhRows, s);
     }

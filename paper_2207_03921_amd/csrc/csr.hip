@@ -16,7 +16,8 @@ constexpr int kEmpty = -1;
 struct CsrArgs {
     int64_t K1, M;
     const int32_t *E;
-    const uint32_t *node_flags;
+    const int32_t *rows;                   // dof nodes
+    const unsigned long long *nrows;       // [1] their number
     const int64_t *ne_ptr;
     const int32_t *ne_list;
     const int64_t *sptr;     // [K + 1]
@@ -54,11 +55,11 @@ __global__ void __launch_bounds__(64) k_csr(CsrArgs a)
     extern __shared__ int32_t tab[];   // [hcap] hash table, then [hcap] sort buffer
     int32_t *buf = tab + a.hcap;
     const int lane = threadIdx.x;
-    for (int64_t i = blockIdx.x; i < a.M; i += gridDim.x) {
-        if (a.node_flags[i] != 1u) {
-            if (!FILL && lane == 0) a.nlen[i] = 0;
-            continue;
-        }
+    const int64_t nrows = (int64_t)*a.nrows;
+    for (int64_t b = blockIdx.x; b < xcd_span(nrows); b += gridDim.x) {
+        const int64_t item = xcd_item(b, nrows);
+        if (item >= nrows) continue;
+        const int64_t i = a.rows[item];
         for (int t = lane; t < a.hcap; t += 64) tab[t] = kEmpty;
         __syncthreads();
         const int32_t mask = a.hcap - 1;
@@ -213,11 +214,11 @@ __global__ void __launch_bounds__(64) k_export(int64_t K, const int64_t *sptr, c
 
 int launch_csr(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
 {
-    CsrArgs a{h->K + 1, h->M, m->elements, h->node_flags, h->ne_ptr, h->ne_list,
+    CsrArgs a{h->K + 1, h->M, m->elements, h->dof_list, h->red + 8, h->ne_ptr, h->ne_list,
               h->loff + (int64_t)kLsS * (h->K + 1), h->snbr, h->hcap, h->nlen, h->red + 9, h->nptr, h->ncol,
               h->err};
     const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap;
-    const unsigned grid = (unsigned)std::min<int64_t>(h->M, 1 << 20);
+    const unsigned grid = xcd_grid(h->M);
     if (fill) hipLaunchKernelGGL(k_csr<true>, dim3(grid), dim3(64), lds, s, a);
     else hipLaunchKernelGGL(k_csr<false>, dim3(grid), dim3(64), lds, s, a);
     NLFEM_HIP(hipGetLastError());

@@ -141,12 +141,30 @@ __global__ void __launch_bounds__(256) k_incidence_fill(int64_t K, int64_t M, co
     }
 }
 
-__global__ void __launch_bounds__(256) k_count_dofs(int64_t M, const uint32_t *flags, unsigned long long *out)
+// Degree-of-freedom nodes: count (out) and list.  Each block appends its
+// 256 consecutive nodes as one contiguous run, so the list keeps mesh
+// locality within runs (the order of the runs is arbitrary).  Also clears
+// the CSR row lengths for the symbolic pass, which visits dof rows only.
+__global__ void __launch_bounds__(256) k_count_dofs(int64_t M, const uint32_t *flags, unsigned long long *out,
+                                                    int32_t *list, int64_t *nlen)
 {
+    __shared__ int wsum[4];
+    __shared__ unsigned long long base;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const bool d = i < M && flags[i] == 1u;
+    if (i < M) nlen[i] = 0;
     const unsigned long long b = __ballot(d);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+    if (lane == 0) wsum[w] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int n = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base = n ? atomicAdd(out, (unsigned long long)n) : 0ull;
+    }
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    if (d) list[base + before + __popcll(b & ((1ull << lane) - 1ull))] = (int32_t)i;
 }
 
 }  // namespace
@@ -154,7 +172,8 @@ __global__ void __launch_bounds__(256) k_count_dofs(int64_t M, const uint32_t *f
 int launch_count_dofs(nlfem_pairs *h, hipStream_t s)
 {
     NLFEM_HIP(hipMemsetAsync(h->red + 8, 0, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(k_count_dofs, dim3(grid_for(h->M, 256)), dim3(256), 0, s, h->M, h->node_flags, h->red + 8);
+    hipLaunchKernelGGL(k_count_dofs, dim3(grid_for(h->M, 256)), dim3(256), 0, s, h->M, h->node_flags, h->red + 8,
+                       h->dof_list, h->nlen);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

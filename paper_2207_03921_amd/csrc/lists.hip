@@ -39,7 +39,9 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
 {
     extern __shared__ unsigned long long key[];
     const int lane = threadIdx.x;
-    for (int64_t e = blockIdx.x; e < a.K; e += gridDim.x) {
+    for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
+        const int64_t e = xcd_item(b, a.K);
+        if (e >= a.K) continue;
         const int64_t s0 = a.sptr[e];
         const int n = (int)(a.sptr[e + 1] - s0);
         if (n == 0) continue;
@@ -77,7 +79,9 @@ __global__ void __launch_bounds__(64) k_worklists(ListArgs a)
 {
     const int lane = threadIdx.x;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    for (int64_t e = blockIdx.x; e < a.K; e += gridDim.x) {
+    for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
+        const int64_t e = xcd_item(b, a.K);
+        if (e >= a.K) continue;
         const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
         int64_t oF = a.loff[kLsUF * a.K1 + e];
         int64_t oI = a.loff[kLsUI * a.K1 + e];
@@ -127,7 +131,9 @@ __global__ void __launch_bounds__(64) k_worklists(ListArgs a)
 __global__ void __launch_bounds__(64) k_link(ListArgs a)
 {
     const int lane = threadIdx.x;
-    for (int64_t e = blockIdx.x; e < a.K; e += gridDim.x) {
+    for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
+        const int64_t e = xcd_item(b, a.K);
+        if (e >= a.K) continue;
         const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
         for (int64_t t = s0 + lane; t < s1; t += 64) {
             const int32_t f = a.snbr[t];
@@ -181,7 +187,7 @@ int launch_sort_lists(nlfem_pairs *h, hipStream_t s)
     if (h->nS == 0) return NLFEM_OK;
     ListArgs a = list_args(h);
     if (a.cap > 8192) return set_error(NLFEM_E_OVERFLOW, "neighbour list longer than 8192 entries");
-    const unsigned grid = (unsigned)std::min<int64_t>(h->K, 1 << 20);
+    const unsigned grid = xcd_grid(h->K);
     hipLaunchKernelGGL(k_sort_lists, dim3(grid), dim3(64), sizeof(unsigned long long) * a.cap, s, a);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
@@ -191,7 +197,7 @@ int launch_worklists(nlfem_pairs *h, const nlfem_mesh *, hipStream_t s)
 {
     if (h->nS == 0) return NLFEM_OK;
     ListArgs a = list_args(h);
-    const unsigned grid = (unsigned)std::min<int64_t>(h->K, 1 << 20);
+    const unsigned grid = xcd_grid(h->K);
     hipLaunchKernelGGL(k_worklists, dim3(grid), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_link, dim3(grid), dim3(64), 0, s, a);
     NLFEM_HIP(hipGetLastError());

@@ -115,6 +115,8 @@ struct nlfem_pairs {
     uint32_t *um_ef = nullptr, *um_fe = nullptr;
     // unordered touching pairs e <= f: [ident | edge | vertex]
     int32_t *te = nullptr, *tf = nullptr;     // [nUT]
+    // degree-of-freedom nodes in runs of consecutive ids (the rows of the matrix)
+    int32_t *dof_list = nullptr; // [M], first n_dof entries used
     // node-level CSR of degree-of-freedom rows
     int64_t *nlen = nullptr;     // [M + 1]
     int64_t *nptr = nullptr;     // [M + 1]
@@ -153,6 +155,25 @@ int hip_error(hipError_t e, const char *what);
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b % 8) and every XCD has its own L2.  Kernels whose neighbouring items
+// (node rows, elements) read the same records let block b take item
+// (b % 8) * per + b / 8, per = ceil(n / 8), so that each XCD walks one
+// contiguous range of items.  Grids are multiples of 8 (xcd_grid) and
+// grid-stride loops step by gridDim.x, which keeps b % 8.
+constexpr int kXcd = 8;
+inline unsigned xcd_grid(int64_t n, int64_t cap = 1 << 20)
+{
+    const int64_t g = kXcd * ((n + kXcd - 1) / kXcd);
+    return (unsigned)(g < cap ? g : cap);
+}
+__device__ inline int64_t xcd_span(int64_t n) { return kXcd * ((n + kXcd - 1) / kXcd); }
+__device__ inline int64_t xcd_item(int64_t b, int64_t n)
+{
+    const int64_t per = (n + kXcd - 1) / kXcd;
+    return (b % kXcd) * per + b / kXcd;
+}
+
 // scan.hip: out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total.
 int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap,
                    hipStream_t s);
@@ -163,7 +184,7 @@ double key_to_double(unsigned long long key);
 int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 int launch_incidence(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);   // needs ne_ptr scanned
 int launch_incidence_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
-int launch_count_dofs(nlfem_pairs *h, hipStream_t s);   // -> red[8]
+int launch_count_dofs(nlfem_pairs *h, hipStream_t s);   // -> red[8], dof_list, nlen = 0
 // grid + pairs (pairs.hip)
 int launch_cell_count(nlfem_pairs *h, hipStream_t s);
 int launch_cell_fill(nlfem_pairs *h, hipStream_t s);   // also sorts cells, max occupancy -> red[6]

@@ -150,7 +150,10 @@ template <bool FILL, bool POLY>
 __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int cell = blockIdx.x;
+    const int64_t ncell = (int64_t)a.gnx * a.gny;
+    const int64_t cell64 = xcd_item(blockIdx.x, ncell);   // grid.x is a multiple of 8
+    if (cell64 >= ncell) return;
+    const int cell = (int)cell64;
     const int64_t cs = a.cell_start[cell], ce = a.cell_start[cell + 1];
     const int64_t t0 = cs + (int64_t)blockIdx.y * kTE;
     if (t0 >= ce) return;
@@ -442,7 +445,7 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     if (slices <= 0) return NLFEM_OK;
     const size_t lds = sizeof(double2) * (size_t)kCH * (1 + a.P + (a.poly ? 3 : 0)) +
                        sizeof(int64_t) * kTE * kLsLast + sizeof(int32_t) * kCH * 5;
-    dim3 grid((unsigned)ncell, (unsigned)slices);
+    dim3 grid(xcd_grid(ncell, INT32_MAX), (unsigned)slices);
     if (a.poly) {
         if (fill) hipLaunchKernelGGL((k_pairs<true, true>), grid, dim3(kBlock), lds, s, a, h->poly);
         else hipLaunchKernelGGL((k_pairs<false, true>), grid, dim3(kBlock), lds, s, a, h->poly);
