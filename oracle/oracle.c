@@ -357,12 +357,25 @@ int64_t orc_pairs(const orc_mesh *m, const orc_cfg *cf, const uint8_t *elem_mask
     const int64_t K = m->n_elements;
     int64_t *cnt = (int64_t *)calloc((size_t)K + 1, sizeof(int64_t));
     if (!cnt) return -1;
+    /* with a mask, an unmasked k only meets the masked l (ascending) */
+    int64_t nmask = 0, *mlist = NULL;
+    if (elem_mask) {
+        mlist = (int64_t *)malloc(sizeof(int64_t) * ((size_t)K + 1));
+        if (!mlist) {
+            free(cnt);
+            return -1;
+        }
+        for (int64_t l = 0; l < K; ++l)
+            if (elem_mask[l]) mlist[nmask++] = l;
+    }
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < K; ++k) {
         int64_t c = 0;
-        for (int64_t l = 0; l < K; ++l) {
+        const int all = !elem_mask || elem_mask[k];
+        const int64_t nl = all ? K : nmask;
+        for (int64_t t = 0; t < nl; ++t) {
+            const int64_t l = all ? t : mlist[t];
             if (!label_ok(m, k, l)) continue;
-            if (elem_mask && !elem_mask[k] && !elem_mask[l]) continue;
             if (interact(m, cf, k, l) >= 0) c++;
         }
         cnt[k + 1] = c;
@@ -373,9 +386,11 @@ int64_t orc_pairs(const orc_mesh *m, const orc_cfg *cf, const uint8_t *elem_mask
 #pragma omp parallel for schedule(dynamic, 16)
         for (int64_t k = 0; k < K; ++k) {
             int64_t o = cnt[k];
-            for (int64_t l = 0; l < K; ++l) {
+            const int all = !elem_mask || elem_mask[k];
+            const int64_t nl = all ? K : nmask;
+            for (int64_t t = 0; t < nl; ++t) {
+                const int64_t l = all ? t : mlist[t];
                 if (!label_ok(m, k, l)) continue;
-                if (elem_mask && !elem_mask[k] && !elem_mask[l]) continue;
                 int c = interact(m, cf, k, l);
                 if (c >= 0) {
                     k_out[o] = (int32_t)k;
@@ -387,6 +402,7 @@ int64_t orc_pairs(const orc_mesh *m, const orc_cfg *cf, const uint8_t *elem_mask
         }
     }
     free(cnt);
+    free(mlist);
     return total;
 }
 

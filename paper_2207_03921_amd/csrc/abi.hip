@@ -13,12 +13,14 @@ namespace nlfem {
 namespace {
 thread_local std::string g_err = "no error";
 
-enum Buf {
+enum Buf : int {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
-    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_LAST
+    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_LAST
 };
+static_assert(B_LAST <= (int)(sizeof(nlfem_pairs::bufs) / sizeof(nlfem_pairs::bufs[0])), "too few buffer slots");
+
 
 int ensure(nlfem_pairs *h, int id, size_t bytes)
 {
@@ -282,6 +284,11 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->max_cell = (int32_t)red[6];
 
     // pair search: count, scan, fill ---------------------------------------
+    if (h->approach == NLFEM_A_APPROXCAPS_POLY) {
+        // h->poly lives as long as the handle, so the copy may run asynchronously
+        NLFEM_TRY(ensure_typed(h, B_POLYDIR, 2 * kMaxPoly, h->poly_dir));
+        NLFEM_HIP(hipMemcpyAsync(h->poly_dir, h->poly.dir, sizeof(double) * 2 * h->poly.N, hipMemcpyHostToDevice, s));
+    }
     NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
     NLFEM_TRY(ensure_typed(h, B_LOFF, kLsLast * K1, h->loff));
     NLFEM_HIP(hipMemsetAsync(h->lcnt, 0, sizeof(int64_t) * kLsLast * K1, s));
@@ -295,7 +302,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     for (int k = 0; k < kLsLast; ++k)
         NLFEM_HIP(hipMemcpyAsync(&tot[k], h->loff + k * K1 + K, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipMemcpyAsync(red + 7, h->red + 7, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipMemcpyAsync(red + 10, h->red + 10, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
+    h->max_clip = (int32_t)red[10];
     h->nS = tot[kLsS];
     h->nP = tot[kLsP];
     h->nUF = tot[kLsUF];
@@ -380,6 +389,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->far_rec = far_rec;
     NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
     NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
+
     NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
     if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");

@@ -146,6 +146,16 @@ struct FarArgs {
     int32_t stride;
     double c;
     int32_t same;
+    // polygon ball only
+    const double2 *xp;       // [K][P] outer points (FP64)
+    int32_t P;
+    const int32_t *E;
+    const double *V;
+    const double *dir;       // [N][2]
+    int32_t N;
+    double delta;
+    int32_t cap;             // clip buffer length per lane
+    int32_t *err;
 };
 
 // rule points of the two roles (A on e, B on f)
@@ -236,7 +246,143 @@ __device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double
     }
 }
 
-template <int KER, typename T, int PM>
+// ---- polygon ball: outer points whose polygon straddles the inner element
+//
+// Sutherland-Hodgman clip of the inner triangle by the regular N-gon around
+// the outer point, in the operation order of the pair search (no
+// contraction), so the polygon is the one whose status the search recorded;
+// then the fan from the first vertex of the clipped polygon with the inner
+// rule on every sub-triangle and the basis functions of the inner element at
+// the mapped points (Sec. 2.4.1, eq. discrete-inner).  The clip buffers are
+// per-lane arrays, [2 buffers][2 coordinates][cap]; passes that cut nothing
+// do not touch them, so only the 1-3 cutting passes of a typical straddling
+// point read and write them.
+
+__device__ inline double &cb(double *buf, int cap, int lane, int b, int c, int i)
+{
+    return buf[((b * 2 + c) * cap + i) + lane];
+}
+
+// returns the vertex count; the polygon is left in buffer *which
+__device__ int clip_polygon(double x, double y, const double vx[3], const double vy[3], const double *dir, int N,
+                            double delta, double *buf, int cap, int lane, int *which, bool *ovf)
+{
+#pragma clang fp contract(off)
+    for (int k = 0; k < 3; ++k) {
+        cb(buf, cap, lane, 0, 0, k) = vx[k];
+        cb(buf, cap, lane, 0, 1, k) = vy[k];
+    }
+    int cnt = 3, cur = 0;
+    for (int j = 0; j < N && cnt > 0; ++j) {
+        const int j1 = j + 1 == N ? 0 : j + 1;
+        const double qa0 = x + delta * dir[2 * j], qa1 = y + delta * dir[2 * j + 1];
+        const double qb0 = x + delta * dir[2 * j1], qb1 = y + delta * dir[2 * j1 + 1];
+        const double e0 = qb0 - qa0, e1 = qb1 - qa1;
+        // a pass that finds every vertex inside returns the list unchanged
+        bool cuts = false;
+        for (int i = 0; i < cnt; ++i)
+            cuts |= !(e0 * (cb(buf, cap, lane, cur, 1, i) - qa1) - e1 * (cb(buf, cap, lane, cur, 0, i) - qa0) >= 0.0);
+        if (!cuts) continue;
+        const int nxt = 1 - cur;
+        int m = 0;
+        for (int i = 0; i < cnt; ++i) {
+            const int i1 = i + 1 == cnt ? 0 : i + 1;
+            const double p0 = cb(buf, cap, lane, cur, 0, i), p1 = cb(buf, cap, lane, cur, 1, i);
+            const double q0 = cb(buf, cap, lane, cur, 0, i1), q1 = cb(buf, cap, lane, cur, 1, i1);
+            const double dp = e0 * (p1 - qa1) - e1 * (p0 - qa0);
+            const double dq = e0 * (q1 - qa1) - e1 * (q0 - qa0);
+            const bool pin = dp >= 0.0, qin = dq >= 0.0;
+            if (m + (pin ? 1 : 0) + (pin != qin ? 1 : 0) > cap) {
+                *ovf = true;
+                return 0;
+            }
+            if (pin) {
+                cb(buf, cap, lane, nxt, 0, m) = p0;
+                cb(buf, cap, lane, nxt, 1, m) = p1;
+                ++m;
+            }
+            if (pin != qin) {
+                const double t = dp / (dp - dq);
+                cb(buf, cap, lane, nxt, 0, m) = p0 + t * (q0 - p0);
+                cb(buf, cap, lane, nxt, 1, m) = p1 + t * (q1 - p1);
+                ++m;
+            }
+        }
+        cnt = m;
+        cur = nxt;
+    }
+    *which = cur;
+    return cnt;
+}
+
+// Samples of one straddling outer point xo (weight wo = w_p |J_outer|, basis
+// values po) against the inner element; the inner rule is role B of r when
+// inner_b, else role A.  outer_e: the outer element is e (rows of X).
+template <int KER, typename T>
+__device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, double xo_y, double wo, const double (&po)[3],
+                               int32_t inner, const double2 &v0i, const double4 &Ji, const RoleArgs &r,
+                               bool inner_b, bool outer_e, double *buf, int lane, T cc,
+                               T (&X)[3][3][Ker<KER>::NK], T (&De)[6][Ker<KER>::NK], T (&Df)[6][Ker<KER>::NK],
+                               bool *ovf)
+{
+    constexpr int NK = Ker<KER>::NK;
+    double vx[3], vy[3];
+    for (int k = 0; k < 3; ++k) {
+        const int32_t n = a.E[3 * (int64_t)inner + k];
+        vx[k] = a.V[2 * (int64_t)n];
+        vy[k] = a.V[2 * (int64_t)n + 1];
+    }
+    int cur = 0;
+    const int cnt = clip_polygon(xo_x, xo_y, vx, vy, a.dir, a.N, a.delta, buf, a.cap, lane, &cur, ovf);
+    if (cnt < 3) return;
+    const double deti = Ji.x * Ji.w - Ji.y * Ji.z;
+    const int Q = inner_b ? r.PB : r.PA;
+    const double s0x = cb(buf, a.cap, lane, cur, 0, 0), s0y = cb(buf, a.cap, lane, cur, 1, 0);
+    const T pe[3] = {(T)po[0], (T)po[1], (T)po[2]};
+    for (int s = 1; s + 1 < cnt; ++s) {
+        const double s1x = cb(buf, a.cap, lane, cur, 0, s), s1y = cb(buf, a.cap, lane, cur, 1, s);
+        const double s2x = cb(buf, a.cap, lane, cur, 0, s + 1), s2y = cb(buf, a.cap, lane, cur, 1, s + 1);
+        const double S00 = s1x - s0x, S01 = s2x - s0x, S10 = s1y - s0y, S11 = s2y - s0y;
+        const double adet = fabs(S00 * S11 - S01 * S10);
+        for (int q = 0; q < Q; ++q) {
+            const double x1 = inner_b ? r.xb[q][0] : r.xa[q][0];
+            const double x2 = inner_b ? r.xb[q][1] : r.xa[q][1];
+            const double wq = inner_b ? r.wb[q] : r.wa[q];
+            const double yx = s0x + (S00 * x1 + S01 * x2), yy = s0y + (S10 * x1 + S11 * x2);
+            const double dx = yx - v0i.x, dy = yy - v0i.y;
+            const double h1 = (Ji.w * dx - Ji.y * dy) / deti;
+            const double h2 = (-Ji.z * dx + Ji.x * dy) / deti;
+            const T pi[3] = {(T)(1.0 - h1 - h2), (T)h1, (T)h2};
+            T kv[NK];
+            kernel_eval<KER, T>((T)(xo_x - yx), (T)(xo_y - yy), cc, kv);
+            const T w = (T)(wo * wq * adet);
+            const T *pr = outer_e ? pe : pi;   // basis of e at its point
+            const T *pc = outer_e ? pi : pe;   // basis of f at its point
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const T hv = w * kv[k];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) X[i][j][k] -= hv * pr[i] * pc[j];
+                De[0][k] += hv * pr[0] * pr[0];
+                De[1][k] += hv * pr[0] * pr[1];
+                De[2][k] += hv * pr[0] * pr[2];
+                De[3][k] += hv * pr[1] * pr[1];
+                De[4][k] += hv * pr[1] * pr[2];
+                De[5][k] += hv * pr[2] * pr[2];
+                Df[0][k] += hv * pc[0] * pc[0];
+                Df[1][k] += hv * pc[0] * pc[1];
+                Df[2][k] += hv * pc[0] * pc[2];
+                Df[3][k] += hv * pc[1] * pc[1];
+                Df[4][k] += hv * pc[1] * pc[2];
+                Df[5][k] += hv * pc[2] * pc[2];
+            }
+        }
+    }
+}
+
+template <int KER, typename T, int PM, bool POLY>
 __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArgs r2)
 {
     constexpr int NK = Ker<KER>::NK;
@@ -265,6 +411,34 @@ __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArg
         far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, 0u, cc, X, De, Df);
         // (f, e): inner rule on e, outer rule on f
         if (!self) far_direction<KER, T, PM>(r2, dx, dy, Je, Jf, dete, detf, 0u, mt, cc, X, De, Df);
+    }
+    if (POLY) {
+        // status 2: the polygon around the point straddles the other element
+        double clipbuf[2 * 2 * (kMaxPoly + 4)];
+        const int lane = 0;
+        bool ovf = false;
+        for (int p = 0; p < r1.PA; ++p) {
+            if (((ms >> (2 * p)) & 3u) != kStraddle) continue;
+            const double2 xo = a.xp[(int64_t)e * a.P + p];
+            const double po[3] = {r1.pa[p][0], r1.pa[p][1], r1.pa[p][2]};
+            straddle_point<KER, T>(a, xo.x, xo.y, r1.wa[p] * dete, po, f, v0f, Jf, r1, true, true, clipbuf, lane,
+                                   cc, X, De, Df, &ovf);
+        }
+        // with one rule both directions use r1; otherwise the outer rule on f is role B of r2
+        for (int q = 0; !self && q < r1.PB; ++q) {
+            if (((mt >> (2 * q)) & 3u) != kStraddle) continue;
+            const double2 xo = a.xp[(int64_t)f * a.P + q];
+            if (a.same) {
+                const double po[3] = {r1.pb[q][0], r1.pb[q][1], r1.pb[q][2]};
+                straddle_point<KER, T>(a, xo.x, xo.y, r1.wb[q] * detf, po, e, v0e, Je, r1, false, false, clipbuf,
+                                       lane, cc, X, De, Df, &ovf);
+            } else {
+                const double po[3] = {r2.pb[q][0], r2.pb[q][1], r2.pb[q][2]};
+                straddle_point<KER, T>(a, xo.x, xo.y, r2.wb[q] * detf, po, e, v0e, Je, r2, false, false, clipbuf,
+                                       lane, cc, X, De, Df, &ovf);
+            }
+        }
+        if (ovf) atomicOr(a.err, kErrClip);
     }
     T *out = (T *)a.rec + idx * a.stride;
     if (self) {
@@ -831,20 +1005,27 @@ RoleArgs roles(const RuleArgs &r, bool a_outer, bool b_outer)
     return o;
 }
 
-template <int KER, typename T>
+template <int KER, typename T, bool POLY>
 void far_launch(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, hipStream_t s)
 {
-    const unsigned grid = grid_for(a.n, 256);
+    const int block = 256;
+    const unsigned grid = grid_for(a.n, block);
+    const size_t lds = 0;
     const bool seven = r1.PA == 7 && r1.PB == 7 && (a.same || (r2.PA == 7 && r2.PB == 7));
-    if (seven) hipLaunchKernelGGL((k_far_rec<KER, T, 7>), dim3(grid), dim3(256), 0, s, a, r1, r2);
-    else hipLaunchKernelGGL((k_far_rec<KER, T, 0>), dim3(grid), dim3(256), 0, s, a, r1, r2);
+    if (seven) hipLaunchKernelGGL((k_far_rec<KER, T, 7, POLY>), dim3(grid), dim3(block), lds, s, a, r1, r2);
+    else hipLaunchKernelGGL((k_far_rec<KER, T, 0, POLY>), dim3(grid), dim3(block), lds, s, a, r1, r2);
 }
 
 template <int KER>
-void far_dispatch(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, bool fp32, hipStream_t s)
+void far_dispatch(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, bool fp32, bool poly, hipStream_t s)
 {
-    if (fp32) far_launch<KER, float>(a, r1, r2, s);
-    else far_launch<KER, double>(a, r1, r2, s);
+    if (poly) {
+        if (fp32) far_launch<KER, float, true>(a, r1, r2, s);
+        else far_launch<KER, double, true>(a, r1, r2, s);
+    } else {
+        if (fp32) far_launch<KER, float, false>(a, r1, r2, s);
+        else far_launch<KER, double, false>(a, r1, r2, s);
+    }
 }
 
 template <int KER>
@@ -898,15 +1079,25 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         a.stride = h->far_stride;
         a.c = cfg->c;
         a.same = h->rules.same;
+        const bool poly = h->approach == NLFEM_A_APPROXCAPS_POLY;
+        a.xp = h->xp;
+        a.P = h->rules.P;
+        a.E = m->elements;
+        a.V = m->vertices;
+        a.dir = h->poly_dir;
+        a.N = h->poly.N;
+        a.delta = h->delta;
+        a.cap = kMaxPoly + 4;
+        a.err = h->err;
         // same rules: one pass, A and B both the outer rule.  Otherwise pass 1
         // (outer on e, inner on f) and pass 2 (inner on e, outer on f).
         const RoleArgs r1 = roles(h->rules, true, h->rules.same ? true : false);
         const RoleArgs r2 = roles(h->rules, false, true);
         timing_begin(kPhFar, s);
         switch (h->kernel) {
-        case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(a, r1, r2, fp32, s); break;
-        case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(a, r1, r2, fp32, s); break;
-        default: far_dispatch<NLFEM_K_PERIDYNAMIC>(a, r1, r2, fp32, s); break;
+        case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(a, r1, r2, fp32, poly, s); break;
+        case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(a, r1, r2, fp32, poly, s); break;
+        default: far_dispatch<NLFEM_K_PERIDYNAMIC>(a, r1, r2, fp32, poly, s); break;
         }
         timing_end(kPhFar, s);
     }

@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(256) k_geometry(GeoArgs a, RuleArgs r)
 
 __global__ void k_init_reduce(unsigned long long *red)
 {
-    if (threadIdx.x < 8) {
-        // min slots start at +inf key, max slots at the smallest key
+    if (threadIdx.x < 16) {
+        // min slots start at +inf key, max slots (and counters) at 0
         red[threadIdx.x] = threadIdx.x < 2 ? ~0ull : 0ull;
     }
 }

@@ -25,6 +25,7 @@ enum : int32_t {
     kErrRowCap = 4,      // CSR row exceeded the symbolic capacity
     kErrSlot = 8,        // scatter target not in the pattern (internal bug)
     kErrCell = 16,       // cell occupancy above the pair-search tile size
+    kErrClip = 32,       // polygon clip longer than the bound found by the pair search (internal bug)
 };
 
 // Quadrature tables passed by value (kernel arguments live in scalar registers).
@@ -76,6 +77,7 @@ struct nlfem_pairs {
     double gx0 = 0, gy0 = 0, gh = 0, far_reach = 0;
     int64_t max_S = 0;
     int32_t gnx = 0, gny = 0, gr = 2, max_cell = 0;   // gr: neighbour-cell radius
+    int32_t max_clip = 0;        // largest intermediate vertex count of a straddling polygon clip
     // ---- device memory (grow-only buffers, sized by cap_*) ----
     // element geometry (SoA)
     double2 *v0 = nullptr;       // [K]
@@ -126,13 +128,14 @@ struct nlfem_pairs {
     void *far_rec = nullptr;     // [nUF][far_stride] FP32 (mixed) or FP64
     double *touch_rec = nullptr; // [nUT][touch_stride]
     double *dsum = nullptr;      // [K][6 * NK] summed element-diagonal blocks of the far pairs
+    double *poly_dir = nullptr;  // [N][2] polygon directions (approach POLY)
     int32_t far_stride = 0, touch_stride = 0;
     // grow-only device buffers behind the typed pointers above
     struct DevBuf {
         void *p = nullptr;
         size_t cap = 0;
     };
-    DevBuf bufs[40];
+    DevBuf bufs[48];
     int64_t scan_cap = 0;
 };
 

@@ -48,6 +48,8 @@ struct PairArgs {
     double delta, delta2, reach2, rin2, out2;
     int64_t *lcnt;          // count pass: [kLsLast][K1]
     unsigned long long *maxS;   // count pass: max |S(e)|
+    unsigned long long *maxClip;   // bound on the vertex count of any straddling clip
+    const double *dir;             // [N][2] polygon directions (device copy)
     const int64_t *loff;    // fill pass:  [kLsLast][K1]
     int32_t *snbr;
     uint8_t *sflag;
@@ -78,8 +80,13 @@ __device__ double point_triangle_dist2(double px, double py, const double2 v[3])
     return d;
 }
 
-// Exact replica of the clip of the plain definition; returns the status.
-__device__ __noinline__ uint32_t clip_status(double x, double y, const double2 v[3], const PolyArgs &pg,
+// The Sutherland-Hodgman clip of the plain definition (vertex j of the
+// polygon at (x, y) + delta * dir_j, a point inside edge j iff
+// cross(q_{j+1} - q_j, v - q_j) >= 0, crossing a + t (b - a) with
+// t = d_a / (d_a - d_b)), same operation order; returns the status.  A pass
+// in which every current vertex is inside outputs the list unchanged, so it
+// is skipped without touching the buffers.
+__device__ __noinline__ uint32_t clip_status(double x, double y, const double2 v[3], const double *dir, int N,
                                              double delta)
 {
     double bx[2][kMaxPoly + 4], by[2][kMaxPoly + 4];
@@ -88,17 +95,20 @@ __device__ __noinline__ uint32_t clip_status(double x, double y, const double2 v
         by[0][a] = v[a].y;
     }
     int cnt = 3, cur = 0;
-    const int N = pg.N;
     for (int j = 0; j < N && cnt > 0; ++j) {
-        int j1 = (j + 1) % N;
-        double qa0 = x + delta * pg.dir[j][0];
-        double qa1 = y + delta * pg.dir[j][1];
-        double qb0 = x + delta * pg.dir[j1][0];
-        double qb1 = y + delta * pg.dir[j1][1];
+        int j1 = j + 1 == N ? 0 : j + 1;
+        double qa0 = x + delta * dir[2 * j];
+        double qa1 = y + delta * dir[2 * j + 1];
+        double qb0 = x + delta * dir[2 * j1];
+        double qb1 = y + delta * dir[2 * j1 + 1];
         double e0 = qb0 - qa0, e1 = qb1 - qa1;
+        bool cuts = false;
+        for (int i = 0; i < cnt; ++i)
+            cuts |= !(e0 * (by[cur][i] - qa1) - e1 * (bx[cur][i] - qa0) >= 0.0);
+        if (!cuts) continue;
         int nxt = 1 - cur, m = 0;
         for (int i = 0; i < cnt; ++i) {
-            int i1 = (i + 1) % cnt;
+            int i1 = i + 1 == cnt ? 0 : i + 1;
             double p0 = bx[cur][i], p1 = by[cur][i];
             double q0 = bx[cur][i1], q1 = by[cur][i1];
             double dp = e0 * (p1 - qa1) - e1 * (p0 - qa0);
@@ -133,15 +143,68 @@ __device__ __noinline__ uint32_t clip_status(double x, double y, const double2 v
     return kStraddle;
 }
 
+// sine of the triangle's angle at vertex a
+__device__ inline double corner_sine(const double2 v[3], int a)
+{
+    const double2 p = v[a], q = v[a == 2 ? 0 : a + 1], r = v[a == 0 ? 2 : a - 1];
+    const double ux = q.x - p.x, uy = q.y - p.y, wx = r.x - p.x, wy = r.y - p.y;
+    return fabs(ux * wy - uy * wx) / (sqrt(ux * ux + uy * uy) * sqrt(wx * wx + wy * wy));
+}
+
+// Status of the outer point (x, y) for the triangle v under the polygon ball:
+// the decisions of clip_status, taken from the edge tests of the original
+// vertices (the clip's own arithmetic) wherever they fix the result:
+//  - the clip returns the triangle unchanged iff every vertex passes every
+//    edge test: whole;
+//  - if all three vertices fail one edge test by a margin, every point the
+//    clip can produce fails it (crossing points are convex combinations up
+//    to rounding far below the margin): out;
+//  - if one vertex passes every test by a margin and the triangle is no
+//    sliver there, the clipped polygon keeps a corner of the triangle whose
+//    area is orders of magnitude above the rounding of the area sum:
+//    straddle.
+// Otherwise the clip runs.  For straddling points *maxcnt is raised to
+// 3 + 2 * (edges at which some vertex is not inside by the margin), a bound
+// on every intermediate vertex count of the clip.
 __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], const PolyArgs &pg,
-                                       const PairArgs &a)
+                                       const PairArgs &a, int *maxcnt)
 {
     double d0 = (v[0].x - x) * (v[0].x - x) + (v[0].y - y) * (v[0].y - y);
     double d1 = (v[1].x - x) * (v[1].x - x) + (v[1].y - y) * (v[1].y - y);
     double d2 = (v[2].x - x) * (v[2].x - x) + (v[2].y - y) * (v[2].y - y);
     if (d0 < a.rin2 && d1 < a.rin2 && d2 < a.rin2) return kWhole;
     if (point_triangle_dist2(x, y, v) > a.out2) return kOut;
-    return clip_status(x, y, v, pg, a.delta);
+    const double C = fmax(fabs(x), fabs(y)) + a.delta;
+    const double m_out = 1e-9 * C, m_in = 1e-5 * C;   // margins as distances
+    const int N = pg.N;
+    bool all_in = true, sep = false, deep0 = true, deep1 = true, deep2 = true;
+    int near = 0;
+    for (int j = 0; j < N; ++j) {
+        const int j1 = j + 1 == N ? 0 : j + 1;
+        const double qa0 = x + a.delta * a.dir[2 * j];
+        const double qa1 = y + a.delta * a.dir[2 * j + 1];
+        const double qb0 = x + a.delta * a.dir[2 * j1];
+        const double qb1 = y + a.delta * a.dir[2 * j1 + 1];
+        const double e0 = qb0 - qa0, e1 = qb1 - qa1;
+        const double p0 = e0 * (v[0].y - qa1) - e1 * (v[0].x - qa0);
+        const double p1 = e0 * (v[1].y - qa1) - e1 * (v[1].x - qa0);
+        const double p2 = e0 * (v[2].y - qa1) - e1 * (v[2].x - qa0);
+        const double el = sqrt(e0 * e0 + e1 * e1);
+        const double tin = m_in * el, tout = m_out * el;
+        all_in &= p0 >= 0.0 && p1 >= 0.0 && p2 >= 0.0;
+        sep |= p0 < -tout && p1 < -tout && p2 < -tout;
+        deep0 &= p0 > tin;
+        deep1 &= p1 > tin;
+        deep2 &= p2 > tin;
+        near += (p0 < tout || p1 < tout || p2 < tout) ? 1 : 0;
+    }
+    if (all_in) return kWhole;
+    if (sep) return kOut;
+    const bool deep = (deep0 && corner_sine(v, 0) > 1e-3) || (deep1 && corner_sine(v, 1) > 1e-3) ||
+                      (deep2 && corner_sine(v, 2) > 1e-3);
+    const uint32_t st = deep ? kStraddle : clip_status(x, y, v, a.dir, N, a.delta);
+    if (st == kStraddle) *maxcnt = max(*maxcnt, 3 + 2 * near);
+    return st;
 }
 
 // ---- the tile kernel --------------------------------------------------------
@@ -194,6 +257,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     const int64_t total = nb_pre[nb_n];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
+    int clipmax = 0;
 
     for (int64_t c0 = 0; c0 < total; c0 += kCH) {
         const int nch = (int)min((int64_t)kCH, total - c0);
@@ -267,11 +331,11 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                                 double2 vf[3] = {c_v[j], c_v[kCH + j], c_v[2 * kCH + j]};
                                 for (int p = 0; p < a.P; ++p) {
                                     const double2 x = a.xp[(int64_t)e * a.P + p];
-                                    mef |= poly_status(x.x, x.y, vf, pg, a) << (2 * p);
+                                    mef |= poly_status(x.x, x.y, vf, pg, a, &clipmax) << (2 * p);
                                 }
                                 for (int q = 0; q < a.P; ++q) {
                                     const double2 x = c_xp[q * kCH + j];
-                                    mfe |= poly_status(x.x, x.y, ve, pg, a) << (2 * q);
+                                    mfe |= poly_status(x.x, x.y, ve, pg, a, &clipmax) << (2 * q);
                                 }
                             }
                         }
@@ -313,6 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
             if (kind == kLsS) atomicMax(a.maxS, (unsigned long long)e_off[t]);
         }
     }
+    if (POLY && clipmax > 0) atomicMax(a.maxClip, (unsigned long long)clipmax);
 }
 
 // ---- grid build ---------------------------------------------------------------
@@ -437,6 +502,8 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     a.out2 = out * out;
     a.lcnt = h->lcnt;
     a.maxS = h->red + 7;
+    a.maxClip = h->red + 10;
+    a.dir = h->poly_dir;
     a.loff = h->loff;
     a.snbr = h->snbr_tmp;
     a.sflag = h->sflag_tmp;

@@ -10,7 +10,7 @@ import pytest
 
 from inputs import square_mesh, gauss7, paper7, collapsed
 from inputs.meshes import Mesh
-from inputs.workloads import small_constant, inv_dist_jittered, peridynamic, c_frac
+from inputs.workloads import small_constant, inv_dist_jittered, peridynamic, constant_polygon, c_frac
 from _gpu import gpu_run, to_sparse, rel_frob, f_affine_of
 
 pytestmark = pytest.mark.gpu
@@ -50,6 +50,14 @@ def _cases():
                                    rule=gauss7(), inner=paper7()),
         "invdist_neumann": _w("inv_dist", square_mesh(12, delta=0.2, jitter=0.2, seed=8, neumann=True), 0.2),
         "const_duffy": _w("constant", square_mesh(12, delta=0.15, jitter=0.2, seed=9), 0.15, singular_n=4),
+        # inscribed 32-gon: straddling points are clipped and fan-triangulated
+        "const_poly_h16": _w("constant", square_mesh(16, delta=0.1), 0.1, approach="poly"),
+        "const_poly_small_delta": _w("constant", square_mesh(8, delta=0.1, jitter=0.1, seed=12), 0.1,
+                                     approach="poly"),
+        "invdist_poly": _w("inv_dist", square_mesh(12, delta=0.15, jitter=0.2, seed=11), 0.15, approach="poly"),
+        "peri_poly": _w("peridynamic", square_mesh(10, delta=0.25, jitter=0.1, seed=13), 0.25, approach="poly"),
+        "const_poly_outer_ne_inner": _w("constant", square_mesh(10, delta=0.15, jitter=0.15, seed=14), 0.15,
+                                        rule=gauss7(), inner=paper7(), approach="poly"),
     }
 
 
@@ -201,19 +209,28 @@ def _sample_rows(P, n_rows=48, seed=0):
     return np.unique(np.concatenate([pick, dof[:2], dof[-2:]]))
 
 
-@pytest.mark.parametrize("name", ["invdist_h64", "peri_h128"])
+@pytest.mark.parametrize("name", ["invdist_h64", "peri_h128", "poly32_h256"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_parity_full_size_sampled(oracle_lib, name, precision):
-    w = inv_dist_jittered() if name == "invdist_h64" else peridynamic()
+    w = {"invdist_h64": inv_dist_jittered, "peri_h128": peridynamic, "poly32_h256": constant_polygon}[name]()
     mesh = w["mesh"]
     print(f"full {name} {precision} K={mesh.n_elements}", flush=True)
     P = oracle_lib.Problem(mesh, w)
     g = gpu_run(mesh, w, precision=precision)
+    rows = _sample_rows(P, n_rows=16 if name == "poly32_h256" else 48)
     if precision == "fp64":
-        k, l, c = P.pairs()
         gk, gl, gc = g["pairs"]
+        if name == "poly32_h256":
+            # all pairs that meet the sampled rows' elements
+            rowsel = np.zeros(mesh.n_vertices, bool)
+            rowsel[rows] = True
+            emask = rowsel[mesh.elements].any(axis=1)
+            k, l, c = P.pairs(elem_mask=emask)
+            keep = emask[gk] | emask[gl]
+            gk, gl, gc = gk[keep], gl[keep], gc[keep]
+        else:
+            k, l, c = P.pairs()
         assert np.array_equal(gk, k) and np.array_equal(gl, l) and np.array_equal(gc, c)
-    rows = _sample_rows(P)
     rp, col, val = P.assemble_rows(rows)
     n = P.n
     G = to_sparse(g["row_ptr"], g["col"], g["val"], n * mesh.n_vertices)

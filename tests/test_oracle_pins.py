@@ -417,3 +417,19 @@ def test_rhs_closed_forms(oracle_lib):
     f1 = -mesh.vertices[:, 1]
     assert np.abs(b[0::2] - Mo @ f0).max() < 1e-15
     assert np.abs(b[1::2] - Mo @ f1).max() < 1e-15
+
+
+def test_masked_pair_search_is_a_filter(oracle_lib):
+    """The row-restricted search (used for sampled rows of large meshes)
+    lists exactly the pairs of the full search that meet a masked element."""
+    from inputs.workloads import inv_dist_jittered
+    w = inv_dist_jittered(n=16, delta=0.15, precision="fp64")
+    mesh = w["mesh"]
+    P = oracle_lib.Problem(mesh, w)
+    k, l, c = P.pairs()
+    rng = np.random.default_rng(3)
+    mask = np.zeros(mesh.n_elements, bool)
+    mask[rng.choice(mesh.n_elements, 25, replace=False)] = True
+    mk, ml, mc = P.pairs(elem_mask=mask)
+    keep = mask[k] | mask[l]
+    assert np.array_equal(mk, k[keep]) and np.array_equal(ml, l[keep]) and np.array_equal(mc, c[keep])
