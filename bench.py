@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-WORKLOADS = ("invdist_h64", "const_h16", "peri_h128", "poly32_h256")
+WORKLOADS = ("invdist_h64", "const_h16", "peri_h128", "poly32_h256", "batched64")
 
 
 def _workload(name, precision):
@@ -128,6 +128,79 @@ def measured_traffic(workload, precision):
         return None
 
 
+def bench_batched(args):
+    """64 independent problems (h from 1/32 to 1/160, delta/h in 2..5, half
+    constant, half 1/|z| with the regularising transforms).  The pair
+    structures are built once (their build time is reported); a step is the
+    assembly of all 64 problems: the batched form replays one HIP graph of
+    persistent launches, the baseline assembles the problems one after the
+    other in plain FP64."""
+    import torch
+    import paper_2207_03921_amd as nl
+    from inputs import workloads as W
+    torch.cuda.set_device(0)
+    ws = W.batched(64, precision=args.precision)
+    dms = [nl.DeviceMesh.from_numpy(w["mesh"]) for w in ws]
+    cfgs = [_config(w, args.precision) for w in ws]
+    cfg64 = [_config(w, "fp64") for w in ws]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs = [nl.nlfem_build_pairs(d, c) for d, c in zip(dms, cfgs)]
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    infos = [nl.nlfem_pairs_info(p) for p in pairs]
+    n_pairs = sum(i["n_pairs"] for i in infos)
+    vals = [torch.empty(max(i["nnz"], 1), dtype=torch.float64, device="cuda") for i in infos]
+    cache = os.path.join(ROOT, "paper_2207_03921_amd", "tune_cache.txt")
+    batch = nl.nlfem_batch_create(dms, cfgs, pairs, vals, tune_cache=cache, tune=1)
+    batch64 = nl.nlfem_batch_create(dms, cfg64, pairs, vals, tune_cache=cache, tune=1)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    t_graph = timed(lambda: nl.nlfem_batch_launch_graph(batch), args.steps, args.warmup)
+    t_graph64 = timed(lambda: nl.nlfem_batch_launch_graph(batch64), args.steps, args.warmup)
+
+    def sequential():
+        for d, c, p, v in zip(dms, cfg64, pairs, vals):
+            nl.nlfem_assemble(d, c, p, val=v)
+
+    t_seq = timed(sequential, max(3, args.steps // 2), 1)
+    out = {
+        "metric": "element-pair interactions assembled/sec",
+        "value": n_pairs / t_graph,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_graph * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched64 (64 problems, h 1/32..1/160, delta/h 2..5, constant and 1/|z|)",
+                   "triangles": int(sum(w["mesh"].n_elements for w in ws)), "ordered_pairs": n_pairs,
+                   "touching_pairs": int(sum(i["n_vertex"] + i["n_edge"] + i["n_ident"] for i in infos)),
+                   "nnz": int(sum(i["nnz"] for i in infos)), "precision": args.precision,
+                   "launch_groups": nl.nlfem_batch_info(batch)["groups"]},
+        "roofline": None,
+        "build_ms_all_problems": t_build * 1e3,
+        "batched_fp64_graph": {"ms_per_step": t_graph64 * 1e3, "value": n_pairs / t_graph64},
+        "sequential_fp64_plain": {"ms_per_step": t_seq * 1e3, "value": n_pairs / t_seq},
+        "speedup_vs_sequential_fp64": t_seq / t_graph,
+        "tuned_shape": nl.nlfem_batch_info(batch)["shape"],
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +216,9 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
               "described in DESIGN.md and not run.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched64":
+        bench_batched(args)
+        return
 
     import torch
     import paper_2207_03921_amd as nl

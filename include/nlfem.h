@@ -222,6 +222,59 @@ int nlfem_timing_read(double *ms, int64_t *launches, int reset);
 /* Releases a handle and its device memory (synchronises the device). */
 void nlfem_pairs_free(nlfem_pairs *pairs);
 
+/* ------------------------------------------------------------------------
+ * Batched assembly: many independent problems (meshes of uneven size, other
+ * kernels, horizons and rules) in a few persistent launches over a global
+ * work queue, one per phase and kernel specialisation, optionally replayed
+ * from a HIP graph.  Results are bit-identical to nlfem_assemble of each
+ * problem.  The paper assembles one problem at a time (Sec. 2.5, Alg. 1);
+ * batching is a property of this implementation.
+ * --------------------------------------------------------------------- */
+typedef struct nlfem_batch nlfem_batch;   /* opaque, library-owned */
+#define NLFEM_MAX_BATCH 4096
+
+/* Fixes a batch of n problems: meshes[n], cfgs[n] (each as accepted by
+   nlfem_assemble for pairs[i]), pairs[n] (distinct built handles) and
+   vals[n] (device output arrays, nnz of pairs[i] entries, owned by the
+   caller).  All of them must stay valid and unchanged while the batch is
+   used; the handles' workspaces are used by the batch.
+   tune: 0 = default launch shapes; 1 = shapes from `tune_cache` (a text
+   file, one line per device and batch structure) or, when absent, chosen by
+   timing candidate shapes on this stream and appended to the file
+   (tune_cache may be NULL: nothing is read or written); 2 = always timed.
+   Tuning runs the assembly, so vals hold a valid result afterwards.
+   Allocates device tables; synchronises.
+   Errors: E_INVALID, E_MISMATCH, E_NOMEM, E_HIP, E_NODEVICE. */
+int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs,
+                       nlfem_pairs *const *pairs, double *const *vals, const char *tune_cache,
+                       int32_t tune, nlfem_batch **batch, void *stream);
+
+/* Assembles all problems of the batch into their vals on `stream`.
+   Allocates nothing, never synchronises, records no memset (safe to
+   capture into a HIP graph).  Two runs of one batch must not overlap.
+   Errors: E_INVALID, E_HIP. */
+int nlfem_batch_assemble(nlfem_batch *batch, void *stream);
+
+/* Same work from a HIP graph: the first call captures the launches of
+   nlfem_batch_assemble on an internal stream and instantiates the graph
+   (host allocation); every call launches it on `stream`.
+   Errors: E_INVALID, E_HIP. */
+int nlfem_batch_launch_graph(nlfem_batch *batch, void *stream);
+
+/* Number of launch groups and the launch shape of the four phases
+   (non-touching, touching, element diagonals, rows) as
+   shape[8] = {chunk, workgroups per CU} x 4.  Errors: E_INVALID. */
+int nlfem_batch_info(const nlfem_batch *batch, int32_t *groups, int32_t *shape);
+
+/* Releases a batch (synchronises the device).  NULL is ignored. */
+void nlfem_batch_free(nlfem_batch *batch);
+
+/* One-shot form: create (tune = 1 if tune_cache is given, else 0), assemble,
+   synchronise, free.  Errors: those of nlfem_batch_create and _assemble. */
+int nlfem_assemble_batched(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs,
+                           nlfem_pairs *const *pairs, double *const *vals, const char *tune_cache,
+                           void *stream);
+
 #ifdef __cplusplus
 }
 #endif

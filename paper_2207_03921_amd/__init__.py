@@ -88,6 +88,18 @@ def lib():
         L.nlfem_timing_enable.restype = i32
         L.nlfem_timing_read.argtypes = [vp, vp, C.c_int]
         L.nlfem_timing_read.restype = i32
+        L.nlfem_batch_create.argtypes = [C.c_int32, vp, vp, vp, vp, C.c_char_p, C.c_int32, C.POINTER(vp), vp]
+        L.nlfem_batch_create.restype = i32
+        L.nlfem_batch_assemble.argtypes = [vp, vp]
+        L.nlfem_batch_assemble.restype = i32
+        L.nlfem_batch_launch_graph.argtypes = [vp, vp]
+        L.nlfem_batch_launch_graph.restype = i32
+        L.nlfem_batch_info.argtypes = [vp, vp, vp]
+        L.nlfem_batch_info.restype = i32
+        L.nlfem_batch_free.argtypes = [vp]
+        L.nlfem_batch_free.restype = None
+        L.nlfem_assemble_batched.argtypes = [C.c_int32, vp, vp, vp, vp, C.c_char_p, vp]
+        L.nlfem_assemble_batched.restype = i32
         _lib = L
     return _lib
 
@@ -304,3 +316,73 @@ def assemble(mesh: DeviceMesh, cfg: Config, f_affine=None, stream=None):
         f_affine = [(0.0, 0.0, 0.0)] * cfg.ncomp
     b = nlfem_rhs(mesh, cfg, f_affine=f_affine, stream=stream)
     return A, b
+
+
+# ---------------------------------------------------------------- batches
+
+class Batch:
+    """Owner of an nlfem_batch; keeps the inputs it refers to alive."""
+
+    def __init__(self, ptr, keep):
+        self.ptr = ptr
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and self.ptr.value and _lib is not None:
+            _lib.nlfem_batch_free(self.ptr)
+            self.ptr = C.c_void_p(None)
+
+
+def _batch_arrays(meshes, cfgs, pairs, vals):
+    import torch
+    n = len(meshes)
+    if not (len(cfgs) == len(pairs) == len(vals) == n):
+        raise ValueError("meshes, cfgs, pairs and vals must have the same length")
+    cm = (_Mesh * n)(*[m.c_struct() for m in meshes])
+    structs, tables = [], []
+    for c in cfgs:   # a config may appear several times: keep every table set alive
+        structs.append(c.c_struct())
+        tables.append(list(c._keep))
+    cc = (_Config * n)(*structs)
+    ph = (C.c_void_p * n)(*[p.ptr.value for p in pairs])
+    vp = (C.c_void_p * n)(*[_dev_ptr(v, torch.float64, "val") for v in vals])
+    cc._tables = tables
+    return n, cm, cc, ph, vp
+
+
+def nlfem_batch_create(meshes, cfgs, pairs, vals, tune_cache=None, tune=0, stream=None) -> Batch:
+    n, cm, cc, ph, vp = _batch_arrays(meshes, cfgs, pairs, vals)
+    h = C.c_void_p(None)
+    path = None if tune_cache is None else os.fsencode(tune_cache)
+    _check(lib().nlfem_batch_create(n, cm, cc, ph, vp, path, int(tune), C.byref(h), _stream(stream)))
+    return Batch(h, (list(meshes), list(cfgs), list(pairs), list(vals), cm, cc, ph, vp))
+
+
+def nlfem_batch_assemble(batch: Batch, stream=None):
+    _check(lib().nlfem_batch_assemble(batch.ptr, _stream(stream)))
+
+
+def nlfem_batch_launch_graph(batch: Batch, stream=None):
+    _check(lib().nlfem_batch_launch_graph(batch.ptr, _stream(stream)))
+
+
+def nlfem_batch_info(batch: Batch) -> dict:
+    g = C.c_int32(0)
+    sh = (C.c_int32 * 8)()
+    _check(lib().nlfem_batch_info(batch.ptr, C.byref(g), sh))
+    names = ("far", "touch", "diag", "rows")
+    return {"groups": int(g.value),
+            "shape": {nm: {"chunk": int(sh[2 * i]), "per_cu": int(sh[2 * i + 1])} for i, nm in enumerate(names)}}
+
+
+def nlfem_batch_free(batch: Batch):
+    if batch.ptr.value:
+        lib().nlfem_batch_free(batch.ptr)
+        batch.ptr = C.c_void_p(None)
+
+
+def nlfem_assemble_batched(meshes, cfgs, pairs, vals, tune_cache=None, stream=None):
+    n, cm, cc, ph, vp = _batch_arrays(meshes, cfgs, pairs, vals)
+    path = None if tune_cache is None else os.fsencode(tune_cache)
+    _check(lib().nlfem_assemble_batched(n, cm, cc, ph, vp, path, _stream(stream)))
+    return vals

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <string>
 
+#include "batch.h"
 #include "nlfem_internal.h"
 
 namespace nlfem {
@@ -53,11 +54,6 @@ int ensure_typed(nlfem_pairs *h, int id, int64_t n, T *&ptr)
     return NLFEM_OK;
 }
 
-#define NLFEM_TRY(x)                 \
-    do {                             \
-        int _rc = (x);               \
-        if (_rc != NLFEM_OK) return _rc; \
-    } while (0)
 
 // Gauss-Legendre nodes and weights on [0, 1]: Newton's method on P_n, with P_n
 // from the three-term recurrence (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}.
@@ -625,6 +621,72 @@ void nlfem_pairs_free(nlfem_pairs *h)
     for (auto &b : h->bufs)
         if (b.p) (void)hipFree(b.p);
     delete h;
+}
+
+int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, nlfem_pairs *const *pairs,
+                       double *const *vals, const char *tune_cache, int32_t tune, nlfem_batch **batch,
+                       void *stream)
+{
+    if (!batch) return set_error(NLFEM_E_INVALID, "batch is NULL");
+    *batch = nullptr;
+    if (n < 1 || n > NLFEM_MAX_BATCH) return set_error(NLFEM_E_INVALID, "batch size outside [1, NLFEM_MAX_BATCH]");
+    if (!meshes || !cfgs || !pairs || !vals) return set_error(NLFEM_E_INVALID, "NULL array argument");
+    if (tune < 0 || tune > 2) return set_error(NLFEM_E_INVALID, "tune must be 0, 1 or 2");
+    NLFEM_TRY(check_device());
+    int dev = -1;
+    NLFEM_HIP(hipGetDevice(&dev));
+    std::vector<items::AssemblePlan> plans;
+    plans.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        const nlfem_pairs *h = pairs[i];
+        if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle " + std::to_string(i) + " is NULL or not built");
+        NLFEM_TRY(check_mesh(&meshes[i]));
+        NLFEM_TRY(check_cfg(&cfgs[i]));
+        if (h->nnz_node > 0 && !vals[i]) return set_error(NLFEM_E_INVALID, "val " + std::to_string(i) + " is NULL");
+        if (!same_build(h, &meshes[i], &cfgs[i]))
+            return set_error(NLFEM_E_MISMATCH, "problem " + std::to_string(i) +
+                                                   ": mesh or configuration differs from the one its pairs were built for");
+        if (dev != h->device) return set_error(NLFEM_E_MISMATCH, "current device differs from a build device");
+        for (int j = 0; j < i; ++j)
+            if (pairs[j] == h) return set_error(NLFEM_E_INVALID, "a pairs handle appears twice (shared workspace)");
+        GaussArgs g{};
+        g.n = cfgs[i].singular_n;
+        if (g.n > 0) gauss_legendre01(g.n, g.x, g.w);
+        plans.push_back(items::make_plan(h, &meshes[i], &cfgs[i], g, vals[i]));
+    }
+    return batch_create(plans, tune_cache, tune, batch, (hipStream_t)stream);
+}
+
+int nlfem_batch_assemble(nlfem_batch *batch, void *stream)
+{
+    if (!batch) return set_error(NLFEM_E_INVALID, "batch is NULL");
+    return batch_run(batch, (hipStream_t)stream);
+}
+
+int nlfem_batch_launch_graph(nlfem_batch *batch, void *stream)
+{
+    if (!batch) return set_error(NLFEM_E_INVALID, "batch is NULL");
+    return batch_graph_launch(batch, (hipStream_t)stream);
+}
+
+int nlfem_batch_info(const nlfem_batch *batch, int32_t *groups, int32_t *shape)
+{
+    if (!batch || !groups || !shape) return set_error(NLFEM_E_INVALID, "NULL argument");
+    return batch_info(batch, groups, shape);
+}
+
+void nlfem_batch_free(nlfem_batch *batch) { batch_free(batch); }
+
+int nlfem_assemble_batched(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, nlfem_pairs *const *pairs,
+                           double *const *vals, const char *tune_cache, void *stream)
+{
+    nlfem_batch *b = nullptr;
+    NLFEM_TRY(nlfem_batch_create(n, meshes, cfgs, pairs, vals, tune_cache, tune_cache ? 1 : 0, &b, stream));
+    int rc = batch_run(b, (hipStream_t)stream);
+    if (rc == NLFEM_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        rc = set_error(NLFEM_E_HIP, "hipStreamSynchronize");
+    batch_free(b);
+    return rc;
 }
 
 }  // extern "C"

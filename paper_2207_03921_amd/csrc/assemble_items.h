@@ -1,0 +1,1020 @@
+// Per-item device code of the assembly (Sec. 2.3-2.4): arguments and the
+// work of one non-touching pair, one touching pair, one element diagonal and
+// one matrix row.  The single-problem kernels (assemble.hip) and the
+// persistent batched kernels (batch.hip) run the same functions, so both give
+// bit-identical results.
+//
+// The local contributions (eq. def:localStiffness) of all interacting pairs
+// are summed into the CSR pattern (eq. biFormApprox).
+//
+// Phase 1 computes one result per unordered pair; phase 2 owns the matrix
+// rows and gathers.  No global atomics, no zero fill: every stored entry is
+// written exactly once by the wave that owns its row.
+//
+// Non-touching pairs (truncation quadrature, Sec. 2.4.1).  For {e, f} both
+// ordered pairs (e,f) and (f,e) are evaluated together.  With the same rule
+// on both sides they share the kernel values
+//   G_pq = w_p |J_e| w_q |J_f| Psi(x_p(e) - x_q(f)),
+// and with the point indicators s_p (x_p(e) sees T_f) and t_q (x_q(f) sees
+// T_e) the four terms of eq. case-one-factoredOut of both directions become
+//   rows e, cols f:  X  = -Phi_e^T H Phi_f,        H_pq = G_pq (s_p + t_q)
+//   rows e, cols e:  De = sum_p (sum_q H_pq) phi_p phi_p^T
+//   rows f, cols f:  Df = sum_q (sum_p H_pq) phi_q phi_q^T
+//   rows f, cols e:  X^T.
+// The record of the pair holds X, De and Df (FP32 in the mixed form: FP32
+// quadrature with FP32 accumulation per pair).  The self pair (e, e) is the
+// single ordered pair with t = 0 and stores X + X^T and De + Df.
+//
+// Touching pairs of a singular configuration (Sec. 2.4.2, Alg. 1): the
+// regularising transforms to (0,1)^4 with the radial direction integrated in
+// closed form.  The integrand is homogeneous of degree d = 2 + deg(Psi) in
+// the radial variable and the Gauss rule integrates that direction exactly,
+// so it is replaced by its exact value.  What remains:
+//   identical: 6 hexagon sectors x n points,   factor 1/((d+2)(d+3)(d+4))
+//   edge:      4 faces x n^2 points,           factor 1/((d+3)(d+4))
+//   vertex:    2 regions x n^3 points,          factor 1/(d+4)
+// A group of lanes shares one pair and reduces through cross-lane shuffles.
+// For a symmetric kernel the rules give L_fe = L_ef, so a row that meets the
+// pair only through one of its elements adds 2 L, a row of a shared vertex
+// meets it twice and adds L each time.
+#pragma once
+
+#include "nlfem_internal.h"
+
+namespace nlfem {
+namespace items {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline double rsqrt64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    for (int it = 0; it < 2; ++it) {
+        const double t = x * y;
+        const double e = fma(-t, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ inline double rsq(double x) { return rsqrt64(x); }
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+template <int KER>
+struct Ker {
+    static constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
+    static constexpr int NK = NC == 1 ? 1 : 3;   // stored values of a symmetric NC x NC block
+    static constexpr int D = KER == NLFEM_K_CONSTANT ? 2 : 1;   // homogeneity degree of the integrand
+};
+
+// kernel values; for two components the symmetric block (k00, k01, k11)
+template <int KER, typename T>
+__device__ inline void kernel_eval(T zx, T zy, T c, T *k)
+{
+    if (KER == NLFEM_K_CONSTANT) {
+        k[0] = c;
+    } else if (KER == NLFEM_K_INV_DIST) {
+        k[0] = c * rsq(zx * zx + zy * zy);
+    } else {
+        const T r = rsq(zx * zx + zy * zy);
+        const T s = c * r * r * r;
+        k[0] = s * zx * zx;
+        k[1] = s * zx * zy;
+        k[2] = s * zy * zy;
+    }
+}
+
+__device__ inline int sym_index(int r, int s, int D)
+{
+    if (r > s) {
+        const int t = r;
+        r = s;
+        s = t;
+    }
+    return r * D - r * (r - 1) / 2 + (s - r);
+}
+
+// Vertex order of the transforms.  identical: the stored order; edge:
+// (P0, P1, A, B) with P0 < P1 the shared nodes, A and B the third vertices
+// of the first and second element; vertex: (P0, A1, A2, B1, B2) with P0 the
+// shared node and each element's other vertices in cyclic order after P0.
+__device__ inline int touch_frame(int cls, const int32_t *ek, const int32_t *el, int32_t *n)
+{
+    if (cls == 3) {
+        n[0] = ek[0];
+        n[1] = ek[1];
+        n[2] = ek[2];
+        return 3;
+    }
+    if (cls == 2) {
+        int32_t sh0 = -1, sh1 = -1, A = -1, B = -1;
+        for (int i = 0; i < 3; ++i) {
+            const bool in = ek[i] == el[0] || ek[i] == el[1] || ek[i] == el[2];
+            if (in) {
+                if (sh0 < 0) sh0 = ek[i];
+                else sh1 = ek[i];
+            } else {
+                A = ek[i];
+            }
+            const bool inl = el[i] == ek[0] || el[i] == ek[1] || el[i] == ek[2];
+            if (!inl) B = el[i];
+        }
+        n[0] = min(sh0, sh1);
+        n[1] = max(sh0, sh1);
+        n[2] = A;
+        n[3] = B;
+        return 4;
+    }
+    int ia = 0, ib = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (ek[i] == el[j]) {
+                ia = i;
+                ib = j;
+            }
+    n[0] = ek[ia];
+    n[1] = ek[(ia + 1) % 3];
+    n[2] = ek[(ia + 2) % 3];
+    n[3] = el[(ib + 1) % 3];
+    n[4] = el[(ib + 2) % 3];
+    return 5;
+}
+
+__device__ inline double2 vtx(const double *V, int32_t n) { return make_double2(V[2 * (int64_t)n], V[2 * (int64_t)n + 1]); }
+
+// ------------------------------------------------------ phase 1: far pairs
+
+struct FarArgs {
+    int64_t n;
+    const int32_t *ue, *uf;
+    const uint32_t *m_ef, *m_fe;
+    const double2 *v0;
+    const double4 *J;
+    const double *det;
+    void *rec;
+    int32_t stride;
+    double c;
+    int32_t same;
+    // polygon ball only
+    const double2 *xp;       // [K][P] outer points (FP64)
+    int32_t P;
+    const int32_t *E;
+    const double *V;
+    const double *dir;       // [N][2]
+    int32_t N;
+    double delta;
+    int32_t cap;             // clip buffer length per lane
+    int32_t *err;
+};
+
+// rule points of the two roles (A on e, B on f)
+struct RoleArgs {
+    int32_t PA, PB;
+    double xa[kMaxRule][2], wa[kMaxRule], pa[kMaxRule][3];
+    double xb[kMaxRule][2], wb[kMaxRule], pb[kMaxRule][3];
+};
+
+template <int KER, typename T, int PM>
+__device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double4 &Je, const double4 &Jf,
+                                     double dete, double detf, uint32_t ms, uint32_t mt, T cc,
+                                     T (&X)[3][3][Ker<KER>::NK], T (&De)[6][Ker<KER>::NK],
+                                     T (&Df)[6][Ker<KER>::NK])
+{
+    constexpr int NK = Ker<KER>::NK;
+    constexpr int PMAX = PM > 0 ? PM : kMaxRule;
+    const int PA = PM > 0 ? PM : r.PA;
+    const int PB = PM > 0 ? PM : r.PB;
+    T fx[PMAX], fy[PMAX], wf[PMAX], tf[PMAX];
+    T beta[PMAX][NK];
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+        if (q < PB) {
+            fx[q] = (T)(Jf.x * r.xb[q][0] + Jf.y * r.xb[q][1]);
+            fy[q] = (T)(Jf.z * r.xb[q][0] + Jf.w * r.xb[q][1]);
+            wf[q] = (T)(r.wb[q] * detf);
+            tf[q] = wf[q] * (T)((mt >> (2 * q)) & 1u);
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) beta[q][k] = 0;
+    }
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+        if (p >= PA) continue;
+        const T ox = (T)(Je.x * r.xa[p][0] + Je.y * r.xa[p][1]) + dx;
+        const T oy = (T)(Je.z * r.xa[p][0] + Je.w * r.xa[p][1]) + dy;
+        const T we0 = (T)(r.wa[p] * dete);
+        const T we = we0 * (T)((ms >> (2 * p)) & 1u);
+        T alpha[NK], tm[3][NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) alpha[k] = tm[0][k] = tm[1][k] = tm[2][k] = 0;
+#pragma unroll
+        for (int q = 0; q < PMAX; ++q) {
+            if (q >= PB) continue;
+            const T zx = ox - fx[q], zy = oy - fy[q];
+            T kv[NK];
+            kernel_eval<KER, T>(zx, zy, cc, kv);
+            const T wgt = we * wf[q] + we0 * tf[q];   // w_p|J_e| w_q|J_f| (s_p + t_q)
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const T hv = wgt * kv[k];
+                alpha[k] += hv;
+                beta[q][k] += hv;
+                tm[0][k] += hv * (T)r.pb[q][0];
+                tm[1][k] += hv * (T)r.pb[q][1];
+                tm[2][k] += hv * (T)r.pb[q][2];
+            }
+        }
+        const T pp[3] = {(T)r.pa[p][0], (T)r.pa[p][1], (T)r.pa[p][2]};
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) X[a][b][k] -= pp[a] * tm[b][k];
+            De[0][k] += alpha[k] * pp[0] * pp[0];
+            De[1][k] += alpha[k] * pp[0] * pp[1];
+            De[2][k] += alpha[k] * pp[0] * pp[2];
+            De[3][k] += alpha[k] * pp[1] * pp[1];
+            De[4][k] += alpha[k] * pp[1] * pp[2];
+            De[5][k] += alpha[k] * pp[2] * pp[2];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+        if (q >= PB) continue;
+        const T b0 = (T)r.pb[q][0], b1 = (T)r.pb[q][1], b2 = (T)r.pb[q][2];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            Df[0][k] += beta[q][k] * b0 * b0;
+            Df[1][k] += beta[q][k] * b0 * b1;
+            Df[2][k] += beta[q][k] * b0 * b2;
+            Df[3][k] += beta[q][k] * b1 * b1;
+            Df[4][k] += beta[q][k] * b1 * b2;
+            Df[5][k] += beta[q][k] * b2 * b2;
+        }
+    }
+}
+
+// ---- polygon ball: outer points whose polygon straddles the inner element
+//
+// Sutherland-Hodgman clip of the inner triangle by the regular N-gon around
+// the outer point, in the operation order of the pair search (no
+// contraction), so the polygon is the one whose status the search recorded;
+// then the fan from the first vertex of the clipped polygon with the inner
+// rule on every sub-triangle and the basis functions of the inner element at
+// the mapped points (Sec. 2.4.1, eq. discrete-inner).  The clip buffers are
+// per-lane arrays, [2 buffers][2 coordinates][cap]; passes that cut nothing
+// do not touch them, so only the 1-3 cutting passes of a typical straddling
+// point read and write them.
+
+__device__ inline double &cb(double *buf, int cap, int lane, int b, int c, int i)
+{
+    return buf[((b * 2 + c) * cap + i) + lane];
+}
+
+// returns the vertex count; the polygon is left in buffer *which
+__device__ inline int clip_polygon(double x, double y, const double vx[3], const double vy[3], const double *dir, int N,
+                            double delta, double *buf, int cap, int lane, int *which, bool *ovf)
+{
+#pragma clang fp contract(off)
+    for (int k = 0; k < 3; ++k) {
+        cb(buf, cap, lane, 0, 0, k) = vx[k];
+        cb(buf, cap, lane, 0, 1, k) = vy[k];
+    }
+    int cnt = 3, cur = 0;
+    for (int j = 0; j < N && cnt > 0; ++j) {
+        const int j1 = j + 1 == N ? 0 : j + 1;
+        const double qa0 = x + delta * dir[2 * j], qa1 = y + delta * dir[2 * j + 1];
+        const double qb0 = x + delta * dir[2 * j1], qb1 = y + delta * dir[2 * j1 + 1];
+        const double e0 = qb0 - qa0, e1 = qb1 - qa1;
+        // a pass that finds every vertex inside returns the list unchanged
+        bool cuts = false;
+        for (int i = 0; i < cnt; ++i)
+            cuts |= !(e0 * (cb(buf, cap, lane, cur, 1, i) - qa1) - e1 * (cb(buf, cap, lane, cur, 0, i) - qa0) >= 0.0);
+        if (!cuts) continue;
+        const int nxt = 1 - cur;
+        int m = 0;
+        for (int i = 0; i < cnt; ++i) {
+            const int i1 = i + 1 == cnt ? 0 : i + 1;
+            const double p0 = cb(buf, cap, lane, cur, 0, i), p1 = cb(buf, cap, lane, cur, 1, i);
+            const double q0 = cb(buf, cap, lane, cur, 0, i1), q1 = cb(buf, cap, lane, cur, 1, i1);
+            const double dp = e0 * (p1 - qa1) - e1 * (p0 - qa0);
+            const double dq = e0 * (q1 - qa1) - e1 * (q0 - qa0);
+            const bool pin = dp >= 0.0, qin = dq >= 0.0;
+            if (m + (pin ? 1 : 0) + (pin != qin ? 1 : 0) > cap) {
+                *ovf = true;
+                return 0;
+            }
+            if (pin) {
+                cb(buf, cap, lane, nxt, 0, m) = p0;
+                cb(buf, cap, lane, nxt, 1, m) = p1;
+                ++m;
+            }
+            if (pin != qin) {
+                const double t = dp / (dp - dq);
+                cb(buf, cap, lane, nxt, 0, m) = p0 + t * (q0 - p0);
+                cb(buf, cap, lane, nxt, 1, m) = p1 + t * (q1 - p1);
+                ++m;
+            }
+        }
+        cnt = m;
+        cur = nxt;
+    }
+    *which = cur;
+    return cnt;
+}
+
+// Samples of one straddling outer point xo (weight wo = w_p |J_outer|, basis
+// values po) against the inner element; the inner rule is role B of r when
+// inner_b, else role A.  outer_e: the outer element is e (rows of X).
+template <int KER, typename T>
+__device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, double xo_y, double wo, const double (&po)[3],
+                               int32_t inner, const double2 &v0i, const double4 &Ji, const RoleArgs &r,
+                               bool inner_b, bool outer_e, double *buf, int lane, T cc,
+                               T (&X)[3][3][Ker<KER>::NK], T (&De)[6][Ker<KER>::NK], T (&Df)[6][Ker<KER>::NK],
+                               bool *ovf)
+{
+    constexpr int NK = Ker<KER>::NK;
+    double vx[3], vy[3];
+    for (int k = 0; k < 3; ++k) {
+        const int32_t n = a.E[3 * (int64_t)inner + k];
+        vx[k] = a.V[2 * (int64_t)n];
+        vy[k] = a.V[2 * (int64_t)n + 1];
+    }
+    int cur = 0;
+    const int cnt = clip_polygon(xo_x, xo_y, vx, vy, a.dir, a.N, a.delta, buf, a.cap, lane, &cur, ovf);
+    if (cnt < 3) return;
+    const double deti = Ji.x * Ji.w - Ji.y * Ji.z;
+    const int Q = inner_b ? r.PB : r.PA;
+    const double s0x = cb(buf, a.cap, lane, cur, 0, 0), s0y = cb(buf, a.cap, lane, cur, 1, 0);
+    const T pe[3] = {(T)po[0], (T)po[1], (T)po[2]};
+    for (int s = 1; s + 1 < cnt; ++s) {
+        const double s1x = cb(buf, a.cap, lane, cur, 0, s), s1y = cb(buf, a.cap, lane, cur, 1, s);
+        const double s2x = cb(buf, a.cap, lane, cur, 0, s + 1), s2y = cb(buf, a.cap, lane, cur, 1, s + 1);
+        const double S00 = s1x - s0x, S01 = s2x - s0x, S10 = s1y - s0y, S11 = s2y - s0y;
+        const double adet = fabs(S00 * S11 - S01 * S10);
+        for (int q = 0; q < Q; ++q) {
+            const double x1 = inner_b ? r.xb[q][0] : r.xa[q][0];
+            const double x2 = inner_b ? r.xb[q][1] : r.xa[q][1];
+            const double wq = inner_b ? r.wb[q] : r.wa[q];
+            const double yx = s0x + (S00 * x1 + S01 * x2), yy = s0y + (S10 * x1 + S11 * x2);
+            const double dx = yx - v0i.x, dy = yy - v0i.y;
+            const double h1 = (Ji.w * dx - Ji.y * dy) / deti;
+            const double h2 = (-Ji.z * dx + Ji.x * dy) / deti;
+            const T pi[3] = {(T)(1.0 - h1 - h2), (T)h1, (T)h2};
+            T kv[NK];
+            kernel_eval<KER, T>((T)(xo_x - yx), (T)(xo_y - yy), cc, kv);
+            const T w = (T)(wo * wq * adet);
+            const T *pr = outer_e ? pe : pi;   // basis of e at its point
+            const T *pc = outer_e ? pi : pe;   // basis of f at its point
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const T hv = w * kv[k];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) X[i][j][k] -= hv * pr[i] * pc[j];
+                De[0][k] += hv * pr[0] * pr[0];
+                De[1][k] += hv * pr[0] * pr[1];
+                De[2][k] += hv * pr[0] * pr[2];
+                De[3][k] += hv * pr[1] * pr[1];
+                De[4][k] += hv * pr[1] * pr[2];
+                De[5][k] += hv * pr[2] * pr[2];
+                Df[0][k] += hv * pc[0] * pc[0];
+                Df[1][k] += hv * pc[0] * pc[1];
+                Df[2][k] += hv * pc[0] * pc[2];
+                Df[3][k] += hv * pc[1] * pc[1];
+                Df[4][k] += hv * pc[1] * pc[2];
+                Df[5][k] += hv * pc[2] * pc[2];
+            }
+        }
+    }
+}
+
+// record of unordered non-touching pair idx
+template <int KER, typename T, int PM, bool POLY>
+__device__ __forceinline__ void far_item(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int64_t idx)
+{
+    constexpr int NK = Ker<KER>::NK;
+    const int32_t e = a.ue[idx], f = a.uf[idx];
+    const uint32_t ms = a.m_ef[idx], mt = a.m_fe[idx];   // mt == 0 for the self pair
+    const bool self = e == f;
+    const double2 v0e = a.v0[e], v0f = a.v0[f];
+    const double4 Je = a.J[e], Jf = a.J[f];
+    const double dete = a.det[e], detf = a.det[f];
+    const T dx = (T)(v0e.x - v0f.x), dy = (T)(v0e.y - v0f.y);
+    const T cc = (T)a.c;
+    T X[3][3][NK], De[6][NK], Df[6][NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) X[i / 3][i % 3][k] = 0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) De[i][k] = Df[i][k] = 0;
+    }
+    if (a.same) {
+        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, mt, cc, X, De, Df);
+    } else {
+        // (e, f): outer rule on e, inner rule on f
+        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, 0u, cc, X, De, Df);
+        // (f, e): inner rule on e, outer rule on f
+        if (!self) far_direction<KER, T, PM>(r2, dx, dy, Je, Jf, dete, detf, 0u, mt, cc, X, De, Df);
+    }
+    if (POLY) {
+        // status 2: the polygon around the point straddles the other element
+        double clipbuf[2 * 2 * (kMaxPoly + 4)];
+        const int lane = 0;
+        bool ovf = false;
+        for (int p = 0; p < r1.PA; ++p) {
+            if (((ms >> (2 * p)) & 3u) != kStraddle) continue;
+            const double2 xo = a.xp[(int64_t)e * a.P + p];
+            const double po[3] = {r1.pa[p][0], r1.pa[p][1], r1.pa[p][2]};
+            straddle_point<KER, T>(a, xo.x, xo.y, r1.wa[p] * dete, po, f, v0f, Jf, r1, true, true, clipbuf, lane,
+                                   cc, X, De, Df, &ovf);
+        }
+        // with one rule both directions use r1; otherwise the outer rule on f is role B of r2
+        for (int q = 0; !self && q < r1.PB; ++q) {
+            if (((mt >> (2 * q)) & 3u) != kStraddle) continue;
+            const double2 xo = a.xp[(int64_t)f * a.P + q];
+            if (a.same) {
+                const double po[3] = {r1.pb[q][0], r1.pb[q][1], r1.pb[q][2]};
+                straddle_point<KER, T>(a, xo.x, xo.y, r1.wb[q] * detf, po, e, v0e, Je, r1, false, false, clipbuf,
+                                       lane, cc, X, De, Df, &ovf);
+            } else {
+                const double po[3] = {r2.pb[q][0], r2.pb[q][1], r2.pb[q][2]};
+                straddle_point<KER, T>(a, xo.x, xo.y, r2.wb[q] * detf, po, e, v0e, Je, r2, false, false, clipbuf,
+                                       lane, cc, X, De, Df, &ovf);
+            }
+        }
+        if (ovf) atomicOr(a.err, kErrClip);
+    }
+    T *out = (T *)a.rec + idx * a.stride;
+    if (self) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) out[(3 * i + j) * NK + k] = X[i][j][k] + X[j][i][k];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                out[(9 + i) * NK + k] = De[i][k] + Df[i][k];
+                out[(15 + i) * NK + k] = 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) out[i * NK + k] = X[i / 3][i % 3][k];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                out[(9 + i) * NK + k] = De[i][k];
+                out[(15 + i) * NK + k] = Df[i][k];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- phase 1: touching pairs
+
+struct TouchArgs {
+    int64_t n;
+    const int32_t *te, *tf;
+    const int32_t *E;
+    const double *V;
+    double *rec;
+    int32_t stride;
+    double c;
+};
+
+// accumulate w * Psi(z) (g g^T) into the packed upper triangle of L
+template <int KER, int NU>
+__device__ inline void acc_sample(double *L, double w, double zx, double zy, const double *g, double c)
+{
+    constexpr int NC = Ker<KER>::NC;
+    constexpr int D = NU * NC;
+    double k[3];
+    kernel_eval<KER, double>(zx, zy, c, k);
+    double kk[2][2];
+    if (NC == 1) {
+        kk[0][0] = k[0];
+    } else {
+        kk[0][0] = k[0];
+        kk[0][1] = kk[1][0] = k[1];
+        kk[1][1] = k[2];
+    }
+    int idx = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        const double wr = w * g[r / NC];
+#pragma unroll
+        for (int s = r; s < D; ++s) L[idx++] += wr * kk[r % NC][s % NC] * g[s / NC];
+    }
+}
+
+// record of touching pair `pair` of class CLS, computed by the G lanes
+// sub = 0..G-1 of an aligned lane group (all of them must call)
+template <int KER, int CLS, int G>
+__device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &g, int64_t pair, int sub)
+{
+    constexpr int NC = Ker<KER>::NC;
+    constexpr int NU = CLS == 3 ? 3 : CLS == 2 ? 4 : 5;
+    constexpr int D = NU * NC;
+    constexpr int NP = D * (D + 1) / 2;
+    const int32_t e = a.te[pair], f = a.tf[pair];
+    const int32_t ek[3] = {a.E[3 * (int64_t)e], a.E[3 * (int64_t)e + 1], a.E[3 * (int64_t)e + 2]};
+    const int32_t el[3] = {a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]};
+    int32_t nd[5];
+    touch_frame(CLS, ek, el, nd);
+    double L[NP];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) L[t] = 0.0;
+    const int n = g.n;
+    double scale;
+    if (CLS == 3) {
+        const double2 p0 = vtx(a.V, nd[0]), p1 = vtx(a.V, nd[1]), p2 = vtx(a.V, nd[2]);
+        const double J00 = p1.x - p0.x, J01 = p2.x - p0.x, J10 = p1.y - p0.y, J11 = p2.y - p0.y;
+        const double det = fabs(J00 * J11 - J01 * J10);
+        for (int ev = sub; ev < 6 * n; ev += G) {
+            const int j = ev / n, iu = ev - j * n;
+            // hexagon corners (1,0),(0,1),(-1,1),(-1,0),(0,-1),(1,-1)
+            const int j1 = j == 5 ? 0 : j + 1;
+            const double cx0 = j == 0 || j == 5 ? 1.0 : (j == 2 || j == 3 ? -1.0 : 0.0);
+            const double cy0 = j == 1 || j == 2 ? 1.0 : (j == 4 || j == 5 ? -1.0 : 0.0);
+            const double cx1 = j1 == 0 || j1 == 5 ? 1.0 : (j1 == 2 || j1 == 3 ? -1.0 : 0.0);
+            const double cy1 = j1 == 1 || j1 == 2 ? 1.0 : (j1 == 4 || j1 == 5 ? -1.0 : 0.0);
+            const double u = g.x[iu];
+            const double wx = (1.0 - u) * cx0 + u * cx1;
+            const double wy = (1.0 - u) * cy0 + u * cy1;
+            // phi(x^) - phi(x^ + z) = -grad phi . z, z = rho w
+            const double gg[3] = {wx + wy, -wx, -wy};
+            acc_sample<KER, 3>(L, g.w[iu], J00 * wx + J01 * wy, J10 * wx + J11 * wy, gg, a.c);
+        }
+        constexpr int d = Ker<KER>::D;
+        scale = det * det / (double)((d + 2) * (d + 3) * (d + 4));
+    } else if (CLS == 2) {
+        const double2 q0 = vtx(a.V, nd[0]), q1 = vtx(a.V, nd[1]), qa = vtx(a.V, nd[2]), qb = vtx(a.V, nd[3]);
+        // x - y = E v,  E = [P1 - P0, A - P0, -(B - P0)]
+        const double E0x = q1.x - q0.x, E0y = q1.y - q0.y;
+        const double E1x = qa.x - q0.x, E1y = qa.y - q0.y;
+        const double E2x = -(qb.x - q0.x), E2y = -(qb.y - q0.y);
+        // faces of the cone {max(v2 + v1+, v3 + v1-) <= 1} are unrolled at
+        // compile time; the lanes of the group share the n^2 points of each
+        // face (a data-dependent face index miscompiled here once: keep it
+        // out of divergent control flow)
+#pragma unroll
+        for (int face = 0; face < 4; ++face) {
+            for (int ev = sub; ev < n * n; ev += G) {
+                const int ip = ev / n, iq = ev - ip * n;
+                const double p = g.x[ip], q = g.x[iq];
+                const double u = 1.0 - p, t = u * q;
+                const double w0 = face < 2 ? p : -p;
+                const double w1 = face == 0 ? u : face == 1 ? t : face == 2 ? 1.0 : q;
+                const double w2 = face == 0 ? q : face == 1 ? 1.0 : face == 2 ? t : u;
+                const double jf = (face == 1 || face == 2) ? u : 1.0;
+                const double gg[4] = {-w0 - w1 + w2, w0, w1, -w2};
+                acc_sample<KER, 4>(L, g.w[ip] * g.w[iq] * jf, E0x * w0 + E1x * w1 + E2x * w2,
+                                   E0y * w0 + E1y * w1 + E2y * w2, gg, a.c);
+            }
+        }
+        const double detk = fabs(E0x * E1y - E1x * E0y), detl = fabs(E0x * E2y - E2x * E0y);
+        constexpr int d = Ker<KER>::D;
+        scale = detk * detl / (double)((d + 3) * (d + 4));
+    } else {
+        const double2 q0 = vtx(a.V, nd[0]), a1 = vtx(a.V, nd[1]), a2 = vtx(a.V, nd[2]);
+        const double2 b1 = vtx(a.V, nd[3]), b2 = vtx(a.V, nd[4]);
+        const double A1x = a1.x - q0.x, A1y = a1.y - q0.y, A2x = a2.x - q0.x, A2y = a2.y - q0.y;
+        const double B1x = b1.x - q0.x, B1y = b1.y - q0.y, B2x = b2.x - q0.x, B2y = b2.y - q0.y;
+        for (int ev = sub; ev < n * n * n; ev += G) {
+            const int iw = ev / (n * n), rem = ev - iw * n * n;
+            const int ia = rem / n, ib = rem - ia * n;
+            const double w = g.x[iw], al = g.x[ia], be = g.x[ib];
+            const double ex = (1.0 - al) * A1x + al * A2x, ey = (1.0 - al) * A1y + al * A2y;
+            const double fx = (1.0 - be) * B1x + be * B2x, fy = (1.0 - be) * B1y + be * B2y;
+            const double wt = g.w[iw] * g.w[ia] * g.w[ib] * w;
+            {   // region t <= s: t = s w
+                const double gg[5] = {w - 1.0, 1.0 - al, al, -w * (1.0 - be), -w * be};
+                acc_sample<KER, 5>(L, wt, ex - w * fx, ey - w * fy, gg, a.c);
+            }
+            {   // region s <= t: s = t w
+                const double gg[5] = {1.0 - w, w * (1.0 - al), w * al, -(1.0 - be), -be};
+                acc_sample<KER, 5>(L, wt, w * ex - fx, w * ey - fy, gg, a.c);
+            }
+        }
+        const double detk = fabs(A1x * A2y - A2x * A1y), detl = fabs(B1x * B2y - B2x * B1y);
+        constexpr int d = Ker<KER>::D;
+        scale = detk * detl / (double)(d + 4);
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int t = 0; t < NP; ++t) L[t] += __shfl_xor(L[t], off, G);
+    double *out = a.rec + pair * a.stride;
+#pragma unroll
+    for (int t = 0; t < NP; ++t)
+        if (t % G == sub) out[t] = scale * L[t];
+}
+
+// ------------------------------------------ phase 1b: element diagonals
+// D_e = sum over the non-touching pairs of e of the element-diagonal part of
+// their records (De when e is the first element, Df when it is the second).
+// One wave per element; the rows then add D_e once per element.
+
+struct DiagArgs {
+    int64_t K;
+    const int64_t *sptr;
+    const int32_t *snbr;
+    const uint8_t *sflag;
+    const int32_t *srec;
+    const void *far_rec;
+    int32_t far_stride;
+    int64_t n_far;
+    double *dsum;
+    int32_t *err;
+};
+
+// D_e of element e by the 64 lanes of one wave
+template <int NK, typename TR>
+__device__ __forceinline__ void diag_item(const DiagArgs &a, int64_t e, int lane)
+{
+    double acc[6 * NK];
+    for (int i = 0; i < 6 * NK; ++i) acc[i] = 0.0;
+    bool bad = false;
+    for (int64_t t = a.sptr[e] + lane; t < a.sptr[e + 1]; t += 64) {
+        if (((a.sflag[t] >> 2) & 3) != 0) continue;
+        const int32_t u = a.srec[t];
+        if (u < 0 || u >= a.n_far) {
+            bad = true;
+            continue;
+        }
+        const int32_t f = a.snbr[t];
+        const TR *r = (const TR *)a.far_rec + (int64_t)u * a.far_stride + (f >= e ? 9 : 15) * NK;
+        for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
+    }
+    for (int i = 0; i < 6 * NK; ++i)
+        for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_xor(acc[i], o);
+    if (bad) atomicOr(a.err, kErrSlot);
+    if (lane < 6 * NK) {
+        double v = 0.0;
+        for (int i = 0; i < 6 * NK; ++i)
+            if (i == lane) v = acc[i];
+        a.dsum[e * 6 * NK + lane] = v;
+    }
+}
+
+// ------------------------------------------------- phase 2: row gather
+//
+// One wave per degree-of-freedom node.  The wave maps the row's column ids to
+// positions through an LDS hash table, accumulates the row in LDS and writes
+// it once.  The work items are the entries (e, f) of the neighbour lists S(e)
+// of the elements e around the node.  Each lane takes kRowU entries per step
+// and issues all their loads (list entry, then vertices of f and record
+// values) before it adds any of them, so the dependent global loads of a
+// step overlap instead of forming one chain per entry.
+
+struct RowArgs {
+    int64_t nrows;
+    const int32_t *rows;     // dof nodes
+    const int64_t *nptr;
+    const int32_t *ncol;
+    const int64_t *ne_ptr;
+    const int32_t *ne_list;
+    const int32_t *E;
+    const int64_t *sptr;
+    const int32_t *snbr;
+    const uint8_t *sflag;
+    const int32_t *srec;
+    const void *far_rec;
+    int32_t far_stride;
+    int64_t n_far;
+    const double *dsum;
+    const double *touch_rec;
+    int32_t touch_stride;
+    int64_t n_touch;
+    int32_t hcap;        // power of two, >= 2 * longest row
+    int32_t maxlen;
+    double *val;
+    int32_t *err;
+};
+
+constexpr int kRowQ = 64;   // elements around a node per batch (one per lane)
+constexpr int kRowU = 4;    // neighbour-list entries per lane per step
+
+__device__ inline int hpos(const int32_t *hk, const int32_t *hv, int32_t mask, int32_t key)
+{
+    uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
+    for (int probe = 0; probe <= mask; ++probe) {
+        const int32_t k = hk[h];
+        if (k == key) return hv[h];
+        if (k < 0) return -1;
+        h = (h + 1) & (uint32_t)mask;
+    }
+    return -1;
+}
+
+template <int NC>
+__device__ inline void add_sym_block(double *acc, int pos, const double *v)
+{
+    if (NC == 1) {
+        atomicAdd(&acc[pos], v[0]);
+    } else {
+        atomicAdd(&acc[pos * 4 + 0], v[0]);
+        atomicAdd(&acc[pos * 4 + 1], v[1]);
+        atomicAdd(&acc[pos * 4 + 2], v[1]);
+        atomicAdd(&acc[pos * 4 + 3], v[2]);
+    }
+}
+
+__device__ inline int32_t pick3(int i, int32_t x0, int32_t x1, int32_t x2)
+{
+    return i == 0 ? x0 : (i == 1 ? x1 : x2);
+}
+
+// The vertex order of touch_frame, on scalars (a: first element of the
+// ordered pair, b: second); unused slots are -1.
+struct Frame {
+    int32_t n0, n1, n2, n3, n4;
+    int nu;
+};
+
+__device__ inline Frame frame_of(int cls, int32_t a0, int32_t a1, int32_t a2, int32_t b0, int32_t b1,
+                                 int32_t b2)
+{
+    if (cls == 3) return Frame{a0, a1, a2, -1, -1, 3};
+    if (cls == 2) {
+        const bool i0 = a0 == b0 || a0 == b1 || a0 == b2;
+        const bool i1 = a1 == b0 || a1 == b1 || a1 == b2;
+        const int32_t s0 = !i0 ? a1 : a0;
+        const int32_t s1 = (!i0 || !i1) ? a2 : a1;
+        const int32_t A = !i0 ? a0 : (!i1 ? a1 : a2);
+        const bool j0 = b0 == a0 || b0 == a1 || b0 == a2;
+        const bool j1 = b1 == a0 || b1 == a1 || b1 == a2;
+        const int32_t B = !j0 ? b0 : (!j1 ? b1 : b2);
+        return Frame{min(s0, s1), max(s0, s1), A, B, -1, 4};
+    }
+    const int32_t av[3] = {a0, a1, a2}, bv[3] = {b0, b1, b2};
+    int ia = 0, ib = 0;
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+            if (av[x] == bv[y]) {
+                ia = x;
+                ib = y;
+            }
+    const int ia1 = ia == 2 ? 0 : ia + 1, ia2 = ia == 0 ? 2 : ia - 1;
+    const int ib1 = ib == 2 ? 0 : ib + 1, ib2 = ib == 0 ? 2 : ib - 1;
+    return Frame{pick3(ia, a0, a1, a2), pick3(ia1, a0, a1, a2), pick3(ia2, a0, a1, a2),
+                 pick3(ib1, b0, b1, b2), pick3(ib2, b0, b1, b2), 5};
+}
+
+// Row i's share of a touching pair: factor * (row rr of L) over the frame
+// nodes, rr the frame slot of i.
+template <int NC>
+__device__ inline bool add_touch(double *acc, const int32_t *hk, const int32_t *hv, int32_t mask, int32_t i,
+                                 int cls, int32_t e, int32_t f, int32_t e0, int32_t e1, int32_t e2,
+                                 int32_t f0, int32_t f1, int32_t f2, const double *L)
+{
+    constexpr int NN = NC * NC;
+    const bool first = e <= f;
+    const Frame fr = first ? frame_of(cls, e0, e1, e2, f0, f1, f2) : frame_of(cls, f0, f1, f2, e0, e1, e2);
+    const int32_t nodes[5] = {fr.n0, fr.n1, fr.n2, fr.n3, fr.n4};
+    int rr = 0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        if (nodes[c] == i) rr = c;
+    const bool ine = e0 == i || e1 == i || e2 == i;
+    const bool inf = f0 == i || f1 == i || f2 == i;
+    const double factor = (cls == 3 || (ine && inf)) ? 1.0 : 2.0;
+    const int D = fr.nu * NC;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        if (c >= fr.nu) break;
+        const int pc = hpos(hk, hv, mask, nodes[c]);
+        if (pc < 0) {
+            ok = false;
+            continue;
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+            for (int dd = 0; dd < NC; ++dd)
+                atomicAdd(&acc[pc * NN + cc * NC + dd], factor * L[sym_index(rr * NC + cc, c * NC + dd, D)]);
+    }
+    return ok;
+}
+
+// LDS of one row gather besides the dynamic part (accumulator, hash table)
+struct RowShared {
+    int64_t qs[kRowQ];
+    int32_t pre[kRowQ + 1], qe[kRowQ], qloc[kRowQ], qn[kRowQ][3], qp[kRowQ][3];
+};
+
+// dynamic LDS bytes of one row gather
+inline size_t row_lds_bytes(int64_t maxlen, int nc, int hcap)
+{
+    return sizeof(double) * (size_t)maxlen * nc * nc + sizeof(int32_t) * 2 * (size_t)hcap;
+}
+
+// row of dof node i by the 64 lanes of a one-wave workgroup; smem holds
+// row_lds_bytes(a.maxlen, NC, a.hcap) bytes
+template <int NC, typename TR>
+__device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned char *smem, RowShared &sh)
+{
+    constexpr int NN = NC * NC;
+    constexpr int NK = NC == 1 ? 1 : 3;
+    double *acc = (double *)smem;                              // [maxlen * NN]
+    int32_t *hk = (int32_t *)(acc + (size_t)a.maxlen * NN);    // [hcap]
+    int32_t *hv = hk + a.hcap;                                 // [hcap]
+    int64_t *qs = sh.qs;
+    int32_t *pre = sh.pre, *qe = sh.qe, *qloc = sh.qloc;
+    int32_t (*qn)[3] = sh.qn;
+    int32_t (*qp)[3] = sh.qp;
+    const int lane = threadIdx.x;
+    const int32_t mask = a.hcap - 1;
+    {
+        const int64_t s = a.nptr[i];
+        const int len = (int)(a.nptr[i + 1] - s);
+        if (len == 0) return;
+        for (int t = lane; t < a.hcap; t += 64) hk[t] = -1;
+        for (int t = lane; t < len * NN; t += 64) acc[t] = 0.0;
+        __syncthreads();
+        for (int t = lane; t < len; t += 64) {
+            const int32_t key = a.ncol[s + t];
+            uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
+            for (int probe = 0; probe <= mask; ++probe) {
+                if (atomicCAS(&hk[h], -1, key) == -1) {
+                    hv[h] = t;
+                    break;
+                }
+                h = (h + 1) & (uint32_t)mask;
+            }
+        }
+        __syncthreads();
+        bool bad = false;
+        const int64_t q0 = a.ne_ptr[i], q1 = a.ne_ptr[i + 1];
+        for (int64_t qb = q0; qb < q1; qb += kRowQ) {
+            const int nq = (int)min((int64_t)kRowQ, q1 - qb);
+            int cnt = 0;
+            if (lane < nq) {
+                // the elements around the node: id, local index of the node,
+                // vertex ids and their column positions
+                const int32_t e = a.ne_list[qb + lane];
+                const int32_t v0 = a.E[3 * (int64_t)e], v1 = a.E[3 * (int64_t)e + 1], v2 = a.E[3 * (int64_t)e + 2];
+                const int64_t se0 = a.sptr[e], se1 = a.sptr[e + 1];
+                qe[lane] = e;
+                qs[lane] = se0;
+                qn[lane][0] = v0;
+                qn[lane][1] = v1;
+                qn[lane][2] = v2;
+                const int p0 = hpos(hk, hv, mask, v0), p1 = hpos(hk, hv, mask, v1), p2 = hpos(hk, hv, mask, v2);
+                qp[lane][0] = p0;
+                qp[lane][1] = p1;
+                qp[lane][2] = p2;
+                const int loc = v0 == (int32_t)i ? 0 : v1 == (int32_t)i ? 1 : 2;
+                qloc[lane] = loc;
+                cnt = (int)(se1 - se0);
+                if (cnt > 0) {
+                    // summed element-diagonal block of e's non-touching pairs, row loc
+                    const double *dv = a.dsum + (int64_t)e * 6 * NK;
+                    const int pb[3] = {p0, p1, p2};
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (pb[b] < 0) {
+                            bad = true;
+                            continue;
+                        }
+                        double ds[NK];
+#pragma unroll
+                        for (int k = 0; k < NK; ++k) ds[k] = dv[sym_index(loc, b, 3) * NK + k];
+                        add_sym_block<NC>(acc, pb[b], ds);
+                    }
+                }
+            }
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            if (lane < nq) pre[lane + 1] = incl;
+            if (lane == 0) pre[0] = 0;
+            const int total = __shfl(incl, nq - 1);
+            __syncthreads();
+            for (int base = 0; base < total; base += 64 * kRowU) {
+                int32_t fe[kRowU], uu[kRowU], qq[kRowU], cl[kRowU], nf0[kRowU], nf1[kRowU], nf2[kRowU];
+                bool act[kRowU];
+                TR xv[kRowU][3][NK];
+#pragma unroll
+                for (int k = 0; k < kRowU; ++k) {
+                    const int flat = base + k * 64 + lane;
+                    act[k] = flat < total;
+                    fe[k] = 0;
+                    uu[k] = -1;
+                    cl[k] = 0;
+                    qq[k] = 0;
+                    if (act[k]) {
+                        // the element q with pre[q] <= flat < pre[q + 1]
+                        int lo = 0, hi = nq;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (pre[mid] <= flat) lo = mid;
+                            else hi = mid;
+                        }
+                        qq[k] = lo;
+                        const int64_t t = qs[lo] + (flat - pre[lo]);
+                        fe[k] = a.snbr[t];
+                        cl[k] = (a.sflag[t] >> 2) & 3;
+                        uu[k] = a.srec[t];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kRowU; ++k) {
+                    nf0[k] = nf1[k] = nf2[k] = -1;
+                    if (!act[k]) continue;
+                    if (uu[k] < 0 || uu[k] >= (cl[k] == 0 ? a.n_far : a.n_touch)) {
+                        bad = true;
+                        act[k] = false;
+                        continue;
+                    }
+                    const int32_t f = fe[k];
+                    nf0[k] = a.E[3 * (int64_t)f];
+                    nf1[k] = a.E[3 * (int64_t)f + 1];
+                    nf2[k] = a.E[3 * (int64_t)f + 2];
+                    if (cl[k] == 0) {
+                        // row loc of X (e first) or column loc (e second); the
+                        // self pair stores X + X^T
+                        const int32_t e = qe[qq[k]];
+                        const int loc = qloc[qq[k]];
+                        const TR *r = (const TR *)a.far_rec + (int64_t)uu[k] * a.far_stride;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const int xi = f >= e ? 3 * loc + b : 3 * b + loc;
+#pragma unroll
+                            for (int kk = 0; kk < NK; ++kk) xv[k][b][kk] = r[xi * NK + kk];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kRowU; ++k) {
+                    if (!act[k]) continue;
+                    const int q = qq[k];
+                    const int32_t e = qe[q], f = fe[k];
+                    if (cl[k] == 0) {
+                        const int32_t nb[3] = {nf0[k], nf1[k], nf2[k]};
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const int px = f == e ? qp[q][b] : hpos(hk, hv, mask, nb[b]);
+                            if (px < 0) {
+                                bad = true;
+                                continue;
+                            }
+                            double xs[NK];
+#pragma unroll
+                            for (int kk = 0; kk < NK; ++kk) xs[kk] = (double)xv[k][b][kk];
+                            add_sym_block<NC>(acc, px, xs);
+                        }
+                    } else {
+                        const double *L = a.touch_rec + (int64_t)uu[k] * a.touch_stride;
+                        if (!add_touch<NC>(acc, hk, hv, mask, (int32_t)i, cl[k], e, f, qn[q][0], qn[q][1], qn[q][2],
+                                           nf0[k], nf1[k], nf2[k], L))
+                            bad = true;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (bad) atomicOr(a.err, kErrSlot);
+        if (NC == 1) {
+            for (int t = lane; t < len; t += 64) a.val[s + t] = acc[t];
+        } else {
+            for (int t = lane; t < len * 4; t += 64) {
+                const int pos = t >> 2, c = (t >> 1) & 1, d = t & 1;
+                a.val[4 * s + (int64_t)c * 2 * len + 2 * pos + d] = acc[t];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- plans
+
+// Everything one assembly of one problem launches with (host side).
+struct AssemblePlan {
+    int kernel, nc;
+    bool fp32, poly, seven;          // seven: both rules have 7 points
+    FarArgs far;                     // far.n == 0: no non-touching pairs
+    RoleArgs r1, r2;
+    TouchArgs touch[3];              // identical, edge, vertex classes
+    GaussArgs gauss;
+    DiagArgs diag;
+    RowArgs rows;                    // rows.nrows == 0: empty pattern
+};
+
+RoleArgs roles(const RuleArgs &r, bool a_outer, bool b_outer);
+AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
+                       double *val);
+
+}  // namespace items
+}  // namespace nlfem

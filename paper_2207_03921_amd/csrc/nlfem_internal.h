@@ -156,6 +156,12 @@ int hip_error(hipError_t e, const char *what);
         if (_e != hipSuccess) return ::nlfem::hip_error(_e, #call);   \
     } while (0)
 
+#define NLFEM_TRY(x)                     \
+    do {                                 \
+        int _rc = (x);                   \
+        if (_rc != NLFEM_OK) return _rc; \
+    } while (0)
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD

@@ -126,3 +126,19 @@ def test_timing_mask_validation(nl):
     assert L.nlfem_timing_read(ms.ctypes.data, n.ctypes.data, 1) == 0
     assert not n.any()
     assert L.nlfem_timing_read(None, None, 1) == -1
+
+
+def test_batch_entry_points_validate_without_device(nl):
+    L = nl.lib()
+    h = C.c_void_p(None)
+    assert L.nlfem_batch_create(0, None, None, None, None, None, 0, C.byref(h), None) == -1
+    assert "batch size" in nl.nlfem_last_error()
+    assert L.nlfem_batch_create(1, None, None, None, None, None, 0, C.byref(h), None) == -1
+    assert L.nlfem_batch_create(1, None, None, None, None, None, 0, None, None) == -1
+    assert L.nlfem_batch_assemble(None, None) == -1
+    assert L.nlfem_batch_launch_graph(None, None) == -1
+    g = C.c_int32(0)
+    sh = (C.c_int32 * 8)()
+    assert L.nlfem_batch_info(None, C.byref(g), sh) == -1
+    assert L.nlfem_assemble_batched(0, None, None, None, None, None, None) == -1
+    L.nlfem_batch_free(None)
