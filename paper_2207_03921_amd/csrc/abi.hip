@@ -226,16 +226,20 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_BARY, K, h->bary));
     NLFEM_TRY(ensure_typed(h, B_XP, K * P, h->xp));
     NLFEM_TRY(ensure_typed(h, B_FLAGS, M, h->node_flags));
-    NLFEM_TRY(ensure_typed(h, B_ERR, 1, h->err));
-    NLFEM_TRY(ensure_typed(h, B_RED, 16, h->red));
+    NLFEM_TRY(ensure_typed(h, B_RED, kRedSlots, h->red));
+    h->err = (int32_t *)(h->red + kRedErr);
+    if (!h->rb) {
+        void *rb = nullptr;
+        NLFEM_HIP(hipHostMalloc(&rb, sizeof(unsigned long long) * kRedSlots, hipHostMallocDefault));
+        h->rb = (unsigned long long *)rb;
+    }
+    unsigned long long *red = h->rb;
     timing_begin(kPhGeometry, s);
     NLFEM_TRY(launch_geometry(h, m, s));
     timing_end(kPhGeometry, s);
-    unsigned long long red[16];
-    int32_t err = 0;
-    NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof red, hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
+    int32_t err = (int32_t)(red[kRedErr] & 0xffffffffull);
     if (err & kErrIndex) return set_error(NLFEM_E_MESH, "element vertex index out of range");
     if (err & kErrArea) return set_error(NLFEM_E_MESH, "element with zero area");
     const double x0 = key_to_double(red[0]), y0 = key_to_double(red[1]);
@@ -269,38 +273,48 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_CELLFILL, ncell, h->cell_fill));
     NLFEM_TRY(ensure_typed(h, B_CELLELEMS, K, h->cell_elems));
     NLFEM_TRY(ensure_typed(h, B_CELLOF, K, h->cell_of));
-    const int64_t scan_need = scan_tmp_size(std::max<int64_t>({K1, M + 1, ncell + 1})) + 1;
+    const int64_t scan_need = std::max({scan_tmp_size(K, kLsLast), scan_tmp_size(M), scan_tmp_size(ncell)}) + 1;
     NLFEM_TRY(ensure_typed(h, B_SCAN, scan_need, h->scan_tmp));
     h->scan_cap = (int64_t)(h->bufs[B_SCAN].cap / sizeof(int64_t));
-    NLFEM_TRY(launch_cell_count(h, s));
-    NLFEM_TRY(exclusive_scan(h->cell_cnt, h->cell_start, ncell, h->scan_tmp, h->scan_cap, s));
-    NLFEM_TRY(launch_cell_fill(h, s));
-    NLFEM_HIP(hipMemcpyAsync(red + 6, h->red + 6, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipStreamSynchronize(s));
-    h->max_cell = (int32_t)red[6];
-
-    // pair search: count, scan, fill ---------------------------------------
+    NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
+    NLFEM_TRY(ensure_typed(h, B_LOFF, kLsLast * K1, h->loff));
+    NLFEM_TRY(ensure_typed(h, B_NLEN, M + 1, h->nlen));
+    NLFEM_TRY(ensure_typed(h, B_NPTR, M + 1, h->nptr));
+    NLFEM_TRY(ensure_typed(h, B_NEPTR, M + 1, h->ne_ptr));
+    NLFEM_TRY(ensure_typed(h, B_NELIST, 3 * K, h->ne_list));
+    NLFEM_TRY(ensure_typed(h, B_NEFILL, M, h->ne_fill));
+    NLFEM_TRY(ensure_typed(h, B_DOFL, M, h->dof_list));
     if (h->approach == NLFEM_A_APPROXCAPS_POLY) {
         // h->poly lives as long as the handle, so the copy may run asynchronously
         NLFEM_TRY(ensure_typed(h, B_POLYDIR, 2 * kMaxPoly, h->poly_dir));
         NLFEM_HIP(hipMemcpyAsync(h->poly_dir, h->poly.dir, sizeof(double) * 2 * h->poly.N, hipMemcpyHostToDevice, s));
     }
-    NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
-    NLFEM_TRY(ensure_typed(h, B_LOFF, kLsLast * K1, h->loff));
-    NLFEM_HIP(hipMemsetAsync(h->lcnt, 0, sizeof(int64_t) * kLsLast * K1, s));
-    NLFEM_HIP(hipMemsetAsync(h->red + 7, 0, sizeof(unsigned long long), s));
+    {
+        // every counter of the rest of the build starts at zero
+        ZeroList z{};
+        z.add(h->cell_cnt, ncell + 1);
+        z.add(h->cell_fill, ncell);
+        z.add(h->lcnt, kLsLast * K1);
+        z.add(h->nlen, M + 1);
+        z.add(h->ne_fill, M);
+        z.add(h->red + kRedMaxCell, kRedErr - kRedMaxCell);   // slots 6..17, keeps the error bits
+        NLFEM_TRY(launch_zero(z, nullptr, s));
+    }
+    NLFEM_TRY(launch_cell_count(h, s));
+    NLFEM_TRY(exclusive_scan(h->cell_cnt, h->cell_start, ncell, h->scan_tmp, h->scan_cap, s));
+    NLFEM_TRY(launch_cell_fill(h, s));
+
+    // pair search: count, scan, fill ---------------------------------------
     timing_begin(kPhPairs, s);
     NLFEM_TRY(launch_pairs(h, m, false, s));
     timing_end(kPhPairs, s);
-    for (int k = 0; k < kLsLast; ++k)
-        NLFEM_TRY(exclusive_scan(h->lcnt + k * K1, h->loff + k * K1, K, h->scan_tmp, h->scan_cap, s));
-    int64_t tot[kLsLast];
-    for (int k = 0; k < kLsLast; ++k)
-        NLFEM_HIP(hipMemcpyAsync(&tot[k], h->loff + k * K1 + K, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipMemcpyAsync(red + 7, h->red + 7, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipMemcpyAsync(red + 10, h->red + 10, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    NLFEM_TRY(exclusive_scan_segments(h->lcnt, h->loff, K, kLsLast, K1, h->scan_tmp, h->scan_cap,
+                                      (int64_t *)(h->red + kRedTot), s));
+    NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
-    h->max_clip = (int32_t)red[10];
+    int64_t tot[kLsLast];
+    for (int k = 0; k < kLsLast; ++k) tot[k] = (int64_t)red[kRedTot + k];
+    h->max_clip = (int32_t)red[kRedClip];
     h->nS = tot[kLsS];
     h->nP = tot[kLsP];
     h->nUF = tot[kLsUF];
@@ -308,7 +322,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->nUTc[1] = tot[kLsUE];
     h->nUTc[2] = tot[kLsUV];
     h->nUT = h->nUTc[0] + h->nUTc[1] + h->nUTc[2];
-    h->max_S = (int64_t)red[7];
+    h->max_S = (int64_t)red[kRedMaxS];
     h->n_pairs = h->nP;
     h->n_ident = h->nUTc[0];
     h->n_edge = 2 * h->nUTc[1];
@@ -334,17 +348,10 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     timing_end(kPhPairs, s);
     timing_begin(kPhLists, s);
     NLFEM_TRY(launch_sort_lists(h, s));
-    NLFEM_HIP(hipMemsetAsync(h->srec, 0xff, sizeof(int32_t) * (size_t)std::max<int64_t>(h->nS, 1), s));
     NLFEM_TRY(launch_worklists(h, m, s));
     timing_end(kPhLists, s);
 
-    // node -> element incidence --------------------------------------------
-    NLFEM_TRY(ensure_typed(h, B_NLEN, M + 1, h->nlen));
-    NLFEM_TRY(ensure_typed(h, B_NPTR, M + 1, h->nptr));
-    NLFEM_TRY(ensure_typed(h, B_NEPTR, M + 1, h->ne_ptr));
-    NLFEM_TRY(ensure_typed(h, B_NELIST, 3 * K, h->ne_list));
-    NLFEM_TRY(ensure_typed(h, B_NEFILL, M, h->ne_fill));
-    NLFEM_TRY(ensure_typed(h, B_DOFL, M, h->dof_list));
+    // node -> element incidence and the dof rows ------------------------------
     NLFEM_TRY(launch_incidence_count(h, m, s));
     NLFEM_TRY(exclusive_scan(h->nlen, h->ne_ptr, M, h->scan_tmp, h->scan_cap, s));
     NLFEM_TRY(launch_incidence(h, m, s));
@@ -355,26 +362,28 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     while (hcap < 4 * (h->max_S + 8) && hcap < 16384) hcap <<= 1;
     for (;;) {
         h->hcap = hcap;
-        NLFEM_HIP(hipMemsetAsync(h->err, 0, sizeof(int32_t), s));
-        NLFEM_HIP(hipMemsetAsync(h->red + 9, 0, sizeof(unsigned long long), s));
         timing_begin(kPhCsr, s);
         NLFEM_TRY(launch_csr(h, m, false, s));
         timing_end(kPhCsr, s);
-        NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
+        NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedNnz)));
+        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
+        err = (int32_t)(red[kRedErr] & 0xffffffffull);
         if (!(err & kErrRowCap)) break;
         if (hcap >= 16384) return set_error(NLFEM_E_OVERFLOW, "matrix row longer than the symbolic capacity");
         hcap <<= 1;
+        ZeroList z{};
+        z.add(h->err, 1);
+        z.add(h->red + kRedMaxRow, 1);
+        NLFEM_TRY(launch_zero(z, nullptr, s));
     }
-    NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s));
-    NLFEM_HIP(hipMemcpyAsync(&h->nnz_node, h->nptr + M, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipMemcpyAsync(red + 8, h->red + 8, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipStreamSynchronize(s));
-    h->n_dof = (int64_t)red[8];
-    h->max_row = (int64_t)red[9];
+    if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");
+    h->nnz_node = (int64_t)red[kRedNnz];
+    h->n_dof = (int64_t)red[kRedDofs];
+    h->max_row = (int64_t)red[kRedMaxRow];
     NLFEM_TRY(ensure_typed(h, B_NCOL, h->nnz_node, h->ncol));
     timing_begin(kPhCsr, s);
-    NLFEM_TRY(launch_csr(h, m, true, s));
+    NLFEM_TRY(launch_csr(h, m, true, s));   // same rows as the count pass: cannot overflow
     timing_end(kPhCsr, s);
 
     // workspace of the assembly: one result record per unordered pair
@@ -385,10 +394,6 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->far_rec = far_rec;
     NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
     NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
-
-    NLFEM_HIP(hipMemcpyAsync(&err, h->err, sizeof err, hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipStreamSynchronize(s));
-    if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");
     return NLFEM_OK;
 }
 
@@ -620,6 +625,7 @@ void nlfem_pairs_free(nlfem_pairs *h)
     if (!h) return;
     for (auto &b : h->bufs)
         if (b.p) (void)hipFree(b.p);
+    if (h->rb) (void)hipHostFree(h->rb);
     delete h;
 }
 

@@ -109,12 +109,14 @@ __global__ void __launch_bounds__(256) k_geometry(GeoArgs a, RuleArgs r)
     }
 }
 
-__global__ void k_init_reduce(unsigned long long *red)
+// Clears up to kZeroMax ranges of 32-bit words in one launch; with init_red
+// also starts the reduction slots (min slots at the +inf key, the rest 0).
+__global__ void __launch_bounds__(256) k_zero(ZeroList z, unsigned long long *red)
 {
-    if (threadIdx.x < 16) {
-        // min slots start at +inf key, max slots (and counters) at 0
-        red[threadIdx.x] = threadIdx.x < 2 ? ~0ull : 0ull;
-    }
+    if (red && blockIdx.x == 0 && threadIdx.x < kRedSlots) red[threadIdx.x] = threadIdx.x < 2 ? ~0ull : 0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int r = 0; r < z.cnt; ++r)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.n[r]; i += stride) z.p[r][i] = 0u;
 }
 
 __global__ void __launch_bounds__(256) k_incidence_count(int64_t K, int64_t M, const int32_t *E, int64_t *cnt)
@@ -169,9 +171,18 @@ __global__ void __launch_bounds__(256) k_count_dofs(int64_t M, const uint32_t *f
 
 }  // namespace
 
+int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s)
+{
+    int64_t most = 1;
+    for (int r = 0; r < z.cnt; ++r) most = std::max<int64_t>(most, z.n[r]);
+    const unsigned grid = (unsigned)std::min<int64_t>(grid_for(most, 256), 2048);
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, z, init_red);
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
+
 int launch_count_dofs(nlfem_pairs *h, hipStream_t s)
 {
-    NLFEM_HIP(hipMemsetAsync(h->red + 8, 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_count_dofs, dim3(grid_for(h->M, 256)), dim3(256), 0, s, h->M, h->node_flags, h->red + 8,
                        h->dof_list, h->nlen);
     NLFEM_HIP(hipGetLastError());
@@ -190,9 +201,9 @@ int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
     GeoArgs a{h->K, h->M, m->vertices, m->elements, m->labels, h->v0, h->J, h->det,
               h->bary, h->xp, h->node_flags, h->err, h->red};
-    NLFEM_HIP(hipMemsetAsync(h->node_flags, 0, sizeof(uint32_t) * h->M, s));
-    NLFEM_HIP(hipMemsetAsync(h->err, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_init_reduce, dim3(1), dim3(64), 0, s, h->red);
+    ZeroList z{};
+    z.add(h->node_flags, h->M);
+    NLFEM_TRY(launch_zero(z, h->red, s));   // also clears err (a reduction slot)
     hipLaunchKernelGGL(k_geometry, dim3(grid_for(h->K, 256)), dim3(256), 0, s, a, h->rules);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
@@ -200,7 +211,6 @@ int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 
 int launch_incidence_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
-    NLFEM_HIP(hipMemsetAsync(h->nlen, 0, sizeof(int64_t) * (h->M + 1), s));
     hipLaunchKernelGGL(k_incidence_count, dim3(grid_for(h->K, 256)), dim3(256), 0, s, h->K, h->M,
                        m->elements, h->nlen);
     NLFEM_HIP(hipGetLastError());
@@ -209,7 +219,6 @@ int launch_incidence_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 
 int launch_incidence(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
-    NLFEM_HIP(hipMemsetAsync(h->ne_fill, 0, sizeof(int32_t) * h->M, s));
     hipLaunchKernelGGL(k_incidence_fill, dim3(grid_for(h->K, 256)), dim3(256), 0, s, h->K, h->M,
                        m->elements, h->ne_ptr, h->ne_fill, h->ne_list);
     NLFEM_HIP(hipGetLastError());

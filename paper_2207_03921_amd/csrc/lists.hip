@@ -70,6 +70,7 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
             a.snbr[s0 + t] = (int32_t)(kk >> 32);
             a.sflag[s0 + t] = a.sflag_tmp[s0 + src];
             a.smask[s0 + t] = a.smask_tmp[s0 + src];
+            a.srec[s0 + t] = -1;   // set by the work lists and the links
         }
         __syncthreads();
     }

@@ -48,6 +48,29 @@ struct GaussArgs {
     double x[kMaxGauss], w[kMaxGauss];   // on [0, 1]
 };
 
+// Slots of the reduction buffer (u64 each), read back in one copy:
+//   0-3 bounding-box keys, 4-5 radii, 6 largest cell, 7 largest |S(e)|,
+//   8 dof count, 9 longest CSR row, 10 polygon clip bound, 11 CSR nnz,
+//   12-17 totals of the per-element pair counts, 18 error bits (int32)
+enum { kRedMaxCell = 6, kRedMaxS = 7, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
+       kRedTot = 12, kRedErr = 18, kRedSlots = 32 };
+
+// up to kZeroMax ranges of 32-bit words cleared by one launch
+constexpr int kZeroMax = 12;
+struct ZeroList {
+    uint32_t *p[kZeroMax];
+    int64_t n[kZeroMax];
+    int cnt;
+    template <class T>
+    void add(T *ptr, int64_t count)   // count elements of T (a multiple of 4 bytes)
+    {
+        static_assert(sizeof(T) % 4 == 0, "32-bit words");
+        p[cnt] = (uint32_t *)ptr;
+        n[cnt] = count * (int64_t)(sizeof(T) / 4);
+        ++cnt;
+    }
+};
+
 // counters filled by the pair search (ordered pairs per class)
 enum { kCntPairs = 0, kCntFar, kCntVertex, kCntEdge, kCntIdent, kCntLast };
 
@@ -76,7 +99,7 @@ struct nlfem_pairs {
     // grid
     double gx0 = 0, gy0 = 0, gh = 0, far_reach = 0;
     int64_t max_S = 0;
-    int32_t gnx = 0, gny = 0, gr = 2, max_cell = 0;   // gr: neighbour-cell radius
+    int32_t gnx = 0, gny = 0, gr = 2;   // gr: neighbour-cell radius
     int32_t max_clip = 0;        // largest intermediate vertex count of a straddling polygon clip
     // ---- device memory (grow-only buffers, sized by cap_*) ----
     // element geometry (SoA)
@@ -87,7 +110,8 @@ struct nlfem_pairs {
     double2 *xp = nullptr;       // [K * P] outer quadrature points (FP64)
     uint32_t *node_flags = nullptr;  // [M] bit0 vertex of an Omega element, bit1 of an Omega_D one
     int32_t *err = nullptr;      // [1] error bits
-    unsigned long long *red = nullptr;   // [16] bbox keys 0-3, radii 4-5, max cell 6, max |S| 7, dofs 8, max row 9
+    unsigned long long *red = nullptr;   // [kRedSlots] reduction slots (see kRed*)
+    unsigned long long *rb = nullptr;    // [kRedSlots] pinned host copy of red
     unsigned long long *counters = nullptr;  // [kCntLast]
     // node -> element incidence
     int64_t *ne_ptr = nullptr;   // [M + 1]
@@ -183,10 +207,15 @@ __device__ inline int64_t xcd_item(int64_t b, int64_t n)
     return (b % kXcd) * per + b / kXcd;
 }
 
-// scan.hip: out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total.
-int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap,
-                   hipStream_t s);
-int64_t scan_tmp_size(int64_t n);
+// scan.hip: out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total
+// (also written to *total when given; device pointer).  n = 0 gives out[0] = 0.
+int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
+                   int64_t *total = nullptr);
+// the same for nseg segments of `stride` slots (segment k at in + k * stride),
+// totals[k] = total of segment k when totals is given
+int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
+                            int64_t tmp_cap, int64_t *totals, hipStream_t s);
+int64_t scan_tmp_size(int64_t n, int nseg = 1);
 double key_to_double(unsigned long long key);
 
 // geometry.hip
@@ -194,6 +223,7 @@ int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 int launch_incidence(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);   // needs ne_ptr scanned
 int launch_incidence_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 int launch_count_dofs(nlfem_pairs *h, hipStream_t s);   // -> red[8], dof_list, nlen = 0
+int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s);
 // grid + pairs (pairs.hip)
 int launch_cell_count(nlfem_pairs *h, hipStream_t s);
 int launch_cell_fill(nlfem_pairs *h, hipStream_t s);   // also sorts cells, max occupancy -> red[6]

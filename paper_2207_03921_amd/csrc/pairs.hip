@@ -218,9 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     if (cell64 >= ncell) return;
     const int cell = (int)cell64;
     const int64_t cs = a.cell_start[cell], ce = a.cell_start[cell + 1];
-    const int64_t t0 = cs + (int64_t)blockIdx.y * kTE;
-    if (t0 >= ce) return;
-    const int ne = (int)min((int64_t)kTE, ce - t0);
+    if (cs >= ce) return;
     const int cx = cell % a.gnx, cy = cell / a.gnx;
 
     double2 *c_b = (double2 *)smem;                       // [kCH]
@@ -247,135 +245,141 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
         nb_pre[n] = pre;
         nb_n = n;
     }
-    for (int t = threadIdx.x; t < kTE * kLsLast; t += kBlock) {
-        int i = t / kLsLast, kind = t % kLsLast;
-        int64_t v = 0;
-        if (FILL && i < ne) v = a.loff[kind * a.K1 + a.cell_elems[t0 + i]];
-        e_off[t] = v;
-    }
     __syncthreads();
     const int64_t total = nb_pre[nb_n];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     int clipmax = 0;
-
-    for (int64_t c0 = 0; c0 < total; c0 += kCH) {
-        const int nch = (int)min((int64_t)kCH, total - c0);
-        if (threadIdx.x < nch) {
-            const int64_t g = c0 + threadIdx.x;
-            int j = 0;
-            while (nb_pre[j + 1] <= g) ++j;
-            const int32_t f = a.cell_elems[nb_start[j] + (g - nb_pre[j])];
-            const int t = threadIdx.x;
-            c_id[t] = f;
-            c_lab[t] = a.lab[f];
-            c_nd[t] = a.E[3 * (int64_t)f];
-            c_nd[kCH + t] = a.E[3 * (int64_t)f + 1];
-            c_nd[2 * kCH + t] = a.E[3 * (int64_t)f + 2];
-            c_b[t] = a.bary[f];
-            for (int p = 0; p < a.P; ++p) c_xp[p * kCH + t] = a.xp[(int64_t)f * a.P + p];
-            if (POLY)
-                for (int v = 0; v < 3; ++v) {
-                    int32_t n = c_nd[v * kCH + t];
-                    c_v[v * kCH + t] = make_double2(a.V[2 * (int64_t)n], a.V[2 * (int64_t)n + 1]);
-                }
+    // the cell's elements in tiles of kTE
+    for (int64_t t0 = cs; t0 < ce; t0 += kTE) {
+        const int ne = (int)min((int64_t)kTE, ce - t0);
+        for (int t = threadIdx.x; t < kTE * kLsLast; t += kBlock) {
+            int i = t / kLsLast, kind = t % kLsLast;
+            int64_t v = 0;
+            if (FILL && i < ne) v = a.loff[kind * a.K1 + a.cell_elems[t0 + i]];
+            e_off[t] = v;
         }
         __syncthreads();
-        for (int i = wv; i < ne; i += 4) {
-            const int32_t e = a.cell_elems[t0 + i];
-            const int32_t lab_e = a.lab[e];
-            const int32_t ne0 = a.E[3 * (int64_t)e], ne1 = a.E[3 * (int64_t)e + 1],
-                          ne2 = a.E[3 * (int64_t)e + 2];
-            const double2 be = a.bary[e];
-            double2 ve[3];
-            if (POLY) {
-                ve[0] = make_double2(a.V[2 * (int64_t)ne0], a.V[2 * (int64_t)ne0 + 1]);
-                ve[1] = make_double2(a.V[2 * (int64_t)ne1], a.V[2 * (int64_t)ne1 + 1]);
-                ve[2] = make_double2(a.V[2 * (int64_t)ne2], a.V[2 * (int64_t)ne2 + 1]);
+
+        for (int64_t c0 = 0; c0 < total; c0 += kCH) {
+            const int nch = (int)min((int64_t)kCH, total - c0);
+            if (threadIdx.x < nch) {
+                const int64_t g = c0 + threadIdx.x;
+                int j = 0;
+                while (nb_pre[j + 1] <= g) ++j;
+                const int32_t f = a.cell_elems[nb_start[j] + (g - nb_pre[j])];
+                const int t = threadIdx.x;
+                c_id[t] = f;
+                c_lab[t] = a.lab[f];
+                c_nd[t] = a.E[3 * (int64_t)f];
+                c_nd[kCH + t] = a.E[3 * (int64_t)f + 1];
+                c_nd[2 * kCH + t] = a.E[3 * (int64_t)f + 2];
+                c_b[t] = a.bary[f];
+                for (int p = 0; p < a.P; ++p) c_xp[p * kCH + t] = a.xp[(int64_t)f * a.P + p];
+                if (POLY)
+                    for (int v = 0; v < 3; ++v) {
+                        int32_t n = c_nd[v * kCH + t];
+                        c_v[v * kCH + t] = make_double2(a.V[2 * (int64_t)n], a.V[2 * (int64_t)n + 1]);
+                    }
             }
-            int64_t off[kLsLast];
-            for (int k = 0; k < kLsLast; ++k) off[k] = e_off[i * kLsLast + k];
-            for (int jj = 0; jj < nch; jj += 64) {
-                const int j = jj + lane;
-                const bool valid = j < nch;
-                bool inS = false, inP = false, isUF = false;
-                int cls = 0;
-                uint32_t mef = 0, mfe = 0;
-                int32_t f = -1;
-                uint8_t flags = 0;
-                if (valid) {
-                    f = c_id[j];
-                    const int32_t lab_f = c_lab[j];
-                    const bool act = (lab_f == 1 || lab_f == 2) && (lab_e == 1 || lab_f == 1);
-                    const int32_t f0 = c_nd[j], f1 = c_nd[kCH + j], f2 = c_nd[2 * kCH + j];
-                    const int shared = (ne0 == f0) + (ne0 == f1) + (ne0 == f2) + (ne1 == f0) +
-                                       (ne1 == f1) + (ne1 == f2) + (ne2 == f0) + (ne2 == f1) +
-                                       (ne2 == f2);
-                    const bool touch = a.singular && shared > 0;
-                    if (act && !touch) {
-                        const double2 bf = c_b[j];
-                        const double dbx = be.x - bf.x, dby = be.y - bf.y;
-                        if (dbx * dbx + dby * dby <= a.reach2) {
-                            if (!POLY) {
-                                for (int p = 0; p < a.P; ++p) {
-                                    const double2 x = a.xp[(int64_t)e * a.P + p];
-                                    const double dx = x.x - bf.x, dy = x.y - bf.y;
-                                    if (dx * dx + dy * dy <= a.delta2) mef |= kWhole << (2 * p);
-                                }
-                                for (int q = 0; q < a.P; ++q) {
-                                    const double2 x = c_xp[q * kCH + j];
-                                    const double dx = x.x - be.x, dy = x.y - be.y;
-                                    if (dx * dx + dy * dy <= a.delta2) mfe |= kWhole << (2 * q);
-                                }
-                            } else {
-                                double2 vf[3] = {c_v[j], c_v[kCH + j], c_v[2 * kCH + j]};
-                                for (int p = 0; p < a.P; ++p) {
-                                    const double2 x = a.xp[(int64_t)e * a.P + p];
-                                    mef |= poly_status(x.x, x.y, vf, pg, a, &clipmax) << (2 * p);
-                                }
-                                for (int q = 0; q < a.P; ++q) {
-                                    const double2 x = c_xp[q * kCH + j];
-                                    mfe |= poly_status(x.x, x.y, ve, pg, a, &clipmax) << (2 * q);
+            __syncthreads();
+            for (int i = wv; i < ne; i += 4) {
+                const int32_t e = a.cell_elems[t0 + i];
+                const int32_t lab_e = a.lab[e];
+                const int32_t ne0 = a.E[3 * (int64_t)e], ne1 = a.E[3 * (int64_t)e + 1],
+                              ne2 = a.E[3 * (int64_t)e + 2];
+                const double2 be = a.bary[e];
+                double2 ve[3];
+                if (POLY) {
+                    ve[0] = make_double2(a.V[2 * (int64_t)ne0], a.V[2 * (int64_t)ne0 + 1]);
+                    ve[1] = make_double2(a.V[2 * (int64_t)ne1], a.V[2 * (int64_t)ne1 + 1]);
+                    ve[2] = make_double2(a.V[2 * (int64_t)ne2], a.V[2 * (int64_t)ne2 + 1]);
+                }
+                int64_t off[kLsLast];
+                for (int k = 0; k < kLsLast; ++k) off[k] = e_off[i * kLsLast + k];
+                for (int jj = 0; jj < nch; jj += 64) {
+                    const int j = jj + lane;
+                    const bool valid = j < nch;
+                    bool inS = false, inP = false, isUF = false;
+                    int cls = 0;
+                    uint32_t mef = 0, mfe = 0;
+                    int32_t f = -1;
+                    uint8_t flags = 0;
+                    if (valid) {
+                        f = c_id[j];
+                        const int32_t lab_f = c_lab[j];
+                        const bool act = (lab_f == 1 || lab_f == 2) && (lab_e == 1 || lab_f == 1);
+                        const int32_t f0 = c_nd[j], f1 = c_nd[kCH + j], f2 = c_nd[2 * kCH + j];
+                        const int shared = (ne0 == f0) + (ne0 == f1) + (ne0 == f2) + (ne1 == f0) +
+                                           (ne1 == f1) + (ne1 == f2) + (ne2 == f0) + (ne2 == f1) +
+                                           (ne2 == f2);
+                        const bool touch = a.singular && shared > 0;
+                        if (act && !touch) {
+                            const double2 bf = c_b[j];
+                            const double dbx = be.x - bf.x, dby = be.y - bf.y;
+                            if (dbx * dbx + dby * dby <= a.reach2) {
+                                if (!POLY) {
+                                    for (int p = 0; p < a.P; ++p) {
+                                        const double2 x = a.xp[(int64_t)e * a.P + p];
+                                        const double dx = x.x - bf.x, dy = x.y - bf.y;
+                                        if (dx * dx + dy * dy <= a.delta2) mef |= kWhole << (2 * p);
+                                    }
+                                    for (int q = 0; q < a.P; ++q) {
+                                        const double2 x = c_xp[q * kCH + j];
+                                        const double dx = x.x - be.x, dy = x.y - be.y;
+                                        if (dx * dx + dy * dy <= a.delta2) mfe |= kWhole << (2 * q);
+                                    }
+                                } else {
+                                    double2 vf[3] = {c_v[j], c_v[kCH + j], c_v[2 * kCH + j]};
+                                    for (int p = 0; p < a.P; ++p) {
+                                        const double2 x = a.xp[(int64_t)e * a.P + p];
+                                        mef |= poly_status(x.x, x.y, vf, pg, a, &clipmax) << (2 * p);
+                                    }
+                                    for (int q = 0; q < a.P; ++q) {
+                                        const double2 x = c_xp[q * kCH + j];
+                                        mfe |= poly_status(x.x, x.y, ve, pg, a, &clipmax) << (2 * q);
+                                    }
                                 }
                             }
                         }
+                        if (touch) cls = shared;
+                        inS = act && (touch || (mef | mfe) != 0u);
+                        inP = act && (touch || mef != 0u);
+                        flags = (uint8_t)((touch ? 3 : ((mef != 0u) | ((mfe != 0u) << 1))) | (cls << 2));
+                        isUF = inS && !touch && f >= e;
                     }
-                    if (touch) cls = shared;
-                    inS = act && (touch || (mef | mfe) != 0u);
-                    inP = act && (touch || mef != 0u);
-                    flags = (uint8_t)((touch ? 3 : ((mef != 0u) | ((mfe != 0u) << 1))) | (cls << 2));
-                    isUF = inS && !touch && f >= e;
+                    const unsigned long long bS = __ballot(inS);
+                    const unsigned long long bP = __ballot(inP);
+                    const unsigned long long bF = __ballot(isUF);
+                    const unsigned long long bI = __ballot(inS && cls == 3);
+                    const unsigned long long bE = __ballot(inS && cls == 2 && f > e);
+                    const unsigned long long bV = __ballot(inS && cls == 1 && f > e);
+                    if (FILL && inS) {
+                        const int64_t o = off[kLsS] + __popcll(bS & lt);
+                        a.snbr[o] = f;
+                        a.sflag[o] = flags;
+                        a.smask[o] = make_uint2(mef, mfe);
+                    }
+                    off[kLsS] += __popcll(bS);
+                    off[kLsP] += __popcll(bP);
+                    off[kLsUF] += __popcll(bF);
+                    off[kLsUI] += __popcll(bI);
+                    off[kLsUE] += __popcll(bE);
+                    off[kLsUV] += __popcll(bV);
                 }
-                const unsigned long long bS = __ballot(inS);
-                const unsigned long long bP = __ballot(inP);
-                const unsigned long long bF = __ballot(isUF);
-                const unsigned long long bI = __ballot(inS && cls == 3);
-                const unsigned long long bE = __ballot(inS && cls == 2 && f > e);
-                const unsigned long long bV = __ballot(inS && cls == 1 && f > e);
-                if (FILL && inS) {
-                    const int64_t o = off[kLsS] + __popcll(bS & lt);
-                    a.snbr[o] = f;
-                    a.sflag[o] = flags;
-                    a.smask[o] = make_uint2(mef, mfe);
-                }
-                off[kLsS] += __popcll(bS);
-                off[kLsP] += __popcll(bP);
-                off[kLsUF] += __popcll(bF);
-                off[kLsUI] += __popcll(bI);
-                off[kLsUE] += __popcll(bE);
-                off[kLsUV] += __popcll(bV);
+                if (lane == 0)
+                    for (int k = 0; k < kLsLast; ++k) e_off[i * kLsLast + k] = off[k];
             }
-            if (lane == 0)
-                for (int k = 0; k < kLsLast; ++k) e_off[i * kLsLast + k] = off[k];
+            __syncthreads();
+        }
+        if (!FILL) {
+            for (int t = threadIdx.x; t < ne * kLsLast; t += kBlock) {
+                int i = t / kLsLast, kind = t % kLsLast;
+                a.lcnt[kind * a.K1 + a.cell_elems[t0 + i]] = e_off[t];
+                if (kind == kLsS) atomicMax(a.maxS, (unsigned long long)e_off[t]);
+            }
         }
         __syncthreads();
-    }
-    if (!FILL) {
-        for (int t = threadIdx.x; t < ne * kLsLast; t += kBlock) {
-            int i = t / kLsLast, kind = t % kLsLast;
-            a.lcnt[kind * a.K1 + a.cell_elems[t0 + i]] = e_off[t];
-            if (kind == kLsS) atomicMax(a.maxS, (unsigned long long)e_off[t]);
-        }
     }
     if (POLY && clipmax > 0) atomicMax(a.maxClip, (unsigned long long)clipmax);
 }
@@ -453,7 +457,6 @@ CellArgs cell_args(nlfem_pairs *h)
 int launch_cell_count(nlfem_pairs *h, hipStream_t s)
 {
     const int64_t ncell = (int64_t)h->gnx * h->gny;
-    NLFEM_HIP(hipMemsetAsync(h->cell_cnt, 0, sizeof(int64_t) * (ncell + 1), s));
     hipLaunchKernelGGL(k_cell_count, dim3(grid_for(h->K, 256)), dim3(256), 0, s, cell_args(h));
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
@@ -462,9 +465,7 @@ int launch_cell_count(nlfem_pairs *h, hipStream_t s)
 int launch_cell_fill(nlfem_pairs *h, hipStream_t s)
 {
     const int64_t ncell = (int64_t)h->gnx * h->gny;
-    NLFEM_HIP(hipMemsetAsync(h->cell_fill, 0, sizeof(int32_t) * ncell, s));
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(h->K, 256)), dim3(256), 0, s, cell_args(h));
-    NLFEM_HIP(hipMemsetAsync(h->red + 6, 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, 256)), dim3(256), 0, s, ncell, h->cell_start,
                        h->cell_elems, h->red + 6);
     NLFEM_HIP(hipGetLastError());
@@ -508,11 +509,9 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     a.snbr = h->snbr_tmp;
     a.sflag = h->sflag_tmp;
     a.smask = h->smask_tmp;
-    const int slices = (h->max_cell + kTE - 1) / kTE;
-    if (slices <= 0) return NLFEM_OK;
     const size_t lds = sizeof(double2) * (size_t)kCH * (1 + a.P + (a.poly ? 3 : 0)) +
                        sizeof(int64_t) * kTE * kLsLast + sizeof(int32_t) * kCH * 5;
-    dim3 grid(xcd_grid(ncell, INT32_MAX), (unsigned)slices);
+    dim3 grid(xcd_grid(ncell, INT32_MAX));
     if (a.poly) {
         if (fill) hipLaunchKernelGGL((k_pairs<true, true>), grid, dim3(kBlock), lds, s, a, h->poly);
         else hipLaunchKernelGGL((k_pairs<false, true>), grid, dim3(kBlock), lds, s, a, h->poly);

@@ -1,5 +1,7 @@
 // Exclusive prefix sum of int64 counts (three passes: block sums, scan of the
 // block sums, block-local scan plus offset).
+#include <algorithm>
+
 #include "nlfem_internal.h"
 
 namespace nlfem {
@@ -27,72 +29,90 @@ __device__ int64_t block_exclusive(int64_t v, int64_t *sh, int64_t *total)
     return incl - v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_block_sums(const int64_t *in, int64_t n, int64_t *sums)
+// Segments k = 0..nseg-1 of `stride` slots each; the first n slots of a
+// segment are scanned.  Block b covers tile b % bps of segment b / bps.
+
+__global__ void __launch_bounds__(kBlock) k_block_sums(const int64_t *in, int64_t n, int64_t stride, int64_t bps,
+                                                       int64_t *sums)
 {
     __shared__ int64_t sh[kBlock];
-    int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * kItems;
+    const int64_t seg = blockIdx.x / bps, lb = blockIdx.x % bps;
+    const int64_t *x = in + seg * stride;
+    const int64_t base = lb * kTile + threadIdx.x * kItems;
     int64_t s = 0;
     for (int i = 0; i < kItems; ++i)
-        if (base + i < n) s += in[base + i];
+        if (base + i < n) s += x[base + i];
     int64_t tot;
     block_exclusive(s, sh, &tot);
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+    if (threadIdx.x == 0) sums[seg * (bps + 1) + lb] = tot;
 }
 
-// single block: exclusive scan of nb block sums in place, total in sums[nb]
-__global__ void __launch_bounds__(kBlock) k_scan_sums(int64_t *sums, int64_t nb)
+// one block per segment: exclusive scan of its bps block sums in place,
+// total in sums[bps] and, if given, in totals[seg]
+__global__ void __launch_bounds__(kBlock) k_scan_sums(int64_t *sums, int64_t bps, int64_t *totals)
 {
     __shared__ int64_t sh[kBlock];
+    int64_t *x = sums + blockIdx.x * (bps + 1);
     int64_t carry = 0;
-    for (int64_t base = 0; base < nb; base += kBlock) {
-        int64_t i = base + threadIdx.x;
-        int64_t v = i < nb ? sums[i] : 0;
+    for (int64_t base = 0; base < bps; base += kBlock) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < bps ? x[i] : 0;
         int64_t tot;
-        int64_t ex = block_exclusive(v, sh, &tot);
-        if (i < nb) sums[i] = carry + ex;
+        const int64_t ex = block_exclusive(v, sh, &tot);
+        if (i < bps) x[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) sums[nb] = carry;
+    if (threadIdx.x == 0) {
+        x[bps] = carry;
+        if (totals) totals[blockIdx.x] = carry;
+    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t *in, int64_t *out, int64_t n,
-                                                       const int64_t *sums, int64_t nb)
+__global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t *in, int64_t *out, int64_t n, int64_t stride,
+                                                       int64_t bps, const int64_t *sums)
 {
     __shared__ int64_t sh[kBlock];
-    int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * kItems;
+    const int64_t seg = blockIdx.x / bps, lb = blockIdx.x % bps;
+    const int64_t *x = in + seg * stride;
+    int64_t *y = out + seg * stride;
+    const int64_t *sm = sums + seg * (bps + 1);
+    const int64_t base = lb * kTile + threadIdx.x * kItems;
     int64_t v[kItems];
     int64_t s = 0;
     for (int i = 0; i < kItems; ++i) {
-        v[i] = base + i < n ? in[base + i] : 0;
+        v[i] = base + i < n ? x[base + i] : 0;
         s += v[i];
     }
     int64_t tot;
-    int64_t ex = block_exclusive(s, sh, &tot) + sums[blockIdx.x];
+    int64_t ex = block_exclusive(s, sh, &tot) + sm[lb];
     for (int i = 0; i < kItems; ++i) {
-        if (base + i < n) out[base + i] = ex;
+        if (base + i < n) y[base + i] = ex;
         ex += v[i];
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = sums[nb];
+    if (lb == bps - 1 && threadIdx.x == 0) y[n] = sm[bps];
 }
 
 }  // namespace
 
-int64_t scan_tmp_size(int64_t n) { return (n + kTile - 1) / kTile + 1; }
+int64_t scan_tmp_size(int64_t n, int nseg) { return (int64_t)nseg * ((n + kTile - 1) / kTile + 1) + 1; }
 
-int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap,
-                   hipStream_t s)
+int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
+                            int64_t tmp_cap, int64_t *totals, hipStream_t s)
 {
-    if (n <= 0) {
-        NLFEM_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
-        return NLFEM_OK;
-    }
-    int64_t nb = (n + kTile - 1) / kTile;
-    if (nb + 1 > tmp_cap) return set_error(NLFEM_E_OVERFLOW, "scan workspace too small");
-    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, tmp, nb);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, tmp, nb);
+    const int64_t bps = std::max<int64_t>((n + kTile - 1) / kTile, 1);
+    if (nseg * (bps + 1) > tmp_cap) return set_error(NLFEM_E_OVERFLOW, "scan workspace too small");
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)(nseg * bps)), dim3(kBlock), 0, s, in, n, stride, bps, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nseg), dim3(kBlock), 0, s, tmp, bps, totals);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(nseg * bps)), dim3(kBlock), 0, s, in, out, n, stride, bps,
+                       (const int64_t *)tmp);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
+}
+
+int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
+                   int64_t *total)
+{
+    return exclusive_scan_segments(in, out, n, 1, n + 1, tmp, tmp_cap, total, s);
 }
 
 }  // namespace nlfem
