@@ -18,7 +18,7 @@ enum Buf : int {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
-    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_LAST
+    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_LAST
 };
 static_assert(B_LAST <= (int)(sizeof(nlfem_pairs::bufs) / sizeof(nlfem_pairs::bufs[0])), "too few buffer slots");
 
@@ -300,6 +300,11 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         z.add(h->red + kRedMaxCell, kRedErr - kRedMaxCell);   // slots 6..17, keeps the error bits
         NLFEM_TRY(launch_zero(z, nullptr, s));
     }
+    // node -> element incidence and the dof rows ------------------------------
+    NLFEM_TRY(launch_incidence_count(h, m, s));
+    NLFEM_TRY(exclusive_scan(h->nlen, h->ne_ptr, M, h->scan_tmp, h->scan_cap, s));
+    NLFEM_TRY(launch_incidence(h, m, s));
+    NLFEM_TRY(launch_count_dofs(h, s));
     NLFEM_TRY(launch_cell_count(h, s));
     NLFEM_TRY(exclusive_scan(h->cell_cnt, h->cell_start, ncell, h->scan_tmp, h->scan_cap, s));
     NLFEM_TRY(launch_cell_fill(h, s));
@@ -309,7 +314,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(launch_pairs(h, m, false, s));
     timing_end(kPhPairs, s);
     NLFEM_TRY(exclusive_scan_segments(h->lcnt, h->loff, K, kLsLast, K1, h->scan_tmp, h->scan_cap,
-                                      (int64_t *)(h->red + kRedTot), s));
+                                      (int64_t *)(h->red + kRedTot), s, (int64_t *)(h->red + kRedSegMax)));
     NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipStreamSynchronize(s));
     int64_t tot[kLsLast];
@@ -322,7 +327,8 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->nUTc[1] = tot[kLsUE];
     h->nUTc[2] = tot[kLsUV];
     h->nUT = h->nUTc[0] + h->nUTc[1] + h->nUTc[2];
-    h->max_S = (int64_t)red[kRedMaxS];
+    h->max_S = (int64_t)red[kRedSegMax + kLsS];
+    h->n_dof = (int64_t)red[kRedDofs];
     h->n_pairs = h->nP;
     h->n_ident = h->nUTc[0];
     h->n_edge = 2 * h->nUTc[1];
@@ -337,6 +343,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_SFLAG, h->nS, h->sflag));
     NLFEM_TRY(ensure_typed(h, B_SMASK, h->nS, h->smask));
     NLFEM_TRY(ensure_typed(h, B_SREC, h->nS, h->srec));
+    NLFEM_TRY(ensure_typed(h, B_SNODE, h->nS, h->snode));
     NLFEM_TRY(ensure_typed(h, B_UE, h->nUF, h->ue));
     NLFEM_TRY(ensure_typed(h, B_UF, h->nUF, h->uf));
     NLFEM_TRY(ensure_typed(h, B_UMEF, h->nUF, h->um_ef));
@@ -351,21 +358,17 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(launch_worklists(h, m, s));
     timing_end(kPhLists, s);
 
-    // node -> element incidence and the dof rows ------------------------------
-    NLFEM_TRY(launch_incidence_count(h, m, s));
-    NLFEM_TRY(exclusive_scan(h->nlen, h->ne_ptr, M, h->scan_tmp, h->scan_cap, s));
-    NLFEM_TRY(launch_incidence(h, m, s));
-    NLFEM_TRY(launch_count_dofs(h, s));
-
     // CSR pattern -------------------------------------------------------------
     int hcap = 64;
     while (hcap < 4 * (h->max_S + 8) && hcap < 16384) hcap <<= 1;
     for (;;) {
         h->hcap = hcap;
+        NLFEM_TRY(ensure_typed(h, B_CSRSTAGE, std::max<int64_t>(h->n_dof, 1) * csr_slot(hcap), h->csr_stage));
         timing_begin(kPhCsr, s);
-        NLFEM_TRY(launch_csr(h, m, false, s));
+        NLFEM_TRY(launch_csr_rows(h, m, s));
         timing_end(kPhCsr, s);
-        NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedNnz)));
+        NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedNnz),
+                                 (int64_t *)(h->red + kRedMaxRow)));
         NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
         err = (int32_t)(red[kRedErr] & 0xffffffffull);
@@ -383,7 +386,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->max_row = (int64_t)red[kRedMaxRow];
     NLFEM_TRY(ensure_typed(h, B_NCOL, h->nnz_node, h->ncol));
     timing_begin(kPhCsr, s);
-    NLFEM_TRY(launch_csr(h, m, true, s));   // same rows as the count pass: cannot overflow
+    NLFEM_TRY(launch_csr_pack(h, s));
     timing_end(kPhCsr, s);
 
     // workspace of the assembly: one result record per unordered pair

@@ -165,7 +165,7 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     r.ne_list = h->ne_list;
     r.E = m->elements;
     r.sptr = h->loff + (int64_t)kLsS * (h->K + 1);
-    r.snbr = h->snbr;
+    r.snode = h->snode;
     r.sflag = h->sflag;
     r.srec = h->srec;
     r.far_rec = h->far_rec;

@@ -681,7 +681,7 @@ struct RowArgs {
     const int32_t *ne_list;
     const int32_t *E;
     const int64_t *sptr;
-    const int32_t *snbr;
+    const int4 *snode;       // (f, vertices of f) per neighbour-list entry
     const uint8_t *sflag;
     const int32_t *srec;
     const void *far_rec;
@@ -911,6 +911,7 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                     const int flat = base + k * 64 + lane;
                     act[k] = flat < total;
                     fe[k] = 0;
+                    nf0[k] = nf1[k] = nf2[k] = -1;
                     uu[k] = -1;
                     cl[k] = 0;
                     qq[k] = 0;
@@ -924,14 +925,17 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                         }
                         qq[k] = lo;
                         const int64_t t = qs[lo] + (flat - pre[lo]);
-                        fe[k] = a.snbr[t];
+                        const int4 sn = a.snode[t];
+                        fe[k] = sn.x;
+                        nf0[k] = sn.y;
+                        nf1[k] = sn.z;
+                        nf2[k] = sn.w;
                         cl[k] = (a.sflag[t] >> 2) & 3;
                         uu[k] = a.srec[t];
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < kRowU; ++k) {
-                    nf0[k] = nf1[k] = nf2[k] = -1;
                     if (!act[k]) continue;
                     if (uu[k] < 0 || uu[k] >= (cl[k] == 0 ? a.n_far : a.n_touch)) {
                         bad = true;
@@ -939,9 +943,6 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                         continue;
                     }
                     const int32_t f = fe[k];
-                    nf0[k] = a.E[3 * (int64_t)f];
-                    nf1[k] = a.E[3 * (int64_t)f + 1];
-                    nf2[k] = a.E[3 * (int64_t)f + 2];
                     if (cl[k] == 0) {
                         // row loc of X (e first) or column loc (e second); the
                         // self pair stores X + X^T

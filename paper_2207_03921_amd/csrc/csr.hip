@@ -4,29 +4,33 @@
 // interacting pairs that have i as a vertex.  With the symmetric neighbour
 // list S(e) this is the union over the elements e containing i (those with
 // S(e) non-empty) of nodes(e) and of nodes(f) for f in S(e).  One wave per
-// row inserts these ids into an open-addressing hash set in LDS, then
-// compacts and bitonic-sorts the unique ids.
+// row inserts these ids into an open-addressing hash set in LDS, compacts and
+// bitonic-sorts the unique ids and writes them to a row slot of a staging
+// buffer; after the scan of the row lengths a copy kernel packs the slots.
+// The entries of all the row's elements are handled as one flat range: each
+// lane loads kCsrU neighbour ids and their vertices before it inserts any,
+// so the dependent loads of a step overlap.
 #include "nlfem_internal.h"
 
 namespace nlfem {
 namespace {
 
 constexpr int kEmpty = -1;
+constexpr int kCsrQ = 64;    // elements around a node per batch
+constexpr int kCsrU = 4;     // entries per lane per step
 
 struct CsrArgs {
-    int64_t K1, M;
     const int32_t *E;
     const int32_t *rows;                   // dof nodes
     const unsigned long long *nrows;       // [1] their number
     const int64_t *ne_ptr;
     const int32_t *ne_list;
     const int64_t *sptr;     // [K + 1]
-    const int32_t *snbr;
+    const int4 *snode;       // (f, vertices of f) per neighbour-list entry
     int32_t hcap;            // power of two
-    int64_t *nlen;           // count pass
-    unsigned long long *max_row;
-    const int64_t *nptr;     // fill pass
-    int32_t *ncol;
+    int32_t cap;             // slot length of the staging buffer (3/4 hcap)
+    int32_t *stage;          // [n_dof][cap]
+    int64_t *nlen;
     int32_t *err;
 };
 
@@ -34,7 +38,7 @@ __device__ inline bool hash_insert(int32_t *tab, int32_t mask, int32_t key, bool
 {
     uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
     for (int probe = 0; probe <= mask; ++probe) {
-        int32_t old = atomicCAS(&tab[h], kEmpty, key);
+        const int32_t old = atomicCAS(&tab[h], kEmpty, key);
         if (old == kEmpty) return true;
         if (old == key) return false;
         h = (h + 1) & (uint32_t)mask;
@@ -49,63 +53,103 @@ __device__ inline int wave_sum(int v)
     return v;
 }
 
-template <bool FILL>
-__global__ void __launch_bounds__(64) k_csr(CsrArgs a)
+// Each wave of a workgroup owns one row and its LDS; the waves never wait
+// for each other.
+__global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
 {
-    extern __shared__ int32_t tab[];   // [hcap] hash table, then [hcap] sort buffer
+    extern __shared__ int32_t dyn[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t *tab = dyn + (size_t)w * 2 * a.hcap;   // [hcap] hash table, then [hcap] sort buffer
     int32_t *buf = tab + a.hcap;
-    const int lane = threadIdx.x;
+    __shared__ int64_t qs_w[kWavesPerRowBlock][kCsrQ];
+    __shared__ int32_t pre_w[kWavesPerRowBlock][kCsrQ + 1];
+    int64_t *qs = qs_w[w];
+    int32_t *pre = pre_w[w];
+    const int32_t mask = a.hcap - 1;
     const int64_t nrows = (int64_t)*a.nrows;
-    for (int64_t b = blockIdx.x; b < xcd_span(nrows); b += gridDim.x) {
-        const int64_t item = xcd_item(b, nrows);
+    const int64_t ngroups = (nrows + kWavesPerRowBlock - 1) / kWavesPerRowBlock;
+    for (int64_t b = blockIdx.x; b < xcd_span(ngroups); b += gridDim.x) {
+        const int64_t item = xcd_item(b, ngroups) * kWavesPerRowBlock + w;
         if (item >= nrows) continue;
         const int64_t i = a.rows[item];
         for (int t = lane; t < a.hcap; t += 64) tab[t] = kEmpty;
-        __syncthreads();
-        const int32_t mask = a.hcap - 1;
+        wave_sync();
         bool overflow = false;
         int added = 0;
-        for (int64_t q = a.ne_ptr[i]; q < a.ne_ptr[i + 1]; ++q) {
-            const int32_t e = a.ne_list[q];
-            const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
-            if (s1 == s0) continue;
-            if (lane < 3) added += hash_insert(tab, mask, a.E[3 * (int64_t)e + lane], &overflow);
-            for (int64_t t = s0 + lane; t < s1; t += 64) {
-                const int32_t f = a.snbr[t];
-                added += hash_insert(tab, mask, a.E[3 * (int64_t)f], &overflow);
-                added += hash_insert(tab, mask, a.E[3 * (int64_t)f + 1], &overflow);
-                added += hash_insert(tab, mask, a.E[3 * (int64_t)f + 2], &overflow);
+        const int64_t q0 = a.ne_ptr[i], q1 = a.ne_ptr[i + 1];
+        for (int64_t qb = q0; qb < q1; qb += kCsrQ) {
+            const int nq = (int)min((int64_t)kCsrQ, q1 - qb);
+            int cnt = 0;
+            if (lane < nq) {
+                const int32_t e = a.ne_list[qb + lane];
+                const int64_t s0 = a.sptr[e];
+                cnt = (int)(a.sptr[e + 1] - s0);
+                qs[lane] = s0;
+                if (cnt > 0) {   // elements of interacting pairs contribute their own nodes
+                    const int32_t v0 = a.E[3 * (int64_t)e], v1 = a.E[3 * (int64_t)e + 1], v2 = a.E[3 * (int64_t)e + 2];
+                    added += hash_insert(tab, mask, v0, &overflow);
+                    added += hash_insert(tab, mask, v1, &overflow);
+                    added += hash_insert(tab, mask, v2, &overflow);
+                }
             }
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            if (lane < nq) pre[lane + 1] = incl;
+            if (lane == 0) pre[0] = 0;
+            const int total = __shfl(incl, nq - 1);
+            wave_sync();
+            for (int base = 0; base < total; base += 64 * kCsrU) {
+                int4 sn[kCsrU];
+#pragma unroll
+                for (int k = 0; k < kCsrU; ++k) {
+                    const int flat = base + k * 64 + lane;
+                    sn[k] = make_int4(-1, -1, -1, -1);
+                    if (flat < total) {
+                        int lo = 0, hi = nq;   // pre[lo] <= flat < pre[hi]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (pre[mid] <= flat) lo = mid;
+                            else hi = mid;
+                        }
+                        sn[k] = a.snode[qs[lo] + (flat - pre[lo])];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kCsrU; ++k) {
+                    if (sn[k].x < 0) continue;
+                    added += hash_insert(tab, mask, sn[k].y, &overflow);
+                    added += hash_insert(tab, mask, sn[k].z, &overflow);
+                    added += hash_insert(tab, mask, sn[k].w, &overflow);
+                }
+            }
+            wave_sync();
         }
         const int n = wave_sum(added);
-        const bool full = __any(overflow) || 4 * n > 3 * a.hcap;
+        const bool full = __any(overflow) || n > a.cap;
         if (full) {
-            if (lane == 0) atomicOr(a.err, kErrRowCap);
-            if (!FILL && lane == 0) a.nlen[i] = 0;
-            __syncthreads();
-            continue;
-        }
-        if (!FILL) {
             if (lane == 0) {
-                a.nlen[i] = n;
-                atomicMax(a.max_row, (unsigned long long)n);
+                atomicOr(a.err, kErrRowCap);
+                a.nlen[i] = 0;
             }
-            __syncthreads();
+            wave_sync();
             continue;
         }
-        __syncthreads();
-        // compact in slot order
-        int base = 0;
+        // compact in slot order, then sort
+        int basec = 0;
         for (int t0 = 0; t0 < a.hcap; t0 += 64) {
             const int32_t v = tab[t0 + lane];
-            const unsigned long long b = __ballot(v != kEmpty);
-            if (v != kEmpty) buf[base + __popcll(b & ((1ull << lane) - 1ull))] = v;
-            base += __popcll(b);
+            const unsigned long long bb = __ballot(v != kEmpty);
+            if (v != kEmpty) buf[basec + __popcll(bb & ((1ull << lane) - 1ull))] = v;
+            basec += __popcll(bb);
         }
         int n2 = 1;
         while (n2 < n) n2 <<= 1;
         for (int t = n + lane; t < n2; t += 64) buf[t] = 0x7fffffff;
-        __syncthreads();
+        wave_sync();
         for (int k = 2; k <= n2; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
                 for (int t = lane; t < n2; t += 64) {
@@ -119,12 +163,28 @@ __global__ void __launch_bounds__(64) k_csr(CsrArgs a)
                         }
                     }
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
-        const int64_t o = a.nptr[i];
-        for (int t = lane; t < n; t += 64) a.ncol[o + t] = buf[t];
-        __syncthreads();
+        int32_t *out = a.stage + item * (int64_t)a.cap;
+        for (int t = lane; t < n; t += 64) out[t] = buf[t];
+        if (lane == 0) a.nlen[i] = n;   // the longest row comes from the scan of nlen
+        wave_sync();
+    }
+}
+
+// packs the staged rows: ncol[nptr[i] ...] = stage[item][0 .. nlen[i])
+__global__ void __launch_bounds__(256) k_csr_pack(const int32_t *rows, const unsigned long long *nrows,
+                                                  const int64_t *nptr, const int32_t *stage, int32_t cap,
+                                                  int32_t *ncol)
+{
+    const int64_t nr = (int64_t)*nrows;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t item = (int64_t)blockIdx.x * 4 + w; item < nr; item += (int64_t)gridDim.x * 4) {
+        const int64_t i = rows[item];
+        const int64_t o = nptr[i], len = nptr[i + 1] - o;
+        const int32_t *src = stage + item * (int64_t)cap;
+        for (int64_t t = lane; t < len; t += 64) ncol[o + t] = src[t];
     }
 }
 
@@ -212,15 +272,23 @@ __global__ void __launch_bounds__(64) k_export(int64_t K, const int64_t *sptr, c
 
 }  // namespace
 
-int launch_csr(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
+int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
-    CsrArgs a{h->K + 1, h->M, m->elements, h->dof_list, h->red + 8, h->ne_ptr, h->ne_list,
-              h->loff + (int64_t)kLsS * (h->K + 1), h->snbr, h->hcap, h->nlen, h->red + 9, h->nptr, h->ncol,
+    CsrArgs a{m->elements, h->dof_list, h->red + kRedDofs, h->ne_ptr, h->ne_list,
+              h->loff + (int64_t)kLsS * (h->K + 1), h->snode, h->hcap, csr_slot(h->hcap), h->csr_stage, h->nlen,
               h->err};
-    const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap;
-    const unsigned grid = xcd_grid(h->M);
-    if (fill) hipLaunchKernelGGL(k_csr<true>, dim3(grid), dim3(64), lds, s, a);
-    else hipLaunchKernelGGL(k_csr<false>, dim3(grid), dim3(64), lds, s, a);
+    const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap * kWavesPerRowBlock;
+    hipLaunchKernelGGL(k_csr_rows, dim3(xcd_grid((h->M + kWavesPerRowBlock - 1) / kWavesPerRowBlock)),
+                       dim3(64 * kWavesPerRowBlock), lds, s, a);
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
+
+int launch_csr_pack(nlfem_pairs *h, hipStream_t s)
+{
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(h->n_dof, 4), 1 << 16));
+    hipLaunchKernelGGL(k_csr_pack, dim3(grid), dim3(256), 0, s, h->dof_list, h->red + kRedDofs, h->nptr,
+                       h->csr_stage, csr_slot(h->hcap), h->ncol);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

@@ -93,19 +93,42 @@ __global__ void __launch_bounds__(256) k_geometry(GeoArgs a, RuleArgs r)
             }
         }
     }
+    // one set of atomics per workgroup (same-address atomics from every
+    // wave would serialise)
+    __shared__ double part[4][6];
     bx = wave_min(bx);
     by = wave_min(by);
     Bx = wave_max(Bx);
     By = wave_max(By);
     rq = wave_max(rq);
     rv = wave_max(rv);
-    if ((threadIdx.x & 63) == 0 && Bx >= bx) {
-        atomicMin(&a.red[0], dkey(bx));
-        atomicMin(&a.red[1], dkey(by));
-        atomicMax(&a.red[2], dkey(Bx));
-        atomicMax(&a.red[3], dkey(By));
-        atomicMax(&a.red[4], dkey(rq));
-        atomicMax(&a.red[5], dkey(rv));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        part[w][0] = bx;
+        part[w][1] = by;
+        part[w][2] = Bx;
+        part[w][3] = By;
+        part[w][4] = rq;
+        part[w][5] = rv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x >> 6); ++v) {
+            bx = fmin(bx, part[v][0]);
+            by = fmin(by, part[v][1]);
+            Bx = fmax(Bx, part[v][2]);
+            By = fmax(By, part[v][3]);
+            rq = fmax(rq, part[v][4]);
+            rv = fmax(rv, part[v][5]);
+        }
+        if (Bx >= bx) {
+            atomicMin(&a.red[0], dkey(bx));
+            atomicMin(&a.red[1], dkey(by));
+            atomicMax(&a.red[2], dkey(Bx));
+            atomicMax(&a.red[3], dkey(By));
+            atomicMax(&a.red[4], dkey(rq));
+            atomicMax(&a.red[5], dkey(rv));
+        }
     }
 }
 

@@ -29,6 +29,8 @@ struct ListArgs {
     uint8_t *sflag;
     uint2 *smask;
     int32_t *srec;
+    int4 *snode;
+    const int32_t *E;
     int32_t *ue, *uf;
     uint32_t *um_ef, *um_fe;
     int32_t *te, *tf;
@@ -71,6 +73,8 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
             a.sflag[s0 + t] = a.sflag_tmp[s0 + src];
             a.smask[s0 + t] = a.smask_tmp[s0 + src];
             a.srec[s0 + t] = -1;   // set by the work lists and the links
+            const int32_t f = (int32_t)(kk >> 32);
+            a.snode[s0 + t] = make_int4(f, a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]);
         }
         __syncthreads();
     }
@@ -171,6 +175,8 @@ ListArgs list_args(nlfem_pairs *h)
     a.sflag = h->sflag;
     a.smask = h->smask;
     a.srec = h->srec;
+    a.snode = h->snode;
+    a.E = h->mesh_elements;
     a.ue = h->ue;
     a.uf = h->uf;
     a.um_ef = h->um_ef;

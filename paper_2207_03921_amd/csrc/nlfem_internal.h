@@ -51,9 +51,10 @@ struct GaussArgs {
 // Slots of the reduction buffer (u64 each), read back in one copy:
 //   0-3 bounding-box keys, 4-5 radii, 6 largest cell, 7 largest |S(e)|,
 //   8 dof count, 9 longest CSR row, 10 polygon clip bound, 11 CSR nnz,
-//   12-17 totals of the per-element pair counts, 18 error bits (int32)
-enum { kRedMaxCell = 6, kRedMaxS = 7, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
-       kRedTot = 12, kRedErr = 18, kRedSlots = 32 };
+//   12-17 totals of the per-element pair counts, 18 error bits (int32),
+//   19-24 largest per-element pair counts (19: largest |S(e)|)
+enum { kRedMaxCell = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
+       kRedTot = 12, kRedErr = 18, kRedSegMax = 19, kRedSlots = 32 };
 
 // up to kZeroMax ranges of 32-bit words cleared by one launch
 constexpr int kZeroMax = 12;
@@ -133,6 +134,7 @@ struct nlfem_pairs {
     uint8_t *sflag = nullptr;    // [nS] bit0 (e,f) in P, bit1 (f,e) in P, bits 2-3 class
     uint2 *smask = nullptr;      // [nS] 2-bit point status: x = e's points vs f, y = f's points vs e
     int32_t *srec = nullptr;     // [nS] record of the unordered pair (far or touching list)
+    int4 *snode = nullptr;       // [nS] (f, the three vertices of f): one load for the row kernels
     int32_t *snbr_tmp = nullptr; // unsorted lists written by the pair search
     uint8_t *sflag_tmp = nullptr;
     uint2 *smask_tmp = nullptr;
@@ -147,6 +149,7 @@ struct nlfem_pairs {
     int64_t *nlen = nullptr;     // [M + 1]
     int64_t *nptr = nullptr;     // [M + 1]
     int32_t *ncol = nullptr;     // [nnz_node]
+    int32_t *csr_stage = nullptr;   // [n_dof][csr_slot(hcap)] sorted rows before packing
     int64_t max_row = 0;         // longest node row
     // per-pair results of the assembly (workspace held by the handle)
     void *far_rec = nullptr;     // [nUF][far_stride] FP32 (mixed) or FP64
@@ -180,6 +183,17 @@ int hip_error(hipError_t e, const char *what);
         if (_e != hipSuccess) return ::nlfem::hip_error(_e, #call);   \
     } while (0)
 
+// rows of the row kernels per workgroup: one wave each, synchronised per wave
+constexpr int kWavesPerRowBlock = 4;
+
+// makes the LDS writes of the wave's lanes visible to its other lanes
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 #define NLFEM_TRY(x)                     \
     do {                                 \
         int _rc = (x);                   \
@@ -209,12 +223,13 @@ __device__ inline int64_t xcd_item(int64_t b, int64_t n)
 
 // scan.hip: out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total
 // (also written to *total when given; device pointer).  n = 0 gives out[0] = 0.
+// *maxval (device) receives the largest input when given.
 int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
-                   int64_t *total = nullptr);
+                   int64_t *total = nullptr, int64_t *maxval = nullptr);
 // the same for nseg segments of `stride` slots (segment k at in + k * stride),
-// totals[k] = total of segment k when totals is given
+// totals[k] = total and maxes[k] = largest input of segment k when given
 int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
-                            int64_t tmp_cap, int64_t *totals, hipStream_t s);
+                            int64_t tmp_cap, int64_t *totals, hipStream_t s, int64_t *maxes = nullptr);
 int64_t scan_tmp_size(int64_t n, int nseg = 1);
 double key_to_double(unsigned long long key);
 
@@ -232,7 +247,10 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
 int launch_sort_lists(nlfem_pairs *h, hipStream_t s);
 int launch_worklists(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 // csr.hip
-int launch_csr(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
+// staged rows: one slot of csr_slot(hcap) ids per dof row
+inline int32_t csr_slot(int32_t hcap) { return hcap / 4 * 3; }
+int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);   // -> nlen, stage, max row
+int launch_csr_pack(nlfem_pairs *h, hipStream_t s);                        // stage -> ncol
 int launch_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
 int launch_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls, hipStream_t s);
 // assemble.hip

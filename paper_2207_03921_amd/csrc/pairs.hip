@@ -47,7 +47,6 @@ struct PairArgs {
     int32_t singular, poly;
     double delta, delta2, reach2, rin2, out2;
     int64_t *lcnt;          // count pass: [kLsLast][K1]
-    unsigned long long *maxS;   // count pass: max |S(e)|
     unsigned long long *maxClip;   // bound on the vertex count of any straddling clip
     const double *dir;             // [N][2] polygon directions (device copy)
     const int64_t *loff;    // fill pass:  [kLsLast][K1]
@@ -376,7 +375,6 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
             for (int t = threadIdx.x; t < ne * kLsLast; t += kBlock) {
                 int i = t / kLsLast, kind = t % kLsLast;
                 a.lcnt[kind * a.K1 + a.cell_elems[t0 + i]] = e_off[t];
-                if (kind == kLsS) atomicMax(a.maxS, (unsigned long long)e_off[t]);
             }
         }
         __syncthreads();
@@ -427,9 +425,8 @@ __global__ void __launch_bounds__(256) k_cell_fill(CellArgs a)
     a.elems[a.start[c] + pos] = (int32_t)k;
 }
 
-// per-cell insertion sort (cells hold tens of elements) and max occupancy
-__global__ void __launch_bounds__(256) k_cell_sort(int64_t ncell, const int64_t *start, int32_t *elems,
-                                                   unsigned long long *maxcnt)
+// per-cell insertion sort (cells hold tens of elements)
+__global__ void __launch_bounds__(256) k_cell_sort(int64_t ncell, const int64_t *start, int32_t *elems)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -443,7 +440,6 @@ __global__ void __launch_bounds__(256) k_cell_sort(int64_t ncell, const int64_t 
         }
         elems[j + 1] = v;
     }
-    atomicMax(maxcnt, (unsigned long long)(e - s));
 }
 
 CellArgs cell_args(nlfem_pairs *h)
@@ -467,7 +463,7 @@ int launch_cell_fill(nlfem_pairs *h, hipStream_t s)
     const int64_t ncell = (int64_t)h->gnx * h->gny;
     hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(h->K, 256)), dim3(256), 0, s, cell_args(h));
     hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, 256)), dim3(256), 0, s, ncell, h->cell_start,
-                       h->cell_elems, h->red + 6);
+                       h->cell_elems);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }
@@ -502,7 +498,6 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     const double out = h->delta * (1.0 + 1e-12);
     a.out2 = out * out;
     a.lcnt = h->lcnt;
-    a.maxS = h->red + 7;
     a.maxClip = h->red + 10;
     a.dir = h->poly_dir;
     a.loff = h->loff;
