@@ -806,10 +806,40 @@ __device__ inline bool add_touch(double *acc, const int32_t *hk, const int32_t *
 }
 
 // LDS of one row gather besides the dynamic part (accumulator, hash table)
+// touching entries of a row are queued and then handled by all lanes at once
+// (they take a longer path than the non-touching ones)
+constexpr int kRowTouchCap = 512;
+
 struct RowShared {
     int64_t qs[kRowQ];
     int32_t pre[kRowQ + 1], qe[kRowQ], qloc[kRowQ], qn[kRowQ][3], qp[kRowQ][3];
+    int32_t tt[kRowTouchCap];   // queued touching entries: list index and element slot
+    uint8_t tq[kRowTouchCap];
 };
+
+// adds the queued touching entries of row i (element slots of the current batch)
+template <int NC>
+__device__ inline bool flush_touch(const RowArgs &a, RowShared &sh, int ntouch, int64_t i, double *acc,
+                                   const int32_t *hk, const int32_t *hv, int32_t mask, int lane)
+{
+    bool ok = true;
+    for (int j = lane; j < ntouch; j += 64) {
+        const int32_t t = sh.tt[j];
+        const int q = sh.tq[j];
+        const int4 sn = a.snode[t];
+        const int cls = (a.sflag[t] >> 2) & 3;
+        const int32_t u = a.srec[t];
+        if (u < 0 || u >= a.n_touch) {
+            ok = false;
+            continue;
+        }
+        const double *L = a.touch_rec + (int64_t)u * a.touch_stride;
+        if (!add_touch<NC>(acc, hk, hv, mask, (int32_t)i, cls, sh.qe[q], sn.x, sh.qn[q][0], sh.qn[q][1],
+                           sh.qn[q][2], sn.y, sn.z, sn.w, L))
+            ok = false;
+    }
+    return ok;
+}
 
 // dynamic LDS bytes of one row gather
 inline size_t row_lds_bytes(int64_t maxlen, int nc, int hcap)
@@ -902,8 +932,9 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
             if (lane == 0) pre[0] = 0;
             const int total = __shfl(incl, nq - 1);
             __syncthreads();
+            int ntouch = 0;
             for (int base = 0; base < total; base += 64 * kRowU) {
-                int32_t fe[kRowU], uu[kRowU], qq[kRowU], cl[kRowU], nf0[kRowU], nf1[kRowU], nf2[kRowU];
+                int32_t fe[kRowU], uu[kRowU], qq[kRowU], cl[kRowU], nf0[kRowU], nf1[kRowU], nf2[kRowU], tt[kRowU];
                 bool act[kRowU];
                 TR xv[kRowU][3][NK];
 #pragma unroll
@@ -925,6 +956,7 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                         }
                         qq[k] = lo;
                         const int64_t t = qs[lo] + (flat - pre[lo]);
+                        tt[k] = (int32_t)t;
                         const int4 sn = a.snode[t];
                         fe[k] = sn.x;
                         nf0[k] = sn.y;
@@ -976,13 +1008,30 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                             for (int kk = 0; kk < NK; ++kk) xs[kk] = (double)xv[k][b][kk];
                             add_sym_block<NC>(acc, px, xs);
                         }
-                    } else {
-                        const double *L = a.touch_rec + (int64_t)uu[k] * a.touch_stride;
-                        if (!add_touch<NC>(acc, hk, hv, mask, (int32_t)i, cl[k], e, f, qn[q][0], qn[q][1], qn[q][2],
-                                           nf0[k], nf1[k], nf2[k], L))
-                            bad = true;
                     }
                 }
+                // queue the touching entries of this step
+#pragma unroll
+                for (int k = 0; k < kRowU; ++k) {
+                    const bool tk = act[k] && cl[k] != 0;
+                    const unsigned long long bl = __ballot(tk);
+                    if (tk) {
+                        const int pos = ntouch + __popcll(bl & ((1ull << lane) - 1ull));
+                        sh.tt[pos] = tt[k];
+                        sh.tq[pos] = (uint8_t)qq[k];
+                    }
+                    ntouch += __popcll(bl);
+                }
+                if (ntouch > kRowTouchCap - 64 * kRowU) {
+                    __syncthreads();
+                    if (!flush_touch<NC>(a, sh, ntouch, i, acc, hk, hv, mask, lane)) bad = true;
+                    ntouch = 0;
+                    __syncthreads();
+                }
+            }
+            if (ntouch > 0) {   // before the element slots of this batch are reused
+                __syncthreads();
+                if (!flush_touch<NC>(a, sh, ntouch, i, acc, hk, hv, mask, lane)) bad = true;
             }
             __syncthreads();
         }
