@@ -230,19 +230,34 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     __shared__ int64_t nb_start[kMaxNbr], nb_pre[kMaxNbr + 1];
     __shared__ int nb_n;
 
-    if (threadIdx.x == 0) {
-        int n = 0;
-        int64_t pre = 0;
-        for (int yy = max(0, cy - a.gr); yy <= min(a.gny - 1, cy + a.gr); ++yy)
-            for (int xx = max(0, cx - a.gr); xx <= min(a.gnx - 1, cx + a.gr); ++xx) {
-                int c = yy * a.gnx + xx;
-                nb_start[n] = a.cell_start[c];
-                nb_pre[n] = pre;
-                pre += a.cell_start[c + 1] - a.cell_start[c];
-                n++;
-            }
-        nb_pre[n] = pre;
-        nb_n = n;
+    // the neighbour cells (row-major, clipped to the grid): one lane each, so
+    // their counts load in parallel, then a prefix sum across the wave
+    if (threadIdx.x < 64) {
+        const int side = 2 * a.gr + 1;
+        const int t = threadIdx.x;
+        const int yy = cy - a.gr + t / side, xx = cx - a.gr + t % side;
+        const bool in = t < side * side && yy >= 0 && yy < a.gny && xx >= 0 && xx < a.gnx;
+        int64_t st = 0, cnt = 0;
+        if (in) {
+            const int c = yy * a.gnx + xx;
+            st = a.cell_start[c];
+            cnt = a.cell_start[c + 1] - st;
+        }
+        const unsigned long long bin = __ballot(in);
+        const int slot = __popcll(bin & ((1ull << t) - 1ull));
+        int64_t incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(incl, o);
+            if (t >= o) incl += y;
+        }
+        if (in) {
+            nb_start[slot] = st;
+            nb_pre[slot] = incl - cnt;
+        }
+        if (t == 63) {
+            nb_n = __popcll(bin);
+            nb_pre[__popcll(bin)] = incl;
+        }
     }
     __syncthreads();
     const int64_t total = nb_pre[nb_n];
@@ -296,6 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                 }
                 int64_t off[kLsLast];
                 for (int k = 0; k < kLsLast; ++k) off[k] = e_off[i * kLsLast + k];
+
                 for (int jj = 0; jj < nch; jj += 64) {
                     const int j = jj + lane;
                     const bool valid = j < nch;
