@@ -234,6 +234,11 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         h->rb = (unsigned long long *)rb;
     }
     unsigned long long *red = h->rb;
+    if (!h->aux) {
+        NLFEM_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+        NLFEM_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        NLFEM_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
     timing_begin(kPhGeometry, s);
     NLFEM_TRY(launch_geometry(h, m, s));
     timing_end(kPhGeometry, s);
@@ -629,6 +634,9 @@ void nlfem_pairs_free(nlfem_pairs *h)
     for (auto &b : h->bufs)
         if (b.p) (void)hipFree(b.p);
     if (h->rb) (void)hipHostFree(h->rb);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
     delete h;
 }
 

@@ -194,6 +194,27 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
                     double *val, hipStream_t s)
 {
     const AssemblePlan p = make_plan(h, m, cfg, g, val);
+    const bool has_touch = p.touch[0].n + p.touch[1].n + p.touch[2].n > 0;
+    // touching pairs on the handle's second stream, beside the non-touching
+    // pairs and their diagonal sums; joined before the row gather
+    const bool fork = has_touch && p.far.n > 0 && h->aux;
+    hipStream_t st = s;
+    bool joined = false;
+    if (fork) {
+        NLFEM_HIP(hipEventRecord(h->ev_fork, s));
+        NLFEM_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+        st = h->aux;
+    }
+    if (has_touch) {
+        timing_begin(kPhTouch, st);
+        switch (p.kernel) {
+        case NLFEM_K_CONSTANT: touch_dispatch<NLFEM_K_CONSTANT>(p, st); break;
+        case NLFEM_K_INV_DIST: touch_dispatch<NLFEM_K_INV_DIST>(p, st); break;
+        default: touch_dispatch<NLFEM_K_PERIDYNAMIC>(p, st); break;
+        }
+        timing_end(kPhTouch, st);
+    }
+    if (fork) NLFEM_HIP(hipEventRecord(h->ev_join, h->aux));
     if (p.far.n > 0) {
         timing_begin(kPhFar, s);
         switch (p.kernel) {
@@ -202,15 +223,6 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         default: far_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
         }
         timing_end(kPhFar, s);
-    }
-    if (p.touch[0].n + p.touch[1].n + p.touch[2].n > 0) {
-        timing_begin(kPhTouch, s);
-        switch (p.kernel) {
-        case NLFEM_K_CONSTANT: touch_dispatch<NLFEM_K_CONSTANT>(p, s); break;
-        case NLFEM_K_INV_DIST: touch_dispatch<NLFEM_K_INV_DIST>(p, s); break;
-        default: touch_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
-        }
-        timing_end(kPhTouch, s);
     }
     if (p.rows.nrows > 0) {
         const int nc = p.nc;
@@ -225,6 +237,10 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
             else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, p.diag);
         }
         timing_end(kPhFar, s);
+        if (fork) {
+            NLFEM_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
+            joined = true;
+        }
         const size_t lds = row_lds_bytes(p.rows.maxlen, nc, p.rows.hcap);
         const unsigned grid = xcd_grid(p.rows.nrows);
         timing_begin(kPhRows, s);
@@ -237,6 +253,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         }
         timing_end(kPhRows, s);
     }
+    if (fork && !joined) NLFEM_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

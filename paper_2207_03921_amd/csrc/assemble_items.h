@@ -535,8 +535,9 @@ __device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &
         const double2 p0 = vtx(a.V, nd[0]), p1 = vtx(a.V, nd[1]), p2 = vtx(a.V, nd[2]);
         const double J00 = p1.x - p0.x, J01 = p2.x - p0.x, J10 = p1.y - p0.y, J11 = p2.y - p0.y;
         const double det = fabs(J00 * J11 - J01 * J10);
+        // point ev = j n + iu; the indices advance by G without divisions
+        int j = sub / n, iu = sub - (sub / n) * n;
         for (int ev = sub; ev < 6 * n; ev += G) {
-            const int j = ev / n, iu = ev - j * n;
             // hexagon corners (1,0),(0,1),(-1,1),(-1,0),(0,-1),(1,-1)
             const int j1 = j == 5 ? 0 : j + 1;
             const double cx0 = j == 0 || j == 5 ? 1.0 : (j == 2 || j == 3 ? -1.0 : 0.0);
@@ -549,6 +550,11 @@ __device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &
             // phi(x^) - phi(x^ + z) = -grad phi . z, z = rho w
             const double gg[3] = {wx + wy, -wx, -wy};
             acc_sample<KER, 3>(L, g.w[iu], J00 * wx + J01 * wy, J10 * wx + J11 * wy, gg, a.c);
+            iu += G;
+            while (iu >= n) {
+                iu -= n;
+                ++j;
+            }
         }
         constexpr int d = Ker<KER>::D;
         scale = det * det / (double)((d + 2) * (d + 3) * (d + 4));
@@ -564,8 +570,8 @@ __device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &
         // out of divergent control flow)
 #pragma unroll
         for (int face = 0; face < 4; ++face) {
+            int ip = sub / n, iq = sub - (sub / n) * n;
             for (int ev = sub; ev < n * n; ev += G) {
-                const int ip = ev / n, iq = ev - ip * n;
                 const double p = g.x[ip], q = g.x[iq];
                 const double u = 1.0 - p, t = u * q;
                 const double w0 = face < 2 ? p : -p;
@@ -575,6 +581,11 @@ __device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &
                 const double gg[4] = {-w0 - w1 + w2, w0, w1, -w2};
                 acc_sample<KER, 4>(L, g.w[ip] * g.w[iq] * jf, E0x * w0 + E1x * w1 + E2x * w2,
                                    E0y * w0 + E1y * w1 + E2y * w2, gg, a.c);
+                iq += G;
+                while (iq >= n) {
+                    iq -= n;
+                    ++ip;
+                }
             }
         }
         const double detk = fabs(E0x * E1y - E1x * E0y), detl = fabs(E0x * E2y - E2x * E0y);
@@ -585,9 +596,8 @@ __device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &
         const double2 b1 = vtx(a.V, nd[3]), b2 = vtx(a.V, nd[4]);
         const double A1x = a1.x - q0.x, A1y = a1.y - q0.y, A2x = a2.x - q0.x, A2y = a2.y - q0.y;
         const double B1x = b1.x - q0.x, B1y = b1.y - q0.y, B2x = b2.x - q0.x, B2y = b2.y - q0.y;
+        int iw = sub / (n * n), ia = (sub - iw * n * n) / n, ib = sub - iw * n * n - ia * n;
         for (int ev = sub; ev < n * n * n; ev += G) {
-            const int iw = ev / (n * n), rem = ev - iw * n * n;
-            const int ia = rem / n, ib = rem - ia * n;
             const double w = g.x[iw], al = g.x[ia], be = g.x[ib];
             const double ex = (1.0 - al) * A1x + al * A2x, ey = (1.0 - al) * A1y + al * A2y;
             const double fx = (1.0 - be) * B1x + be * B2x, fy = (1.0 - be) * B1y + be * B2y;
@@ -599,6 +609,15 @@ __device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &
             {   // region s <= t: s = t w
                 const double gg[5] = {1.0 - w, w * (1.0 - al), w * al, -(1.0 - be), -be};
                 acc_sample<KER, 5>(L, wt, w * ex - fx, w * ey - fy, gg, a.c);
+            }
+            ib += G;
+            while (ib >= n) {
+                ib -= n;
+                ++ia;
+            }
+            while (ia >= n) {
+                ia -= n;
+                ++iw;
             }
         }
         const double detk = fabs(A1x * A2y - A2x * A1y), detl = fabs(B1x * B2y - B2x * B1y);

@@ -157,6 +157,10 @@ struct nlfem_pairs {
     double *dsum = nullptr;      // [K][6 * NK] summed element-diagonal blocks of the far pairs
     double *poly_dir = nullptr;  // [N][2] polygon directions (approach POLY)
     int32_t far_stride = 0, touch_stride = 0;
+    // second stream of the assembly: touching pairs run beside the
+    // non-touching ones (fork and join through the two events)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // grow-only device buffers behind the typed pointers above
     struct DevBuf {
         void *p = nullptr;
