@@ -100,10 +100,16 @@ def rows_algorithmic_bytes(info, n_vertices, n_elements, ncomp, precision):
             + info["nnz"] * 8)                          # values, written once
 
 
-def _source_digest(path):
+ROW_SOURCES = ("assemble_items.h", "assemble.hip")   # the row-gather kernel and its launch
+
+
+def _source_digest(paths):
     import hashlib
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, precision):
@@ -119,8 +125,8 @@ def measured_traffic(workload, precision):
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2207_03921_amd", "csrc", "assemble.hip")
-    if kv.get("source_sha256_16") != _source_digest(src):
+    srcs = [os.path.join(ROOT, "paper_2207_03921_amd", "csrc", f) for f in ROW_SOURCES]
+    if kv.get("source_sha256_16") != _source_digest(srcs):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
