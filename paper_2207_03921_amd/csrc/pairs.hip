@@ -150,8 +150,9 @@ __device__ inline double corner_sine(const double2 v[3], int a)
     return fabs(ux * wy - uy * wx) / (sqrt(ux * ux + uy * uy) * sqrt(wx * wx + wy * wy));
 }
 
-// Status of the outer point (x, y) for the triangle v under the polygon ball:
-// the decisions of clip_status, taken from the edge tests of the original
+// Status of the outer point (x, y) for the triangle v under the polygon ball
+// when poly_quick is unsure: the decisions of clip_status, taken from the
+// edge tests of the original
 // vertices (the clip's own arithmetic) wherever they fix the result:
 //  - the clip returns the triangle unchanged iff every vertex passes every
 //    edge test: whole;
@@ -165,14 +166,22 @@ __device__ inline double corner_sine(const double2 v[3], int a)
 // Otherwise the clip runs.  For straddling points *maxcnt is raised to
 // 3 + 2 * (edges at which some vertex is not inside by the margin), a bound
 // on every intermediate vertex count of the clip.
-__device__ inline uint32_t poly_status(double x, double y, const double2 v[3], const PolyArgs &pg,
-                                       const PairArgs &a, int *maxcnt)
+// The distance tests alone: whole if the triangle lies inside the inscribed
+// circle, out if it is farther than delta; kUnsure otherwise.
+constexpr uint32_t kUnsure = 3u;
+__device__ inline uint32_t poly_quick(double x, double y, const double2 v[3], const PairArgs &a)
 {
     double d0 = (v[0].x - x) * (v[0].x - x) + (v[0].y - y) * (v[0].y - y);
     double d1 = (v[1].x - x) * (v[1].x - x) + (v[1].y - y) * (v[1].y - y);
     double d2 = (v[2].x - x) * (v[2].x - x) + (v[2].y - y) * (v[2].y - y);
     if (d0 < a.rin2 && d1 < a.rin2 && d2 < a.rin2) return kWhole;
     if (point_triangle_dist2(x, y, v) > a.out2) return kOut;
+    return kUnsure;
+}
+
+__device__ inline uint32_t poly_status(double x, double y, const double2 v[3], const PolyArgs &pg,
+                                       const PairArgs &a, int *maxcnt)
+{
     const double C = fmax(fabs(x), fabs(y)) + a.delta;
     const double m_out = 1e-9 * C, m_in = 1e-5 * C;   // margins as distances
     const int N = pg.N;
@@ -229,6 +238,11 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     int32_t *c_nd = c_lab + kCH;                          // [3][kCH]
     __shared__ int64_t nb_start[kMaxNbr], nb_pre[kMaxNbr + 1];
     __shared__ int nb_n;
+    // polygon ball: per wave, queue of unsure (candidate, direction, point)
+    // items and the statuses they decide
+    __shared__ int32_t pq_all[POLY ? kBlock / 64 : 1][POLY ? 64 * 2 * kMaxRule : 1];
+    __shared__ uint32_t pm_all[POLY ? kBlock / 64 : 1][2][64];
+    __shared__ int pq_cnt[kBlock / 64];
 
     // the neighbour cells (row-major, clipped to the grid): one lane each, so
     // their counts load in parallel, then a prefix sum across the wave
@@ -264,6 +278,11 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     int clipmax = 0;
+    int32_t *pq = pq_all[POLY ? wv : 0];
+    uint32_t *pm_ef = pm_all[POLY ? wv : 0][0], *pm_fe = pm_all[POLY ? wv : 0][1];
+    int *pq_n = &pq_cnt[wv];
+    if (lane == 0) *pq_n = 0;
+    wave_sync();
     // the cell's elements in tiles of kTE
     for (int64_t t0 = cs; t0 < ce; t0 += kTE) {
         const int ne = (int)min((int64_t)kTE, ce - t0);
@@ -345,18 +364,62 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                                         if (dx * dx + dy * dy <= a.delta2) mfe |= kWhole << (2 * q);
                                     }
                                 } else {
+                                    // distance tests now; the unsure (point, triangle) items go to
+                                    // the wave's queue and are decided below by all lanes at once
                                     double2 vf[3] = {c_v[j], c_v[kCH + j], c_v[2 * kCH + j]};
                                     for (int p = 0; p < a.P; ++p) {
                                         const double2 x = a.xp[(int64_t)e * a.P + p];
-                                        mef |= poly_status(x.x, x.y, vf, pg, a, &clipmax) << (2 * p);
+                                        const uint32_t st = poly_quick(x.x, x.y, vf, a);
+                                        if (st == kUnsure) pq[atomicAdd(pq_n, 1)] = (lane << 5) | p;
+                                        else mef |= st << (2 * p);
                                     }
                                     for (int q = 0; q < a.P; ++q) {
                                         const double2 x = c_xp[q * kCH + j];
-                                        mfe |= poly_status(x.x, x.y, ve, pg, a, &clipmax) << (2 * q);
+                                        const uint32_t st = poly_quick(x.x, x.y, ve, a);
+                                        if (st == kUnsure) pq[atomicAdd(pq_n, 1)] = (lane << 5) | 16 | q;
+                                        else mfe |= st << (2 * q);
                                     }
                                 }
                             }
                         }
+                    }
+                    if (POLY) {
+                        // decide the queued items, one per lane
+                        wave_sync();
+                        pm_ef[lane] = 0u;
+                        pm_fe[lane] = 0u;
+                        const int nq = *pq_n;
+                        wave_sync();
+                        for (int it = lane; it < nq; it += 64) {
+                            const int code = pq[it];
+                            const int jl = code >> 5, fe_dir = code & 16, p = code & 15;
+                            const int jc = jj + jl;
+                            uint32_t st;
+                            if (!fe_dir) {
+                                const double2 x = a.xp[(int64_t)e * a.P + p];
+                                double2 vf[3] = {c_v[jc], c_v[kCH + jc], c_v[2 * kCH + jc]};
+                                st = poly_status(x.x, x.y, vf, pg, a, &clipmax);
+                                atomicOr(&pm_ef[jl], st << (2 * p));
+                            } else {
+                                const double2 x = c_xp[p * kCH + jc];
+                                st = poly_status(x.x, x.y, ve, pg, a, &clipmax);
+                                atomicOr(&pm_fe[jl], st << (2 * p));
+                            }
+                        }
+                        wave_sync();
+                        mef |= pm_ef[lane];
+                        mfe |= pm_fe[lane];
+                        wave_sync();
+                        if (lane == 0) *pq_n = 0;
+                        wave_sync();
+                    }
+                    if (valid) {
+                        const bool act = (c_lab[j] == 1 || c_lab[j] == 2) && (lab_e == 1 || c_lab[j] == 1);
+                        const int32_t f0 = c_nd[j], f1 = c_nd[kCH + j], f2 = c_nd[2 * kCH + j];
+                        const int shared = (ne0 == f0) + (ne0 == f1) + (ne0 == f2) + (ne1 == f0) +
+                                           (ne1 == f1) + (ne1 == f2) + (ne2 == f0) + (ne2 == f1) +
+                                           (ne2 == f2);
+                        const bool touch = a.singular && shared > 0;
                         if (touch) cls = shared;
                         inS = act && (touch || (mef | mfe) != 0u);
                         inP = act && (touch || mef != 0u);
