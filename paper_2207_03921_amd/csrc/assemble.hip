@@ -14,6 +14,18 @@ __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArg
     far_item<KER, T, PM, POLY>(a, r1, r2, idx);
 }
 
+// polygon ball: one wave per workgroup shares the straddling points of its pairs
+template <int KER, typename T, int PM>
+__global__ void __launch_bounds__(64) k_far_rec_poly(FarArgs a, RoleArgs r1, RoleArgs r2)
+{
+    constexpr int NV = 21 * Ker<KER>::NK;
+    __shared__ int32_t queue[64 * 2 * kMaxRule];
+    __shared__ int32_t pe[64], pf[64];
+    __shared__ T slots[64 * NV];
+    const int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    far_wave_poly<KER, T, PM>(a, r1, r2, idx, idx < a.n, queue, pe, pf, slots);
+}
+
 template <int KER, int CLS, int G>
 __global__ void __launch_bounds__(256) k_touch_rec(TouchArgs a, GaussArgs g)
 {
@@ -48,6 +60,12 @@ __global__ void __launch_bounds__(64) k_rows(RowArgs a)
 template <int KER, typename T, bool POLY>
 void far_launch(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, bool seven, hipStream_t s)
 {
+    if (POLY) {
+        const unsigned grid = grid_for(a.n, 64);
+        if (seven) hipLaunchKernelGGL((k_far_rec_poly<KER, T, 7>), dim3(grid), dim3(64), 0, s, a, r1, r2);
+        else hipLaunchKernelGGL((k_far_rec_poly<KER, T, 0>), dim3(grid), dim3(64), 0, s, a, r1, r2);
+        return;
+    }
     const unsigned grid = grid_for(a.n, 256);
     if (seven) hipLaunchKernelGGL((k_far_rec<KER, T, 7, POLY>), dim3(grid), dim3(256), 0, s, a, r1, r2);
     else hipLaunchKernelGGL((k_far_rec<KER, T, 0, POLY>), dim3(grid), dim3(256), 0, s, a, r1, r2);

@@ -391,62 +391,99 @@ __device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, do
 }
 
 // record of unordered non-touching pair idx
-template <int KER, typename T, int PM, bool POLY>
-__device__ __forceinline__ void far_item(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int64_t idx)
+// Record values of one unordered non-touching pair.
+template <int KER, typename T>
+struct FarAcc {
+    static constexpr int NK = Ker<KER>::NK;
+    T X[3][3][NK], De[6][NK], Df[6][NK];
+    __device__ inline void zero()
+    {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) X[i / 3][i % 3][k] = 0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) De[i][k] = Df[i][k] = 0;
+        }
+    }
+    __device__ inline void add(const FarAcc &o)
+    {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) X[i / 3][i % 3][k] += o.X[i / 3][i % 3][k];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                De[i][k] += o.De[i][k];
+                Df[i][k] += o.Df[i][k];
+            }
+        }
+    }
+};
+
+// points whose ball covers the other element wholly (status 1)
+template <int KER, typename T, int PM>
+__device__ __forceinline__ void far_whole(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int32_t e,
+                                          int32_t f, uint32_t ms, uint32_t mt, FarAcc<KER, T> &acc)
 {
-    constexpr int NK = Ker<KER>::NK;
-    const int32_t e = a.ue[idx], f = a.uf[idx];
-    const uint32_t ms = a.m_ef[idx], mt = a.m_fe[idx];   // mt == 0 for the self pair
-    const bool self = e == f;
     const double2 v0e = a.v0[e], v0f = a.v0[f];
     const double4 Je = a.J[e], Jf = a.J[f];
     const double dete = a.det[e], detf = a.det[f];
     const T dx = (T)(v0e.x - v0f.x), dy = (T)(v0e.y - v0f.y);
     const T cc = (T)a.c;
-    T X[3][3][NK], De[6][NK], Df[6][NK];
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) X[i / 3][i % 3][k] = 0;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) De[i][k] = Df[i][k] = 0;
-    }
+    acc.zero();
     if (a.same) {
-        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, mt, cc, X, De, Df);
+        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, mt, cc, acc.X, acc.De, acc.Df);
     } else {
         // (e, f): outer rule on e, inner rule on f
-        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, 0u, cc, X, De, Df);
+        far_direction<KER, T, PM>(r1, dx, dy, Je, Jf, dete, detf, ms, 0u, cc, acc.X, acc.De, acc.Df);
         // (f, e): inner rule on e, outer rule on f
-        if (!self) far_direction<KER, T, PM>(r2, dx, dy, Je, Jf, dete, detf, 0u, mt, cc, X, De, Df);
+        if (e != f) far_direction<KER, T, PM>(r2, dx, dy, Je, Jf, dete, detf, 0u, mt, cc, acc.X, acc.De, acc.Df);
     }
-    if (POLY) {
-        // status 2: the polygon around the point straddles the other element
-        double clipbuf[2 * 2 * (kMaxPoly + 4)];
-        const int lane = 0;
-        bool ovf = false;
-        for (int p = 0; p < r1.PA; ++p) {
-            if (((ms >> (2 * p)) & 3u) != kStraddle) continue;
-            const double2 xo = a.xp[(int64_t)e * a.P + p];
-            const double po[3] = {r1.pa[p][0], r1.pa[p][1], r1.pa[p][2]};
-            straddle_point<KER, T>(a, xo.x, xo.y, r1.wa[p] * dete, po, f, v0f, Jf, r1, true, true, clipbuf, lane,
-                                   cc, X, De, Df, &ovf);
-        }
-        // with one rule both directions use r1; otherwise the outer rule on f is role B of r2
-        for (int q = 0; !self && q < r1.PB; ++q) {
-            if (((mt >> (2 * q)) & 3u) != kStraddle) continue;
-            const double2 xo = a.xp[(int64_t)f * a.P + q];
-            if (a.same) {
-                const double po[3] = {r1.pb[q][0], r1.pb[q][1], r1.pb[q][2]};
-                straddle_point<KER, T>(a, xo.x, xo.y, r1.wb[q] * detf, po, e, v0e, Je, r1, false, false, clipbuf,
-                                       lane, cc, X, De, Df, &ovf);
-            } else {
-                const double po[3] = {r2.pb[q][0], r2.pb[q][1], r2.pb[q][2]};
-                straddle_point<KER, T>(a, xo.x, xo.y, r2.wb[q] * detf, po, e, v0e, Je, r2, false, false, clipbuf,
-                                       lane, cc, X, De, Df, &ovf);
-            }
-        }
-        if (ovf) atomicOr(a.err, kErrClip);
+}
+
+// Contribution of one straddling point (status 2), computed from zero:
+// side 0 is outer point p of e against f, side 1 outer point p of f
+// against e.  Every path adds these contributions to the pair's values one
+// by one in the order (side 0, p ascending), (side 1, p ascending).
+template <int KER, typename T>
+__device__ __forceinline__ void straddle_item(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int side,
+                                              int p, int32_t e, int32_t f, FarAcc<KER, T> &c, bool *ovf)
+{
+    double clipbuf[2 * 2 * (kMaxPoly + 4)];
+    const T cc = (T)a.c;
+    c.zero();
+    if (side == 0) {
+        const double2 xo = a.xp[(int64_t)e * a.P + p];
+        const double po[3] = {r1.pa[p][0], r1.pa[p][1], r1.pa[p][2]};
+        straddle_point<KER, T>(a, xo.x, xo.y, r1.wa[p] * a.det[e], po, f, a.v0[f], a.J[f], r1, true, true, clipbuf,
+                               0, cc, c.X, c.De, c.Df, ovf);
+    } else if (a.same) {   // one rule: both directions use r1
+        const double2 xo = a.xp[(int64_t)f * a.P + p];
+        const double po[3] = {r1.pb[p][0], r1.pb[p][1], r1.pb[p][2]};
+        straddle_point<KER, T>(a, xo.x, xo.y, r1.wb[p] * a.det[f], po, e, a.v0[e], a.J[e], r1, false, false,
+                               clipbuf, 0, cc, c.X, c.De, c.Df, ovf);
+    } else {               // the outer rule on f is role B of r2
+        const double2 xo = a.xp[(int64_t)f * a.P + p];
+        const double po[3] = {r2.pb[p][0], r2.pb[p][1], r2.pb[p][2]};
+        straddle_point<KER, T>(a, xo.x, xo.y, r2.wb[p] * a.det[f], po, e, a.v0[e], a.J[e], r2, false, false,
+                               clipbuf, 0, cc, c.X, c.De, c.Df, ovf);
     }
+}
+
+// straddling points of a pair: bits p of the two status masks
+__device__ inline uint32_t straddle_bits(uint32_t m, int P)
+{
+    uint32_t b = 0;
+    for (int p = 0; p < P; ++p)
+        if (((m >> (2 * p)) & 3u) == kStraddle) b |= 1u << p;
+    return b;
+}
+
+template <int KER, typename T>
+__device__ __forceinline__ void far_store(const FarArgs &a, int64_t idx, bool self, const FarAcc<KER, T> &acc)
+{
+    constexpr int NK = Ker<KER>::NK;
     T *out = (T *)a.rec + idx * a.stride;
     if (self) {
 #pragma unroll
@@ -454,10 +491,10 @@ __device__ __forceinline__ void far_item(const FarArgs &a, const RoleArgs &r1, c
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) out[(3 * i + j) * NK + k] = X[i][j][k] + X[j][i][k];
+                for (int j = 0; j < 3; ++j) out[(3 * i + j) * NK + k] = acc.X[i][j][k] + acc.X[j][i][k];
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
-                out[(9 + i) * NK + k] = De[i][k] + Df[i][k];
+                out[(9 + i) * NK + k] = acc.De[i][k] + acc.Df[i][k];
                 out[(15 + i) * NK + k] = 0;
             }
         }
@@ -465,14 +502,126 @@ __device__ __forceinline__ void far_item(const FarArgs &a, const RoleArgs &r1, c
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) out[i * NK + k] = X[i / 3][i % 3][k];
+            for (int i = 0; i < 9; ++i) out[i * NK + k] = acc.X[i / 3][i % 3][k];
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
-                out[(9 + i) * NK + k] = De[i][k];
-                out[(15 + i) * NK + k] = Df[i][k];
+                out[(9 + i) * NK + k] = acc.De[i][k];
+                out[(15 + i) * NK + k] = acc.Df[i][k];
             }
         }
     }
+}
+
+// record of unordered non-touching pair idx, one lane alone
+template <int KER, typename T, int PM, bool POLY>
+__device__ __forceinline__ void far_item(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int64_t idx)
+{
+    const int32_t e = a.ue[idx], f = a.uf[idx];
+    const uint32_t ms = a.m_ef[idx], mt = a.m_fe[idx];   // mt == 0 for the self pair
+    FarAcc<KER, T> acc;
+    far_whole<KER, T, PM>(a, r1, r2, e, f, ms, mt, acc);
+    if (POLY) {
+        bool ovf = false;
+        FarAcc<KER, T> c;
+        // both masks cover the outer points (a.P) of their element
+        const uint32_t b0 = straddle_bits(ms, a.P), b1 = e == f ? 0u : straddle_bits(mt, a.P);
+        for (int p = 0; p < kMaxRule; ++p)
+            if ((b0 >> p) & 1u) {
+                straddle_item<KER, T>(a, r1, r2, 0, p, e, f, c, &ovf);
+                acc.add(c);
+            }
+        for (int p = 0; p < kMaxRule; ++p)
+            if ((b1 >> p) & 1u) {
+                straddle_item<KER, T>(a, r1, r2, 1, p, e, f, c, &ovf);
+                acc.add(c);
+            }
+        if (ovf) atomicOr(a.err, kErrClip);
+    }
+    far_store<KER, T>(a, idx, e == f, acc);
+}
+
+// The same for the 64 pairs of a one-wave workgroup (polygon ball): the
+// straddling points of all pairs are queued in pair order and computed by
+// all lanes; each pair then adds its own contributions in queue order, so
+// the values are those of far_item.
+template <int KER, typename T, int PM>
+__device__ __forceinline__ void far_wave_poly(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int64_t idx,
+                                              bool active, int32_t *queue, int32_t *pe, int32_t *pf, T *slots)
+{
+    constexpr int NV = 21 * Ker<KER>::NK;   // values of one record
+    const int lane = threadIdx.x & 63;
+    int32_t e = 0, f = 0;
+    uint32_t ms = 0, mt = 0;
+    FarAcc<KER, T> acc;
+    acc.zero();
+    if (active) {
+        e = a.ue[idx];
+        f = a.uf[idx];
+        ms = a.m_ef[idx];
+        mt = a.m_fe[idx];
+        far_whole<KER, T, PM>(a, r1, r2, e, f, ms, mt, acc);
+    }
+    const uint32_t b0 = active ? straddle_bits(ms, a.P) : 0u;
+    const uint32_t b1 = active && e != f ? straddle_bits(mt, a.P) : 0u;
+    const int cnt = __popc(b0) + __popc(b1);
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    const int off = incl - cnt, total = __shfl(incl, 63);
+    {   // this pair's items: side 0 in point order, then side 1
+        int k = off;
+        for (int p = 0; p < kMaxRule; ++p)
+            if ((b0 >> p) & 1u) queue[k++] = (lane << 5) | p;
+        for (int p = 0; p < kMaxRule; ++p)
+            if ((b1 >> p) & 1u) queue[k++] = (lane << 5) | 16 | p;
+    }
+    pe[lane] = e;
+    pf[lane] = f;
+    wave_sync();
+    bool ovf = false;
+    for (int r0 = 0; r0 < total; r0 += 64) {
+        const int it = r0 + lane;
+        if (it < total) {
+            const int code = queue[it];
+            const int ol = code >> 5;
+            FarAcc<KER, T> c;
+            straddle_item<KER, T>(a, r1, r2, (code >> 4) & 1, code & 15, pe[ol], pf[ol], c, &ovf);
+            T *sl = slots + lane * NV;
+#pragma unroll
+            for (int k = 0; k < Ker<KER>::NK; ++k) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) sl[i * Ker<KER>::NK + k] = c.X[i / 3][i % 3][k];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    sl[(9 + i) * Ker<KER>::NK + k] = c.De[i][k];
+                    sl[(15 + i) * Ker<KER>::NK + k] = c.Df[i][k];
+                }
+            }
+        }
+        wave_sync();
+        // the pair's items that fell into this round, in order
+        const int lo = max(off, r0), hi = min(off + cnt, r0 + 64);
+        for (int it2 = lo; it2 < hi; ++it2) {
+            const T *sl = slots + (it2 - r0) * NV;
+            FarAcc<KER, T> c;
+#pragma unroll
+            for (int k = 0; k < Ker<KER>::NK; ++k) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) c.X[i / 3][i % 3][k] = sl[i * Ker<KER>::NK + k];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    c.De[i][k] = sl[(9 + i) * Ker<KER>::NK + k];
+                    c.Df[i][k] = sl[(15 + i) * Ker<KER>::NK + k];
+                }
+            }
+            acc.add(c);
+        }
+        wave_sync();
+    }
+    if (ovf) atomicOr(a.err, kErrClip);
+    if (active) far_store<KER, T>(a, idx, e == f, acc);
 }
 
 // ------------------------------------------------- phase 1: touching pairs
