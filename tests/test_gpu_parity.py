@@ -8,7 +8,7 @@ FP32 far-field error bound: relative coordinates keep z accurate to a few
 import numpy as np
 import pytest
 
-from inputs import square_mesh, gauss7, paper7, collapsed
+from inputs import square_mesh, gauss7, paper7, collapsed, centroid1
 from inputs.meshes import Mesh
 from inputs.workloads import small_constant, inv_dist_jittered, peridynamic, constant_polygon, c_frac
 from _gpu import gpu_run, to_sparse, rel_frob, f_affine_of
@@ -58,6 +58,11 @@ def _cases():
         "peri_poly": _w("peridynamic", square_mesh(10, delta=0.25, jitter=0.1, seed=13), 0.25, approach="poly"),
         "const_poly_outer_ne_inner": _w("constant", square_mesh(10, delta=0.15, jitter=0.15, seed=14), 0.15,
                                         rule=gauss7(), inner=paper7(), approach="poly"),
+        # outer and inner rules of different sizes (7 and 4 points; 7 and 1)
+        "const_poly_p7_q4": _w("constant", square_mesh(10, delta=0.15, jitter=0.1, seed=15), 0.15,
+                               rule=gauss7(), inner=collapsed(2), approach="poly"),
+        "invdist_p7_q1": _w("inv_dist", square_mesh(10, delta=0.2, jitter=0.15, seed=16), 0.2,
+                            rule=gauss7(), inner=centroid1()),
     }
 
 
