@@ -40,6 +40,16 @@ struct QueueArgs {
     int32_t chunk;
 };
 
+// Problem of item `it`.  Waves whose lanes share one problem (the common
+// case: chunks are long) use the scalar copy, so the per-problem tables are
+// read with scalar loads.
+__device__ inline int uniform_or(int p, bool *uniform)
+{
+    const int p0 = __builtin_amdgcn_readfirstlane(p);
+    *uniform = __all(p == p0);
+    return p0;
+}
+
 __device__ inline int find_prob(const int64_t *pre, int n, int64_t it)
 {
     int lo = 0, hi = n;   // pre[lo] <= it < pre[hi]
@@ -80,9 +90,17 @@ __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *fa, co
         const int64_t b0 = grab(q, &slot);
         if (b0 >= total) break;
         const int64_t b1 = min(b0 + (int64_t)q.chunk, total);
-        for (int64_t it = b0 + threadIdx.x; it < b1; it += blockDim.x) {
-            const int p = find_prob(pre, q.nprob, it);
-            far_item<KER, T, PM, POLY>(fa[p], r1[p], r2[p], it - pre[p]);
+        for (int64_t it0 = b0; it0 < b1; it0 += blockDim.x) {
+            const int64_t it = it0 + threadIdx.x;
+            const bool act = it < b1;
+            const int p = find_prob(pre, q.nprob, act ? it : b0);
+            bool uni;
+            const int p0 = uniform_or(p, &uni);
+            if (uni) {
+                if (act) far_item<KER, T, PM, POLY>(fa[p0], r1[p0], r2[p0], it - pre[p0]);
+            } else if (act) {
+                far_item<KER, T, PM, POLY>(fa[p], r1[p], r2[p], it - pre[p]);
+            }
         }
     }
 }
@@ -99,9 +117,17 @@ __global__ void __launch_bounds__(256) kb_touch(QueueArgs q, const TouchArgs *ta
         const int64_t b0 = grab(q, &slot);
         if (b0 >= total) break;
         const int64_t b1 = min(b0 + (int64_t)q.chunk, total);
-        for (int64_t it = b0 + group; it < b1; it += groups) {   // uniform within a lane group
-            const int p = find_prob(pre, q.nprob, it);
-            touch_item<KER, CLS, G>(ta[p], ga[p], it - pre[p], sub);
+        for (int64_t it0 = b0; it0 < b1; it0 += groups) {
+            const int64_t it = it0 + group;   // uniform within a lane group
+            const bool act = it < b1;
+            const int p = find_prob(pre, q.nprob, act ? it : b0);
+            bool uni;
+            const int p0 = uniform_or(p, &uni);
+            if (uni) {
+                if (act) touch_item<KER, CLS, G>(ta[p0], ga[p0], it - pre[p0], sub);
+            } else if (act) {
+                touch_item<KER, CLS, G>(ta[p], ga[p], it - pre[p], sub);
+            }
         }
     }
 }
@@ -119,30 +145,31 @@ __global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *da)
         if (b0 >= total) break;
         const int64_t b1 = min(b0 + (int64_t)q.chunk, total);
         for (int64_t it = b0 + wave; it < b1; it += waves) {
-            const int p = find_prob(pre, q.nprob, it);
+            // one element per wave: the problem is uniform
+            const int p = __builtin_amdgcn_readfirstlane(find_prob(pre, q.nprob, it));
             diag_item<NK, TR>(da[p], it - pre[p], lane);
         }
     }
 }
 
+// Rows cost about the same each, so they are spread statically, one per
+// workgroup of one wave, with the XCD-aware order of the single-problem
+// kernel over the rows of all problems of the group (no queue).
 template <int NC, typename TR>
 __global__ void __launch_bounds__(64) kb_rows(QueueArgs q, const RowArgs *ra, size_t pre_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ unsigned long long slot;
     __shared__ RowShared sh;
     int64_t *pre = (int64_t *)dyn;
     unsigned char *rowmem = dyn + pre_bytes;
     const int64_t total = load_prefix(q, pre);
-    for (;;) {
-        const int64_t b0 = grab(q, &slot);
-        if (b0 >= total) break;
-        const int64_t b1 = min(b0 + (int64_t)q.chunk, total);
-        for (int64_t it = b0; it < b1; ++it) {
-            const int p = find_prob(pre, q.nprob, it);
-            const RowArgs &a = ra[p];
-            row_item<NC, TR>(a, a.rows[it - pre[p]], rowmem, sh);
-        }
+    for (int64_t b = blockIdx.x; b < xcd_span(total); b += gridDim.x) {
+        const int64_t it = xcd_item(b, total);
+        if (it >= total) continue;
+        // one row per workgroup of one wave: the problem is uniform
+        const int p = __builtin_amdgcn_readfirstlane(find_prob(pre, q.nprob, it));
+        const RowArgs &a = ra[p];
+        row_item<NC, TR>(a, a.rows[it - pre[p]], rowmem, sh);
     }
 }
 
@@ -182,6 +209,8 @@ struct nlfem_batch {
     unsigned long long *counters = nullptr;
     Shape shape[kPhases] = {{1024, 4}, {256, 4}, {64, 4}, {4, 16}};
     hipStream_t capture = nullptr;
+    hipStream_t aux = nullptr;            // touching pairs beside the non-touching ones
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -262,7 +291,7 @@ void launch_group(const nlfem_batch *b, const Group &g, const Shape &sh, hipStre
         break;
     }
     default: {
-        const dim3 grid((unsigned)(b->cus * sh.per_cu)), block(64);
+        const dim3 grid(xcd_grid(g.pre.back())), block(64);
         const RowArgs *ra = dptr<RowArgs>(b, g.off_args);
         const size_t lds = pre_lds + g.row_lds;
         if (g.nc == 1) {
@@ -284,10 +313,19 @@ int run_phase(const nlfem_batch *b, Phase ph, const Shape &sh, hipStream_t s)
     return NLFEM_OK;
 }
 
+// far pairs then element diagonals on s; touching pairs on the batch's
+// second stream beside them; rows after the join
 int run_all(const nlfem_batch *b, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, b->counters, (int)b->groups.size());
-    for (int ph = 0; ph < kPhases; ++ph) NLFEM_TRY(run_phase(b, (Phase)ph, b->shape[ph], s));
+    NLFEM_HIP(hipEventRecord(b->ev_fork, s));
+    NLFEM_HIP(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
+    NLFEM_TRY(run_phase(b, kTouch, b->shape[kTouch], b->aux));
+    NLFEM_HIP(hipEventRecord(b->ev_join, b->aux));
+    NLFEM_TRY(run_phase(b, kFar, b->shape[kFar], s));
+    NLFEM_TRY(run_phase(b, kDiag, b->shape[kDiag], s));
+    NLFEM_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
+    NLFEM_TRY(run_phase(b, kRows, b->shape[kRows], s));
     return NLFEM_OK;
 }
 
@@ -485,6 +523,11 @@ int tune(nlfem_batch *b, hipStream_t s)
         bool any = false;
         for (const Group &g : b->groups) any |= g.phase == ph;
         if (!any) continue;
+        if (ph == kRows) {   // static mapping: nothing to choose
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, b->counters, (int)b->groups.size());
+            rc = run_phase(b, (Phase)ph, b->shape[ph], s);
+            continue;
+        }
         float best = 1e30f;
         for (const Shape &cand : kCandidates[ph]) {
             float total = 0.f;
@@ -534,6 +577,10 @@ int batch_create(const std::vector<AssemblePlan> &plans, const char *tune_cache,
         make_groups(b);
         rc = upload_tables(b);
     }
+    if (rc == NLFEM_OK && (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
+                           hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                           hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess))
+        rc = set_error(NLFEM_E_HIP, "cannot create the batch's second stream");
     if (rc == NLFEM_OK && tune_mode != 0) {
         const std::string key = tune_key(b);
         if (tune_mode == 2 || !cache_read(tune_cache, key, b->shape)) {
@@ -575,13 +622,14 @@ int batch_graph_launch(nlfem_batch *b, hipStream_t s)
 void batch_free(nlfem_batch *b)
 {
     if (!b) return;
+    (void)hipDeviceSynchronize();   // no launch of the batch may still be running
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->capture) (void)hipStreamDestroy(b->capture);
-    if (b->dev) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(b->dev);
-    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
+    if (b->dev) (void)hipFree(b->dev);
     delete b;
 }
 
