@@ -6,12 +6,33 @@ namespace nlfem {
 using namespace items;
 namespace {
 
+// record staging through LDS (coalesced stores) where it fits: all but the
+// two-component FP64 records (32 KB per wave)
+template <int KER, typename T>
+constexpr bool far_staged() { return !(Ker<KER>::NK == 3 && sizeof(T) == 8); }
+
 template <int KER, typename T, int PM, bool POLY>
 __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArgs r2)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.n) return;
-    far_item<KER, T, PM, POLY>(a, r1, r2, idx);
+    if (!far_staged<KER, T>() || POLY) {
+        if (idx >= a.n) return;
+        far_item<KER, T, PM, POLY>(a, r1, r2, idx);
+        return;
+    }
+    constexpr int NV = 21 * Ker<KER>::NK;
+    __shared__ T slots[far_staged<KER, T>() ? 4 * 64 * NV : 1];
+    const int64_t idx0 = idx - (threadIdx.x & 63);
+    if (idx0 >= a.n) return;   // whole waves leave together
+    const int nvalid = (int)min((int64_t)64, a.n - idx0);
+    FarAcc<KER, T> acc;
+    bool self = false;
+    if (idx < a.n) {
+        const int32_t e = a.ue[idx], f = a.uf[idx];
+        self = e == f;
+        far_whole<KER, T, PM>(a, r1, r2, e, f, a.m_ef[idx], a.m_fe[idx], acc);
+    }
+    far_store_wave<KER, T>(a, idx0, nvalid, self, acc, slots + (threadIdx.x >> 6) * 64 * NV);
 }
 
 // polygon ball: one wave per workgroup shares the straddling points of its pairs

@@ -512,6 +512,49 @@ __device__ __forceinline__ void far_store(const FarArgs &a, int64_t idx, bool se
     }
 }
 
+// Records of the pairs idx0 .. idx0 + nvalid - 1 of one wave (lane l holds
+// pair idx0 + l), written through LDS so that the wave stores its
+// contiguous block of records with consecutive addresses.
+template <int KER, typename T>
+__device__ __forceinline__ void far_store_wave(const FarArgs &a, int64_t idx0, int nvalid, bool self,
+                                               const FarAcc<KER, T> &acc, T *slots)
+{
+    constexpr int NK = Ker<KER>::NK, NV = 21 * NK;
+    const int lane = threadIdx.x & 63;
+    T *sl = slots + lane * NV;
+    if (lane < nvalid) {
+        if (self) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) sl[(3 * i + j) * NK + k] = acc.X[i][j][k] + acc.X[j][i][k];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    sl[(9 + i) * NK + k] = acc.De[i][k] + acc.Df[i][k];
+                    sl[(15 + i) * NK + k] = 0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) sl[i * NK + k] = acc.X[i / 3][i % 3][k];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    sl[(9 + i) * NK + k] = acc.De[i][k];
+                    sl[(15 + i) * NK + k] = acc.Df[i][k];
+                }
+            }
+        }
+    }
+    wave_sync();
+    T *out = (T *)a.rec + idx0 * NV;   // the record stride is NV
+    for (int t = lane; t < nvalid * NV; t += 64) out[t] = slots[t];
+    wave_sync();
+}
+
 // record of unordered non-touching pair idx, one lane alone
 template <int KER, typename T, int PM, bool POLY>
 __device__ __forceinline__ void far_item(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int64_t idx)

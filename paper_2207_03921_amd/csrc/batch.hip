@@ -79,13 +79,21 @@ __device__ inline int64_t grab(const QueueArgs &q, unsigned long long *slot)
     return b0;
 }
 
+// records staged through LDS as in the single-problem kernel where it fits
+template <int KER, typename T>
+constexpr bool batch_far_staged() { return !(Ker<KER>::NK == 3 && sizeof(T) == 8); }
+
 template <int KER, typename T, int PM, bool POLY>
 __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *fa, const RoleArgs *r1, const RoleArgs *r2)
 {
+    constexpr bool STAGED = batch_far_staged<KER, T>() && !POLY;
+    constexpr int NV = 21 * Ker<KER>::NK;
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
+    __shared__ T slots[STAGED ? 4 * 64 * NV : 1];
     int64_t *pre = (int64_t *)dyn;
     const int64_t total = load_prefix(q, pre);
+    const int lane = threadIdx.x & 63;
     for (;;) {
         const int64_t b0 = grab(q, &slot);
         if (b0 >= total) break;
@@ -96,7 +104,22 @@ __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *fa, co
             const int p = find_prob(pre, q.nprob, act ? it : b0);
             bool uni;
             const int p0 = uniform_or(p, &uni);
-            if (uni) {
+            if (uni && STAGED) {
+                // the wave's active lanes hold consecutive pairs of one problem
+                const FarArgs &a = fa[p0];
+                const int64_t first = it - lane;
+                const int nvalid = (int)max((int64_t)0, min((int64_t)64, b1 - first));
+                FarAcc<KER, T> acc;
+                bool self = false;
+                if (act) {
+                    const int64_t idx = it - pre[p0];
+                    const int32_t e = a.ue[idx], f = a.uf[idx];
+                    self = e == f;
+                    far_whole<KER, T, PM>(a, r1[p0], r2[p0], e, f, a.m_ef[idx], a.m_fe[idx], acc);
+                }
+                if (nvalid > 0)
+                    far_store_wave<KER, T>(a, first - pre[p0], nvalid, self, acc, slots + (threadIdx.x >> 6) * 64 * NV);
+            } else if (uni) {
                 if (act) far_item<KER, T, PM, POLY>(fa[p0], r1[p0], r2[p0], it - pre[p0]);
             } else if (act) {
                 far_item<KER, T, PM, POLY>(fa[p], r1[p], r2[p], it - pre[p]);
