@@ -47,13 +47,43 @@ __global__ void __launch_bounds__(64) k_far_rec_poly(FarArgs a, RoleArgs r1, Rol
     far_wave_poly<KER, T, PM>(a, r1, r2, idx, idx < a.n, queue, pe, pf, slots);
 }
 
-template <int KER, int CLS, int G>
-__global__ void __launch_bounds__(256) k_touch_rec(TouchArgs a, GaussArgs g)
+// the three classes in one launch: blocks [0, nb[0]) take the vertex class
+// (the longest items first), then edge, then identical
+struct TouchLaunch {
+    TouchArgs t[3];   // identical, edge, vertex
+    int64_t nb[3];    // blocks of the vertex, edge and identical classes
+};
+
+template <int KER, int CLS>
+__device__ __forceinline__ void touch_block(const TouchArgs &a, const GaussView &g, int64_t b)
 {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int G = touch_lanes(CLS);
+    const int64_t gid = b * 256 + threadIdx.x;
     const int64_t pair = gid / G;
     if (pair >= a.n) return;   // whole groups leave together
     touch_item<KER, CLS, G>(a, g, pair, (int)(gid % G));
+}
+
+template <int KER>
+__global__ void __launch_bounds__(256) k_touch_rec(TouchLaunch L, GaussArgs g)
+{
+    // the rule in LDS: the point loops read it at every step
+    __shared__ double gs[2 * kMaxGauss];
+    if (threadIdx.x < 2 * kMaxGauss)
+        gs[threadIdx.x] = threadIdx.x < kMaxGauss ? g.x[threadIdx.x] : g.w[threadIdx.x - kMaxGauss];
+    __syncthreads();
+    const GaussView gv{gs, gs + kMaxGauss, g.n};
+    int64_t b = blockIdx.x;
+    if (b < L.nb[0]) {
+        touch_block<KER, 1>(L.t[2], gv, b);
+        return;
+    }
+    b -= L.nb[0];
+    if (b < L.nb[1]) {
+        touch_block<KER, 2>(L.t[1], gv, b);
+        return;
+    }
+    touch_block<KER, 3>(L.t[0], gv, b - L.nb[1]);
 }
 
 template <int NK, typename TR>
@@ -107,16 +137,13 @@ void far_dispatch(const AssemblePlan &p, hipStream_t s)
 template <int KER>
 void touch_dispatch(const AssemblePlan &p, hipStream_t s)
 {
-    constexpr int G = 16;
-    if (p.touch[0].n > 0)
-        hipLaunchKernelGGL((k_touch_rec<KER, 3, G>), dim3(grid_for(p.touch[0].n * G, 256)), dim3(256), 0, s,
-                           p.touch[0], p.gauss);
-    if (p.touch[1].n > 0)
-        hipLaunchKernelGGL((k_touch_rec<KER, 2, G>), dim3(grid_for(p.touch[1].n * G, 256)), dim3(256), 0, s,
-                           p.touch[1], p.gauss);
-    if (p.touch[2].n > 0)
-        hipLaunchKernelGGL((k_touch_rec<KER, 1, G>), dim3(grid_for(p.touch[2].n * G, 256)), dim3(256), 0, s,
-                           p.touch[2], p.gauss);
+    TouchLaunch L{};
+    for (int c = 0; c < 3; ++c) L.t[c] = p.touch[c];
+    L.nb[0] = (p.touch[2].n * touch_lanes(1) + 255) / 256;
+    L.nb[1] = (p.touch[1].n * touch_lanes(2) + 255) / 256;
+    L.nb[2] = (p.touch[0].n * touch_lanes(3) + 255) / 256;
+    const int64_t blocks = L.nb[0] + L.nb[1] + L.nb[2];
+    if (blocks > 0) hipLaunchKernelGGL((k_touch_rec<KER>), dim3((unsigned)blocks), dim3(256), 0, s, L, p.gauss);
 }
 
 }  // namespace

@@ -131,11 +131,14 @@ __device__ inline int touch_frame(int cls, const int32_t *ek, const int32_t *el,
                 ia = i;
                 ib = j;
             }
-    n[0] = ek[ia];
-    n[1] = ek[(ia + 1) % 3];
-    n[2] = ek[(ia + 2) % 3];
-    n[3] = el[(ib + 1) % 3];
-    n[4] = el[(ib + 2) % 3];
+    // selects instead of indexing, so the triples stay in registers
+    const int a1 = ia == 2 ? 0 : ia + 1, a2 = ia == 0 ? 2 : ia - 1;
+    const int b1 = ib == 2 ? 0 : ib + 1, b2 = ib == 0 ? 2 : ib - 1;
+    n[0] = ia == 0 ? ek[0] : ia == 1 ? ek[1] : ek[2];
+    n[1] = a1 == 0 ? ek[0] : a1 == 1 ? ek[1] : ek[2];
+    n[2] = a2 == 0 ? ek[0] : a2 == 1 ? ek[1] : ek[2];
+    n[3] = b1 == 0 ? el[0] : b1 == 1 ? el[1] : el[2];
+    n[4] = b2 == 0 ? el[0] : b2 == 1 ? el[1] : el[2];
     return 5;
 }
 
@@ -679,6 +682,13 @@ struct TouchArgs {
     double c;
 };
 
+// 1-D Gauss rule on [0, 1] as the touching-pair loops read it (in LDS
+// where the caller staged it)
+struct GaussView {
+    const double *x, *w;
+    int n;
+};
+
 // accumulate w * Psi(z) (g g^T) into the packed upper triangle of L
 template <int KER, int NU>
 __device__ inline void acc_sample(double *L, double w, double zx, double zy, const double *g, double c)
@@ -687,27 +697,33 @@ __device__ inline void acc_sample(double *L, double w, double zx, double zy, con
     constexpr int D = NU * NC;
     double k[3];
     kernel_eval<KER, double>(zx, zy, c, k);
-    double kk[2][2];
+    double wk[2][2];
     if (NC == 1) {
-        kk[0][0] = k[0];
+        wk[0][0] = w * k[0];
     } else {
-        kk[0][0] = k[0];
-        kk[0][1] = kk[1][0] = k[1];
-        kk[1][1] = k[2];
+        wk[0][0] = w * k[0];
+        wk[0][1] = wk[1][0] = w * k[1];
+        wk[1][1] = w * k[2];
     }
     int idx = 0;
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-        const double wr = w * g[r / NC];
+        const double gr = g[r / NC];
 #pragma unroll
-        for (int s = r; s < D; ++s) L[idx++] += wr * kk[r % NC][s % NC] * g[s / NC];
+        for (int s = r; s < D; ++s) L[idx++] += (gr * wk[r % NC][s % NC]) * g[s / NC];
     }
 }
+
+// lanes per touching pair: the vertex class (2n^3 points) runs in groups of
+// 8, so a launch holds fewer, longer waves and the gathers that start each
+// wave are paid less often; the others in groups of 16.  The grouping fixes
+// the order of the sums, so every path uses this one.
+__host__ __device__ constexpr int touch_lanes(int cls) { return cls == 1 ? 8 : 16; }
 
 // record of touching pair `pair` of class CLS, computed by the G lanes
 // sub = 0..G-1 of an aligned lane group (all of them must call)
 template <int KER, int CLS, int G>
-__device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussArgs &g, int64_t pair, int sub)
+__device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussView &g, int64_t pair, int sub)
 {
     constexpr int NC = Ker<KER>::NC;
     constexpr int NU = CLS == 3 ? 3 : CLS == 2 ? 4 : 5;

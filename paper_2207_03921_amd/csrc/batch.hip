@@ -133,9 +133,13 @@ __global__ void __launch_bounds__(256) kb_touch(QueueArgs q, const TouchArgs *ta
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
+    __shared__ double gst[4][2 * kMaxGauss];   // the rule of the wave's problem
     int64_t *pre = (int64_t *)dyn;
     const int64_t total = load_prefix(q, pre);
     const int group = threadIdx.x / G, sub = threadIdx.x % G, groups = blockDim.x / G;
+    const int lane = threadIdx.x & 63;
+    double *gw = gst[threadIdx.x >> 6];
+    int staged = -1;   // problem whose rule gw holds (uniform in the wave)
     for (;;) {
         const int64_t b0 = grab(q, &slot);
         if (b0 >= total) break;
@@ -147,9 +151,15 @@ __global__ void __launch_bounds__(256) kb_touch(QueueArgs q, const TouchArgs *ta
             bool uni;
             const int p0 = uniform_or(p, &uni);
             if (uni) {
-                if (act) touch_item<KER, CLS, G>(ta[p0], ga[p0], it - pre[p0], sub);
+                if (p0 != staged) {
+                    wave_sync();
+                    gw[lane] = lane < kMaxGauss ? ga[p0].x[lane] : ga[p0].w[lane - kMaxGauss];
+                    wave_sync();
+                    staged = p0;
+                }
+                if (act) touch_item<KER, CLS, G>(ta[p0], GaussView{gw, gw + kMaxGauss, ga[p0].n}, it - pre[p0], sub);
             } else if (act) {
-                touch_item<KER, CLS, G>(ta[p], ga[p], it - pre[p], sub);
+                touch_item<KER, CLS, G>(ta[p], GaussView{ga[p].x, ga[p].w, ga[p].n}, it - pre[p], sub);
             }
         }
     }
@@ -276,14 +286,13 @@ void far_group_k(const nlfem_batch *b, const Group &g, const QueueArgs &q, const
 template <int KER>
 void touch_group(const nlfem_batch *b, const Group &g, const QueueArgs &q, const Shape &sh, hipStream_t s)
 {
-    constexpr int G = 16;
     const size_t lds = sizeof(int64_t) * (g.probs.size() + 1);
     const dim3 grid((unsigned)(b->cus * sh.per_cu)), block(256);
     const TouchArgs *ta = dptr<TouchArgs>(b, g.off_args);
     const GaussArgs *ga = dptr<GaussArgs>(b, g.off_r1);
-    if (g.cls == 3) hipLaunchKernelGGL((kb_touch<KER, 3, G>), grid, block, lds, s, q, ta, ga);
-    else if (g.cls == 2) hipLaunchKernelGGL((kb_touch<KER, 2, G>), grid, block, lds, s, q, ta, ga);
-    else hipLaunchKernelGGL((kb_touch<KER, 1, G>), grid, block, lds, s, q, ta, ga);
+    if (g.cls == 3) hipLaunchKernelGGL((kb_touch<KER, 3, touch_lanes(3)>), grid, block, lds, s, q, ta, ga);
+    else if (g.cls == 2) hipLaunchKernelGGL((kb_touch<KER, 2, touch_lanes(2)>), grid, block, lds, s, q, ta, ga);
+    else hipLaunchKernelGGL((kb_touch<KER, 1, touch_lanes(1)>), grid, block, lds, s, q, ta, ga);
 }
 
 void launch_group(const nlfem_batch *b, const Group &g, const Shape &sh, hipStream_t s)
