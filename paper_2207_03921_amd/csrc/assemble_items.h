@@ -199,9 +199,7 @@ __device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double
 #pragma unroll
         for (int k = 0; k < NK; ++k) beta[q][k] = 0;
     }
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-        if (p >= PA) continue;
+    auto outer = [&](int p) {
         const T ox = (T)(Je.x * r.xa[p][0] + Je.y * r.xa[p][1]) + dx;
         const T oy = (T)(Je.z * r.xa[p][0] + Je.w * r.xa[p][1]) + dy;
         const T we0 = (T)(r.wa[p] * dete);
@@ -240,6 +238,17 @@ __device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double
             De[4][k] += alpha[k] * pp[1] * pp[2];
             De[5][k] += alpha[k] * pp[2] * pp[2];
         }
+    };
+    if constexpr (PM > 0) {
+        // a fixed rule: the outer points in a loop (uniform index into the
+        // rule tables), the inner ones unrolled, which keeps the register
+        // count at an occupancy of 4 waves (FP32)
+#pragma unroll 1
+        for (int p = 0; p < PM; ++p) outer(p);
+    } else {
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p)
+            if (p < PA) outer(p);
     }
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) {
@@ -515,17 +524,19 @@ __device__ __forceinline__ void far_store(const FarArgs &a, int64_t idx, bool se
     }
 }
 
-// Records of the pairs idx0 .. idx0 + nvalid - 1 of one wave (lane l holds
-// pair idx0 + l), written through LDS so that the wave stores its
-// contiguous block of records with consecutive addresses.
+// Records of the pairs idx0 .. idx0 + nvalid - 1 of one wave (lane
+// lane0 + l holds pair idx0 + l), written through LDS so that the wave
+// stores its contiguous block of records with consecutive addresses.  All
+// lanes of the wave call it.
 template <int KER, typename T>
 __device__ __forceinline__ void far_store_wave(const FarArgs &a, int64_t idx0, int nvalid, bool self,
-                                               const FarAcc<KER, T> &acc, T *slots)
+                                               const FarAcc<KER, T> &acc, T *slots, int lane0 = 0)
 {
     constexpr int NK = Ker<KER>::NK, NV = 21 * NK;
-    const int lane = threadIdx.x & 63;
+    const int hw = threadIdx.x & 63;
+    const int lane = hw - lane0;   // position of this lane's pair in the run
     T *sl = slots + lane * NV;
-    if (lane < nvalid) {
+    if (lane >= 0 && lane < nvalid) {
         if (self) {
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
@@ -554,7 +565,7 @@ __device__ __forceinline__ void far_store_wave(const FarArgs &a, int64_t idx0, i
     }
     wave_sync();
     T *out = (T *)a.rec + idx0 * NV;   // the record stride is NV
-    for (int t = lane; t < nvalid * NV; t += 64) out[t] = slots[t];
+    for (int t = hw; t < nvalid * NV; t += 64) out[t] = slots[t];
     wave_sync();
 }
 

@@ -40,14 +40,24 @@ struct QueueArgs {
     int32_t chunk;
 };
 
-// Problem of item `it`.  Waves whose lanes share one problem (the common
-// case: chunks are long) use the scalar copy, so the per-problem tables are
-// read with scalar loads.
-__device__ inline int uniform_or(int p, bool *uniform)
+// The lanes of a wave hold consecutive items, so the items of one problem
+// sit in a run of consecutive lanes.  A wave takes its problems one run at a
+// time: `next_run` returns the problem of the first pending lane as a
+// wave-uniform value (the per-problem tables are then read with scalar
+// loads), its first lane and its lane mask, and removes the run from `todo`.
+struct Run {
+    int p, lane0;
+    unsigned long long mask;
+};
+
+__device__ inline Run next_run(int p, unsigned long long *todo)
 {
-    const int p0 = __builtin_amdgcn_readfirstlane(p);
-    *uniform = __all(p == p0);
-    return p0;
+    Run r;
+    r.lane0 = (int)__builtin_ctzll(*todo);
+    r.p = __builtin_amdgcn_readlane(p, r.lane0);
+    r.mask = __ballot(p == r.p);
+    *todo &= ~r.mask;
+    return r;
 }
 
 __device__ inline int find_prob(const int64_t *pre, int n, int64_t it)
@@ -84,7 +94,8 @@ template <int KER, typename T>
 constexpr bool batch_far_staged() { return !(Ker<KER>::NK == 3 && sizeof(T) == 8); }
 
 template <int KER, typename T, int PM, bool POLY>
-__global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *fa, const RoleArgs *r1, const RoleArgs *r2)
+__global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *__restrict__ fa, const RoleArgs *__restrict__ r1,
+                                                const RoleArgs *__restrict__ r2)
 {
     constexpr bool STAGED = batch_far_staged<KER, T>() && !POLY;
     constexpr int NV = 21 * Ker<KER>::NK;
@@ -101,35 +112,34 @@ __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *fa, co
         for (int64_t it0 = b0; it0 < b1; it0 += blockDim.x) {
             const int64_t it = it0 + threadIdx.x;
             const bool act = it < b1;
-            const int p = find_prob(pre, q.nprob, act ? it : b0);
-            bool uni;
-            const int p0 = uniform_or(p, &uni);
-            if (uni && STAGED) {
-                // the wave's active lanes hold consecutive pairs of one problem
-                const FarArgs &a = fa[p0];
-                const int64_t first = it - lane;
-                const int nvalid = (int)max((int64_t)0, min((int64_t)64, b1 - first));
-                FarAcc<KER, T> acc;
-                bool self = false;
-                if (act) {
-                    const int64_t idx = it - pre[p0];
-                    const int32_t e = a.ue[idx], f = a.uf[idx];
-                    self = e == f;
-                    far_whole<KER, T, PM>(a, r1[p0], r2[p0], e, f, a.m_ef[idx], a.m_fe[idx], acc);
+            const int p = act ? find_prob(pre, q.nprob, it) : -1;
+            unsigned long long todo = __ballot(act);
+            while (todo) {
+                const Run r = next_run(p, &todo);
+                const bool mine = p == r.p;
+                const int64_t base = pre[r.p];
+                if (STAGED) {
+                    const FarArgs &a = fa[r.p];
+                    FarAcc<KER, T> acc;
+                    bool self = false;
+                    if (mine) {
+                        const int64_t idx = it - base;
+                        const int32_t e = a.ue[idx], f = a.uf[idx];
+                        self = e == f;
+                        far_whole<KER, T, PM>(a, r1[r.p], r2[r.p], e, f, a.m_ef[idx], a.m_fe[idx], acc);
+                    }
+                    far_store_wave<KER, T>(a, it - lane + r.lane0 - base, __popcll(r.mask), self, acc,
+                                           slots + (threadIdx.x >> 6) * 64 * NV, r.lane0);
+                } else if (mine) {
+                    far_item<KER, T, PM, POLY>(fa[r.p], r1[r.p], r2[r.p], it - base);
                 }
-                if (nvalid > 0)
-                    far_store_wave<KER, T>(a, first - pre[p0], nvalid, self, acc, slots + (threadIdx.x >> 6) * 64 * NV);
-            } else if (uni) {
-                if (act) far_item<KER, T, PM, POLY>(fa[p0], r1[p0], r2[p0], it - pre[p0]);
-            } else if (act) {
-                far_item<KER, T, PM, POLY>(fa[p], r1[p], r2[p], it - pre[p]);
             }
         }
     }
 }
 
 template <int KER, int CLS, int G>
-__global__ void __launch_bounds__(256) kb_touch(QueueArgs q, const TouchArgs *ta, const GaussArgs *ga)
+__global__ void __launch_bounds__(256) kb_touch(QueueArgs q, const TouchArgs *__restrict__ ta, const GaussArgs *__restrict__ ga)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
@@ -147,26 +157,25 @@ __global__ void __launch_bounds__(256) kb_touch(QueueArgs q, const TouchArgs *ta
         for (int64_t it0 = b0; it0 < b1; it0 += groups) {
             const int64_t it = it0 + group;   // uniform within a lane group
             const bool act = it < b1;
-            const int p = find_prob(pre, q.nprob, act ? it : b0);
-            bool uni;
-            const int p0 = uniform_or(p, &uni);
-            if (uni) {
-                if (p0 != staged) {
+            const int p = act ? find_prob(pre, q.nprob, it) : -1;
+            unsigned long long todo = __ballot(act);
+            while (todo) {
+                const Run r = next_run(p, &todo);   // whole lane groups
+                if (r.p != staged) {
                     wave_sync();
-                    gw[lane] = lane < kMaxGauss ? ga[p0].x[lane] : ga[p0].w[lane - kMaxGauss];
+                    gw[lane] = lane < kMaxGauss ? ga[r.p].x[lane] : ga[r.p].w[lane - kMaxGauss];
                     wave_sync();
-                    staged = p0;
+                    staged = r.p;
                 }
-                if (act) touch_item<KER, CLS, G>(ta[p0], GaussView{gw, gw + kMaxGauss, ga[p0].n}, it - pre[p0], sub);
-            } else if (act) {
-                touch_item<KER, CLS, G>(ta[p], GaussView{ga[p].x, ga[p].w, ga[p].n}, it - pre[p], sub);
+                if (p == r.p)
+                    touch_item<KER, CLS, G>(ta[r.p], GaussView{gw, gw + kMaxGauss, ga[r.p].n}, it - pre[r.p], sub);
             }
         }
     }
 }
 
 template <int NK, typename TR>
-__global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *da)
+__global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *__restrict__ da)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
@@ -189,7 +198,7 @@ __global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *da)
 // workgroup of one wave, with the XCD-aware order of the single-problem
 // kernel over the rows of all problems of the group (no queue).
 template <int NC, typename TR>
-__global__ void __launch_bounds__(64) kb_rows(QueueArgs q, const RowArgs *ra, size_t pre_bytes)
+__global__ void __launch_bounds__(64) kb_rows(QueueArgs q, const RowArgs *__restrict__ ra, size_t pre_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ RowShared sh;
