@@ -278,7 +278,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_CELLFILL, ncell, h->cell_fill));
     NLFEM_TRY(ensure_typed(h, B_CELLELEMS, K, h->cell_elems));
     NLFEM_TRY(ensure_typed(h, B_CELLOF, K, h->cell_of));
-    const int64_t scan_need = std::max({scan_tmp_size(K, kLsLast), scan_tmp_size(M), scan_tmp_size(ncell)}) + 1;
+    const int64_t scan_need = std::max(scan_tmp_size(K, kLsLast), scan_tmp_size(M) + scan_tmp_size(ncell)) + 1;
     NLFEM_TRY(ensure_typed(h, B_SCAN, scan_need, h->scan_tmp));
     h->scan_cap = (int64_t)(h->bufs[B_SCAN].cap / sizeof(int64_t));
     NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
@@ -305,14 +305,14 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         z.add(h->red + kRedMaxCell, kRedErr - kRedMaxCell);   // slots 6..17, keeps the error bits
         NLFEM_TRY(launch_zero(z, nullptr, s));
     }
-    // node -> element incidence and the dof rows ------------------------------
-    NLFEM_TRY(launch_incidence_count(h, m, s));
-    NLFEM_TRY(exclusive_scan(h->nlen, h->ne_ptr, M, h->scan_tmp, h->scan_cap, s));
-    NLFEM_TRY(launch_incidence(h, m, s));
-    NLFEM_TRY(launch_count_dofs(h, s));
-    NLFEM_TRY(launch_cell_count(h, s));
-    NLFEM_TRY(exclusive_scan(h->cell_cnt, h->cell_start, ncell, h->scan_tmp, h->scan_cap, s));
-    NLFEM_TRY(launch_cell_fill(h, s));
+    // node -> element incidence, grid cells, dof rows ---------------------
+    NLFEM_TRY(launch_bucket_count(h, m, s));
+    {
+        const ScanPart parts[2] = {{h->nlen, h->ne_ptr, M, nullptr, nullptr},
+                                   {h->cell_cnt, h->cell_start, ncell, nullptr, nullptr}};
+        NLFEM_TRY(exclusive_scan_multi(parts, 2, h->scan_tmp, h->scan_cap, s));
+    }
+    NLFEM_TRY(launch_bucket_fill(h, m, s));
 
     // pair search: count, scan, fill ---------------------------------------
     timing_begin(kPhPairs, s);

@@ -142,56 +142,6 @@ __global__ void __launch_bounds__(256) k_zero(ZeroList z, unsigned long long *re
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.n[r]; i += stride) z.p[r][i] = 0u;
 }
 
-__global__ void __launch_bounds__(256) k_incidence_count(int64_t K, int64_t M, const int32_t *E, int64_t *cnt)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    for (int a = 0; a < 3; ++a) {
-        int32_t n = E[3 * k + a];
-        if (n >= 0 && n < M) atomicAdd((unsigned long long *)&cnt[n], 1ull);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_incidence_fill(int64_t K, int64_t M, const int32_t *E,
-                                                        const int64_t *ptr, int32_t *fill, int32_t *list)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    for (int a = 0; a < 3; ++a) {
-        int32_t n = E[3 * k + a];
-        if (n >= 0 && n < M) {
-            int32_t pos = atomicAdd(&fill[n], 1);
-            list[ptr[n] + pos] = (int32_t)k;
-        }
-    }
-}
-
-// Degree-of-freedom nodes: count (out) and list.  Each block appends its
-// 256 consecutive nodes as one contiguous run, so the list keeps mesh
-// locality within runs (the order of the runs is arbitrary).  Also clears
-// the CSR row lengths for the symbolic pass, which visits dof rows only.
-__global__ void __launch_bounds__(256) k_count_dofs(int64_t M, const uint32_t *flags, unsigned long long *out,
-                                                    int32_t *list, int64_t *nlen)
-{
-    __shared__ int wsum[4];
-    __shared__ unsigned long long base;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const bool d = i < M && flags[i] == 1u;
-    if (i < M) nlen[i] = 0;
-    const unsigned long long b = __ballot(d);
-    if (lane == 0) wsum[w] = __popcll(b);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int n = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        base = n ? atomicAdd(out, (unsigned long long)n) : 0ull;
-    }
-    __syncthreads();
-    int before = 0;
-    for (int k = 0; k < w; ++k) before += wsum[k];
-    if (d) list[base + before + __popcll(b & ((1ull << lane) - 1ull))] = (int32_t)i;
-}
-
 }  // namespace
 
 int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s)
@@ -200,14 +150,6 @@ int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s)
     for (int r = 0; r < z.cnt; ++r) most = std::max<int64_t>(most, z.n[r]);
     const unsigned grid = (unsigned)std::min<int64_t>(grid_for(most, 256), 2048);
     hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, z, init_red);
-    NLFEM_HIP(hipGetLastError());
-    return NLFEM_OK;
-}
-
-int launch_count_dofs(nlfem_pairs *h, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_count_dofs, dim3(grid_for(h->M, 256)), dim3(256), 0, s, h->M, h->node_flags, h->red + 8,
-                       h->dof_list, h->nlen);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }
@@ -232,20 +174,5 @@ int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     return NLFEM_OK;
 }
 
-int launch_incidence_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_incidence_count, dim3(grid_for(h->K, 256)), dim3(256), 0, s, h->K, h->M,
-                       m->elements, h->nlen);
-    NLFEM_HIP(hipGetLastError());
-    return NLFEM_OK;
-}
-
-int launch_incidence(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_incidence_fill, dim3(grid_for(h->K, 256)), dim3(256), 0, s, h->K, h->M,
-                       m->elements, h->ne_ptr, h->ne_fill, h->ne_list);
-    NLFEM_HIP(hipGetLastError());
-    return NLFEM_OK;
-}
 
 }  // namespace nlfem

@@ -234,18 +234,29 @@ int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int
 // totals[k] = total and maxes[k] = largest input of segment k when given
 int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
                             int64_t tmp_cap, int64_t *totals, hipStream_t s, int64_t *maxes = nullptr);
+// up to kScanParts independent arrays in one pair of launches; the workspace
+// needs the sum of scan_tmp_size(n_k) over the parts
+constexpr int kScanParts = 8;
+struct ScanPart {
+    const int64_t *in;
+    int64_t *out;       // [n + 1]
+    int64_t n;
+    int64_t *total;     // device, optional
+    int64_t *maxv;      // device, optional
+};
+int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t tmp_cap, hipStream_t s);
 int64_t scan_tmp_size(int64_t n, int nseg = 1);
 double key_to_double(unsigned long long key);
 
 // geometry.hip
 int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
-int launch_incidence(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);   // needs ne_ptr scanned
-int launch_incidence_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
-int launch_count_dofs(nlfem_pairs *h, hipStream_t s);   // -> red[8], dof_list, nlen = 0
 int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s);
 // grid + pairs (pairs.hip)
-int launch_cell_count(nlfem_pairs *h, hipStream_t s);
-int launch_cell_fill(nlfem_pairs *h, hipStream_t s);   // also sorts cells, max occupancy -> red[6]
+// node -> element incidence counts (nlen) and grid cell counts (cell_cnt)
+int launch_bucket_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
+// incidence lists and cell element lists (needs ne_ptr and cell_start),
+// the dof-node list and count (red[8]); clears nlen
+int launch_bucket_fill(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
 // lists.hip: sorted neighbour lists, work lists and record links
 int launch_sort_lists(nlfem_pairs *h, hipStream_t s);

@@ -463,23 +463,37 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
 
 // ---- grid build ---------------------------------------------------------------
 
-struct CellArgs {
-    int64_t K;
-    const int32_t *lab;
+// Per element: its three node -> element incidences and its grid cell (by
+// barycentre; elements outside the domain labels get no cell).  Counting and
+// filling use atomics, so the order within an incidence list or a cell is
+// arbitrary; every consumer either sorts (neighbour lists, CSR columns) or
+// does not depend on it.
+struct BucketArgs {
+    int64_t K, M;
+    const int32_t *E, *lab;
     const double2 *bary;
     double x0, y0, h;
     int32_t nx, ny;
-    int64_t *cnt;
-    const int64_t *start;
-    int32_t *fill;
-    int32_t *elems;
-    int32_t *cell_of;
+    int64_t *cell_cnt;
+    const int64_t *cell_start;
+    int32_t *cell_fill, *cell_elems, *cell_of;
+    int64_t *inc_cnt;              // count pass; cleared by the fill pass
+    const int64_t *inc_ptr;
+    int32_t *inc_fill, *inc_list;
+    const uint32_t *node_flags;    // 1: dof node
+    unsigned long long *ndof;
+    int32_t *dof_list;
+    int64_t elem_blocks;           // fill pass: blocks over elements, then over nodes
 };
 
-__global__ void __launch_bounds__(256) k_cell_count(CellArgs a)
+__global__ void __launch_bounds__(256) k_bucket_count(BucketArgs a)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.K) return;
+    for (int v = 0; v < 3; ++v) {
+        const int32_t n = a.E[3 * k + v];
+        if (n >= 0 && n < a.M) atomicAdd((unsigned long long *)&a.inc_cnt[n], 1ull);
+    }
     const int32_t l = a.lab[k];
     if (l != 1 && l != 2) {
         a.cell_of[k] = -1;
@@ -491,58 +505,98 @@ __global__ void __launch_bounds__(256) k_cell_count(CellArgs a)
     cy = min(max(cy, 0), a.ny - 1);
     const int c = cy * a.nx + cx;
     a.cell_of[k] = c;
-    atomicAdd((unsigned long long *)&a.cnt[c], 1ull);
+    atomicAdd((unsigned long long *)&a.cell_cnt[c], 1ull);
 }
 
-__global__ void __launch_bounds__(256) k_cell_fill(CellArgs a)
+// Degree-of-freedom nodes: count and list.  Each block appends its 256
+// consecutive nodes as one contiguous run, so the list keeps mesh locality
+// within runs (the order of the runs is arbitrary).  Also clears the CSR row
+// lengths (the incidence counts, scanned by now) for the symbolic pass.
+__device__ void dof_block(const BucketArgs &a, int64_t blk)
 {
+    __shared__ int wsum[4];
+    __shared__ unsigned long long base;
+    const int64_t i = blk * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bool d = i < a.M && a.node_flags[i] == 1u;
+    if (i < a.M) a.inc_cnt[i] = 0;
+    const unsigned long long b = __ballot(d);
+    if (lane == 0) wsum[w] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int n = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base = n ? atomicAdd(a.ndof, (unsigned long long)n) : 0ull;
+    }
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    if (d) a.dof_list[base + before + __popcll(b & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(256) k_bucket_fill(BucketArgs a)
+{
+    if ((int64_t)blockIdx.x >= a.elem_blocks) {
+        dof_block(a, blockIdx.x - a.elem_blocks);
+        return;
+    }
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.K) return;
+    for (int v = 0; v < 3; ++v) {
+        const int32_t n = a.E[3 * k + v];
+        if (n >= 0 && n < a.M) {
+            const int32_t pos = atomicAdd(&a.inc_fill[n], 1);
+            a.inc_list[a.inc_ptr[n] + pos] = (int32_t)k;
+        }
+    }
     const int c = a.cell_of[k];
     if (c < 0) return;
-    const int32_t pos = atomicAdd(&a.fill[c], 1);
-    a.elems[a.start[c] + pos] = (int32_t)k;
+    const int32_t pos = atomicAdd(&a.cell_fill[c], 1);
+    a.cell_elems[a.cell_start[c] + pos] = (int32_t)k;
 }
 
-// per-cell insertion sort (cells hold tens of elements)
-__global__ void __launch_bounds__(256) k_cell_sort(int64_t ncell, const int64_t *start, int32_t *elems)
+BucketArgs bucket_args(nlfem_pairs *h, const nlfem_mesh *m)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int64_t s = start[c], e = start[c + 1];
-    for (int64_t i = s + 1; i < e; ++i) {
-        int32_t v = elems[i];
-        int64_t j = i - 1;
-        while (j >= s && elems[j] > v) {
-            elems[j + 1] = elems[j];
-            --j;
-        }
-        elems[j + 1] = v;
-    }
-}
-
-CellArgs cell_args(nlfem_pairs *h)
-{
-    return CellArgs{h->K, h->mesh_labels, h->bary, h->gx0, h->gy0, h->gh, h->gnx, h->gny,
-                    h->cell_cnt, h->cell_start, h->cell_fill, h->cell_elems, h->cell_of};
+    BucketArgs a{};
+    a.K = h->K;
+    a.M = h->M;
+    a.E = m->elements;
+    a.lab = h->mesh_labels;
+    a.bary = h->bary;
+    a.x0 = h->gx0;
+    a.y0 = h->gy0;
+    a.h = h->gh;
+    a.nx = h->gnx;
+    a.ny = h->gny;
+    a.cell_cnt = h->cell_cnt;
+    a.cell_start = h->cell_start;
+    a.cell_fill = h->cell_fill;
+    a.cell_elems = h->cell_elems;
+    a.cell_of = h->cell_of;
+    a.inc_cnt = h->nlen;
+    a.inc_ptr = h->ne_ptr;
+    a.inc_fill = h->ne_fill;
+    a.inc_list = h->ne_list;
+    a.node_flags = h->node_flags;
+    a.ndof = h->red + kRedDofs;
+    a.dof_list = h->dof_list;
+    a.elem_blocks = grid_for(h->K, 256);
+    return a;
 }
 
 }  // namespace
 
-int launch_cell_count(nlfem_pairs *h, hipStream_t s)
+int launch_bucket_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
-    const int64_t ncell = (int64_t)h->gnx * h->gny;
-    hipLaunchKernelGGL(k_cell_count, dim3(grid_for(h->K, 256)), dim3(256), 0, s, cell_args(h));
+    if (h->K > 0) hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(h->K, 256)), dim3(256), 0, s, bucket_args(h, m));
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }
 
-int launch_cell_fill(nlfem_pairs *h, hipStream_t s)
+int launch_bucket_fill(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
-    const int64_t ncell = (int64_t)h->gnx * h->gny;
-    hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(h->K, 256)), dim3(256), 0, s, cell_args(h));
-    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, 256)), dim3(256), 0, s, ncell, h->cell_start,
-                       h->cell_elems);
+    const BucketArgs a = bucket_args(h, m);
+    const int64_t blocks = a.elem_blocks + grid_for(h->M, 256);
+    if (blocks > 0) hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)blocks), dim3(256), 0, s, a);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }
