@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define NLFEM_ABI_VERSION 1
+#define NLFEM_ABI_VERSION 2
 
 /* return codes */
 enum {
@@ -138,6 +138,10 @@ typedef struct {
     int64_t n_upper_touch;/* unordered touching pairs processed by assemble */
     int64_t n_nbr;        /* entries of the symmetric neighbour lists
                              S(k) = {l : (k,l) or (l,k) interacts}, summed over k */
+    int64_t rebuild;      /* how the last nlfem_build_pairs ran: 0 plain build,
+                             1 rebuild with the sizes of the build before it
+                             (one synchronisation), 2 such a rebuild found other
+                             sizes and ran as a plain build */
 } nlfem_pairs_info_t;
 
 /* ABI version (NLFEM_ABI_VERSION of the built library). */
@@ -157,7 +161,12 @@ const char *nlfem_last_error(void);
    (no fused multiply-add), so the pattern does not depend on `precision`.
    *pairs: if NULL a new handle is created; otherwise the given handle is
    rebuilt in place, reusing its device memory when large enough.
-   Synchronises with `stream` (sizes are needed to allocate).
+   Synchronises with `stream` (sizes are needed to allocate): three times for
+   a plain build; once for a rebuild of a handle whose last build had the
+   same numbers of vertices and elements and the same kernel, delta, ball,
+   rules and singular flag, which first runs with the last build's sizes and
+   checks them on the device, falling back to a plain build when they differ
+   (see nlfem_pairs_info_t.rebuild).
    Errors: E_INVALID, E_MESH, E_NOMEM, E_HIP, E_OVERFLOW, E_NODEVICE. */
 int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg,
                       nlfem_pairs **pairs, void *stream);

@@ -54,9 +54,11 @@ class _Config(C.Structure):
 
 class _Info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_pairs", "n_far", "n_vertex", "n_edge", "n_ident",
-                                         "n_dof", "n_rows", "nnz", "n_upper_far", "n_upper_touch", "n_nbr")]
+                                         "n_dof", "n_rows", "nnz", "n_upper_far", "n_upper_touch", "n_nbr",
+                                         "rebuild")]
 
 
+ABI_VERSION = 2   # layout of the structs below
 _lib = None
 
 
@@ -69,6 +71,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i32 = C.c_void_p, C.c_int
         L.nlfem_version.restype = C.c_int32
+        if L.nlfem_version() != ABI_VERSION:
+            raise NlfemError(-4, f"{LIB_PATH} has ABI {L.nlfem_version()}, the binding expects {ABI_VERSION}")
         L.nlfem_last_error.restype = C.c_char_p
         L.nlfem_build_pairs.argtypes = [vp, vp, C.POINTER(vp), vp]
         L.nlfem_build_pairs.restype = i32

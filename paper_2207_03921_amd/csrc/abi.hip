@@ -202,8 +202,25 @@ int check_device()
     return NLFEM_OK;
 }
 
-int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStream_t s)
+// Slots compared by the checks of a speculative rebuild: after the geometry
+// (bounding box, radii), after the pair count (dofs, clip bound, list totals
+// and maxima), after the symbolic pass (longest row, nnz).
+constexpr uint32_t kSpecGeo = 0x3fu;
+constexpr uint32_t kSpecPairs = (1u << kRedDofs) | (1u << kRedClip) | (0x3fu << kRedTot) | (0x3fu << kRedSegMax);
+constexpr uint32_t kSpecCsr = (1u << kRedMaxRow) | (1u << kRedNnz);
+constexpr int kSpecFailed = 1;   // internal return: the rebuild has to run synchronously
+
+// Builds the pair structures.  The plain build reads the reduction slots
+// back three times to size buffers and launches.  A speculative rebuild
+// (spec: same sizes and configuration as the handle's last build) launches
+// everything with the last build's sizes; device-side checks compare the
+// slots with the last build's at those three points and close a gate that
+// every later build kernel tests on entry, and one read-back at the end
+// decides: kSpecFailed asks the caller for the plain build.
+int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStream_t s, bool spec)
 {
+    h->gate = nullptr;
+    if (!spec) h->spec_ok = false;
     NLFEM_HIP(hipGetDevice(&h->device));
     h->mesh_vertices = m->vertices;
     h->mesh_elements = m->elements;
@@ -242,35 +259,42 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     timing_begin(kPhGeometry, s);
     NLFEM_TRY(launch_geometry(h, m, s));
     timing_end(kPhGeometry, s);
-    NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipStreamSynchronize(s));
-    int32_t err = (int32_t)(red[kRedErr] & 0xffffffffull);
-    if (err & kErrIndex) return set_error(NLFEM_E_MESH, "element vertex index out of range");
-    if (err & kErrArea) return set_error(NLFEM_E_MESH, "element with zero area");
-    const double x0 = key_to_double(red[0]), y0 = key_to_double(red[1]);
-    const double x1 = key_to_double(red[2]), y1 = key_to_double(red[3]);
-    const double rq = key_to_double(red[4]), rv = key_to_double(red[5]);
-    const bool any = x1 >= x0 && y1 >= y0;
+    int32_t err = 0;
+    if (spec) {
+        // the grid of the last build holds while the box and radii are equal
+        h->gate = h->red + kRedGate;
+        NLFEM_TRY(launch_spec_check(h->red, h->spec_red, kSpecGeo, s));
+    } else {
+        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
+        NLFEM_HIP(hipStreamSynchronize(s));
+        err = (int32_t)(red[kRedErr] & 0xffffffffull);
+        if (err & kErrIndex) return set_error(NLFEM_E_MESH, "element vertex index out of range");
+        if (err & kErrArea) return set_error(NLFEM_E_MESH, "element with zero area");
+        const double x0 = key_to_double(red[0]), y0 = key_to_double(red[1]);
+        const double x1 = key_to_double(red[2]), y1 = key_to_double(red[3]);
+        const double rq = key_to_double(red[4]), rv = key_to_double(red[5]);
+        const bool any = x1 >= x0 && y1 >= y0;
 
-    // uniform grid over the barycentres -----------------------------------
-    double far = h->delta + rq + (h->approach == NLFEM_A_APPROXCAPS_POLY ? rv : 0.0);
-    far = far * (1.0 + 1e-9) + 1e-300;
-    h->far_reach = far;
-    double reach = std::max(far, h->singular ? 2.0 * rv * (1.0 + 1e-9) : 0.0);
-    h->gr = 2;
-    h->gh = reach / h->gr;
-    h->gx0 = any ? x0 : 0.0;
-    h->gy0 = any ? y0 : 0.0;
-    const double wx = any ? x1 - x0 : 0.0, wy = any ? y1 - y0 : 0.0;
-    // keep the number of cells in the order of the number of elements
-    for (;;) {
-        const double nx = std::floor(wx / h->gh) + 1.0, ny = std::floor(wy / h->gh) + 1.0;
-        if (nx * ny <= 2.0 * (double)K + 64.0) {
-            h->gnx = (int32_t)nx;
-            h->gny = (int32_t)ny;
-            break;
+        // uniform grid over the barycentres -------------------------------
+        double far = h->delta + rq + (h->approach == NLFEM_A_APPROXCAPS_POLY ? rv : 0.0);
+        far = far * (1.0 + 1e-9) + 1e-300;
+        h->far_reach = far;
+        double reach = std::max(far, h->singular ? 2.0 * rv * (1.0 + 1e-9) : 0.0);
+        h->gr = 2;
+        h->gh = reach / h->gr;
+        h->gx0 = any ? x0 : 0.0;
+        h->gy0 = any ? y0 : 0.0;
+        const double wx = any ? x1 - x0 : 0.0, wy = any ? y1 - y0 : 0.0;
+        // keep the number of cells in the order of the number of elements
+        for (;;) {
+            const double nx = std::floor(wx / h->gh) + 1.0, ny = std::floor(wy / h->gh) + 1.0;
+            if (nx * ny <= 2.0 * (double)K + 64.0) {
+                h->gnx = (int32_t)nx;
+                h->gny = (int32_t)ny;
+                break;
+            }
+            h->gh *= 1.5;
         }
-        h->gh *= 1.5;
     }
     const int64_t ncell = (int64_t)h->gnx * h->gny;
     NLFEM_TRY(ensure_typed(h, B_CELLCNT, ncell + 1, h->cell_cnt));
@@ -319,28 +343,33 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(launch_pairs(h, m, false, s));
     timing_end(kPhPairs, s);
     NLFEM_TRY(exclusive_scan_segments(h->lcnt, h->loff, K, kLsLast, K1, h->scan_tmp, h->scan_cap,
-                                      (int64_t *)(h->red + kRedTot), s, (int64_t *)(h->red + kRedSegMax)));
-    NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
-    NLFEM_HIP(hipStreamSynchronize(s));
-    int64_t tot[kLsLast];
-    for (int k = 0; k < kLsLast; ++k) tot[k] = (int64_t)red[kRedTot + k];
-    h->max_clip = (int32_t)red[kRedClip];
-    h->nS = tot[kLsS];
-    h->nP = tot[kLsP];
-    h->nUF = tot[kLsUF];
-    h->nUTc[0] = tot[kLsUI];
-    h->nUTc[1] = tot[kLsUE];
-    h->nUTc[2] = tot[kLsUV];
-    h->nUT = h->nUTc[0] + h->nUTc[1] + h->nUTc[2];
-    h->max_S = (int64_t)red[kRedSegMax + kLsS];
-    h->n_dof = (int64_t)red[kRedDofs];
-    h->n_pairs = h->nP;
-    h->n_ident = h->nUTc[0];
-    h->n_edge = 2 * h->nUTc[1];
-    h->n_vertex = 2 * h->nUTc[2];
-    h->n_far = h->n_pairs - h->n_ident - h->n_edge - h->n_vertex;
-    if (h->nS >= (int64_t)INT32_MAX || h->nUF >= (int64_t)INT32_MAX || h->nUT >= (int64_t)INT32_MAX)
-        return set_error(NLFEM_E_OVERFLOW, "more than 2^31 neighbour entries");
+                                      (int64_t *)(h->red + kRedTot), s, (int64_t *)(h->red + kRedSegMax), h->gate));
+    if (spec) {
+        // list sizes, dof count and clip bound of the last build
+        NLFEM_TRY(launch_spec_check(h->red, h->spec_red, kSpecPairs, s));
+    } else {
+        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
+        NLFEM_HIP(hipStreamSynchronize(s));
+        int64_t tot[kLsLast];
+        for (int k = 0; k < kLsLast; ++k) tot[k] = (int64_t)red[kRedTot + k];
+        h->max_clip = (int32_t)red[kRedClip];
+        h->nS = tot[kLsS];
+        h->nP = tot[kLsP];
+        h->nUF = tot[kLsUF];
+        h->nUTc[0] = tot[kLsUI];
+        h->nUTc[1] = tot[kLsUE];
+        h->nUTc[2] = tot[kLsUV];
+        h->nUT = h->nUTc[0] + h->nUTc[1] + h->nUTc[2];
+        h->max_S = (int64_t)red[kRedSegMax + kLsS];
+        h->n_dof = (int64_t)red[kRedDofs];
+        h->n_pairs = h->nP;
+        h->n_ident = h->nUTc[0];
+        h->n_edge = 2 * h->nUTc[1];
+        h->n_vertex = 2 * h->nUTc[2];
+        h->n_far = h->n_pairs - h->n_ident - h->n_edge - h->n_vertex;
+        if (h->nS >= (int64_t)INT32_MAX || h->nUF >= (int64_t)INT32_MAX || h->nUT >= (int64_t)INT32_MAX)
+            return set_error(NLFEM_E_OVERFLOW, "more than 2^31 neighbour entries");
+    }
     NLFEM_TRY(ensure_typed(h, B_SNBRT, h->nS, h->snbr_tmp));
     NLFEM_TRY(ensure_typed(h, B_SFLAGT, h->nS, h->sflag_tmp));
     NLFEM_TRY(ensure_typed(h, B_SMASKT, h->nS, h->smask_tmp));
@@ -366,6 +395,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     // CSR pattern -------------------------------------------------------------
     int hcap = 64;
     while (hcap < 4 * (h->max_S + 8) && hcap < 16384) hcap <<= 1;
+    if (spec) hcap = h->hcap;
     for (;;) {
         h->hcap = hcap;
         NLFEM_TRY(ensure_typed(h, B_CSRSTAGE, std::max<int64_t>(h->n_dof, 1) * csr_slot(hcap), h->csr_stage));
@@ -373,7 +403,13 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         NLFEM_TRY(launch_csr_rows(h, m, s));
         timing_end(kPhCsr, s);
         NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedNnz),
-                                 (int64_t *)(h->red + kRedMaxRow)));
+                                 (int64_t *)(h->red + kRedMaxRow), h->gate));
+        if (spec) {
+            // the row capacity and nnz of the last build; the decision waits
+            // for the one read-back at the end
+            NLFEM_TRY(launch_spec_check(h->red, h->spec_red, kSpecCsr, s));
+            break;
+        }
         NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
         err = (int32_t)(red[kRedErr] & 0xffffffffull);
@@ -386,9 +422,11 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         NLFEM_TRY(launch_zero(z, nullptr, s));
     }
     if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");
-    h->nnz_node = (int64_t)red[kRedNnz];
-    h->n_dof = (int64_t)red[kRedDofs];
-    h->max_row = (int64_t)red[kRedMaxRow];
+    if (!spec) {
+        h->nnz_node = (int64_t)red[kRedNnz];
+        h->n_dof = (int64_t)red[kRedDofs];
+        h->max_row = (int64_t)red[kRedMaxRow];
+    }
     NLFEM_TRY(ensure_typed(h, B_NCOL, h->nnz_node, h->ncol));
     timing_begin(kPhCsr, s);
     NLFEM_TRY(launch_csr_pack(h, s));
@@ -402,13 +440,22 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->far_rec = far_rec;
     NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
     NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
+    if (spec) {
+        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
+        NLFEM_HIP(hipStreamSynchronize(s));
+        h->gate = nullptr;
+        if (red[kRedGate] != 0ull || (red[kRedErr] & 0xffffffffull) != 0ull) return kSpecFailed;
+        return NLFEM_OK;
+    }
+    // the slots of this build, expected by the next speculative rebuild
+    std::memcpy(h->spec_red, red, sizeof h->spec_red);
+    h->spec_ok = true;
     return NLFEM_OK;
 }
 
-bool same_build(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c)
+// same sizes and the same configuration of the pair search as the handle
+bool same_shape(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c)
 {
-    if (h->mesh_vertices != m->vertices || h->mesh_elements != m->elements || h->mesh_labels != m->labels)
-        return false;
     if (h->M != m->n_vertices || h->K != m->n_elements) return false;
     if (h->kernel != c->kernel || h->approach != c->approach || h->delta != c->delta) return false;
     if (h->singular != (c->singular_n > 0)) return false;
@@ -422,6 +469,13 @@ bool same_build(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c
         if (p.N != h->poly.N || std::memcmp(p.dir, h->poly.dir, sizeof p.dir)) return false;
     }
     return true;
+}
+
+bool same_build(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c)
+{
+    if (h->mesh_vertices != m->vertices || h->mesh_elements != m->elements || h->mesh_labels != m->labels)
+        return false;
+    return same_shape(h, m, c);
 }
 
 }  // namespace
@@ -509,8 +563,16 @@ int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pai
     const bool fresh = *pairs == nullptr;
     nlfem_pairs *h = fresh ? new (std::nothrow) nlfem_pairs() : *pairs;
     if (!h) return set_error(NLFEM_E_NOMEM, "host allocation failed");
-    int rc = build(mesh, cfg, h, (hipStream_t)stream);
+    const bool spec = !fresh && h->spec_ok && same_shape(h, mesh, cfg);
+    int rc = build(mesh, cfg, h, (hipStream_t)stream, spec);
+    h->last_build = spec ? 1 : 0;
+    if (rc == kSpecFailed) {
+        h->last_build = 2;
+        rc = build(mesh, cfg, h, (hipStream_t)stream, false);
+    }
     if (rc != NLFEM_OK) {
+        h->spec_ok = false;
+        h->gate = nullptr;
         if (fresh) nlfem_pairs_free(h);
         else h->K = 0;   // leave a reused handle unusable rather than half built
         return rc;
@@ -533,6 +595,7 @@ int nlfem_pairs_info(const nlfem_pairs *h, nlfem_pairs_info_t *info)
     info->n_upper_far = h->nUF;
     info->n_upper_touch = h->nUT;
     info->n_nbr = h->nS;
+    info->rebuild = h->last_build;
     return NLFEM_OK;
 }
 

@@ -32,6 +32,7 @@ struct CsrArgs {
     int32_t *stage;          // [n_dof][cap]
     int64_t *nlen;
     int32_t *err;
+    const unsigned long long *gate;
 };
 
 __device__ inline bool hash_insert(int32_t *tab, int32_t mask, int32_t key, bool *overflow)
@@ -58,6 +59,7 @@ __device__ inline int wave_sum(int v)
 __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
 {
     extern __shared__ int32_t dyn[];
+    if (gated(a.gate)) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t *tab = dyn + (size_t)w * 2 * a.hcap;   // [hcap] hash table, then [hcap] sort buffer
     int32_t *buf = tab + a.hcap;
@@ -176,8 +178,9 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
 // packs the staged rows: ncol[nptr[i] ...] = stage[item][0 .. nlen[i])
 __global__ void __launch_bounds__(256) k_csr_pack(const int32_t *rows, const unsigned long long *nrows,
                                                   const int64_t *nptr, const int32_t *stage, int32_t cap,
-                                                  int32_t *ncol)
+                                                  int32_t *ncol, const unsigned long long *gate)
 {
+    if (gated(gate)) return;
     const int64_t nr = (int64_t)*nrows;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int64_t item = (int64_t)blockIdx.x * 4 + w; item < nr; item += (int64_t)gridDim.x * 4) {
@@ -276,7 +279,7 @@ int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
     CsrArgs a{m->elements, h->dof_list, h->red + kRedDofs, h->ne_ptr, h->ne_list,
               h->loff + (int64_t)kLsS * (h->K + 1), h->snode, h->hcap, csr_slot(h->hcap), h->csr_stage, h->nlen,
-              h->err};
+              h->err, h->gate};
     const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap * kWavesPerRowBlock;
     hipLaunchKernelGGL(k_csr_rows, dim3(xcd_grid((h->M + kWavesPerRowBlock - 1) / kWavesPerRowBlock)),
                        dim3(64 * kWavesPerRowBlock), lds, s, a);
@@ -288,7 +291,7 @@ int launch_csr_pack(nlfem_pairs *h, hipStream_t s)
 {
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(h->n_dof, 4), 1 << 16));
     hipLaunchKernelGGL(k_csr_pack, dim3(grid), dim3(256), 0, s, h->dof_list, h->red + kRedDofs, h->nptr,
-                       h->csr_stage, csr_slot(h->hcap), h->ncol);
+                       h->csr_stage, csr_slot(h->hcap), h->ncol, h->gate);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

@@ -142,7 +142,31 @@ __global__ void __launch_bounds__(256) k_zero(ZeroList z, unsigned long long *re
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.n[r]; i += stride) z.p[r][i] = 0u;
 }
 
+struct SpecWant {
+    unsigned long long v[kRedSlots];
+    uint32_t mask;
+};
+
+__global__ void __launch_bounds__(64) k_spec_check(unsigned long long *red, SpecWant w)
+{
+    const int i = threadIdx.x;
+    bool bad = false;
+    if (i < kRedSlots && ((w.mask >> i) & 1u)) bad = red[i] != w.v[i];
+    if (i == kRedErr) bad = bad || (red[i] & 0xffffffffull) != 0ull;
+    if (__any(bad) && i == 0) red[kRedGate] = 1ull;
+}
+
 }  // namespace
+
+int launch_spec_check(unsigned long long *red, const unsigned long long *want, uint32_t mask, hipStream_t s)
+{
+    SpecWant w{};
+    std::memcpy(w.v, want, sizeof w.v);
+    w.mask = mask;
+    hipLaunchKernelGGL(k_spec_check, dim3(1), dim3(64), 0, s, red, w);
+    NLFEM_HIP(hipGetLastError());
+    return NLFEM_OK;
+}
 
 int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s)
 {

@@ -35,11 +35,13 @@ struct ListArgs {
     uint32_t *um_ef, *um_fe;
     int32_t *te, *tf;
     int32_t *err;
+    const unsigned long long *gate;
 };
 
 __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
 {
     extern __shared__ unsigned long long key[];
+    if (gated(a.gate)) return;
     const int lane = threadIdx.x;
     for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
         const int64_t e = xcd_item(b, a.K);
@@ -82,6 +84,7 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
 
 __global__ void __launch_bounds__(64) k_worklists(ListArgs a)
 {
+    if (gated(a.gate)) return;
     const int lane = threadIdx.x;
     const unsigned long long lt = (1ull << lane) - 1ull;
     for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
@@ -135,6 +138,7 @@ __global__ void __launch_bounds__(64) k_worklists(ListArgs a)
 // lower entries (f < e) point at the record of their mirror (f, e) in S(f)
 __global__ void __launch_bounds__(64) k_link(ListArgs a)
 {
+    if (gated(a.gate)) return;
     const int lane = threadIdx.x;
     for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
         const int64_t e = xcd_item(b, a.K);
@@ -184,6 +188,7 @@ ListArgs list_args(nlfem_pairs *h)
     a.te = h->te;
     a.tf = h->tf;
     a.err = h->err;
+    a.gate = h->gate;
     return a;
 }
 

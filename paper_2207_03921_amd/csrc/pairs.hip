@@ -53,6 +53,7 @@ struct PairArgs {
     int32_t *snbr;
     uint8_t *sflag;
     uint2 *smask;           // (status of e's points seeing f, status of f's points seeing e)
+    const unsigned long long *gate;
 };
 
 // ---- polygon ball -------------------------------------------------------
@@ -221,6 +222,7 @@ template <bool FILL, bool POLY>
 __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (gated(a.gate)) return;
     const int64_t ncell = (int64_t)a.gnx * a.gny;
     const int64_t cell64 = xcd_item(blockIdx.x, ncell);   // grid.x is a multiple of 8
     if (cell64 >= ncell) return;
@@ -484,10 +486,12 @@ struct BucketArgs {
     unsigned long long *ndof;
     int32_t *dof_list;
     int64_t elem_blocks;           // fill pass: blocks over elements, then over nodes
+    const unsigned long long *gate;
 };
 
 __global__ void __launch_bounds__(256) k_bucket_count(BucketArgs a)
 {
+    if (gated(a.gate)) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.K) return;
     for (int v = 0; v < 3; ++v) {
@@ -535,6 +539,7 @@ __device__ void dof_block(const BucketArgs &a, int64_t blk)
 
 __global__ void __launch_bounds__(256) k_bucket_fill(BucketArgs a)
 {
+    if (gated(a.gate)) return;
     if ((int64_t)blockIdx.x >= a.elem_blocks) {
         dof_block(a, blockIdx.x - a.elem_blocks);
         return;
@@ -580,6 +585,7 @@ BucketArgs bucket_args(nlfem_pairs *h, const nlfem_mesh *m)
     a.ndof = h->red + kRedDofs;
     a.dof_list = h->dof_list;
     a.elem_blocks = grid_for(h->K, 256);
+    a.gate = h->gate;
     return a;
 }
 
@@ -637,6 +643,7 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     a.snbr = h->snbr_tmp;
     a.sflag = h->sflag_tmp;
     a.smask = h->smask_tmp;
+    a.gate = h->gate;
     const size_t lds = sizeof(double2) * (size_t)kCH * (1 + a.P + (a.poly ? 3 : 0)) +
                        sizeof(int64_t) * kTE * kLsLast + sizeof(int32_t) * kCH * 5;
     dim3 grid(xcd_grid(ncell, INT32_MAX));

@@ -18,6 +18,7 @@ struct ScanList {
     int64_t first[kScanParts + 1];        // first tile of each part
     int32_t cnt;
     int64_t *sums, *bmax;                 // [tiles]
+    const unsigned long long *gate;
 };
 
 __device__ int64_t block_exclusive(int64_t v, int64_t *sh, int64_t *total)
@@ -64,6 +65,7 @@ __device__ inline int part_of(const ScanList &L, int64_t b)
 __global__ void __launch_bounds__(kBlock) k_scan_tiles(ScanList L)
 {
     __shared__ int64_t sh[kBlock / 64];
+    if (gated(L.gate)) return;
     const int64_t b = blockIdx.x;
     const ScanPart &P = L.p[part_of(L, b)];
     const int64_t lb = b - L.first[part_of(L, b)];
@@ -86,6 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_tiles(ScanList L)
 __global__ void __launch_bounds__(kBlock) k_scan_apply(ScanList L)
 {
     __shared__ int64_t sh[kBlock];
+    if (gated(L.gate)) return;
     const int64_t b = blockIdx.x;
     const int k = part_of(L, b);
     const ScanPart &P = L.p[k];
@@ -131,7 +134,8 @@ int64_t scan_tmp_size(int64_t n, int nseg)
     return 2 * (int64_t)nseg * tiles_of(n) + 1;
 }
 
-int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t tmp_cap, hipStream_t s)
+int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
+                         const unsigned long long *gate)
 {
     if (cnt < 1 || cnt > kScanParts) return set_error(NLFEM_E_INVALID, "scan: 1..8 arrays per call");
     ScanList L{};
@@ -146,6 +150,7 @@ int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t t
     if (2 * tiles > tmp_cap) return set_error(NLFEM_E_OVERFLOW, "scan workspace too small");
     L.sums = tmp;
     L.bmax = tmp + tiles;
+    L.gate = gate;
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kBlock), 0, s, L);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kBlock), 0, s, L);
     NLFEM_HIP(hipGetLastError());
@@ -153,21 +158,22 @@ int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t t
 }
 
 int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
-                            int64_t tmp_cap, int64_t *totals, hipStream_t s, int64_t *maxes)
+                            int64_t tmp_cap, int64_t *totals, hipStream_t s, int64_t *maxes,
+                            const unsigned long long *gate)
 {
     ScanPart parts[kScanParts];
     if (nseg < 1 || nseg > kScanParts) return set_error(NLFEM_E_INVALID, "scan: 1..8 segments per call");
     for (int k = 0; k < nseg; ++k)
         parts[k] = ScanPart{in + k * stride, out + k * stride, n, totals ? totals + k : nullptr,
                             maxes ? maxes + k : nullptr};
-    return exclusive_scan_multi(parts, nseg, tmp, tmp_cap, s);
+    return exclusive_scan_multi(parts, nseg, tmp, tmp_cap, s, gate);
 }
 
 int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
-                   int64_t *total, int64_t *maxval)
+                   int64_t *total, int64_t *maxval, const unsigned long long *gate)
 {
     const ScanPart p{in, out, n, total, maxval};
-    return exclusive_scan_multi(&p, 1, tmp, tmp_cap, s);
+    return exclusive_scan_multi(&p, 1, tmp, tmp_cap, s, gate);
 }
 
 }  // namespace nlfem
