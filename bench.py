@@ -265,6 +265,7 @@ def main():
         return dt, rows[0] / max(rows[1], 1)
 
     t_step, t_rows = timed(cfg, args.steps, args.warmup)
+    rebuild = nl.nlfem_pairs_info(pairs)["rebuild"]
 
     # assemble alone (HIP events on the library's stream)
     def assemble_ms(c, reps=20):
@@ -316,6 +317,9 @@ def main():
                    "touching_pairs": info["n_vertex"] + info["n_edge"] + info["n_ident"],
                    "nnz": info["nnz"], "precision": args.precision},
         "roofline": roofline,
+        "build": {0: "plain build (three host synchronisations)",
+                  1: "rebuild with the sizes of the previous build (one host synchronisation)",
+                  2: "rebuild fell back to a plain build"}[rebuild],
         "assemble_ms": t_asm,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "assemble_pairs_per_s": n_pairs / (t_asm * 1e-3),
