@@ -89,9 +89,10 @@ __global__ void __launch_bounds__(256) k_touch_rec(TouchLaunch L, GaussArgs g)
 template <int NK, typename TR>
 __global__ void __launch_bounds__(256) k_elem_diag(DiagArgs a)
 {
-    const int64_t e = xcd_item(blockIdx.x, (a.K + 3) / 4) * 4 + (threadIdx.x >> 6);
-    if (e >= a.K) return;
-    diag_item<NK, TR>(a, e, threadIdx.x & 63);
+    constexpr int per = 256 / kDiagG;   // elements per workgroup
+    const int64_t e = xcd_item(blockIdx.x, (a.K + per - 1) / per) * per + threadIdx.x / kDiagG;
+    if (e >= a.K) return;   // whole lane groups leave together
+    diag_item<NK, TR>(a, e, threadIdx.x % kDiagG);
 }
 
 template <int NC, typename TR>
@@ -294,7 +295,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         const int nc = p.nc;
         const bool fp32 = p.fp32;
         timing_begin(kPhFar, s);
-        const unsigned dg = xcd_grid((h->K + 3) / 4, INT32_MAX);
+        const unsigned dg = xcd_grid((h->K + 256 / kDiagG - 1) / (256 / kDiagG), INT32_MAX);
         if (nc == 1) {
             if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float>), dim3(dg), dim3(256), 0, s, p.diag);
             else hipLaunchKernelGGL((k_elem_diag<1, double>), dim3(dg), dim3(256), 0, s, p.diag);

@@ -239,10 +239,12 @@ __device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double
             De[5][k] += alpha[k] * pp[2] * pp[2];
         }
     };
-    if constexpr (PM > 0) {
-        // a fixed rule: the outer points in a loop (uniform index into the
-        // rule tables), the inner ones unrolled, which keeps the register
-        // count at an occupancy of 4 waves (FP32)
+    if constexpr (PM > 0 && sizeof(T) == 4 && NK == 1) {
+        // a fixed rule in FP32, scalar kernel: the outer points in a loop
+        // (uniform index into the rule tables), the inner ones unrolled; this
+        // halves the register count (4 waves per SIMD instead of 2).  The
+        // other cases keep their occupancy either way and run faster
+        // unrolled.
 #pragma unroll 1
         for (int p = 0; p < PM; ++p) outer(p);
     } else {
@@ -871,33 +873,53 @@ struct DiagArgs {
     int32_t *err;
 };
 
-// D_e of element e by the 64 lanes of one wave
+// D_e of element e by the kDiagG lanes sub = 0..kDiagG-1 of an aligned lane
+// group (all of them call).  Lane sub adds the entries sub, sub + kDiagG, ...
+// of S(e) in that order, kDiagU of them with their loads in flight at once,
+// then the group sums by shuffles; the grouping fixes the order of the sums,
+// so every path uses these constants.
+constexpr int kDiagG = 16;
+constexpr int kDiagU = 4;
+
 template <int NK, typename TR>
-__device__ __forceinline__ void diag_item(const DiagArgs &a, int64_t e, int lane)
+__device__ __forceinline__ void diag_item(const DiagArgs &a, int64_t e, int sub)
 {
+    constexpr int G = kDiagG;
     double acc[6 * NK];
+#pragma unroll
     for (int i = 0; i < 6 * NK; ++i) acc[i] = 0.0;
     bool bad = false;
-    for (int64_t t = a.sptr[e] + lane; t < a.sptr[e + 1]; t += 64) {
-        if (((a.sflag[t] >> 2) & 3) != 0) continue;
-        const int32_t u = a.srec[t];
-        if (u < 0 || u >= a.n_far) {
-            bad = true;
-            continue;
+    const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
+    for (int64_t t0 = s0 + sub; t0 < s1; t0 += G * kDiagU) {
+        int32_t u[kDiagU], f[kDiagU];
+        bool use[kDiagU];
+#pragma unroll
+        for (int k = 0; k < kDiagU; ++k) {
+            const int64_t t = t0 + (int64_t)k * G;
+            use[k] = t < s1 && ((a.sflag[t] >> 2) & 3) == 0;
+            u[k] = use[k] ? a.srec[t] : 0;
+            f[k] = use[k] ? a.snbr[t] : 0;
         }
-        const int32_t f = a.snbr[t];
-        const TR *r = (const TR *)a.far_rec + (int64_t)u * a.far_stride + (f >= e ? 9 : 15) * NK;
-        for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
+#pragma unroll
+        for (int k = 0; k < kDiagU; ++k) {
+            if (!use[k]) continue;
+            if (u[k] < 0 || u[k] >= a.n_far) {
+                bad = true;
+                continue;
+            }
+            const TR *r = (const TR *)a.far_rec + (int64_t)u[k] * a.far_stride + (f[k] >= e ? 9 : 15) * NK;
+#pragma unroll
+            for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
+        }
     }
-    for (int i = 0; i < 6 * NK; ++i)
-        for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_xor(acc[i], o);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < 6 * NK; ++i) acc[i] += __shfl_xor(acc[i], o, G);
     if (bad) atomicOr(a.err, kErrSlot);
-    if (lane < 6 * NK) {
-        double v = 0.0;
-        for (int i = 0; i < 6 * NK; ++i)
-            if (i == lane) v = acc[i];
-        a.dsum[e * 6 * NK + lane] = v;
-    }
+#pragma unroll
+    for (int i = 0; i < 6 * NK; ++i)
+        if (i % G == sub) a.dsum[e * 6 * NK + i] = acc[i];
 }
 
 // ------------------------------------------------- phase 2: row gather

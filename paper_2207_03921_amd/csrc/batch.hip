@@ -181,15 +181,19 @@ __global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *__re
     __shared__ unsigned long long slot;
     int64_t *pre = (int64_t *)dyn;
     const int64_t total = load_prefix(q, pre);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, waves = blockDim.x >> 6;
+    const int group = threadIdx.x / kDiagG, sub = threadIdx.x % kDiagG, groups = blockDim.x / kDiagG;
     for (;;) {
         const int64_t b0 = grab(q, &slot);
         if (b0 >= total) break;
         const int64_t b1 = min(b0 + (int64_t)q.chunk, total);
-        for (int64_t it = b0 + wave; it < b1; it += waves) {
-            // one element per wave: the problem is uniform
-            const int p = __builtin_amdgcn_readfirstlane(find_prob(pre, q.nprob, it));
-            diag_item<NK, TR>(da[p], it - pre[p], lane);
+        for (int64_t it0 = b0; it0 < b1; it0 += groups) {
+            const int64_t it = it0 + group;   // one element per lane group
+            const int p = it < b1 ? find_prob(pre, q.nprob, it) : -1;
+            unsigned long long todo = __ballot(it < b1);
+            while (todo) {
+                const Run r = next_run(p, &todo);   // whole lane groups
+                if (p == r.p) diag_item<NK, TR>(da[r.p], it - pre[r.p], sub);
+            }
         }
     }
 }
