@@ -18,7 +18,7 @@ enum Buf : int {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
-    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_LAST
+    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_SPEC, B_LAST
 };
 static_assert(B_LAST <= (int)(sizeof(nlfem_pairs::bufs) / sizeof(nlfem_pairs::bufs[0])), "too few buffer slots");
 
@@ -202,24 +202,39 @@ int check_device()
     return NLFEM_OK;
 }
 
-// Slots compared by the checks of a speculative rebuild: after the geometry
-// (bounding box, radii), after the pair count (dofs, clip bound, list totals
-// and maxima), after the symbolic pass (longest row, nnz).
-constexpr uint32_t kSpecGeo = 0x3fu;
-constexpr uint32_t kSpecPairs = (1u << kRedDofs) | (1u << kRedClip) | (0x3fu << kRedTot) | (0x3fu << kRedSegMax);
-constexpr uint32_t kSpecCsr = (1u << kRedMaxRow) | (1u << kRedNnz);
+// Slots a speculative rebuild compares with the last build's, by the point
+// of the build where they are final: after the geometry (bounding box, radii,
+// error bits), after the pair count (dofs, clip bound, list totals and
+// maxima), after the symbolic pass (longest row, nnz).
+constexpr uint32_t kSpecGeo = 0x3fu | (1u << kRedErr);
+constexpr uint32_t kSpecPairs =
+    kSpecGeo | (1u << kRedDofs) | (1u << kRedClip) | (0x3fu << kRedTot) | (0x3fu << kRedSegMax);
+constexpr uint32_t kSpecCsr = kSpecPairs | (1u << kRedMaxRow) | (1u << kRedNnz);
 constexpr int kSpecFailed = 1;   // internal return: the rebuild has to run synchronously
+
+// Counters of the build after the geometry, all cleared by one launch.
+ZeroList build_counters(nlfem_pairs *h)
+{
+    const int64_t ncell = (int64_t)h->gnx * h->gny;
+    ZeroList z{};
+    z.add(h->cell_cnt, ncell + 1);
+    z.add(h->cell_fill, ncell);
+    z.add(h->lcnt, kLsLast * (h->K + 1));
+    z.add(h->nlen, h->M + 1);
+    z.add(h->ne_fill, h->M);
+    return z;
+}
 
 // Builds the pair structures.  The plain build reads the reduction slots
 // back three times to size buffers and launches.  A speculative rebuild
 // (spec: same sizes and configuration as the handle's last build) launches
-// everything with the last build's sizes; device-side checks compare the
-// slots with the last build's at those three points and close a gate that
-// every later build kernel tests on entry, and one read-back at the end
-// decides: kSpecFailed asks the caller for the plain build.
+// everything with the last build's sizes, and every build kernel after the
+// geometry first compares the slots final by its launch with the last
+// build's (on the device) and returns when one differs; one read-back at the
+// end decides: kSpecFailed asks the caller for the plain build.
 int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStream_t s, bool spec)
 {
-    h->gate = nullptr;
+    h->gate = SpecGate{};
     if (!spec) h->spec_ok = false;
     NLFEM_HIP(hipGetDevice(&h->device));
     h->mesh_vertices = m->vertices;
@@ -257,13 +272,16 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         NLFEM_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     }
     timing_begin(kPhGeometry, s);
-    NLFEM_TRY(launch_geometry(h, m, s));
+    {
+        // a rebuild clears the later counters (last build's sizes) here too
+        const ZeroList later = spec ? build_counters(h) : ZeroList{};
+        NLFEM_TRY(launch_geometry(h, m, s, later));
+    }
     timing_end(kPhGeometry, s);
     int32_t err = 0;
     if (spec) {
         // the grid of the last build holds while the box and radii are equal
-        h->gate = h->red + kRedGate;
-        NLFEM_TRY(launch_spec_check(h->red, h->spec_red, kSpecGeo, s));
+        h->gate = SpecGate{h->red, h->spec_want, kSpecGeo};
     } else {
         NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
@@ -318,14 +336,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         NLFEM_TRY(ensure_typed(h, B_POLYDIR, 2 * kMaxPoly, h->poly_dir));
         NLFEM_HIP(hipMemcpyAsync(h->poly_dir, h->poly.dir, sizeof(double) * 2 * h->poly.N, hipMemcpyHostToDevice, s));
     }
-    {
+    if (!spec) {
         // every counter of the rest of the build starts at zero
-        ZeroList z{};
-        z.add(h->cell_cnt, ncell + 1);
-        z.add(h->cell_fill, ncell);
-        z.add(h->lcnt, kLsLast * K1);
-        z.add(h->nlen, M + 1);
-        z.add(h->ne_fill, M);
+        ZeroList z = build_counters(h);
         z.add(h->red + kRedMaxCell, kRedErr - kRedMaxCell);   // slots 6..17, keeps the error bits
         NLFEM_TRY(launch_zero(z, nullptr, s));
     }
@@ -346,7 +359,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
                                       (int64_t *)(h->red + kRedTot), s, (int64_t *)(h->red + kRedSegMax), h->gate));
     if (spec) {
         // list sizes, dof count and clip bound of the last build
-        NLFEM_TRY(launch_spec_check(h->red, h->spec_red, kSpecPairs, s));
+        h->gate.mask = kSpecPairs;
     } else {
         NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
@@ -407,7 +420,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         if (spec) {
             // the row capacity and nnz of the last build; the decision waits
             // for the one read-back at the end
-            NLFEM_TRY(launch_spec_check(h->red, h->spec_red, kSpecCsr, s));
+            h->gate.mask = kSpecCsr;
             break;
         }
         NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
@@ -443,11 +456,16 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     if (spec) {
         NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
         NLFEM_HIP(hipStreamSynchronize(s));
-        h->gate = nullptr;
-        if (red[kRedGate] != 0ull || (red[kRedErr] & 0xffffffffull) != 0ull) return kSpecFailed;
+        h->gate = SpecGate{};
+        for (int i = 0; i < kRedSlots; ++i)
+            if (((kSpecCsr >> i) & 1u) && red[i] != h->spec_red[i]) return kSpecFailed;
         return NLFEM_OK;
     }
-    // the slots of this build, expected by the next speculative rebuild
+    // the slots of this build, expected by the next speculative rebuild (the
+    // device copy is taken from the device slots, in stream order)
+    NLFEM_TRY(ensure_typed(h, B_SPEC, kRedSlots, h->spec_want));
+    NLFEM_HIP(hipMemcpyAsync(h->spec_want, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToDevice,
+                             s));
     std::memcpy(h->spec_red, red, sizeof h->spec_red);
     h->spec_ok = true;
     return NLFEM_OK;
@@ -572,7 +590,7 @@ int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pai
     }
     if (rc != NLFEM_OK) {
         h->spec_ok = false;
-        h->gate = nullptr;
+        h->gate = SpecGate{};
         if (fresh) nlfem_pairs_free(h);
         else h->K = 0;   // leave a reused handle unusable rather than half built
         return rc;

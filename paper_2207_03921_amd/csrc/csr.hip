@@ -32,7 +32,7 @@ struct CsrArgs {
     int32_t *stage;          // [n_dof][cap]
     int64_t *nlen;
     int32_t *err;
-    const unsigned long long *gate;
+    SpecGate gate;
 };
 
 __device__ inline bool hash_insert(int32_t *tab, int32_t mask, int32_t key, bool *overflow)
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
 // packs the staged rows: ncol[nptr[i] ...] = stage[item][0 .. nlen[i])
 __global__ void __launch_bounds__(256) k_csr_pack(const int32_t *rows, const unsigned long long *nrows,
                                                   const int64_t *nptr, const int32_t *stage, int32_t cap,
-                                                  int32_t *ncol, const unsigned long long *gate)
+                                                  int32_t *ncol, SpecGate gate)
 {
     if (gated(gate)) return;
     const int64_t nr = (int64_t)*nrows;

@@ -142,31 +142,7 @@ __global__ void __launch_bounds__(256) k_zero(ZeroList z, unsigned long long *re
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.n[r]; i += stride) z.p[r][i] = 0u;
 }
 
-struct SpecWant {
-    unsigned long long v[kRedSlots];
-    uint32_t mask;
-};
-
-__global__ void __launch_bounds__(64) k_spec_check(unsigned long long *red, SpecWant w)
-{
-    const int i = threadIdx.x;
-    bool bad = false;
-    if (i < kRedSlots && ((w.mask >> i) & 1u)) bad = red[i] != w.v[i];
-    if (i == kRedErr) bad = bad || (red[i] & 0xffffffffull) != 0ull;
-    if (__any(bad) && i == 0) red[kRedGate] = 1ull;
-}
-
 }  // namespace
-
-int launch_spec_check(unsigned long long *red, const unsigned long long *want, uint32_t mask, hipStream_t s)
-{
-    SpecWant w{};
-    std::memcpy(w.v, want, sizeof w.v);
-    w.mask = mask;
-    hipLaunchKernelGGL(k_spec_check, dim3(1), dim3(64), 0, s, red, w);
-    NLFEM_HIP(hipGetLastError());
-    return NLFEM_OK;
-}
 
 int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s)
 {
@@ -186,11 +162,11 @@ double key_to_double(unsigned long long key)
     return v;
 }
 
-int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
+int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, const ZeroList &later)
 {
     GeoArgs a{h->K, h->M, m->vertices, m->elements, m->labels, h->v0, h->J, h->det,
               h->bary, h->xp, h->node_flags, h->err, h->red};
-    ZeroList z{};
+    ZeroList z = later;
     z.add(h->node_flags, h->M);
     NLFEM_TRY(launch_zero(z, h->red, s));   // also clears err (a reduction slot)
     hipLaunchKernelGGL(k_geometry, dim3(grid_for(h->K, 256)), dim3(256), 0, s, a, h->rules);

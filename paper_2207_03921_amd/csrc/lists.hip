@@ -35,7 +35,7 @@ struct ListArgs {
     uint32_t *um_ef, *um_fe;
     int32_t *te, *tf;
     int32_t *err;
-    const unsigned long long *gate;
+    SpecGate gate;
 };
 
 __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)

@@ -52,13 +52,29 @@ struct GaussArgs {
 //   0-3 bounding-box keys, 4-5 radii, 6 largest cell, 7 largest |S(e)|,
 //   8 dof count, 9 longest CSR row, 10 polygon clip bound, 11 CSR nnz,
 //   12-17 totals of the per-element pair counts, 18 error bits (int32),
-//   19-24 largest per-element pair counts (19: largest |S(e)|),
-//   25 speculation gate (nonzero: a check failed, later build kernels skip)
+//   19-24 largest per-element pair counts (19: largest |S(e)|)
 enum { kRedMaxCell = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
-       kRedTot = 12, kRedErr = 18, kRedSegMax = 19, kRedGate = 25, kRedSlots = 32 };
+       kRedTot = 12, kRedErr = 18, kRedSegMax = 19, kRedSlots = 32 };
 
-// true when a gate is given and closed: the kernel returns at once
-__device__ inline bool gated(const unsigned long long *gate) { return gate && *(const volatile unsigned long long *)gate; }
+// A rebuild launched with the last build's sizes: a build kernel runs only
+// while the reduction slots that are final at its launch (mask) equal the
+// last build's (want, on the device); the error slot is among them.
+struct SpecGate {
+    const unsigned long long *red = nullptr;    // nullptr: not gated
+    const unsigned long long *want = nullptr;   // [kRedSlots]
+    uint32_t mask = 0;
+};
+
+// true when a compared slot differs: the calling wave returns.  Every lane of
+// the wave calls it, and every wave of a workgroup gets the same answer.
+__device__ inline bool gated(const SpecGate &g)
+{
+    if (!g.red) return false;
+    const int lane = threadIdx.x & 63;
+    bool bad = false;
+    if (lane < kRedSlots && ((g.mask >> lane) & 1u)) bad = g.red[lane] != g.want[lane];
+    return __any(bad);
+}
 
 // up to kZeroMax ranges of 32-bit words cleared by one launch
 constexpr int kZeroMax = 12;
@@ -120,8 +136,9 @@ struct nlfem_pairs {
     // rebuilds with the sizes of the last build: expected reduction slots and
     // the gate the build kernels test while such a build runs
     bool spec_ok = false;
-    unsigned long long spec_red[nlfem::kRedSlots] = {};
-    const unsigned long long *gate = nullptr;
+    unsigned long long spec_red[nlfem::kRedSlots] = {};   // host copy
+    unsigned long long *spec_want = nullptr;              // device copy
+    nlfem::SpecGate gate{};
     int32_t last_build = 0;   // 0 plain, 1 speculative rebuild held, 2 it fell back
     unsigned long long *counters = nullptr;  // [kCntLast]
     // node -> element incidence
@@ -239,12 +256,12 @@ __device__ inline int64_t xcd_item(int64_t b, int64_t n)
 // (also written to *total when given; device pointer).  n = 0 gives out[0] = 0.
 // *maxval (device) receives the largest input when given.
 int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
-                   int64_t *total = nullptr, int64_t *maxval = nullptr, const unsigned long long *gate = nullptr);
+                   int64_t *total = nullptr, int64_t *maxval = nullptr, const SpecGate &gate = SpecGate{});
 // the same for nseg segments of `stride` slots (segment k at in + k * stride),
 // totals[k] = total and maxes[k] = largest input of segment k when given
 int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
                             int64_t tmp_cap, int64_t *totals, hipStream_t s, int64_t *maxes = nullptr,
-                            const unsigned long long *gate = nullptr);
+                            const SpecGate &gate = SpecGate{});
 // up to kScanParts independent arrays in one pair of launches; the workspace
 // needs the sum of scan_tmp_size(n_k) over the parts
 constexpr int kScanParts = 8;
@@ -256,16 +273,14 @@ struct ScanPart {
     int64_t *maxv;      // device, optional
 };
 int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
-                         const unsigned long long *gate = nullptr);
+                         const SpecGate &gate = SpecGate{});
 int64_t scan_tmp_size(int64_t n, int nseg = 1);
 double key_to_double(unsigned long long key);
 
 // geometry.hip
-int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
+// also clears the ranges of `later` in its first launch
+int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, const ZeroList &later);
 int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s);
-// closes the gate red[kRedGate] when a slot i with bit i of `mask` set differs
-// from want[i] or an error bit is set
-int launch_spec_check(unsigned long long *red, const unsigned long long *want, uint32_t mask, hipStream_t s);
 // grid + pairs (pairs.hip)
 // node -> element incidence counts (nlen) and grid cell counts (cell_cnt)
 int launch_bucket_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);

@@ -53,7 +53,7 @@ struct PairArgs {
     int32_t *snbr;
     uint8_t *sflag;
     uint2 *smask;           // (status of e's points seeing f, status of f's points seeing e)
-    const unsigned long long *gate;
+    SpecGate gate;
 };
 
 // ---- polygon ball -------------------------------------------------------
@@ -486,7 +486,7 @@ struct BucketArgs {
     unsigned long long *ndof;
     int32_t *dof_list;
     int64_t elem_blocks;           // fill pass: blocks over elements, then over nodes
-    const unsigned long long *gate;
+    SpecGate gate;
 };
 
 __global__ void __launch_bounds__(256) k_bucket_count(BucketArgs a)

@@ -18,7 +18,7 @@ struct ScanList {
     int64_t first[kScanParts + 1];        // first tile of each part
     int32_t cnt;
     int64_t *sums, *bmax;                 // [tiles]
-    const unsigned long long *gate;
+    SpecGate gate;
 };
 
 __device__ int64_t block_exclusive(int64_t v, int64_t *sh, int64_t *total)
@@ -135,7 +135,7 @@ int64_t scan_tmp_size(int64_t n, int nseg)
 }
 
 int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
-                         const unsigned long long *gate)
+                         const SpecGate &gate)
 {
     if (cnt < 1 || cnt > kScanParts) return set_error(NLFEM_E_INVALID, "scan: 1..8 arrays per call");
     ScanList L{};
@@ -159,7 +159,7 @@ int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t t
 
 int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
                             int64_t tmp_cap, int64_t *totals, hipStream_t s, int64_t *maxes,
-                            const unsigned long long *gate)
+                            const SpecGate &gate)
 {
     ScanPart parts[kScanParts];
     if (nseg < 1 || nseg > kScanParts) return set_error(NLFEM_E_INVALID, "scan: 1..8 segments per call");
@@ -170,7 +170,7 @@ int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg
 }
 
 int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
-                   int64_t *total, int64_t *maxval, const unsigned long long *gate)
+                   int64_t *total, int64_t *maxval, const SpecGate &gate)
 {
     const ScanPart p{in, out, n, total, maxval};
     return exclusive_scan_multi(&p, 1, tmp, tmp_cap, s, gate);
