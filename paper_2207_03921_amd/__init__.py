@@ -177,17 +177,29 @@ class Config:
         return 2 if self.kernel == "peridynamic" else 1
 
     def c_struct(self):
+        # reused while no field was rebound and every table is already a
+        # contiguous float64 array (the struct then points at the caller's
+        # arrays, so changes made in place are seen)
+        key = (self.kernel, self.c, self.delta, self.approach, self.singular_n, self.precision,
+               id(self.outer_xi), id(self.outer_w), id(self.inner_xi), id(self.inner_w), id(self.polygon_dirs))
+        cached = self.__dict__.get("_cs")
+        if cached is not None and cached[0] == key:
+            return cached[1]
         arrs = [np.ascontiguousarray(a, np.float64) for a in
                 (self.outer_xi, self.outer_w, self.inner_xi, self.inner_w)]
         dirs = None if self.polygon_dirs is None else np.ascontiguousarray(self.polygon_dirs, np.float64)
         self._keep = arrs + [dirs]
         oxi, ow, ixi, iw = arrs
-        return _Config(KERNELS[self.kernel], float(self.c), float(self.delta),
-                       APPROACHES[self.approach], 0 if dirs is None else dirs.shape[0],
-                       None if dirs is None else dirs.ctypes.data,
-                       _Rule(ow.shape[0], oxi.ctypes.data, ow.ctypes.data),
-                       _Rule(iw.shape[0], ixi.ctypes.data, iw.ctypes.data),
-                       int(self.singular_n), PRECISIONS[self.precision])
+        cs = _Config(KERNELS[self.kernel], float(self.c), float(self.delta),
+                     APPROACHES[self.approach], 0 if dirs is None else dirs.shape[0],
+                     None if dirs is None else dirs.ctypes.data,
+                     _Rule(ow.shape[0], oxi.ctypes.data, ow.ctypes.data),
+                     _Rule(iw.shape[0], ixi.ctypes.data, iw.ctypes.data),
+                     int(self.singular_n), PRECISIONS[self.precision])
+        src = (self.outer_xi, self.outer_w, self.inner_xi, self.inner_w)
+        if all(a is b for a, b in zip(arrs, src)) and (dirs is None or dirs is self.polygon_dirs):
+            self.__dict__["_cs"] = (key, cs)
+        return cs
 
 
 class Pairs:

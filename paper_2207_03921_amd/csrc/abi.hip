@@ -212,6 +212,20 @@ constexpr uint32_t kSpecPairs =
 constexpr uint32_t kSpecCsr = kSpecPairs | (1u << kRedMaxRow) | (1u << kRedNnz);
 constexpr int kSpecFailed = 1;   // internal return: the rebuild has to run synchronously
 
+// Copies the reduction slots to the pinned host buffer and waits for them.
+// The wait polls an event rather than blocking in the runtime: it lasts tens
+// of microseconds, and a blocking wait adds the wake-up of the host thread.
+int read_slots(nlfem_pairs *h, hipStream_t s)
+{
+    NLFEM_HIP(hipMemcpyAsync(h->rb, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
+    NLFEM_HIP(hipEventRecord(h->ev_rb, s));
+    for (;;) {
+        const hipError_t e = hipEventQuery(h->ev_rb);
+        if (e == hipSuccess) return NLFEM_OK;
+        if (e != hipErrorNotReady) return hip_error(e, "hipEventQuery");
+    }
+}
+
 // Counters of the build after the geometry, all cleared by one launch.
 ZeroList build_counters(nlfem_pairs *h)
 {
@@ -270,6 +284,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         NLFEM_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
         NLFEM_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         NLFEM_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        NLFEM_HIP(hipEventCreateWithFlags(&h->ev_rb, hipEventDisableTiming));
     }
     timing_begin(kPhGeometry, s);
     {
@@ -283,8 +298,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         // the grid of the last build holds while the box and radii are equal
         h->gate = SpecGate{h->red, h->spec_want, kSpecGeo};
     } else {
-        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
-        NLFEM_HIP(hipStreamSynchronize(s));
+        NLFEM_TRY(read_slots(h, s));
         err = (int32_t)(red[kRedErr] & 0xffffffffull);
         if (err & kErrIndex) return set_error(NLFEM_E_MESH, "element vertex index out of range");
         if (err & kErrArea) return set_error(NLFEM_E_MESH, "element with zero area");
@@ -361,8 +375,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         // list sizes, dof count and clip bound of the last build
         h->gate.mask = kSpecPairs;
     } else {
-        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
-        NLFEM_HIP(hipStreamSynchronize(s));
+        NLFEM_TRY(read_slots(h, s));
         int64_t tot[kLsLast];
         for (int k = 0; k < kLsLast; ++k) tot[k] = (int64_t)red[kRedTot + k];
         h->max_clip = (int32_t)red[kRedClip];
@@ -423,8 +436,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
             h->gate.mask = kSpecCsr;
             break;
         }
-        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
-        NLFEM_HIP(hipStreamSynchronize(s));
+        NLFEM_TRY(read_slots(h, s));
         err = (int32_t)(red[kRedErr] & 0xffffffffull);
         if (!(err & kErrRowCap)) break;
         if (hcap >= 16384) return set_error(NLFEM_E_OVERFLOW, "matrix row longer than the symbolic capacity");
@@ -454,8 +466,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
     NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
     if (spec) {
-        NLFEM_HIP(hipMemcpyAsync(red, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
-        NLFEM_HIP(hipStreamSynchronize(s));
+        NLFEM_TRY(read_slots(h, s));
         h->gate = SpecGate{};
         for (int i = 0; i < kRedSlots; ++i)
             if (((kSpecCsr >> i) & 1u) && red[i] != h->spec_red[i]) return kSpecFailed;
@@ -717,6 +728,7 @@ void nlfem_pairs_free(nlfem_pairs *h)
     if (h->rb) (void)hipHostFree(h->rb);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_rb) (void)hipEventDestroy(h->ev_rb);
     if (h->aux) (void)hipStreamDestroy(h->aux);
     delete h;
 }

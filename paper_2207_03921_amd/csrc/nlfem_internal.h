@@ -188,6 +188,7 @@ struct nlfem_pairs {
     // non-touching ones (fork and join through the two events)
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_rb = nullptr;   // completion of a read-back of the reduction slots
     // grow-only device buffers behind the typed pointers above
     struct DevBuf {
         void *p = nullptr;
