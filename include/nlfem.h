@@ -161,12 +161,20 @@ const char *nlfem_last_error(void);
    (no fused multiply-add), so the pattern does not depend on `precision`.
    *pairs: if NULL a new handle is created; otherwise the given handle is
    rebuilt in place, reusing its device memory when large enough.
-   Synchronises with `stream` (sizes are needed to allocate): three times for
-   a plain build; once for a rebuild of a handle whose last build had the
-   same numbers of vertices and elements and the same kernel, delta, ball,
-   rules and singular flag, which first runs with the last build's sizes and
-   checks them on the device, falling back to a plain build when they differ
-   (see nlfem_pairs_info_t.rebuild).
+   A plain build synchronises with `stream` three times (sizes are needed to
+   allocate).  A rebuild of a handle whose last plain build had the same
+   numbers of vertices and elements and the same kernel, delta, ball, rules
+   and singular flag is launched with that build's sizes and returns without
+   waiting; its kernels compare the device-side counts with the expected ones
+   and skip their work on a difference.  The next call that uses the handle
+   (nlfem_pairs_info, _export, _csr_pattern, nlfem_assemble - after queueing
+   its own launches, which skip their work likewise -, nlfem_batch_*) waits
+   for the rebuild's counts and, when they differ, runs the plain build (and,
+   in nlfem_assemble, the assembly again); nlfem_pairs_info_t.rebuild tells
+   which happened.  Until that call the mesh arrays must stay valid, and an
+   error of the rebuild (E_MESH, ...) is returned by that call.  A batch
+   holding the handle stays valid across rebuilds that keep the sizes; after
+   a plain rebuild its runs return E_MISMATCH.
    Errors: E_INVALID, E_MESH, E_NOMEM, E_HIP, E_OVERFLOW, E_NODEVICE. */
 int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg,
                       nlfem_pairs **pairs, void *stream);
@@ -259,15 +267,17 @@ int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *
                        int32_t tune, nlfem_batch **batch, void *stream);
 
 /* Assembles all problems of the batch into their vals on `stream`.
-   Allocates nothing, never synchronises, records no memset (safe to
-   capture into a HIP graph).  Two runs of one batch must not overlap.
-   Errors: E_INVALID, E_HIP. */
+   Allocates nothing, records no memset (safe to capture into a HIP graph),
+   and synchronises only to finish the check of a handle rebuilt without
+   waiting (see nlfem_build_pairs).  Two runs of one batch must not overlap.
+   Errors: E_INVALID, E_HIP, E_MISMATCH (a handle was built plainly since
+   the batch was created), and the errors of a rebuild finished here. */
 int nlfem_batch_assemble(nlfem_batch *batch, void *stream);
 
 /* Same work from a HIP graph: the first call captures the launches of
    nlfem_batch_assemble on an internal stream and instantiates the graph
    (host allocation); every call launches it on `stream`.
-   Errors: E_INVALID, E_HIP. */
+   Errors: as nlfem_batch_assemble. */
 int nlfem_batch_launch_graph(nlfem_batch *batch, void *stream);
 
 /* Number of launch groups and the launch shape of the four phases

@@ -210,20 +210,24 @@ constexpr uint32_t kSpecGeo = 0x3fu | (1u << kRedErr);
 constexpr uint32_t kSpecPairs =
     kSpecGeo | (1u << kRedDofs) | (1u << kRedClip) | (0x3fu << kRedTot) | (0x3fu << kRedSegMax);
 constexpr uint32_t kSpecCsr = kSpecPairs | (1u << kRedMaxRow) | (1u << kRedNnz);
-constexpr int kSpecFailed = 1;   // internal return: the rebuild has to run synchronously
 
 // Copies the reduction slots to the pinned host buffer and waits for them.
 // The wait polls an event rather than blocking in the runtime: it lasts tens
 // of microseconds, and a blocking wait adds the wake-up of the host thread.
+int wait_event(hipEvent_t ev)
+{
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) return NLFEM_OK;
+        if (e != hipErrorNotReady) return hip_error(e, "hipEventQuery");
+    }
+}
+
 int read_slots(nlfem_pairs *h, hipStream_t s)
 {
     NLFEM_HIP(hipMemcpyAsync(h->rb, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
     NLFEM_HIP(hipEventRecord(h->ev_rb, s));
-    for (;;) {
-        const hipError_t e = hipEventQuery(h->ev_rb);
-        if (e == hipSuccess) return NLFEM_OK;
-        if (e != hipErrorNotReady) return hip_error(e, "hipEventQuery");
-    }
+    return wait_event(h->ev_rb);
 }
 
 // Counters of the build after the geometry, all cleared by one launch.
@@ -244,8 +248,9 @@ ZeroList build_counters(nlfem_pairs *h)
 // (spec: same sizes and configuration as the handle's last build) launches
 // everything with the last build's sizes, and every build kernel after the
 // geometry first compares the slots final by its launch with the last
-// build's (on the device) and returns when one differs; one read-back at the
-// end decides: kSpecFailed asks the caller for the plain build.
+// build's (on the device) and returns when one differs.  Its read-back is
+// checked by the next call that uses the handle (resolve), which runs the
+// plain build when a slot differs.
 int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStream_t s, bool spec)
 {
     h->gate = SpecGate{};
@@ -466,10 +471,16 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
     NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
     if (spec) {
-        NLFEM_TRY(read_slots(h, s));
+        // the read-back is checked by the next call that uses the handle
+        // (resolve); until then assembly launches test the slots themselves
+        NLFEM_HIP(hipMemcpyAsync(h->rb, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
+        NLFEM_HIP(hipEventRecord(h->ev_rb, s));
         h->gate = SpecGate{};
-        for (int i = 0; i < kRedSlots; ++i)
-            if (((kSpecCsr >> i) & 1u) && red[i] != h->spec_red[i]) return kSpecFailed;
+        h->pending = true;
+        h->pend_mesh = *m;
+        h->pend_cfg.set(*cfg);
+        h->pend_stream = s;
+        h->asm_gate = SpecGate{h->red, h->spec_want, kSpecCsr & ~(1u << kRedErr)};
         return NLFEM_OK;
     }
     // the slots of this build, expected by the next speculative rebuild (the
@@ -479,8 +490,39 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
                              s));
     std::memcpy(h->spec_red, red, sizeof h->spec_red);
     h->spec_ok = true;
+    ++h->generation;
     return NLFEM_OK;
 }
+
+}  // namespace
+
+int resolve(nlfem_pairs *h, hipEvent_t after)
+{
+    if (!h->pending) return NLFEM_OK;
+    h->pending = false;
+    h->asm_gate = SpecGate{};
+    NLFEM_TRY(wait_event(h->ev_rb));
+    bool same = true;
+    for (int i = 0; i < kRedSlots; ++i)
+        if (((kSpecCsr >> i) & 1u) && h->rb[i] != h->spec_red[i]) same = false;
+    if (same) return NLFEM_OK;
+    h->last_build = 2;
+    if (after) NLFEM_TRY(wait_event(after));
+    int rc = build(&h->pend_mesh, &h->pend_cfg.c, h, h->pend_stream, false);
+    if (rc == NLFEM_OK) {
+        // the plain build's last launches are still queued on its stream
+        NLFEM_HIP(hipEventRecord(h->ev_rb, h->pend_stream));
+        rc = wait_event(h->ev_rb);
+    }
+    if (rc != NLFEM_OK) {
+        h->spec_ok = false;
+        h->gate = SpecGate{};
+        h->K = 0;   // unusable rather than half built
+    }
+    return rc;
+}
+
+namespace {
 
 // same sizes and the same configuration of the pair search as the handle
 bool same_shape(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c)
@@ -592,13 +634,15 @@ int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pai
     const bool fresh = *pairs == nullptr;
     nlfem_pairs *h = fresh ? new (std::nothrow) nlfem_pairs() : *pairs;
     if (!h) return set_error(NLFEM_E_NOMEM, "host allocation failed");
+    if (!fresh && h->pending) {
+        // a newer build replaces an unchecked one: only its read-back is awaited
+        NLFEM_TRY(wait_event(h->ev_rb));
+        h->pending = false;
+        h->asm_gate = SpecGate{};
+    }
     const bool spec = !fresh && h->spec_ok && same_shape(h, mesh, cfg);
     int rc = build(mesh, cfg, h, (hipStream_t)stream, spec);
     h->last_build = spec ? 1 : 0;
-    if (rc == kSpecFailed) {
-        h->last_build = 2;
-        rc = build(mesh, cfg, h, (hipStream_t)stream, false);
-    }
     if (rc != NLFEM_OK) {
         h->spec_ok = false;
         h->gate = SpecGate{};
@@ -613,6 +657,7 @@ int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pai
 int nlfem_pairs_info(const nlfem_pairs *h, nlfem_pairs_info_t *info)
 {
     if (!h || !info) return set_error(NLFEM_E_INVALID, "NULL argument");
+    NLFEM_TRY(resolve(const_cast<nlfem_pairs *>(h)));
     info->n_pairs = h->n_pairs;
     info->n_far = h->n_far;
     info->n_vertex = h->n_vertex;
@@ -630,6 +675,7 @@ int nlfem_pairs_info(const nlfem_pairs *h, nlfem_pairs_info_t *info)
 
 int nlfem_pairs_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls, void *stream)
 {
+    if (h) NLFEM_TRY(resolve(const_cast<nlfem_pairs *>(h)));
     if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle is NULL or not built");
     if (h->n_pairs > 0 && (!k || !l || !cls)) return set_error(NLFEM_E_INVALID, "NULL output array");
     return launch_export(h, k, l, cls, (hipStream_t)stream);
@@ -637,6 +683,7 @@ int nlfem_pairs_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls
 
 int nlfem_csr_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, void *stream)
 {
+    if (h) NLFEM_TRY(resolve(const_cast<nlfem_pairs *>(h)));
     if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle is NULL or not built");
     if (!row_ptr || (h->nnz_node > 0 && !col)) return set_error(NLFEM_E_INVALID, "NULL output array");
     return launch_pattern(h, row_ptr, col, (hipStream_t)stream);
@@ -657,7 +704,16 @@ int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg, const nlfem_
     GaussArgs g{};
     g.n = cfg->singular_n;
     if (g.n > 0) gauss_legendre01(g.n, g.x, g.w);
-    return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
+    nlfem_pairs *hm = const_cast<nlfem_pairs *>(h);
+    if (!hm->pending) return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
+    // after an unchecked rebuild the launches test its slots on the device
+    // and the check finishes here, with the assembly already queued; a
+    // failed one is built plainly and assembled again
+    NLFEM_TRY(launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream));
+    NLFEM_HIP(hipEventRecord(hm->ev_fork, (hipStream_t)stream));
+    NLFEM_TRY(resolve(hm, hm->ev_fork));
+    if (hm->last_build == 2) return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
+    return NLFEM_OK;
 }
 
 int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_qp, const double *f_affine,
@@ -746,9 +802,11 @@ int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *
     int dev = -1;
     NLFEM_HIP(hipGetDevice(&dev));
     std::vector<items::AssemblePlan> plans;
+    std::vector<nlfem_pairs *> handles;
     plans.reserve(n);
     for (int i = 0; i < n; ++i) {
-        const nlfem_pairs *h = pairs[i];
+        nlfem_pairs *h = pairs[i];
+        if (h) NLFEM_TRY(resolve(h));
         if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle " + std::to_string(i) + " is NULL or not built");
         NLFEM_TRY(check_mesh(&meshes[i]));
         NLFEM_TRY(check_cfg(&cfgs[i]));
@@ -763,8 +821,9 @@ int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *
         g.n = cfgs[i].singular_n;
         if (g.n > 0) gauss_legendre01(g.n, g.x, g.w);
         plans.push_back(items::make_plan(h, &meshes[i], &cfgs[i], g, vals[i]));
+        handles.push_back(h);
     }
-    return batch_create(plans, tune_cache, tune, batch, (hipStream_t)stream);
+    return batch_create(plans, handles, tune_cache, tune, batch, (hipStream_t)stream);
 }
 
 int nlfem_batch_assemble(nlfem_batch *batch, void *stream)

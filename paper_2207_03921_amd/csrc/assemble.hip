@@ -14,6 +14,7 @@ constexpr bool far_staged() { return !(Ker<KER>::NK == 3 && sizeof(T) == 8); }
 template <int KER, typename T, int PM, bool POLY>
 __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArgs r2)
 {
+    if (gated(a.gate)) return;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!far_staged<KER, T>() || POLY) {
         if (idx >= a.n) return;
@@ -43,6 +44,7 @@ __global__ void __launch_bounds__(64) k_far_rec_poly(FarArgs a, RoleArgs r1, Rol
     __shared__ int32_t queue[64 * 2 * kMaxRule];
     __shared__ int32_t pe[64], pf[64];
     __shared__ T slots[64 * NV];
+    if (gated(a.gate)) return;
     const int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x;
     far_wave_poly<KER, T, PM>(a, r1, r2, idx, idx < a.n, queue, pe, pf, slots);
 }
@@ -52,6 +54,7 @@ __global__ void __launch_bounds__(64) k_far_rec_poly(FarArgs a, RoleArgs r1, Rol
 struct TouchLaunch {
     TouchArgs t[3];   // identical, edge, vertex
     int64_t nb[3];    // blocks of the vertex, edge and identical classes
+    SpecGate gate;
 };
 
 template <int KER, int CLS>
@@ -67,6 +70,7 @@ __device__ __forceinline__ void touch_block(const TouchArgs &a, const GaussView 
 template <int KER>
 __global__ void __launch_bounds__(256) k_touch_rec(TouchLaunch L, GaussArgs g)
 {
+    if (gated(L.gate)) return;
     // the rule in LDS: the point loops read it at every step
     __shared__ double gs[2 * kMaxGauss];
     if (threadIdx.x < 2 * kMaxGauss)
@@ -89,6 +93,7 @@ __global__ void __launch_bounds__(256) k_touch_rec(TouchLaunch L, GaussArgs g)
 template <int NK, typename TR>
 __global__ void __launch_bounds__(256) k_elem_diag(DiagArgs a)
 {
+    if (gated(a.gate)) return;
     constexpr int per = 256 / kDiagG;   // elements per workgroup
     const int64_t e = xcd_item(blockIdx.x, (a.K + per - 1) / per) * per + threadIdx.x / kDiagG;
     if (e >= a.K) return;   // whole lane groups leave together
@@ -100,6 +105,7 @@ __global__ void __launch_bounds__(64) k_rows(RowArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ RowShared sh;
+    if (gated(a.gate)) return;
     for (int64_t b = blockIdx.x; b < xcd_span(a.nrows); b += gridDim.x) {
         const int64_t item = xcd_item(b, a.nrows);
         if (item >= a.nrows) continue;
@@ -140,6 +146,7 @@ void touch_dispatch(const AssemblePlan &p, hipStream_t s)
 {
     TouchLaunch L{};
     for (int c = 0; c < 3; ++c) L.t[c] = p.touch[c];
+    L.gate = p.far.gate;
     L.nb[0] = (p.touch[2].n * touch_lanes(1) + 255) / 256;
     L.nb[1] = (p.touch[1].n * touch_lanes(2) + 255) / 256;
     L.nb[2] = (p.touch[0].n * touch_lanes(3) + 255) / 256;
@@ -203,6 +210,7 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     a.delta = h->delta;
     a.cap = kMaxPoly + 4;
     a.err = h->err;
+    a.gate = h->asm_gate;
     // same rules: one pass, A and B both the outer rule.  Otherwise pass 1
     // (outer on e, inner on f) and pass 2 (inner on e, outer on f).
     p.r1 = roles(h->rules, true, h->rules.same ? true : false);
@@ -248,7 +256,9 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     r.maxlen = (int32_t)h->max_row;
     r.val = val;
     r.err = h->err;
-    p.diag = DiagArgs{h->K, r.sptr, h->snbr, h->sflag, h->srec, h->far_rec, h->far_stride, h->nUF, h->dsum, h->err};
+    r.gate = h->asm_gate;
+    p.diag = DiagArgs{h->K,        r.sptr,   h->snbr, h->sflag, h->srec, h->far_rec, h->far_stride,
+                      h->nUF,      h->dsum,  h->err,  h->asm_gate};
     return p;
 }
 

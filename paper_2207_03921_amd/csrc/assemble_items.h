@@ -167,6 +167,7 @@ struct FarArgs {
     double delta;
     int32_t cap;             // clip buffer length per lane
     int32_t *err;
+    SpecGate gate;           // single-problem launches after an unchecked rebuild
 };
 
 // rule points of the two roles (A on e, B on f)
@@ -871,6 +872,7 @@ struct DiagArgs {
     int64_t n_far;
     double *dsum;
     int32_t *err;
+    SpecGate gate;
 };
 
 // D_e of element e by the kDiagG lanes sub = 0..kDiagG-1 of an aligned lane
@@ -955,6 +957,7 @@ struct RowArgs {
     int32_t maxlen;
     double *val;
     int32_t *err;
+    SpecGate gate;
 };
 
 constexpr int kRowQ = 64;   // elements around a node per batch (one per lane)

@@ -10,8 +10,10 @@ struct nlfem_batch;
 namespace nlfem {
 
 // tune_mode: 0 default shapes, 1 cached or tuned (cache written), 2 always tuned
-int batch_create(const std::vector<items::AssemblePlan> &plans, const char *tune_cache, int tune_mode,
-                 nlfem_batch **out, hipStream_t s);
+// handles: the problems' pair handles (checked again before every run: a
+// plain rebuild of one since the creation makes the batch stale)
+int batch_create(const std::vector<items::AssemblePlan> &plans, const std::vector<nlfem_pairs *> &handles,
+                 const char *tune_cache, int tune_mode, nlfem_batch **out, hipStream_t s);
 int batch_run(nlfem_batch *b, hipStream_t s);
 int batch_graph_launch(nlfem_batch *b, hipStream_t s);
 int batch_info(const nlfem_batch *b, int32_t *groups, int32_t *shape);

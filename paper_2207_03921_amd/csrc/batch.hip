@@ -259,6 +259,8 @@ struct nlfem_batch {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<nlfem_pairs *> handles;
+    std::vector<uint64_t> generation;   // of each handle at creation
 };
 
 namespace {
@@ -606,13 +608,15 @@ int tune(nlfem_batch *b, hipStream_t s)
 
 namespace nlfem {
 
-int batch_create(const std::vector<AssemblePlan> &plans, const char *tune_cache, int tune_mode, nlfem_batch **out,
-                 hipStream_t s)
+int batch_create(const std::vector<AssemblePlan> &plans, const std::vector<nlfem_pairs *> &handles,
+                 const char *tune_cache, int tune_mode, nlfem_batch **out, hipStream_t s)
 {
     nlfem_batch *b = new (std::nothrow) nlfem_batch();
     if (!b) return set_error(NLFEM_E_NOMEM, "host allocation failed");
     b->n = (int)plans.size();
     b->plans = plans;
+    b->handles = handles;
+    for (const nlfem_pairs *h : handles) b->generation.push_back(h->generation);
     int dev = 0;
     int rc = NLFEM_OK;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -642,10 +646,32 @@ int batch_create(const std::vector<AssemblePlan> &plans, const char *tune_cache,
     return NLFEM_OK;
 }
 
-int batch_run(nlfem_batch *b, hipStream_t s) { return run_all(b, s); }
+namespace {
+
+// finishes unchecked rebuilds of the batch's handles; a handle built plainly
+// since the batch was created may have other sizes and buffers
+int check_handles(nlfem_batch *b)
+{
+    for (size_t i = 0; i < b->handles.size(); ++i) {
+        NLFEM_TRY(resolve(b->handles[i]));
+        if (b->handles[i]->generation != b->generation[i])
+            return set_error(NLFEM_E_MISMATCH, "pairs handle " + std::to_string(i) +
+                                                   " was rebuilt since the batch was created");
+    }
+    return NLFEM_OK;
+}
+
+}  // namespace
+
+int batch_run(nlfem_batch *b, hipStream_t s)
+{
+    NLFEM_TRY(check_handles(b));
+    return run_all(b, s);
+}
 
 int batch_graph_launch(nlfem_batch *b, hipStream_t s)
 {
+    NLFEM_TRY(check_handles(b));
     if (!b->exec) {
         if (!b->capture) NLFEM_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
         NLFEM_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/nlfem.h"
 
@@ -55,6 +56,28 @@ struct GaussArgs {
 //   19-24 largest per-element pair counts (19: largest |S(e)|)
 enum { kRedMaxCell = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
        kRedTot = 12, kRedErr = 18, kRedSegMax = 19, kRedSlots = 32 };
+
+// Deep copy of a configuration (its host tables), for a build that may have
+// to run again after the call that gave it has returned.
+struct ConfigCopy {
+    nlfem_config c{};
+    std::vector<double> oxi, ow, ixi, iw, dirs;
+    void set(const nlfem_config &src)
+    {
+        c = src;
+        oxi.assign(src.outer.xi, src.outer.xi + 2 * src.outer.n);
+        ow.assign(src.outer.w, src.outer.w + src.outer.n);
+        ixi.assign(src.inner.xi, src.inner.xi + 2 * src.inner.n);
+        iw.assign(src.inner.w, src.inner.w + src.inner.n);
+        if (src.polygon_dirs && src.polygon_n > 0) dirs.assign(src.polygon_dirs, src.polygon_dirs + 2 * src.polygon_n);
+        else dirs.clear();
+        c.outer.xi = oxi.data();
+        c.outer.w = ow.data();
+        c.inner.xi = ixi.data();
+        c.inner.w = iw.data();
+        c.polygon_dirs = dirs.empty() ? nullptr : dirs.data();
+    }
+};
 
 // A rebuild launched with the last build's sizes: a build kernel runs only
 // while the reduction slots that are final at its launch (mask) equal the
@@ -139,6 +162,14 @@ struct nlfem_pairs {
     unsigned long long spec_red[nlfem::kRedSlots] = {};   // host copy
     unsigned long long *spec_want = nullptr;              // device copy
     nlfem::SpecGate gate{};
+    // a rebuild whose read-back has not been checked yet: what a plain build
+    // needs if the check fails, and the gate of assembly launches until then
+    bool pending = false;
+    nlfem_mesh pend_mesh{};
+    nlfem::ConfigCopy pend_cfg;
+    hipStream_t pend_stream = nullptr;
+    nlfem::SpecGate asm_gate{};
+    uint64_t generation = 0;   // counts plain builds (batches check it)
     int32_t last_build = 0;   // 0 plain, 1 speculative rebuild held, 2 it fell back
     unsigned long long *counters = nullptr;  // [kCntLast]
     // node -> element incidence
@@ -208,6 +239,9 @@ void timing_end(int phase, hipStream_t s);
 // error reporting (abi.hip) --------------------------------------------
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *what);
+// abi.hip: finishes an unchecked rebuild of h (waits for its read-back; runs
+// the plain build when the sizes differ, after `after` when given)
+int resolve(nlfem_pairs *h, hipEvent_t after = nullptr);
 
 #define NLFEM_HIP(call)                                               \
     do {                                                              \

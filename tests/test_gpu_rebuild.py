@@ -1,10 +1,12 @@
 """Rebuilding a pairs handle in place (MI355X only).
 
 A rebuild of a handle whose last build had the same sizes and configuration
-runs with the last build's sizes and one synchronisation; device-side checks
-send it back to a plain build when the counts differ.  Every rebuild must
-give what a fresh handle gives: the same counts, pairs and CSR pattern, and
-values equal up to the order of floating-point sums (fp64 here).
+runs with the last build's sizes without waiting; device-side checks gate its
+kernels, and the next call on the handle checks its read-back and runs the
+plain build when the counts differ.  Every rebuild must give what a fresh
+handle gives: the same counts, pairs and CSR pattern, and values equal up to
+the order of floating-point sums (fp64 here), whichever call finishes the
+check.
 """
 import numpy as np
 import pytest
@@ -35,6 +37,19 @@ def _assert_same(a, b):
         assert np.array_equal(x, y)
     scale = max(np.abs(b["val"]).max(), 1e-300)
     assert np.abs(a["val"] - b["val"]).max() <= 1e-13 * scale
+
+
+def _result_assemble_first(nl, dm, cfg, pairs):
+    """The same, with the assembly as the first call after the rebuild."""
+    import torch
+    nnz_cap = 4 << 20
+    val = torch.full((nnz_cap,), float("nan"), dtype=torch.float64, device="cuda")
+    nl.nlfem_assemble(dm, cfg, pairs, val=val)
+    r = _result(nl, dm, cfg, pairs)
+    torch.cuda.synchronize()
+    got = val[:r["info"]["nnz"]].cpu().numpy()
+    assert np.array_equal(got, r["val"]) or np.abs(got - r["val"]).max() <= 1e-13 * max(np.abs(r["val"]).max(), 1e-300)
+    return r
 
 
 def _fresh(nl, mesh, cfg):
@@ -72,12 +87,46 @@ def test_rebuild_same_and_changed_meshes():
         r = _result(nl, dm[name], cfg, pairs)
         assert r["rebuild"] == path, (name, r["rebuild"])
         _assert_same(r, ref[name])
+    # the same sequence with the assembly as the first call after each rebuild
+    for name, path in (("B", 2), ("B", 1), ("A", 2), ("A", 1)):
+        print("rebuild with", name, "assembly first", flush=True)
+        pairs = nl.nlfem_build_pairs(dm[name], cfg, pairs=pairs)
+        r = _result_assemble_first(nl, dm[name], cfg, pairs)
+        assert r["rebuild"] == path, (name, r["rebuild"])
+        _assert_same(r, ref[name])
     # a new device copy of the same mesh (other pointers, same values)
     dA2 = nl.DeviceMesh.from_numpy(A)
     pairs = nl.nlfem_build_pairs(dA2, cfg, pairs=pairs)
     r = _result(nl, dA2, cfg, pairs)
     assert r["rebuild"] == 1
     _assert_same(r, ref["A"])
+    nl.nlfem_pairs_free(pairs)
+
+
+def test_batch_sees_rebuilds():
+    """A batch stays valid across rebuilds that keep the sizes and reports a
+    plain rebuild of one of its handles."""
+    import torch
+    import paper_2207_03921_amd as nl
+    w = inv_dist_jittered(n=16, delta=0.12, precision="fp64")
+    cfg = make_config(w)
+    dm = nl.DeviceMesh.from_numpy(w["mesh"])
+    pairs = nl.nlfem_build_pairs(dm, cfg)
+    single = nl.nlfem_assemble(dm, cfg, pairs).clone()
+    nnz = nl.nlfem_pairs_info(pairs)["nnz"]
+    val = torch.full((nnz,), float("nan"), dtype=torch.float64, device="cuda")
+    b = nl.nlfem_batch_create([dm], [cfg], [pairs], [val], tune=0)
+    pairs = nl.nlfem_build_pairs(dm, cfg, pairs=pairs)   # same sizes: no wait
+    nl.nlfem_batch_assemble(b)
+    torch.cuda.synchronize()
+    assert nl.nlfem_pairs_info(pairs)["rebuild"] == 1
+    scale = single.abs().max().item()
+    assert (val - single[:nnz]).abs().max().item() <= 1e-13 * scale
+    pairs = nl.nlfem_build_pairs(dm, make_config(w, delta=0.13), pairs=pairs)   # plain
+    with pytest.raises(nl.NlfemError) as e:
+        nl.nlfem_batch_assemble(b)
+    assert e.value.code == -6
+    nl.nlfem_batch_free(b)
     nl.nlfem_pairs_free(pairs)
 
 
