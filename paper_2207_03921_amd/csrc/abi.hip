@@ -285,11 +285,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         h->rb = (unsigned long long *)rb;
     }
     unsigned long long *red = h->rb;
-    if (!h->aux) {
-        NLFEM_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-        NLFEM_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-        NLFEM_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    if (!h->ev_rb) {
         NLFEM_HIP(hipEventCreateWithFlags(&h->ev_rb, hipEventDisableTiming));
+        NLFEM_HIP(hipEventCreateWithFlags(&h->ev_asm, hipEventDisableTiming));
     }
     timing_begin(kPhGeometry, s);
     {
@@ -710,8 +708,8 @@ int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg, const nlfem_
     // and the check finishes here, with the assembly already queued; a
     // failed one is built plainly and assembled again
     NLFEM_TRY(launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream));
-    NLFEM_HIP(hipEventRecord(hm->ev_fork, (hipStream_t)stream));
-    NLFEM_TRY(resolve(hm, hm->ev_fork));
+    NLFEM_HIP(hipEventRecord(hm->ev_asm, (hipStream_t)stream));
+    NLFEM_TRY(resolve(hm, hm->ev_asm));
     if (hm->last_build == 2) return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
     return NLFEM_OK;
 }
@@ -782,10 +780,8 @@ void nlfem_pairs_free(nlfem_pairs *h)
     for (auto &b : h->bufs)
         if (b.p) (void)hipFree(b.p);
     if (h->rb) (void)hipHostFree(h->rb);
-    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_asm) (void)hipEventDestroy(h->ev_asm);
     if (h->ev_rb) (void)hipEventDestroy(h->ev_rb);
-    if (h->aux) (void)hipStreamDestroy(h->aux);
     delete h;
 }
 

@@ -272,26 +272,17 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
 {
     const AssemblePlan p = make_plan(h, m, cfg, g, val);
     const bool has_touch = p.touch[0].n + p.touch[1].n + p.touch[2].n > 0;
-    // touching pairs on the handle's second stream, beside the non-touching
-    // pairs and their diagonal sums; joined before the row gather
-    const bool fork = has_touch && p.far.n > 0 && h->aux;
-    hipStream_t st = s;
-    bool joined = false;
-    if (fork) {
-        NLFEM_HIP(hipEventRecord(h->ev_fork, s));
-        NLFEM_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
-        st = h->aux;
-    }
+    // one stream: a second stream for the touching pairs costs more in the
+    // two cross-queue waits than their overlap with the far records gains
     if (has_touch) {
-        timing_begin(kPhTouch, st);
+        timing_begin(kPhTouch, s);
         switch (p.kernel) {
-        case NLFEM_K_CONSTANT: touch_dispatch<NLFEM_K_CONSTANT>(p, st); break;
-        case NLFEM_K_INV_DIST: touch_dispatch<NLFEM_K_INV_DIST>(p, st); break;
-        default: touch_dispatch<NLFEM_K_PERIDYNAMIC>(p, st); break;
+        case NLFEM_K_CONSTANT: touch_dispatch<NLFEM_K_CONSTANT>(p, s); break;
+        case NLFEM_K_INV_DIST: touch_dispatch<NLFEM_K_INV_DIST>(p, s); break;
+        default: touch_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
         }
-        timing_end(kPhTouch, st);
+        timing_end(kPhTouch, s);
     }
-    if (fork) NLFEM_HIP(hipEventRecord(h->ev_join, h->aux));
     if (p.far.n > 0) {
         timing_begin(kPhFar, s);
         switch (p.kernel) {
@@ -314,10 +305,6 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
             else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, p.diag);
         }
         timing_end(kPhFar, s);
-        if (fork) {
-            NLFEM_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
-            joined = true;
-        }
         const size_t lds = row_lds_bytes(p.rows.maxlen, nc, p.rows.hcap);
         const unsigned grid = xcd_grid(p.rows.nrows);
         timing_begin(kPhRows, s);
@@ -330,7 +317,6 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         }
         timing_end(kPhRows, s);
     }
-    if (fork && !joined) NLFEM_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

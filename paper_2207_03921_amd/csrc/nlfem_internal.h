@@ -215,11 +215,8 @@ struct nlfem_pairs {
     double *dsum = nullptr;      // [K][6 * NK] summed element-diagonal blocks of the far pairs
     double *poly_dir = nullptr;  // [N][2] polygon directions (approach POLY)
     int32_t far_stride = 0, touch_stride = 0;
-    // second stream of the assembly: touching pairs run beside the
-    // non-touching ones (fork and join through the two events)
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_rb = nullptr;   // completion of a read-back of the reduction slots
+    hipEvent_t ev_rb = nullptr;    // completion of a read-back of the reduction slots
+    hipEvent_t ev_asm = nullptr;   // end of an assembly queued before a rebuild's check
     // grow-only device buffers behind the typed pointers above
     struct DevBuf {
         void *p = nullptr;
