@@ -245,6 +245,9 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     __shared__ int32_t pq_all[POLY ? kBlock / 64 : 1][POLY ? 64 * 2 * kMaxRule : 1];
     __shared__ uint32_t pm_all[POLY ? kBlock / 64 : 1][2][64];
     __shared__ int pq_cnt[kBlock / 64];
+    // per wave: the chunk positions of the candidates that can interact with
+    // the wave's current element, in chunk order
+    __shared__ int16_t cand_all[kBlock / 64][kCH];
 
     // the neighbour cells (row-major, clipped to the grid): one lane each, so
     // their counts load in parallel, then a prefix sum across the wave
@@ -333,9 +336,37 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                 int64_t off[kLsLast];
                 for (int k = 0; k < kLsLast; ++k) off[k] = e_off[i * kLsLast + k];
 
+                // keep the candidates that are active and touching or within
+                // reach of the barycentre, so the point tests below run on
+                // full waves
+                int16_t *cand = cand_all[wv];
+                int ncand = 0;
+                wave_sync();   // the previous element's reads of cand are done
                 for (int jj = 0; jj < nch; jj += 64) {
                     const int j = jj + lane;
-                    const bool valid = j < nch;
+                    bool keep = false;
+                    if (j < nch) {
+                        const int32_t lab_f = c_lab[j];
+                        const bool act = (lab_f == 1 || lab_f == 2) && (lab_e == 1 || lab_f == 1);
+                        const int32_t f0 = c_nd[j], f1 = c_nd[kCH + j], f2 = c_nd[2 * kCH + j];
+                        const bool sh = ne0 == f0 || ne0 == f1 || ne0 == f2 || ne1 == f0 || ne1 == f1 ||
+                                        ne1 == f2 || ne2 == f0 || ne2 == f1 || ne2 == f2;
+                        if (act && a.singular && sh) {
+                            keep = true;
+                        } else if (act) {
+                            const double2 bf = c_b[j];
+                            const double dbx = be.x - bf.x, dby = be.y - bf.y;
+                            keep = dbx * dbx + dby * dby <= a.reach2;
+                        }
+                    }
+                    const unsigned long long bk = __ballot(keep);
+                    if (keep) cand[ncand + __popcll(bk & lt)] = (int16_t)j;
+                    ncand += __popcll(bk);
+                }
+                wave_sync();
+                for (int kb = 0; kb < ncand; kb += 64) {
+                    const bool valid = kb + lane < ncand;
+                    const int j = valid ? cand[kb + lane] : 0;
                     bool inS = false, inP = false, isUF = false;
                     int cls = 0;
                     uint32_t mef = 0, mfe = 0;
@@ -395,7 +426,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                         for (int it = lane; it < nq; it += 64) {
                             const int code = pq[it];
                             const int jl = code >> 5, fe_dir = code & 16, p = code & 15;
-                            const int jc = jj + jl;
+                            const int jc = cand[kb + jl];   // chunk slot of lane jl's candidate
                             uint32_t st;
                             if (!fe_dir) {
                                 const double2 x = a.xp[(int64_t)e * a.P + p];
