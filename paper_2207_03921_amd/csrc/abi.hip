@@ -418,7 +418,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     timing_end(kPhPairs, s);
     timing_begin(kPhLists, s);
     NLFEM_TRY(launch_sort_lists(h, s));
-    NLFEM_TRY(launch_worklists(h, m, s));
+    NLFEM_TRY(launch_links(h, s));
     timing_end(kPhLists, s);
 
     // CSR pattern -------------------------------------------------------------

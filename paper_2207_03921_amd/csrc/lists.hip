@@ -3,11 +3,12 @@
 // 1. Every segment S(e) is sorted by neighbour id (bitonic sort in LDS, one
 //    wave per element), so that the pair (f, e) can be found in S(f) by
 //    binary search.
-// 2. The entries with f >= e are the unordered pairs.  They are compacted
-//    into work lists: non-touching pairs with their point status, touching
-//    pairs grouped by class (identical, edge, vertex).  Each upper entry
-//    records the index of its work item; each lower entry (f < e) takes the
-//    index of its mirror (f, e).  The assembly computes one result per work
+// 2. The entries with f >= e are the unordered pairs.  The same wave, with
+//    the sorted list in LDS, compacts them into work lists: non-touching
+//    pairs with their point status, touching pairs grouped by class
+//    (identical, edge, vertex).  Each upper entry records the index of its
+//    work item; each lower entry (f < e) takes the index of its mirror
+//    (f, e) in a second launch.  The assembly computes one result per work
 //    item and every matrix row finds the results of all its pairs through
 //    these indices.
 #include "nlfem_internal.h"
@@ -68,70 +69,61 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
                 }
                 __syncthreads();
             }
-        for (int t = lane; t < n; t += 64) {
-            const unsigned long long kk = key[t];
-            const int src = (int)(kk & 0xffffffffull);
-            a.snbr[s0 + t] = (int32_t)(kk >> 32);
-            a.sflag[s0 + t] = a.sflag_tmp[s0 + src];
-            a.smask[s0 + t] = a.smask_tmp[s0 + src];
-            a.srec[s0 + t] = -1;   // set by the work lists and the links
-            const int32_t f = (int32_t)(kk >> 32);
-            a.snode[s0 + t] = make_int4(f, a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]);
-        }
-        __syncthreads();
-    }
-}
-
-__global__ void __launch_bounds__(64) k_worklists(ListArgs a)
-{
-    if (gated(a.gate)) return;
-    const int lane = threadIdx.x;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
-        const int64_t e = xcd_item(b, a.K);
-        if (e >= a.K) continue;
-        const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
+        // the sorted list, and the upper entries (f >= e) appended to the work
+        // lists of their class in list order; lower entries get their record
+        // from the mirror (k_link)
+        const unsigned long long lt = (1ull << lane) - 1ull;
         int64_t oF = a.loff[kLsUF * a.K1 + e];
         int64_t oI = a.loff[kLsUI * a.K1 + e];
         int64_t oE = a.baseE + a.loff[kLsUE * a.K1 + e];
         int64_t oV = a.baseV + a.loff[kLsUV * a.K1 + e];
-        for (int64_t t0 = s0; t0 < s1; t0 += 64) {
-            const int64_t t = t0 + lane;
+        for (int t0 = 0; t0 < n; t0 += 64) {
+            const int t = t0 + lane;
             bool isF = false, isI = false, isE = false, isV = false;
             int32_t f = 0;
             uint2 m = make_uint2(0u, 0u);
-            if (t < s1) {
-                f = a.snbr[t];
-                const int cls = (a.sflag[t] >> 2) & 3;
+            if (t < n) {
+                const unsigned long long kk = key[t];
+                const int src = (int)(kk & 0xffffffffull);
+                f = (int32_t)(kk >> 32);
+                const uint8_t fl = a.sflag_tmp[s0 + src];
+                m = a.smask_tmp[s0 + src];
+                a.snbr[s0 + t] = f;
+                a.sflag[s0 + t] = fl;
+                a.smask[s0 + t] = m;
+                a.snode[s0 + t] = make_int4(f, a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]);
+                const int cls = (fl >> 2) & 3;
                 const bool upper = f >= e;
                 isF = upper && cls == 0;
                 isI = upper && cls == 3;
                 isE = upper && cls == 2;
                 isV = upper && cls == 1;
-                if (isF) m = a.smask[t];
             }
             const unsigned long long bF = __ballot(isF), bI = __ballot(isI);
             const unsigned long long bE = __ballot(isE), bV = __ballot(isV);
+            int32_t rec = -1;
             if (isF) {
                 const int64_t u = oF + __popcll(bF & lt);
                 a.ue[u] = (int32_t)e;
                 a.uf[u] = f;
                 a.um_ef[u] = m.x;
                 a.um_fe[u] = f == e ? 0u : m.y;
-                a.srec[t] = (int32_t)u;
+                rec = (int32_t)u;
             }
             if (isI || isE || isV) {
                 const int64_t u = isI ? oI + __popcll(bI & lt) : isE ? oE + __popcll(bE & lt)
                                                                       : oV + __popcll(bV & lt);
                 a.te[u] = (int32_t)e;
                 a.tf[u] = f;
-                a.srec[t] = (int32_t)u;
+                rec = (int32_t)u;
             }
+            if (t < n) a.srec[s0 + t] = rec;
             oF += __popcll(bF);
             oI += __popcll(bI);
             oE += __popcll(bE);
             oV += __popcll(bV);
         }
+        __syncthreads();
     }
 }
 
@@ -205,12 +197,11 @@ int launch_sort_lists(nlfem_pairs *h, hipStream_t s)
     return NLFEM_OK;
 }
 
-int launch_worklists(nlfem_pairs *h, const nlfem_mesh *, hipStream_t s)
+int launch_links(nlfem_pairs *h, hipStream_t s)
 {
     if (h->nS == 0) return NLFEM_OK;
     ListArgs a = list_args(h);
     const unsigned grid = xcd_grid(h->K);
-    hipLaunchKernelGGL(k_worklists, dim3(grid), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_link, dim3(grid), dim3(64), 0, s, a);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;

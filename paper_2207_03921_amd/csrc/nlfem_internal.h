@@ -322,7 +322,7 @@ int launch_bucket_fill(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
 // lists.hip: sorted neighbour lists, work lists and record links
 int launch_sort_lists(nlfem_pairs *h, hipStream_t s);
-int launch_worklists(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
+int launch_links(nlfem_pairs *h, hipStream_t s);   // lower entries -> mirror records
 // csr.hip
 // staged rows: one slot of csr_slot(hcap) ids per dof row
 inline int32_t csr_slot(int32_t hcap) { return hcap / 4 * 3; }
