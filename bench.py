@@ -100,6 +100,45 @@ def rows_algorithmic_bytes(info, n_vertices, n_elements, ncomp, precision):
             + info["nnz"] * 8)                          # values, written once
 
 
+# Vector-ALU peaks of MI355X (256 CUs at 2.4 GHz): FP32 157.3 TFLOP/s counts
+# packed FP32 (two lanes per operation), which this build does not emit, so
+# FP32 arithmetic here can reach at most half of it; FP64 78.6 TFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+# Kernel values Psi(z) after |z|^2: flops (a reciprocal square root counts
+# one) and components
+_KV = {"constant": (0, 1), "inv_dist": (2, 1), "peridynamic": (10, 3)}
+
+
+def far_flops(info, kernel, p, q):
+    """Flops of the non-touching records: per (outer, inner) point pair the
+    difference (2), |z|^2 (3), Psi, the weight w_p|J_e| w_q|J_f| (s_p + t_q)
+    (3) and per component the product, the row/column sums and three basis
+    products (9); per outer point the X and D_e updates (36 per component)
+    and its mapping (6); per inner point the D_f update (18 per component)
+    and its mapping (6).  Equal rules take one pass for both orders of a
+    pair, different rules two."""
+    kv, nk = _KV[kernel]
+    one = p * q * (8 + kv + 9 * nk) + p * (36 * nk + 6) + q * (18 * nk + 6)
+    return info["n_upper_far"] * (one if p == q else 2 * one)
+
+
+def touch_flops(info, kernel, n, ncomp):
+    """Flops of the touching records: per quadrature point of the
+    regularising transforms (identical 6n, edge 4n^2, vertex 2n^3 points) the
+    difference (4), |z|^2 (3), Psi, the weighted kernel (one per component)
+    and the outer product g g^T of the D = (3, 4 or 5) * ncomp local basis
+    differences (D products, D (D + 1) / 2 multiply-adds)."""
+    kv, nk = _KV[kernel]
+    total = 0
+    for pairs, pts, nu in ((info["n_ident"], 6 * n, 3), (info["n_edge"] // 2, 4 * n * n, 4),
+                           (info["n_vertex"] // 2, 2 * n ** 3, 5)):
+        d = nu * ncomp
+        total += pairs * pts * (7 + kv + nk + d + d * (d + 1))
+    return total
+
+
 ROW_SOURCES = ("assemble_items.h", "assemble.hip")   # the row-gather kernel and its launch
 
 
@@ -295,6 +334,21 @@ def main():
     n_pairs = info["n_pairs"]
     alg = rows_algorithmic_bytes(info, mesh.n_vertices, mesh.n_elements, cfg.ncomp, args.precision)
     achieved = alg / (t_rows * 1e-3) / 1e9
+    # the quadrature kernels against the vector-ALU peaks (per-phase loop)
+    quad = {}
+    if phase_ms.get("far", 0) > 0:
+        fl = far_flops(info, w["kernel"], len(w["outer"].w), len(w["inner"].w))
+        tf = fl / (phase_ms["far"] * 1e-3) / 1e12
+        pk = FP32_PEAK_TFLOPS if args.precision == "mixed" else FP64_PEAK_TFLOPS
+        quad["far"] = {"bound": "alu", "dtype": "f32" if args.precision == "mixed" else "f64",
+                       "achieved": tf, "peak": pk, "unit": "TFLOP/s", "frac": tf / pk,
+                       "flops": fl, "launch_ms": phase_ms["far"], "kernel": "k_far_rec"}
+    if phase_ms.get("touch", 0) > 0 and int(w.get("singular_n", 0)) > 0:
+        fl = touch_flops(info, w["kernel"], int(w["singular_n"]), cfg.ncomp)
+        tf = fl / (phase_ms["touch"] * 1e-3) / 1e12
+        quad["touch"] = {"bound": "alu", "dtype": "f64", "achieved": tf, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS, "flops": fl,
+                         "launch_ms": phase_ms["touch"], "kernel": "k_touch_rec"}
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(args.workload, args.precision),
@@ -320,6 +374,7 @@ def main():
         "build": {0: "plain build (three host synchronisations)",
                   1: "rebuild with the sizes of the previous build (one host synchronisation)",
                   2: "rebuild fell back to a plain build"}[rebuild],
+        "roofline_quadrature": quad,
         "assemble_ms": t_asm,
         "phase_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "assemble_pairs_per_s": n_pairs / (t_asm * 1e-3),

@@ -226,13 +226,14 @@ int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_q
    nlfem_timing_read waits for them and returns the accumulated milliseconds
    and the number of timed groups per phase since the last reset.  Phases:
      0 geometry and grid     1 pair search        2 list sorting/linking
-     3 CSR pattern           4 non-touching pairs (records, then the
-                               per-element sums of their diagonal blocks)
-     5 touching pairs        6 row gather (one kernel)   7 load vector
+     3 CSR pattern           4 non-touching pair records (one kernel)
+     5 touching pairs (one kernel)                6 row gather (one kernel)
+     7 load vector           8 per-element sums of the non-touching
+                               diagonal blocks (one kernel)
    Enabling creates events (host allocation); nlfem_assemble then still
    allocates no device memory.  Not thread-safe.
    Errors: E_INVALID (mask outside [0, 2^NLFEM_TIMING_PHASES)), E_HIP. */
-#define NLFEM_TIMING_PHASES 8
+#define NLFEM_TIMING_PHASES 9
 int nlfem_timing_enable(int mask);
 int nlfem_timing_read(double *ms, int64_t *launches, int reset);
 

@@ -289,7 +289,7 @@ def nlfem_rhs(mesh: DeviceMesh, cfg: Config, f_qp=None, f_affine=None, b=None, s
     return b
 
 
-TIMING_PHASES = ("geometry", "pairs", "lists", "csr", "far", "touch", "rows", "rhs")
+TIMING_PHASES = ("geometry", "pairs", "lists", "csr", "far", "touch", "rows", "rhs", "diag")
 
 
 def nlfem_timing_enable(phases=True):

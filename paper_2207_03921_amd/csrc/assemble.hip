@@ -295,7 +295,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
     if (p.rows.nrows > 0) {
         const int nc = p.nc;
         const bool fp32 = p.fp32;
-        timing_begin(kPhFar, s);
+        timing_begin(kPhDiag, s);
         const unsigned dg = xcd_grid((h->K + 256 / kDiagG - 1) / (256 / kDiagG), INT32_MAX);
         if (nc == 1) {
             if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float>), dim3(dg), dim3(256), 0, s, p.diag);
@@ -304,7 +304,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
             if (fp32) hipLaunchKernelGGL((k_elem_diag<3, float>), dim3(dg), dim3(256), 0, s, p.diag);
             else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, p.diag);
         }
-        timing_end(kPhFar, s);
+        timing_end(kPhDiag, s);
         const size_t lds = row_lds_bytes(p.rows.maxlen, nc, p.rows.hcap);
         const unsigned grid = xcd_grid(p.rows.nrows);
         timing_begin(kPhRows, s);

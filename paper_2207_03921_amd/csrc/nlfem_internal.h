@@ -229,7 +229,7 @@ struct nlfem_pairs {
 namespace nlfem {
 
 // per-phase timing (abi.hip): no-ops unless enabled ------------------------
-enum { kPhGeometry = 0, kPhPairs, kPhLists, kPhCsr, kPhFar, kPhTouch, kPhRows, kPhRhs, kPhLast };
+enum { kPhGeometry = 0, kPhPairs, kPhLists, kPhCsr, kPhFar, kPhTouch, kPhRows, kPhRhs, kPhDiag, kPhLast };
 void timing_begin(int phase, hipStream_t s);
 void timing_end(int phase, hipStream_t s);
 

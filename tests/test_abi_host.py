@@ -118,11 +118,11 @@ def test_binding_fails_loudly_without_library(monkeypatch, nl):
 def test_timing_mask_validation(nl):
     L = nl.lib()
     assert L.nlfem_timing_enable(-1) == -1
-    assert L.nlfem_timing_enable(1 << 8) == -1
+    assert L.nlfem_timing_enable(1 << 9) == -1
     assert "mask" in nl.nlfem_last_error()
     assert L.nlfem_timing_enable(0) == 0          # off while off: nothing to do
-    ms = np.zeros(8)
-    n = np.zeros(8, np.int64)
+    ms = np.zeros(9)
+    n = np.zeros(9, np.int64)
     assert L.nlfem_timing_read(ms.ctypes.data, n.ctypes.data, 1) == 0
     assert not n.any()
     assert L.nlfem_timing_read(None, None, 1) == -1
