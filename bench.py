@@ -139,15 +139,23 @@ def touch_flops(info, kernel, n, ncomp):
     return total
 
 
-ROW_SOURCES = ("assemble_items.h", "assemble.hip")   # the row-gather kernel and its launch
+# The source of the row gather: its section of assemble_items.h (from the
+# "phase 2: row gather" banner to the "plans" banner) and the k_rows kernel
+# in assemble.hip.  A counter summary holds the digest of this text from
+# when the counters were taken.
+ROW_SECTIONS = (("assemble_items.h", "phase 2: row gather", "-- plans"),
+                ("assemble.hip", "k_rows(RowArgs a)", "\n}\n"))
 
 
-def _source_digest(paths):
+def row_gather_digest():
     import hashlib
     h = hashlib.sha256()
-    for p in paths:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+    for fn, start, end in ROW_SECTIONS:
+        with open(os.path.join(ROOT, "paper_2207_03921_amd", "csrc", fn)) as fh:
+            text = fh.read()
+        a = text.index(start)
+        b = text.index(end, a + len(start))
+        h.update(text[a:b].encode())
     return h.hexdigest()[:16]
 
 
@@ -164,8 +172,7 @@ def measured_traffic(workload, precision):
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    srcs = [os.path.join(ROOT, "paper_2207_03921_amd", "csrc", f) for f in ROW_SOURCES]
-    if kv.get("source_sha256_16") != _source_digest(srcs):
+    if kv.get("source_sha256_16") != row_gather_digest():
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
