@@ -18,7 +18,8 @@ enum Buf : int {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
-    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_SPEC, B_LAST
+    B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_SPEC,
+    B_NCODE, B_CODECNT, B_CODESTART, B_CODEFILL, B_LAST
 };
 static_assert(B_LAST <= (int)(sizeof(nlfem_pairs::bufs) / sizeof(nlfem_pairs::bufs[0])), "too few buffer slots");
 
@@ -231,12 +232,22 @@ int read_slots(nlfem_pairs *h, hipStream_t s)
 }
 
 // Counters of the build after the geometry, all cleared by one launch.
+// codes of the order of the dof rows: the Morton codes of the grid cells
+// (2 * bits interleaved bits), or the row-major cell index for grids too
+// elongated for a compact Morton range (morton_bits < 0)
+int64_t morton_codes(const nlfem_pairs *h)
+{
+    return h->morton_bits >= 0 ? (int64_t)1 << (2 * h->morton_bits) : (int64_t)h->gnx * h->gny;
+}
+
 ZeroList build_counters(nlfem_pairs *h)
 {
     const int64_t ncell = (int64_t)h->gnx * h->gny;
     ZeroList z{};
     z.add(h->cell_cnt, ncell + 1);
     z.add(h->cell_fill, ncell);
+    z.add(h->code_cnt, morton_codes(h) + 1);
+    z.add(h->code_fill, morton_codes(h));
     z.add(h->lcnt, kLsLast * (h->K + 1));
     z.add(h->nlen, h->M + 1);
     z.add(h->ne_fill, h->M);
@@ -337,7 +348,18 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_CELLFILL, ncell, h->cell_fill));
     NLFEM_TRY(ensure_typed(h, B_CELLELEMS, K, h->cell_elems));
     NLFEM_TRY(ensure_typed(h, B_CELLOF, K, h->cell_of));
-    const int64_t scan_need = std::max(scan_tmp_size(K, kLsLast), scan_tmp_size(M) + scan_tmp_size(ncell)) + 1;
+    if (!spec) {
+        int bits = 0;
+        while (((int64_t)1 << bits) < std::max<int64_t>(h->gnx, h->gny)) ++bits;
+        h->morton_bits = ((int64_t)1 << (2 * bits)) <= 16 * ncell + 1024 ? bits : -1;
+    }
+    const int64_t ncode = morton_codes(h);   // <= 4 * max(gnx, gny)^2
+    NLFEM_TRY(ensure_typed(h, B_NCODE, M, h->node_code));
+    NLFEM_TRY(ensure_typed(h, B_CODECNT, ncode + 1, h->code_cnt));
+    NLFEM_TRY(ensure_typed(h, B_CODESTART, ncode + 1, h->code_start));
+    NLFEM_TRY(ensure_typed(h, B_CODEFILL, ncode, h->code_fill));
+    const int64_t scan_need =
+        std::max(scan_tmp_size(K, kLsLast), scan_tmp_size(M) + scan_tmp_size(ncell) + scan_tmp_size(ncode)) + 1;
     NLFEM_TRY(ensure_typed(h, B_SCAN, scan_need, h->scan_tmp));
     h->scan_cap = (int64_t)(h->bufs[B_SCAN].cap / sizeof(int64_t));
     NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
@@ -362,9 +384,10 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     // node -> element incidence, grid cells, dof rows ---------------------
     NLFEM_TRY(launch_bucket_count(h, m, s));
     {
-        const ScanPart parts[2] = {{h->nlen, h->ne_ptr, M, nullptr, nullptr},
-                                   {h->cell_cnt, h->cell_start, ncell, nullptr, nullptr}};
-        NLFEM_TRY(exclusive_scan_multi(parts, 2, h->scan_tmp, h->scan_cap, s));
+        const ScanPart parts[3] = {{h->nlen, h->ne_ptr, M, nullptr, nullptr},
+                                   {h->cell_cnt, h->cell_start, ncell, nullptr, nullptr},
+                                   {h->code_cnt, h->code_start, ncode, (int64_t *)(h->red + kRedDofs), nullptr}};
+        NLFEM_TRY(exclusive_scan_multi(parts, 3, h->scan_tmp, h->scan_cap, s, h->gate));
     }
     NLFEM_TRY(launch_bucket_fill(h, m, s));
 

@@ -201,8 +201,14 @@ struct nlfem_pairs {
     uint32_t *um_ef = nullptr, *um_fe = nullptr;
     // unordered touching pairs e <= f: [ident | edge | vertex]
     int32_t *te = nullptr, *tf = nullptr;     // [nUT]
-    // degree-of-freedom nodes in runs of consecutive ids (the rows of the matrix)
+    // degree-of-freedom nodes (the rows of the matrix) in the Morton order of
+    // their grid cells, so that rows worked on together are close in space
     int32_t *dof_list = nullptr; // [M], first n_dof entries used
+    int32_t morton_bits = 0;     // bits per axis of the cell codes
+    int32_t *node_code = nullptr;        // [M] cell code of a dof node, -1 otherwise
+    int64_t *code_cnt = nullptr;         // [ncode + 1] dof nodes per code
+    int64_t *code_start = nullptr;       // [ncode + 1]
+    int32_t *code_fill = nullptr;        // [ncode]
     // node-level CSR of degree-of-freedom rows
     int64_t *nlen = nullptr;     // [M + 1]
     int64_t *nptr = nullptr;     // [M + 1]
@@ -314,10 +320,11 @@ double key_to_double(unsigned long long key);
 int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, const ZeroList &later);
 int launch_zero(const ZeroList &z, unsigned long long *init_red, hipStream_t s);
 // grid + pairs (pairs.hip)
-// node -> element incidence counts (nlen) and grid cell counts (cell_cnt)
+// node -> element incidence counts (nlen), grid cell counts (cell_cnt) and
+// dof nodes per cell code (code_cnt; their scan total is the dof count)
 int launch_bucket_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
-// incidence lists and cell element lists (needs ne_ptr and cell_start),
-// the dof-node list and count (red[8]); clears nlen
+// incidence lists, cell element lists and the dof-node list in code order
+// (needs ne_ptr, cell_start and code_start); clears nlen
 int launch_bucket_fill(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
 // lists.hip: sorted neighbour lists, work lists and record links

@@ -514,15 +514,57 @@ struct BucketArgs {
     const int64_t *inc_ptr;
     int32_t *inc_fill, *inc_list;
     const uint32_t *node_flags;    // 1: dof node
-    unsigned long long *ndof;
+    const double *V;
+    int32_t morton_bits;           // < 0: row-major cell index as the code
+    int32_t *node_code;            // [M] code of a dof node, -1 otherwise
+    int64_t *code_cnt;             // count pass
+    const int64_t *code_start;     // fill pass
+    int32_t *code_fill;
     int32_t *dof_list;
-    int64_t elem_blocks;           // fill pass: blocks over elements, then over nodes
+    int64_t elem_blocks;           // blocks over elements, then over nodes
     SpecGate gate;
 };
+
+// interleaves the low 16 bits of v with zeros
+__device__ inline uint32_t spread_bits(uint32_t v)
+{
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// code of the grid cell of point (x, y): its position in the order of the rows
+__device__ inline int32_t cell_code(const BucketArgs &a, double x, double y)
+{
+    int cx = (int)floor((x - a.x0) / a.h), cy = (int)floor((y - a.y0) / a.h);
+    cx = min(max(cx, 0), a.nx - 1);
+    cy = min(max(cy, 0), a.ny - 1);
+    if (a.morton_bits < 0) return cy * a.nx + cx;
+    return (int32_t)(spread_bits((uint32_t)cx) | (spread_bits((uint32_t)cy) << 1));
+}
+
+// count pass over the nodes: the dof nodes per code
+__device__ void node_count(const BucketArgs &a, int64_t n)
+{
+    if (n >= a.M) return;
+    int32_t code = -1;
+    if (a.node_flags[n] == 1u) {
+        code = cell_code(a, a.V[2 * n], a.V[2 * n + 1]);
+        atomicAdd((unsigned long long *)&a.code_cnt[code], 1ull);
+    }
+    a.node_code[n] = code;
+}
 
 __global__ void __launch_bounds__(256) k_bucket_count(BucketArgs a)
 {
     if (gated(a.gate)) return;
+    if ((int64_t)blockIdx.x >= a.elem_blocks) {
+        node_count(a, ((int64_t)blockIdx.x - a.elem_blocks) * 256 + threadIdx.x);
+        return;
+    }
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.K) return;
     for (int v = 0; v < 3; ++v) {
@@ -543,36 +585,24 @@ __global__ void __launch_bounds__(256) k_bucket_count(BucketArgs a)
     atomicAdd((unsigned long long *)&a.cell_cnt[c], 1ull);
 }
 
-// Degree-of-freedom nodes: count and list.  Each block appends its 256
-// consecutive nodes as one contiguous run, so the list keeps mesh locality
-// within runs (the order of the runs is arbitrary).  Also clears the CSR row
-// lengths (the incidence counts, scanned by now) for the symbolic pass.
-__device__ void dof_block(const BucketArgs &a, int64_t blk)
+// fill pass over the nodes: the dof list in code order (arbitrary within a
+// code); also clears the CSR row lengths (the incidence counts, scanned by
+// now) for the symbolic pass
+__device__ void node_fill(const BucketArgs &a, int64_t n)
 {
-    __shared__ int wsum[4];
-    __shared__ unsigned long long base;
-    const int64_t i = blk * 256 + threadIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const bool d = i < a.M && a.node_flags[i] == 1u;
-    if (i < a.M) a.inc_cnt[i] = 0;
-    const unsigned long long b = __ballot(d);
-    if (lane == 0) wsum[w] = __popcll(b);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int n = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        base = n ? atomicAdd(a.ndof, (unsigned long long)n) : 0ull;
-    }
-    __syncthreads();
-    int before = 0;
-    for (int k = 0; k < w; ++k) before += wsum[k];
-    if (d) a.dof_list[base + before + __popcll(b & ((1ull << lane) - 1ull))] = (int32_t)i;
+    if (n >= a.M) return;
+    a.inc_cnt[n] = 0;
+    const int32_t code = a.node_code[n];
+    if (code < 0) return;
+    const int32_t pos = atomicAdd(&a.code_fill[code], 1);
+    a.dof_list[a.code_start[code] + pos] = (int32_t)n;
 }
 
 __global__ void __launch_bounds__(256) k_bucket_fill(BucketArgs a)
 {
     if (gated(a.gate)) return;
     if ((int64_t)blockIdx.x >= a.elem_blocks) {
-        dof_block(a, blockIdx.x - a.elem_blocks);
+        node_fill(a, ((int64_t)blockIdx.x - a.elem_blocks) * 256 + threadIdx.x);
         return;
     }
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -613,7 +643,12 @@ BucketArgs bucket_args(nlfem_pairs *h, const nlfem_mesh *m)
     a.inc_fill = h->ne_fill;
     a.inc_list = h->ne_list;
     a.node_flags = h->node_flags;
-    a.ndof = h->red + kRedDofs;
+    a.V = m->vertices;
+    a.morton_bits = h->morton_bits;
+    a.node_code = h->node_code;
+    a.code_cnt = h->code_cnt;
+    a.code_start = h->code_start;
+    a.code_fill = h->code_fill;
     a.dof_list = h->dof_list;
     a.elem_blocks = grid_for(h->K, 256);
     a.gate = h->gate;
@@ -624,7 +659,9 @@ BucketArgs bucket_args(nlfem_pairs *h, const nlfem_mesh *m)
 
 int launch_bucket_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
-    if (h->K > 0) hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(h->K, 256)), dim3(256), 0, s, bucket_args(h, m));
+    const BucketArgs a = bucket_args(h, m);
+    const int64_t blocks = a.elem_blocks + grid_for(h->M, 256);
+    if (blocks > 0) hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)blocks), dim3(256), 0, s, a);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }
