@@ -83,7 +83,7 @@ __device__ inline void kernel_eval(T zx, T zy, T c, T *k)
     }
 }
 
-__device__ inline int sym_index(int r, int s, int D)
+__host__ __device__ constexpr int sym_index(int r, int s, int D)
 {
     if (r > s) {
         const int t = r;
@@ -703,12 +703,16 @@ struct GaussView {
     int n;
 };
 
-// accumulate w * Psi(z) (g g^T) into the packed upper triangle of L
+// accumulate w * Psi(z) (g g^T) into the packed upper triangle of L, but
+// only the rows and columns of the first NU - 1 nodes: the basis
+// differences g of every sample sum to zero over the nodes, so the last
+// node's rows follow from the others (touch_last_node)
 template <int KER, int NU>
 __device__ inline void acc_sample(double *L, double w, double zx, double zy, const double *g, double c)
 {
     constexpr int NC = Ker<KER>::NC;
     constexpr int D = NU * NC;
+    constexpr int DC = D - NC;
     double k[3];
     kernel_eval<KER, double>(zx, zy, c, k);
     double wk[2][2];
@@ -719,13 +723,39 @@ __device__ inline void acc_sample(double *L, double w, double zx, double zy, con
         wk[0][1] = wk[1][0] = w * k[1];
         wk[1][1] = w * k[2];
     }
-    int idx = 0;
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
+    for (int r = 0; r < DC; ++r) {
         const double gr = g[r / NC];
 #pragma unroll
-        for (int s = r; s < D; ++s) L[idx++] += (gr * wk[r % NC][s % NC]) * g[s / NC];
+        for (int s = r; s < DC; ++s) L[sym_index(r, s, D)] += (gr * wk[r % NC][s % NC]) * g[s / NC];
     }
+}
+
+// the rows of the last node from the zero sums over the nodes:
+// L[(last, c), (v, d)] = -sum over u < last of L[(u, c), (v, d)]
+template <int NC, int NU>
+__device__ inline void touch_last_node(double *L)
+{
+    constexpr int D = NU * NC;
+    constexpr int DC = D - NC;
+#pragma unroll
+    for (int r = 0; r < DC; ++r)
+#pragma unroll
+        for (int d = 0; d < NC; ++d) {
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < NU - 1; ++u) v -= L[sym_index(r, u * NC + d, D)];
+            L[sym_index(r, DC + d, D)] = v;
+        }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int d = c; d < NC; ++d) {
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < NU - 1; ++u) v -= L[sym_index(u * NC + c, DC + d, D)];
+            L[sym_index(DC + c, DC + d, D)] = v;
+        }
 }
 
 // lanes per touching pair: the vertex class (2n^3 points) runs in groups of
@@ -846,10 +876,17 @@ __device__ __forceinline__ void touch_item(const TouchArgs &a, const GaussView &
         constexpr int d = Ker<KER>::D;
         scale = detk * detl / (double)(d + 4);
     }
+    constexpr int DC = D - NC;
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1)
 #pragma unroll
-        for (int t = 0; t < NP; ++t) L[t] += __shfl_xor(L[t], off, G);
+        for (int r = 0; r < DC; ++r)
+#pragma unroll
+            for (int s = r; s < DC; ++s) {
+                const int t = sym_index(r, s, D);
+                L[t] += __shfl_xor(L[t], off, G);
+            }
+    touch_last_node<NC, NU>(L);
     double *out = a.rec + pair * a.stride;
 #pragma unroll
     for (int t = 0; t < NP; ++t)
