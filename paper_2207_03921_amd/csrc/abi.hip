@@ -292,7 +292,8 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->err = (int32_t *)(h->red + kRedErr);
     if (!h->rb) {
         void *rb = nullptr;
-        NLFEM_HIP(hipHostMalloc(&rb, sizeof(unsigned long long) * kRedSlots, hipHostMallocDefault));
+        // coherent: a kernel of a rebuild writes the slots here directly
+        NLFEM_HIP(hipHostMalloc(&rb, sizeof(unsigned long long) * kRedSlots, hipHostMallocCoherent));
         h->rb = (unsigned long long *)rb;
     }
     unsigned long long *red = h->rb;
@@ -480,7 +481,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     }
     NLFEM_TRY(ensure_typed(h, B_NCOL, h->nnz_node, h->ncol));
     timing_begin(kPhCsr, s);
-    NLFEM_TRY(launch_csr_pack(h, s));
+    // a rebuild's read-back: the pack launch copies the slots to the pinned
+    // buffer itself
+    NLFEM_TRY(launch_csr_pack(h, s, spec ? h->rb : nullptr));
     timing_end(kPhCsr, s);
 
     // workspace of the assembly: one result record per unordered pair
@@ -492,9 +495,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
     NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
     if (spec) {
-        // the read-back is checked by the next call that uses the handle
-        // (resolve); until then assembly launches test the slots themselves
-        NLFEM_HIP(hipMemcpyAsync(h->rb, h->red, sizeof(unsigned long long) * kRedSlots, hipMemcpyDeviceToHost, s));
+        // the read-back (written by the pack launch) is checked by the next
+        // call that uses the handle (resolve); until then assembly launches
+        // test the slots themselves
         NLFEM_HIP(hipEventRecord(h->ev_rb, s));
         h->gate = SpecGate{};
         h->pending = true;

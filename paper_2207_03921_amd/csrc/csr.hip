@@ -176,10 +176,15 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
 }
 
 // packs the staged rows: ncol[nptr[i] ...] = stage[item][0 .. nlen[i])
+// With slots_out (pinned host memory), the first workgroup also copies the
+// reduction slots there before anything else (every slot is final by this
+// launch), so a rebuild needs no separate read-back copy.
 __global__ void __launch_bounds__(256) k_csr_pack(const int32_t *rows, const unsigned long long *nrows,
                                                   const int64_t *nptr, const int32_t *stage, int32_t cap,
-                                                  int32_t *ncol, SpecGate gate)
+                                                  int32_t *ncol, SpecGate gate, const unsigned long long *slots,
+                                                  unsigned long long *slots_out)
 {
+    if (slots_out && blockIdx.x == 0 && threadIdx.x < kRedSlots) slots_out[threadIdx.x] = slots[threadIdx.x];
     if (gated(gate)) return;
     const int64_t nr = (int64_t)*nrows;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -287,11 +292,11 @@ int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     return NLFEM_OK;
 }
 
-int launch_csr_pack(nlfem_pairs *h, hipStream_t s)
+int launch_csr_pack(nlfem_pairs *h, hipStream_t s, unsigned long long *slots_out)
 {
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(h->n_dof, 4), 1 << 16));
     hipLaunchKernelGGL(k_csr_pack, dim3(grid), dim3(256), 0, s, h->dof_list, h->red + kRedDofs, h->nptr,
-                       h->csr_stage, csr_slot(h->hcap), h->ncol, h->gate);
+                       h->csr_stage, csr_slot(h->hcap), h->ncol, h->gate, h->red, slots_out);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

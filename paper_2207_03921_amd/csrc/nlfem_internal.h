@@ -334,7 +334,8 @@ int launch_links(nlfem_pairs *h, hipStream_t s);   // lower entries -> mirror re
 // staged rows: one slot of csr_slot(hcap) ids per dof row
 inline int32_t csr_slot(int32_t hcap) { return hcap / 4 * 3; }
 int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);   // -> nlen, stage, max row
-int launch_csr_pack(nlfem_pairs *h, hipStream_t s);                        // stage -> ncol
+// stage -> ncol; with slots_out (pinned host) also copies the reduction slots
+int launch_csr_pack(nlfem_pairs *h, hipStream_t s, unsigned long long *slots_out = nullptr);
 int launch_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
 int launch_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls, hipStream_t s);
 // assemble.hip
