@@ -379,7 +379,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     if (!spec) {
         // every counter of the rest of the build starts at zero
         ZeroList z = build_counters(h);
-        z.add(h->red + kRedMaxCell, kRedErr - kRedMaxCell);   // slots 6..17, keeps the error bits
+        z.add(h->red + kRedCounts, kRedErr - kRedCounts);   // slots 6..17, keeps the error bits
         NLFEM_TRY(launch_zero(z, nullptr, s));
     }
     // node -> element incidence, grid cells, dof rows ---------------------

@@ -498,7 +498,6 @@ const Shape kCandidates[kPhases][6] = {
     {{16, 4}, {64, 4}, {256, 4}, {64, 8}, {16, 8}, {256, 8}},
     {{1, 16}, {4, 16}, {16, 16}, {1, 32}, {4, 32}, {4, 8}},
 };
-const char *kPhaseName[kPhases] = {"far", "touch", "diag", "rows"};
 
 std::string tune_key(const nlfem_batch *b)
 {

@@ -50,11 +50,11 @@ struct GaussArgs {
 };
 
 // Slots of the reduction buffer (u64 each), read back in one copy:
-//   0-3 bounding-box keys, 4-5 radii, 6 largest cell, 7 largest |S(e)|,
-//   8 dof count, 9 longest CSR row, 10 polygon clip bound, 11 CSR nnz,
-//   12-17 totals of the per-element pair counts, 18 error bits (int32),
-//   19-24 largest per-element pair counts (19: largest |S(e)|)
-enum { kRedMaxCell = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
+//   0-3 bounding-box keys, 4-5 radii, 6-7 unused, 8 dof count, 9 longest
+//   CSR row, 10 polygon clip bound, 11 CSR nnz, 12-17 totals of the
+//   per-element pair counts, 18 error bits (int32), 19-24 largest
+//   per-element pair counts (19: largest |S(e)|)
+enum { kRedCounts = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
        kRedTot = 12, kRedErr = 18, kRedSegMax = 19, kRedSlots = 32 };
 
 // Deep copy of a configuration (its host tables), for a build that may have
