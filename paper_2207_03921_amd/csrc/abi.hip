@@ -19,7 +19,7 @@ enum Buf : int {
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SMASK, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
     B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_SPEC,
-    B_NCODE, B_CODECNT, B_CODESTART, B_CODEFILL, B_LAST
+    B_NCODE, B_CODECNT, B_CODESTART, B_CODEFILL, B_CAND, B_SCROFF, B_LAST
 };
 static_assert(B_LAST <= (int)(sizeof(nlfem_pairs::bufs) / sizeof(nlfem_pairs::bufs[0])), "too few buffer slots");
 
@@ -208,8 +208,9 @@ int check_device()
 // error bits), after the pair count (dofs, clip bound, list totals and
 // maxima), after the symbolic pass (longest row, nnz).
 constexpr uint32_t kSpecGeo = 0x3fu | (1u << kRedErr);
+constexpr uint32_t kSpecCand = kSpecGeo | (1u << kRedCand);   // the search's scratch size
 constexpr uint32_t kSpecPairs =
-    kSpecGeo | (1u << kRedDofs) | (1u << kRedClip) | (0x3fu << kRedTot) | (0x3fu << kRedSegMax);
+    kSpecCand | (1u << kRedDofs) | (1u << kRedClip) | (0x3fu << kRedTot) | (0x3fu << kRedSegMax);
 constexpr uint32_t kSpecCsr = kSpecPairs | (1u << kRedMaxRow) | (1u << kRedNnz);
 
 // Copies the reduction slots to the pinned host buffer and waits for them.
@@ -364,6 +365,8 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_SCAN, scan_need, h->scan_tmp));
     h->scan_cap = (int64_t)(h->bufs[B_SCAN].cap / sizeof(int64_t));
     NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
+    NLFEM_TRY(ensure_typed(h, B_CAND, std::max<int64_t>(K, 1), h->cand));
+    NLFEM_TRY(ensure_typed(h, B_SCROFF, K1, h->scr_off));
     NLFEM_TRY(ensure_typed(h, B_LOFF, kLsLast * K1, h->loff));
     NLFEM_TRY(ensure_typed(h, B_NLEN, M + 1, h->nlen));
     NLFEM_TRY(ensure_typed(h, B_NPTR, M + 1, h->nptr));
@@ -392,9 +395,21 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     }
     NLFEM_TRY(launch_bucket_fill(h, m, s));
 
-    // pair search: count, scan, fill ---------------------------------------
+    // pair search: one pass into per-element scratch segments sized by the
+    // candidates, then the scan of the six per-element counts ---------------
+    NLFEM_TRY(exclusive_scan(h->cand, h->scr_off, K, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedCand),
+                             nullptr, h->gate));
+    if (spec) {
+        h->gate.mask = kSpecCand;
+    } else {
+        NLFEM_TRY(read_slots(h, s));
+        h->total_cand = (int64_t)red[kRedCand];
+    }
+    NLFEM_TRY(ensure_typed(h, B_SNBRT, std::max<int64_t>(h->total_cand, 1), h->snbr_tmp));
+    NLFEM_TRY(ensure_typed(h, B_SFLAGT, std::max<int64_t>(h->total_cand, 1), h->sflag_tmp));
+    NLFEM_TRY(ensure_typed(h, B_SMASKT, std::max<int64_t>(h->total_cand, 1), h->smask_tmp));
     timing_begin(kPhPairs, s);
-    NLFEM_TRY(launch_pairs(h, m, false, s));
+    NLFEM_TRY(launch_pairs(h, m, s));
     timing_end(kPhPairs, s);
     NLFEM_TRY(exclusive_scan_segments(h->lcnt, h->loff, K, kLsLast, K1, h->scan_tmp, h->scan_cap,
                                       (int64_t *)(h->red + kRedTot), s, (int64_t *)(h->red + kRedSegMax), h->gate));
@@ -423,9 +438,6 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         if (h->nS >= (int64_t)INT32_MAX || h->nUF >= (int64_t)INT32_MAX || h->nUT >= (int64_t)INT32_MAX)
             return set_error(NLFEM_E_OVERFLOW, "more than 2^31 neighbour entries");
     }
-    NLFEM_TRY(ensure_typed(h, B_SNBRT, h->nS, h->snbr_tmp));
-    NLFEM_TRY(ensure_typed(h, B_SFLAGT, h->nS, h->sflag_tmp));
-    NLFEM_TRY(ensure_typed(h, B_SMASKT, h->nS, h->smask_tmp));
     NLFEM_TRY(ensure_typed(h, B_SNBR, h->nS, h->snbr));
     NLFEM_TRY(ensure_typed(h, B_SFLAG, h->nS, h->sflag));
     NLFEM_TRY(ensure_typed(h, B_SMASK, h->nS, h->smask));
@@ -437,9 +449,6 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_UMFE, h->nUF, h->um_fe));
     NLFEM_TRY(ensure_typed(h, B_TE, h->nUT, h->te));
     NLFEM_TRY(ensure_typed(h, B_TF, h->nUT, h->tf));
-    timing_begin(kPhPairs, s);
-    NLFEM_TRY(launch_pairs(h, m, true, s));
-    timing_end(kPhPairs, s);
     timing_begin(kPhLists, s);
     NLFEM_TRY(launch_sort_lists(h, s));
     NLFEM_TRY(launch_links(h, s));

@@ -23,6 +23,7 @@ struct ListArgs {
     int32_t cap;               // power of two >= longest segment
     int32_t singular;
     int64_t baseE, baseV;
+    const int64_t *scr;        // [K + 1] scratch segments of the pair search
     const int32_t *snbr_tmp;
     const uint8_t *sflag_tmp;
     const uint2 *smask_tmp;
@@ -47,13 +48,13 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
     for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
         const int64_t e = xcd_item(b, a.K);
         if (e >= a.K) continue;
-        const int64_t s0 = a.sptr[e];
+        const int64_t s0 = a.sptr[e], r0 = a.scr[e];   // final list, scratch segment
         const int n = (int)(a.sptr[e + 1] - s0);
         if (n == 0) continue;
         int n2 = 1;
         while (n2 < n) n2 <<= 1;
         for (int t = lane; t < n2; t += 64)
-            key[t] = t < n ? (((unsigned long long)(uint32_t)a.snbr_tmp[s0 + t]) << 32) | (uint32_t)t : ~0ull;
+            key[t] = t < n ? (((unsigned long long)(uint32_t)a.snbr_tmp[r0 + t]) << 32) | (uint32_t)t : ~0ull;
         __syncthreads();
         for (int k = 2; k <= n2; k <<= 1)
             for (int j = k >> 1; j > 0; j >>= 1) {
@@ -86,8 +87,8 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
                 const unsigned long long kk = key[t];
                 const int src = (int)(kk & 0xffffffffull);
                 f = (int32_t)(kk >> 32);
-                const uint8_t fl = a.sflag_tmp[s0 + src];
-                m = a.smask_tmp[s0 + src];
+                const uint8_t fl = a.sflag_tmp[r0 + src];
+                m = a.smask_tmp[r0 + src];
                 a.snbr[s0 + t] = f;
                 a.sflag[s0 + t] = fl;
                 a.smask[s0 + t] = m;
@@ -164,6 +165,7 @@ ListArgs list_args(nlfem_pairs *h)
     a.singular = h->singular;
     a.baseE = h->nUTc[0];
     a.baseV = h->nUTc[0] + h->nUTc[1];
+    a.scr = h->scr_off;
     a.snbr_tmp = h->snbr_tmp;
     a.sflag_tmp = h->sflag_tmp;
     a.smask_tmp = h->smask_tmp;

@@ -50,11 +50,11 @@ struct GaussArgs {
 };
 
 // Slots of the reduction buffer (u64 each), read back in one copy:
-//   0-3 bounding-box keys, 4-5 radii, 6-7 unused, 8 dof count, 9 longest
+//   0-3 bounding-box keys, 4-5 radii, 6 candidate total, 7 unused, 8 dof count, 9 longest
 //   CSR row, 10 polygon clip bound, 11 CSR nnz, 12-17 totals of the
 //   per-element pair counts, 18 error bits (int32), 19-24 largest
 //   per-element pair counts (19: largest |S(e)|)
-enum { kRedCounts = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
+enum { kRedCounts = 6, kRedCand = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
        kRedTot = 12, kRedErr = 18, kRedSegMax = 19, kRedSlots = 32 };
 
 // Deep copy of a configuration (its host tables), for a build that may have
@@ -193,7 +193,13 @@ struct nlfem_pairs {
     uint2 *smask = nullptr;      // [nS] 2-bit point status: x = e's points vs f, y = f's points vs e
     int32_t *srec = nullptr;     // [nS] record of the unordered pair (far or touching list)
     int4 *snode = nullptr;       // [nS] (f, the three vertices of f): one load for the row kernels
-    int32_t *snbr_tmp = nullptr; // unsorted lists written by the pair search
+    // unsorted lists written by the pair search, element e's in the segment
+    // [scr_off[e], scr_off[e] + |S(e)|) of a scratch sized by the candidates
+    // the search visits (cand[e])
+    int64_t *cand = nullptr;     // [K]
+    int64_t *scr_off = nullptr;  // [K + 1]
+    int64_t total_cand = 0;
+    int32_t *snbr_tmp = nullptr;
     uint8_t *sflag_tmp = nullptr;
     uint2 *smask_tmp = nullptr;
     // unordered non-touching pairs e <= f (far work list)
@@ -228,7 +234,7 @@ struct nlfem_pairs {
         void *p = nullptr;
         size_t cap = 0;
     };
-    DevBuf bufs[48];
+    DevBuf bufs[64];
     int64_t scan_cap = 0;
 };
 
@@ -326,7 +332,9 @@ int launch_bucket_count(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 // incidence lists, cell element lists and the dof-node list in code order
 // (needs ne_ptr, cell_start and code_start); clears nlen
 int launch_bucket_fill(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
-int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s);
+// one pass: the neighbour entries of every element into its scratch segment
+// (scr_off), the six per-element counts into lcnt
+int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 // lists.hip: sorted neighbour lists, work lists and record links
 int launch_sort_lists(nlfem_pairs *h, hipStream_t s);
 int launch_links(nlfem_pairs *h, hipStream_t s);   // lower entries -> mirror records

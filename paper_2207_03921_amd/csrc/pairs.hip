@@ -49,7 +49,7 @@ struct PairArgs {
     int64_t *lcnt;          // count pass: [kLsLast][K1]
     unsigned long long *maxClip;   // bound on the vertex count of any straddling clip
     const double *dir;             // [N][2] polygon directions (device copy)
-    const int64_t *loff;    // fill pass:  [kLsLast][K1]
+    const int64_t *scr;     // [K + 1] start of each element's scratch segment
     int32_t *snbr;
     uint8_t *sflag;
     uint2 *smask;           // (status of e's points seeing f, status of f's points seeing e)
@@ -218,7 +218,7 @@ __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], c
 
 // ---- the tile kernel --------------------------------------------------------
 
-template <bool FILL, bool POLY>
+template <bool POLY>
 __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -239,6 +239,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     int32_t *c_lab = c_id + kCH;                          // [kCH]
     int32_t *c_nd = c_lab + kCH;                          // [3][kCH]
     __shared__ int64_t nb_start[kMaxNbr], nb_pre[kMaxNbr + 1];
+    __shared__ int64_t e_scr[kTE];   // scratch segment of each tile element
     __shared__ int nb_n;
     // polygon ball: per wave, queue of unsure (candidate, direction, point)
     // items and the statuses they decide
@@ -291,12 +292,8 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     // the cell's elements in tiles of kTE
     for (int64_t t0 = cs; t0 < ce; t0 += kTE) {
         const int ne = (int)min((int64_t)kTE, ce - t0);
-        for (int t = threadIdx.x; t < kTE * kLsLast; t += kBlock) {
-            int i = t / kLsLast, kind = t % kLsLast;
-            int64_t v = 0;
-            if (FILL && i < ne) v = a.loff[kind * a.K1 + a.cell_elems[t0 + i]];
-            e_off[t] = v;
-        }
+        for (int t = threadIdx.x; t < kTE * kLsLast; t += kBlock) e_off[t] = 0;
+        if (threadIdx.x < ne) e_scr[threadIdx.x] = a.scr[a.cell_elems[t0 + threadIdx.x]];
         __syncthreads();
 
         for (int64_t c0 = 0; c0 < total; c0 += kCH) {
@@ -465,8 +462,8 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                     const unsigned long long bI = __ballot(inS && cls == 3);
                     const unsigned long long bE = __ballot(inS && cls == 2 && f > e);
                     const unsigned long long bV = __ballot(inS && cls == 1 && f > e);
-                    if (FILL && inS) {
-                        const int64_t o = off[kLsS] + __popcll(bS & lt);
+                    if (inS) {
+                        const int64_t o = e_scr[i] + off[kLsS] + __popcll(bS & lt);
                         a.snbr[o] = f;
                         a.sflag[o] = flags;
                         a.smask[o] = make_uint2(mef, mfe);
@@ -483,11 +480,9 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
             }
             __syncthreads();
         }
-        if (!FILL) {
-            for (int t = threadIdx.x; t < ne * kLsLast; t += kBlock) {
-                int i = t / kLsLast, kind = t % kLsLast;
-                a.lcnt[kind * a.K1 + a.cell_elems[t0 + i]] = e_off[t];
-            }
+        for (int t = threadIdx.x; t < ne * kLsLast; t += kBlock) {
+            int i = t / kLsLast, kind = t % kLsLast;
+            a.lcnt[kind * a.K1 + a.cell_elems[t0 + i]] = e_off[t];
         }
         __syncthreads();
     }
@@ -521,6 +516,8 @@ struct BucketArgs {
     const int64_t *code_start;     // fill pass
     int32_t *code_fill;
     int32_t *dof_list;
+    int32_t gr;                    // neighbour-cell radius of the pair search
+    int64_t *cand;                 // fill pass: [K] candidates of each element
     int64_t elem_blocks;           // blocks over elements, then over nodes
     SpecGate gate;
 };
@@ -615,9 +612,20 @@ __global__ void __launch_bounds__(256) k_bucket_fill(BucketArgs a)
         }
     }
     const int c = a.cell_of[k];
-    if (c < 0) return;
-    const int32_t pos = atomicAdd(&a.cell_fill[c], 1);
-    a.cell_elems[a.cell_start[c] + pos] = (int32_t)k;
+    int64_t cand = 0;
+    if (c >= 0) {
+        const int32_t pos = atomicAdd(&a.cell_fill[c], 1);
+        a.cell_elems[a.cell_start[c] + pos] = (int32_t)k;
+        // the elements of the neighbour cells the pair search visits: a
+        // bound on |S(k)| that sizes k's segment of the search's output
+        const int cx = c % a.nx, cy = c / a.nx;
+        for (int yy = max(cy - a.gr, 0); yy <= min(cy + a.gr, a.ny - 1); ++yy) {
+            const int64_t r = (int64_t)yy * a.nx;
+            const int x0 = max(cx - a.gr, 0), x1 = min(cx + a.gr, a.nx - 1);
+            cand += a.cell_start[r + x1 + 1] - a.cell_start[r + x0];
+        }
+    }
+    a.cand[k] = cand;
 }
 
 BucketArgs bucket_args(nlfem_pairs *h, const nlfem_mesh *m)
@@ -650,6 +658,8 @@ BucketArgs bucket_args(nlfem_pairs *h, const nlfem_mesh *m)
     a.code_start = h->code_start;
     a.code_fill = h->code_fill;
     a.dof_list = h->dof_list;
+    a.gr = h->gr;
+    a.cand = h->cand;
     a.elem_blocks = grid_for(h->K, 256);
     a.gate = h->gate;
     return a;
@@ -675,7 +685,7 @@ int launch_bucket_fill(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     return NLFEM_OK;
 }
 
-int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
+int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
 {
     const int64_t ncell = (int64_t)h->gnx * h->gny;
     if ((2 * h->gr + 1) * (2 * h->gr + 1) > kMaxNbr)
@@ -707,7 +717,7 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     a.lcnt = h->lcnt;
     a.maxClip = h->red + 10;
     a.dir = h->poly_dir;
-    a.loff = h->loff;
+    a.scr = h->scr_off;
     a.snbr = h->snbr_tmp;
     a.sflag = h->sflag_tmp;
     a.smask = h->smask_tmp;
@@ -715,13 +725,8 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, bool fill, hipStream_t s)
     const size_t lds = sizeof(double2) * (size_t)kCH * (1 + a.P + (a.poly ? 3 : 0)) +
                        sizeof(int64_t) * kTE * kLsLast + sizeof(int32_t) * kCH * 5;
     dim3 grid(xcd_grid(ncell, INT32_MAX));
-    if (a.poly) {
-        if (fill) hipLaunchKernelGGL((k_pairs<true, true>), grid, dim3(kBlock), lds, s, a, h->poly);
-        else hipLaunchKernelGGL((k_pairs<false, true>), grid, dim3(kBlock), lds, s, a, h->poly);
-    } else {
-        if (fill) hipLaunchKernelGGL((k_pairs<true, false>), grid, dim3(kBlock), lds, s, a, h->poly);
-        else hipLaunchKernelGGL((k_pairs<false, false>), grid, dim3(kBlock), lds, s, a, h->poly);
-    }
+    if (a.poly) hipLaunchKernelGGL((k_pairs<true>), grid, dim3(kBlock), lds, s, a, h->poly);
+    else hipLaunchKernelGGL((k_pairs<false>), grid, dim3(kBlock), lds, s, a, h->poly);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }
