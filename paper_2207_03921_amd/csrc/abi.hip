@@ -205,7 +205,7 @@ int check_device()
 
 // Slots a speculative rebuild compares with the last build's, by the point
 // of the build where they are final: after the geometry (bounding box, radii,
-// error bits), after the pair count (dofs, clip bound, list totals and
+// error bits), after the pair search (dofs, clip bound, list totals and
 // maxima), after the symbolic pass (longest row, nnz).
 constexpr uint32_t kSpecGeo = 0x3fu | (1u << kRedErr);
 constexpr uint32_t kSpecCand = kSpecGeo | (1u << kRedCand);   // the search's scratch size

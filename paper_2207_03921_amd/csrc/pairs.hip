@@ -6,8 +6,10 @@
 // elements of the (2 gr + 1)^2 neighbouring cells through LDS in chunks of
 // kCH candidates.  Each wave takes one element e of the tile at a time and
 // tests 64 candidates per step, one per lane; ballots give every lane its
-// output position, so the lists come out in a fixed order (cell order, then
-// element id) without sorting.
+// output position in e's scratch segment, whose length is the number of
+// candidates the search visits for e (counted when the grid is filled), so a
+// single pass writes the entries and counts them; the list sort compacts
+// the segments.
 //
 // For every unordered pair both directions are tested at once:
 //   status_p(e -> f) for the outer points x_p of e against T_f, and
@@ -46,7 +48,7 @@ struct PairArgs {
     int32_t gnx, gny, gr, P;
     int32_t singular, poly;
     double delta, delta2, reach2, rin2, out2;
-    int64_t *lcnt;          // count pass: [kLsLast][K1]
+    int64_t *lcnt;          // [kLsLast][K1] per-element counts
     unsigned long long *maxClip;   // bound on the vertex count of any straddling clip
     const double *dir;             // [N][2] polygon directions (device copy)
     const int64_t *scr;     // [K + 1] start of each element's scratch segment
@@ -505,15 +507,15 @@ struct BucketArgs {
     int64_t *cell_cnt;
     const int64_t *cell_start;
     int32_t *cell_fill, *cell_elems, *cell_of;
-    int64_t *inc_cnt;              // count pass; cleared by the fill pass
+    int64_t *inc_cnt;              // bucket count; cleared by the bucket fill
     const int64_t *inc_ptr;
     int32_t *inc_fill, *inc_list;
     const uint32_t *node_flags;    // 1: dof node
     const double *V;
     int32_t morton_bits;           // < 0: row-major cell index as the code
     int32_t *node_code;            // [M] code of a dof node, -1 otherwise
-    int64_t *code_cnt;             // count pass
-    const int64_t *code_start;     // fill pass
+    int64_t *code_cnt;             // bucket count
+    const int64_t *code_start;     // bucket fill
     int32_t *code_fill;
     int32_t *dof_list;
     int32_t gr;                    // neighbour-cell radius of the pair search
