@@ -451,18 +451,17 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_TF, h->nUT, h->tf));
     timing_begin(kPhLists, s);
     NLFEM_TRY(launch_sort_lists(h, s));
-    NLFEM_TRY(launch_links(h, s));
     timing_end(kPhLists, s);
 
     // CSR pattern -------------------------------------------------------------
     int hcap = 64;
     while (hcap < 4 * (h->max_S + 8) && hcap < 16384) hcap <<= 1;
     if (spec) hcap = h->hcap;
-    for (;;) {
+    for (bool links = true;; links = false) {
         h->hcap = hcap;
         NLFEM_TRY(ensure_typed(h, B_CSRSTAGE, std::max<int64_t>(h->n_dof, 1) * csr_slot(hcap), h->csr_stage));
         timing_begin(kPhCsr, s);
-        NLFEM_TRY(launch_csr_rows(h, m, s));
+        NLFEM_TRY(launch_csr_rows(h, m, s, links));   // the mirror links ride on the first launch
         timing_end(kPhCsr, s);
         NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedNnz),
                                  (int64_t *)(h->red + kRedMaxRow), h->gate));

@@ -33,7 +33,30 @@ struct CsrArgs {
     int64_t *nlen;
     int32_t *err;
     SpecGate gate;
+    // mirror links, run by the first link_blocks workgroups of the launch
+    int64_t K, link_blocks;
+    const int32_t *snbr;     // sorted neighbour lists
+    int32_t *srec;
 };
+
+// Lower entries (f < e) of S(e) take the record of their mirror (f, e) in
+// S(f), found by binary search (the lists are sorted); one wave per element.
+__device__ void link_element(const CsrArgs &a, int64_t e, int lane)
+{
+    const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
+    for (int64_t t = s0 + lane; t < s1; t += 64) {
+        const int32_t f = a.snbr[t];
+        if (f >= e) continue;
+        int64_t lo = a.sptr[f], hi = a.sptr[f + 1];
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (a.snbr[mid] < e) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < a.sptr[f + 1] && a.snbr[lo] == (int32_t)e) a.srec[t] = a.srec[lo];
+        else atomicOr(a.err, kErrSlot);
+    }
+}
 
 __device__ inline bool hash_insert(int32_t *tab, int32_t mask, int32_t key, bool *overflow)
 {
@@ -61,6 +84,15 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
     extern __shared__ int32_t dyn[];
     if (gated(a.gate)) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if ((int64_t)blockIdx.x < a.link_blocks) {
+        // the links share the launch: both are latency-bound and independent
+        const int64_t ng = (a.K + kWavesPerRowBlock - 1) / kWavesPerRowBlock;
+        for (int64_t b = blockIdx.x; b < xcd_span(ng); b += a.link_blocks) {
+            const int64_t e = xcd_item(b, ng) * kWavesPerRowBlock + w;
+            if (e < a.K) link_element(a, e, lane);
+        }
+        return;
+    }
     int32_t *tab = dyn + (size_t)w * 2 * a.hcap;   // [hcap] hash table, then [hcap] sort buffer
     int32_t *buf = tab + a.hcap;
     __shared__ int64_t qs_w[kWavesPerRowBlock][kCsrQ];
@@ -70,7 +102,7 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
     const int32_t mask = a.hcap - 1;
     const int64_t nrows = (int64_t)*a.nrows;
     const int64_t ngroups = (nrows + kWavesPerRowBlock - 1) / kWavesPerRowBlock;
-    for (int64_t b = blockIdx.x; b < xcd_span(ngroups); b += gridDim.x) {
+    for (int64_t b = blockIdx.x - a.link_blocks; b < xcd_span(ngroups); b += gridDim.x - a.link_blocks) {
         const int64_t item = xcd_item(b, ngroups) * kWavesPerRowBlock + w;
         if (item >= nrows) continue;
         const int64_t i = a.rows[item];
@@ -280,14 +312,20 @@ __global__ void __launch_bounds__(64) k_export(int64_t K, const int64_t *sptr, c
 
 }  // namespace
 
-int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
+int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool links)
 {
     CsrArgs a{m->elements, h->dof_list, h->red + kRedDofs, h->ne_ptr, h->ne_list,
               h->loff + (int64_t)kLsS * (h->K + 1), h->snode, h->hcap, csr_slot(h->hcap), h->csr_stage, h->nlen,
               h->err, h->gate};
+    // with links: the first workgroups set the mirror records (once per build)
+    a.K = h->K;
+    a.link_blocks = links && h->nS > 0 ? xcd_grid((h->K + kWavesPerRowBlock - 1) / kWavesPerRowBlock) : 0;
+    a.snbr = h->snbr;
+    a.srec = h->srec;
     const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap * kWavesPerRowBlock;
-    hipLaunchKernelGGL(k_csr_rows, dim3(xcd_grid((h->M + kWavesPerRowBlock - 1) / kWavesPerRowBlock)),
-                       dim3(64 * kWavesPerRowBlock), lds, s, a);
+    const int64_t row_blocks = xcd_grid((h->M + kWavesPerRowBlock - 1) / kWavesPerRowBlock);
+    hipLaunchKernelGGL(k_csr_rows, dim3((unsigned)(a.link_blocks + row_blocks)), dim3(64 * kWavesPerRowBlock), lds, s,
+                       a);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

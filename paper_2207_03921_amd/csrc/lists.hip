@@ -8,7 +8,7 @@
 //    pairs with their point status, touching pairs grouped by class
 //    (identical, edge, vertex).  Each upper entry records the index of its
 //    work item; each lower entry (f < e) takes the index of its mirror
-//    (f, e) in a second launch.  The assembly computes one result per work
+//    (f, e) later, in the first workgroups of the CSR rows launch.  The assembly computes one result per work
 //    item and every matrix row finds the results of all its pairs through
 //    these indices.
 #include "nlfem_internal.h"
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
             }
         // the sorted list, and the upper entries (f >= e) appended to the work
         // lists of their class in list order; lower entries get their record
-        // from the mirror (k_link)
+        // from the mirror (link_element, in the CSR rows launch)
         const unsigned long long lt = (1ull << lane) - 1ull;
         int64_t oF = a.loff[kLsUF * a.K1 + e];
         int64_t oI = a.loff[kLsUI * a.K1 + e];
@@ -128,30 +128,6 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
     }
 }
 
-// lower entries (f < e) point at the record of their mirror (f, e) in S(f)
-__global__ void __launch_bounds__(64) k_link(ListArgs a)
-{
-    if (gated(a.gate)) return;
-    const int lane = threadIdx.x;
-    for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
-        const int64_t e = xcd_item(b, a.K);
-        if (e >= a.K) continue;
-        const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
-        for (int64_t t = s0 + lane; t < s1; t += 64) {
-            const int32_t f = a.snbr[t];
-            if (f >= e) continue;
-            int64_t lo = a.sptr[f], hi = a.sptr[f + 1];
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (a.snbr[mid] < e) lo = mid + 1;
-                else hi = mid;
-            }
-            if (lo < a.sptr[f + 1] && a.snbr[lo] == (int32_t)e) a.srec[t] = a.srec[lo];
-            else atomicOr(a.err, kErrSlot);
-        }
-    }
-}
-
 ListArgs list_args(nlfem_pairs *h)
 {
     ListArgs a{};
@@ -199,14 +175,5 @@ int launch_sort_lists(nlfem_pairs *h, hipStream_t s)
     return NLFEM_OK;
 }
 
-int launch_links(nlfem_pairs *h, hipStream_t s)
-{
-    if (h->nS == 0) return NLFEM_OK;
-    ListArgs a = list_args(h);
-    const unsigned grid = xcd_grid(h->K);
-    hipLaunchKernelGGL(k_link, dim3(grid), dim3(64), 0, s, a);
-    NLFEM_HIP(hipGetLastError());
-    return NLFEM_OK;
-}
 
 }  // namespace nlfem

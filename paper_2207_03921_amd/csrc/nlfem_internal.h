@@ -337,11 +337,12 @@ int launch_bucket_fill(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);
 // lists.hip: sorted neighbour lists, work lists and record links
 int launch_sort_lists(nlfem_pairs *h, hipStream_t s);
-int launch_links(nlfem_pairs *h, hipStream_t s);   // lower entries -> mirror records
 // csr.hip
 // staged rows: one slot of csr_slot(hcap) ids per dof row
 inline int32_t csr_slot(int32_t hcap) { return hcap / 4 * 3; }
-int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s);   // -> nlen, stage, max row
+// -> nlen, stage, max row; with links also the mirror records of the lower
+// neighbour-list entries (after the list sort)
+int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool links);
 // stage -> ncol; with slots_out (pinned host) also copies the reduction slots
 int launch_csr_pack(nlfem_pairs *h, hipStream_t s, unsigned long long *slots_out = nullptr);
 int launch_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
