@@ -252,6 +252,7 @@ ZeroList build_counters(nlfem_pairs *h)
     z.add(h->lcnt, kLsLast * (h->K + 1));
     z.add(h->nlen, h->M + 1);
     z.add(h->ne_fill, h->M);
+    z.add(h->scan_tmp, h->scan_hdr);   // tickets and flags of the chained scans
     return z;
 }
 
@@ -360,10 +361,20 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_CODECNT, ncode + 1, h->code_cnt));
     NLFEM_TRY(ensure_typed(h, B_CODESTART, ncode + 1, h->code_start));
     NLFEM_TRY(ensure_typed(h, B_CODEFILL, ncode, h->code_fill));
-    const int64_t scan_need =
-        std::max(scan_tmp_size(K, kLsLast), scan_tmp_size(M) + scan_tmp_size(ncell) + scan_tmp_size(ncode)) + 1;
-    NLFEM_TRY(ensure_typed(h, B_SCAN, scan_need, h->scan_tmp));
-    h->scan_cap = (int64_t)(h->bufs[B_SCAN].cap / sizeof(int64_t));
+    {
+        // the four scans of a build (cleared with the counters)
+        const int64_t tiles[4] = {scan_tiles(M) + scan_tiles(ncell) + scan_tiles(ncode), scan_tiles(K),
+                                  scan_tiles(K, kLsLast), scan_tiles(M)};
+        int64_t words = 0;
+        for (int c = 0; c < 4; ++c) words += 1 + tiles[c];
+        NLFEM_TRY(ensure_typed(h, B_SCAN, words, h->scan_tmp));
+        h->scan_hdr = words;
+        int64_t o = 0;
+        for (int c = 0; c < 4; ++c) {
+            h->scan_w[c] = ScanWork{h->scan_tmp + o, tiles[c]};
+            o += 1 + tiles[c];
+        }
+    }
     NLFEM_TRY(ensure_typed(h, B_LCNT, kLsLast * K1, h->lcnt));
     NLFEM_TRY(ensure_typed(h, B_CAND, std::max<int64_t>(K, 1), h->cand));
     NLFEM_TRY(ensure_typed(h, B_SCROFF, K1, h->scr_off));
@@ -391,13 +402,13 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         const ScanPart parts[3] = {{h->nlen, h->ne_ptr, M, nullptr, nullptr},
                                    {h->cell_cnt, h->cell_start, ncell, nullptr, nullptr},
                                    {h->code_cnt, h->code_start, ncode, (int64_t *)(h->red + kRedDofs), nullptr}};
-        NLFEM_TRY(exclusive_scan_multi(parts, 3, h->scan_tmp, h->scan_cap, s, h->gate));
+        NLFEM_TRY(exclusive_scan_multi(parts, 3, h->scan_w[0], s, h->gate));
     }
     NLFEM_TRY(launch_bucket_fill(h, m, s));
 
     // pair search: one pass into per-element scratch segments sized by the
     // candidates, then the scan of the six per-element counts ---------------
-    NLFEM_TRY(exclusive_scan(h->cand, h->scr_off, K, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedCand),
+    NLFEM_TRY(exclusive_scan(h->cand, h->scr_off, K, h->scan_w[1], s, (int64_t *)(h->red + kRedCand),
                              nullptr, h->gate));
     if (spec) {
         h->gate.mask = kSpecCand;
@@ -411,7 +422,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     timing_begin(kPhPairs, s);
     NLFEM_TRY(launch_pairs(h, m, s));
     timing_end(kPhPairs, s);
-    NLFEM_TRY(exclusive_scan_segments(h->lcnt, h->loff, K, kLsLast, K1, h->scan_tmp, h->scan_cap,
+    NLFEM_TRY(exclusive_scan_segments(h->lcnt, h->loff, K, kLsLast, K1, h->scan_w[2],
                                       (int64_t *)(h->red + kRedTot), s, (int64_t *)(h->red + kRedSegMax), h->gate));
     if (spec) {
         // list sizes, dof count and clip bound of the last build
@@ -463,7 +474,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         timing_begin(kPhCsr, s);
         NLFEM_TRY(launch_csr_rows(h, m, s, links));   // the mirror links ride on the first launch
         timing_end(kPhCsr, s);
-        NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_tmp, h->scan_cap, s, (int64_t *)(h->red + kRedNnz),
+        NLFEM_TRY(exclusive_scan(h->nlen, h->nptr, M, h->scan_w[3], s, (int64_t *)(h->red + kRedNnz),
                                  (int64_t *)(h->red + kRedMaxRow), h->gate));
         if (spec) {
             // the row capacity and nnz of the last build; the decision waits
@@ -479,6 +490,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         ZeroList z{};
         z.add(h->err, 1);
         z.add(h->red + kRedMaxRow, 1);
+        z.add(h->scan_w[3].hdr, 1 + h->scan_w[3].tiles);
         NLFEM_TRY(launch_zero(z, nullptr, s));
     }
     if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");

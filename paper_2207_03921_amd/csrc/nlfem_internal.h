@@ -115,6 +115,13 @@ struct ZeroList {
     }
 };
 
+// workspace of one chained scan of up to `tiles` tiles: hdr = [1 + tiles]
+// (ticket, per-tile words), zero before the launch
+struct ScanWork {
+    int64_t *hdr = nullptr;
+    int64_t tiles = 0;
+};
+
 // counters filled by the pair search (ordered pairs per class)
 enum { kCntPairs = 0, kCntFar, kCntVertex, kCntEdge, kCntIdent, kCntLast };
 
@@ -185,7 +192,9 @@ struct nlfem_pairs {
     // per-element counts and offsets [kLsLast][K + 1]
     int64_t *lcnt = nullptr;
     int64_t *loff = nullptr;
-    int64_t *scan_tmp = nullptr;
+    int64_t *scan_tmp = nullptr;   // the workspaces of the build's four scans
+    nlfem::ScanWork scan_w[4];     // node/cell/code buckets, candidates, list counts, row lengths
+    int64_t scan_hdr = 0;          // their words
     // symmetric neighbour list S(e) = {f : (e,f) or (f,e) interacts}, each
     // segment sorted by neighbour id
     int32_t *snbr = nullptr;     // [nS]
@@ -235,7 +244,6 @@ struct nlfem_pairs {
         size_t cap = 0;
     };
     DevBuf bufs[64];
-    int64_t scan_cap = 0;
 };
 
 namespace nlfem {
@@ -298,16 +306,17 @@ __device__ inline int64_t xcd_item(int64_t b, int64_t n)
 
 // scan.hip: out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total
 // (also written to *total when given; device pointer).  n = 0 gives out[0] = 0.
-// *maxval (device) receives the largest input when given.
-int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
+// *maxval (device, zero before the call) receives the largest input when
+// given.  One launch; the workspace must be zero when the launch starts.
+int exclusive_scan(const int64_t *in, int64_t *out, int64_t n, const ScanWork &w, hipStream_t s,
                    int64_t *total = nullptr, int64_t *maxval = nullptr, const SpecGate &gate = SpecGate{});
 // the same for nseg segments of `stride` slots (segment k at in + k * stride),
 // totals[k] = total and maxes[k] = largest input of segment k when given
-int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride, int64_t *tmp,
-                            int64_t tmp_cap, int64_t *totals, hipStream_t s, int64_t *maxes = nullptr,
+int exclusive_scan_segments(const int64_t *in, int64_t *out, int64_t n, int nseg, int64_t stride,
+                            const ScanWork &w, int64_t *totals, hipStream_t s, int64_t *maxes = nullptr,
                             const SpecGate &gate = SpecGate{});
-// up to kScanParts independent arrays in one pair of launches; the workspace
-// needs the sum of scan_tmp_size(n_k) over the parts
+// up to kScanParts independent arrays in one launch; the workspace needs the
+// sum of scan_tiles(n_k) over the parts
 constexpr int kScanParts = 8;
 struct ScanPart {
     const int64_t *in;
@@ -316,9 +325,10 @@ struct ScanPart {
     int64_t *total;     // device, optional
     int64_t *maxv;      // device, optional
 };
-int exclusive_scan_multi(const ScanPart *parts, int cnt, int64_t *tmp, int64_t tmp_cap, hipStream_t s,
+int exclusive_scan_multi(const ScanPart *parts, int cnt, const ScanWork &w, hipStream_t s,
                          const SpecGate &gate = SpecGate{});
-int64_t scan_tmp_size(int64_t n, int nseg = 1);
+// tiles of a scan of nseg arrays of n counts
+int64_t scan_tiles(int64_t n, int nseg = 1);
 double key_to_double(unsigned long long key);
 
 // geometry.hip

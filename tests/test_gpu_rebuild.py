@@ -160,3 +160,24 @@ def test_rebuild_vector_and_polygon(kind):
         assert r["rebuild"] == 1
         _assert_same(r, ref)
     nl.nlfem_pairs_free(pairs)
+
+
+def test_scans_by_direct_sums(monkeypatch):
+    """The prefix sums of a build take, past a bounded wait for the tiles
+    before them, the direct sum of the inputs before their tile.  Forcing that
+    path everywhere (NLFEM_SCAN_SPIN=-1, read at every launch) must give the
+    same build as the chained look-back, plainly built and rebuilt."""
+    import paper_2207_03921_amd as nl
+    w = inv_dist_jittered(n=48, delta=0.05, precision="fp64")
+    cfg = make_config(w)
+    assert w["mesh"].elements.shape[0] > 4 * 1024   # several tiles per scan
+    ref = _fresh(nl, w["mesh"], cfg)
+    monkeypatch.setenv("NLFEM_SCAN_SPIN", "-1")
+    dm = nl.DeviceMesh.from_numpy(w["mesh"])
+    pairs = nl.nlfem_build_pairs(dm, cfg)
+    for path in (0, 1):
+        r = _result(nl, dm, cfg, pairs)
+        assert r["rebuild"] == path
+        _assert_same(r, ref)
+        pairs = nl.nlfem_build_pairs(dm, cfg, pairs=pairs)
+    nl.nlfem_pairs_free(pairs)
