@@ -7,6 +7,9 @@
 // row inserts these ids into an open-addressing hash set in LDS, compacts and
 // bitonic-sorts the unique ids and writes them to a row slot of a staging
 // buffer; after the scan of the row lengths a copy kernel packs the slots.
+// A neighbour f met again through another element of the row adds nothing
+// new: a second hash set of element ids lets only the first meeting insert
+// the vertices of f.
 // The entries of all the row's elements are handled as one flat range: each
 // lane loads kCsrU neighbour ids and their vertices before it inserts any,
 // so the dependent loads of a step overlap.
@@ -33,8 +36,9 @@ struct CsrArgs {
     int64_t *nlen;
     int32_t *err;
     SpecGate gate;
-    // mirror links, run by the first link_blocks workgroups of the launch
-    int64_t K, link_blocks;
+    // mirror links, run by the link_blocks workgroups after the row_blocks
+    // workgroups of the rows
+    int64_t K, link_blocks, row_blocks;
     const int32_t *snbr;     // sorted neighbour lists
     int32_t *srec;
 };
@@ -71,6 +75,20 @@ __device__ inline bool hash_insert(int32_t *tab, int32_t mask, int32_t key, bool
     return false;
 }
 
+// true when key was in the table already; inserts it otherwise (a full table
+// answers false, so the caller treats the key as new)
+__device__ inline bool hash_seen(int32_t *tab, int32_t mask, int32_t key)
+{
+    uint32_t h = ((uint32_t)key * 2654435761u) & (uint32_t)mask;
+    for (int probe = 0; probe <= mask; ++probe) {
+        const int32_t old = atomicCAS(&tab[h], kEmpty, key);
+        if (old == kEmpty) return false;
+        if (old == key) return true;
+        h = (h + 1) & (uint32_t)mask;
+    }
+    return false;
+}
+
 __device__ inline int wave_sum(int v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -84,17 +102,20 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
     extern __shared__ int32_t dyn[];
     if (gated(a.gate)) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if ((int64_t)blockIdx.x < a.link_blocks) {
-        // the links share the launch: both are latency-bound and independent
+    if ((int64_t)blockIdx.x >= a.row_blocks) {
+        // the links share the launch: both are latency-bound and independent,
+        // and the shorter link items fill the tail of the rows
         const int64_t ng = (a.K + kWavesPerRowBlock - 1) / kWavesPerRowBlock;
-        for (int64_t b = blockIdx.x; b < xcd_span(ng); b += a.link_blocks) {
+        for (int64_t b = blockIdx.x - a.row_blocks; b < xcd_span(ng); b += a.link_blocks) {
             const int64_t e = xcd_item(b, ng) * kWavesPerRowBlock + w;
             if (e < a.K) link_element(a, e, lane);
         }
         return;
     }
-    int32_t *tab = dyn + (size_t)w * 2 * a.hcap;   // [hcap] hash table, then [hcap] sort buffer
-    int32_t *buf = tab + a.hcap;
+    // [hcap] node hash table, then [hcap] element hash table, which becomes
+    // the sort buffer once the row's ids are in
+    int32_t *tab = dyn + (size_t)w * 2 * a.hcap;
+    int32_t *etab = tab + a.hcap, *buf = etab;
     __shared__ int64_t qs_w[kWavesPerRowBlock][kCsrQ];
     __shared__ int32_t pre_w[kWavesPerRowBlock][kCsrQ + 1];
     int64_t *qs = qs_w[w];
@@ -102,11 +123,14 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
     const int32_t mask = a.hcap - 1;
     const int64_t nrows = (int64_t)*a.nrows;
     const int64_t ngroups = (nrows + kWavesPerRowBlock - 1) / kWavesPerRowBlock;
-    for (int64_t b = blockIdx.x - a.link_blocks; b < xcd_span(ngroups); b += gridDim.x - a.link_blocks) {
+    for (int64_t b = blockIdx.x; b < xcd_span(ngroups); b += a.row_blocks) {
         const int64_t item = xcd_item(b, ngroups) * kWavesPerRowBlock + w;
         if (item >= nrows) continue;
         const int64_t i = a.rows[item];
-        for (int t = lane; t < a.hcap; t += 64) tab[t] = kEmpty;
+        for (int t = lane; t < a.hcap; t += 64) {
+            tab[t] = kEmpty;
+            etab[t] = kEmpty;
+        }
         wave_sync();
         bool overflow = false;
         int added = 0;
@@ -152,9 +176,12 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
                         sn[k] = a.snode[qs[lo] + (flat - pre[lo])];
                     }
                 }
+                bool fresh[kCsrU];
+#pragma unroll
+                for (int k = 0; k < kCsrU; ++k) fresh[k] = sn[k].x >= 0 && !hash_seen(etab, mask, sn[k].x);
 #pragma unroll
                 for (int k = 0; k < kCsrU; ++k) {
-                    if (sn[k].x < 0) continue;
+                    if (!fresh[k]) continue;
                     added += hash_insert(tab, mask, sn[k].y, &overflow);
                     added += hash_insert(tab, mask, sn[k].z, &overflow);
                     added += hash_insert(tab, mask, sn[k].w, &overflow);
@@ -317,15 +344,15 @@ int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool lin
     CsrArgs a{m->elements, h->dof_list, h->red + kRedDofs, h->ne_ptr, h->ne_list,
               h->loff + (int64_t)kLsS * (h->K + 1), h->snode, h->hcap, csr_slot(h->hcap), h->csr_stage, h->nlen,
               h->err, h->gate};
-    // with links: the first workgroups set the mirror records (once per build)
+    // with links: the last workgroups set the mirror records (once per build)
     a.K = h->K;
     a.link_blocks = links && h->nS > 0 ? xcd_grid((h->K + kWavesPerRowBlock - 1) / kWavesPerRowBlock) : 0;
+    a.row_blocks = xcd_grid((h->M + kWavesPerRowBlock - 1) / kWavesPerRowBlock);
     a.snbr = h->snbr;
     a.srec = h->srec;
     const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap * kWavesPerRowBlock;
-    const int64_t row_blocks = xcd_grid((h->M + kWavesPerRowBlock - 1) / kWavesPerRowBlock);
-    hipLaunchKernelGGL(k_csr_rows, dim3((unsigned)(a.link_blocks + row_blocks)), dim3(64 * kWavesPerRowBlock), lds, s,
-                       a);
+    hipLaunchKernelGGL(k_csr_rows, dim3((unsigned)(a.row_blocks + a.link_blocks)), dim3(64 * kWavesPerRowBlock), lds,
+                       s, a);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

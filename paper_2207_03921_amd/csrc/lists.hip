@@ -8,9 +8,9 @@
 //    pairs with their point status, touching pairs grouped by class
 //    (identical, edge, vertex).  Each upper entry records the index of its
 //    work item; each lower entry (f < e) takes the index of its mirror
-//    (f, e) later, in the first workgroups of the CSR rows launch.  The assembly computes one result per work
-//    item and every matrix row finds the results of all its pairs through
-//    these indices.
+//    (f, e) later, in the last workgroups of the CSR rows launch.  The
+//    assembly computes one result per work item and every matrix row finds
+//    the results of all its pairs through these indices.
 #include "nlfem_internal.h"
 
 namespace nlfem {
