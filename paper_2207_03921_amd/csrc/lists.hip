@@ -29,7 +29,6 @@ struct ListArgs {
     const uint2 *smask_tmp;
     int32_t *snbr;
     uint8_t *sflag;
-    uint2 *smask;
     int32_t *srec;
     int4 *snode;
     const int32_t *E;
@@ -82,16 +81,14 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
             const int t = t0 + lane;
             bool isF = false, isI = false, isE = false, isV = false;
             int32_t f = 0;
-            uint2 m = make_uint2(0u, 0u);
+            int src = 0;
             if (t < n) {
                 const unsigned long long kk = key[t];
-                const int src = (int)(kk & 0xffffffffull);
+                src = (int)(kk & 0xffffffffull);
                 f = (int32_t)(kk >> 32);
                 const uint8_t fl = a.sflag_tmp[r0 + src];
-                m = a.smask_tmp[r0 + src];
                 a.snbr[s0 + t] = f;
                 a.sflag[s0 + t] = fl;
-                a.smask[s0 + t] = m;
                 a.snode[s0 + t] = make_int4(f, a.E[3 * (int64_t)f], a.E[3 * (int64_t)f + 1], a.E[3 * (int64_t)f + 2]);
                 const int cls = (fl >> 2) & 3;
                 const bool upper = f >= e;
@@ -104,6 +101,8 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
             const unsigned long long bE = __ballot(isE), bV = __ballot(isV);
             int32_t rec = -1;
             if (isF) {
+                // the point status travels with the non-touching work item only
+                const uint2 m = a.smask_tmp[r0 + src];
                 const int64_t u = oF + __popcll(bF & lt);
                 a.ue[u] = (int32_t)e;
                 a.uf[u] = f;
@@ -147,7 +146,6 @@ ListArgs list_args(nlfem_pairs *h)
     a.smask_tmp = h->smask_tmp;
     a.snbr = h->snbr;
     a.sflag = h->sflag;
-    a.smask = h->smask;
     a.srec = h->srec;
     a.snode = h->snode;
     a.E = h->mesh_elements;

@@ -199,7 +199,6 @@ struct nlfem_pairs {
     // segment sorted by neighbour id
     int32_t *snbr = nullptr;     // [nS]
     uint8_t *sflag = nullptr;    // [nS] bit0 (e,f) in P, bit1 (f,e) in P, bits 2-3 class
-    uint2 *smask = nullptr;      // [nS] 2-bit point status: x = e's points vs f, y = f's points vs e
     int32_t *srec = nullptr;     // [nS] record of the unordered pair (far or touching list)
     int4 *snode = nullptr;       // [nS] (f, the three vertices of f): one load for the row kernels
     // unsorted lists written by the pair search, element e's in the segment
