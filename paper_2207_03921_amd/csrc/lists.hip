@@ -1,8 +1,8 @@
 // Post-processing of the interaction lists.
 //
-// 1. Every segment S(e) is sorted by neighbour id (bitonic sort in LDS, one
-//    wave per element), so that the pair (f, e) can be found in S(f) by
-//    binary search.
+// 1. Every segment S(e) is sorted by neighbour id (in LDS, one wave per
+//    element: by ranks up to kRankMax entries, else a bitonic network), so
+//    that the pair (f, e) can be found in S(f) by binary search.
 // 2. The entries with f >= e are the unordered pairs.  The same wave, with
 //    the sorted list in LDS, compacts them into work lists: non-touching
 //    pairs with their point status, touching pairs grouped by class
@@ -15,6 +15,8 @@
 
 namespace nlfem {
 namespace {
+
+constexpr int kRankMax = 256;   // longest list sorted by ranks
 
 struct ListArgs {
     int64_t K, K1;
@@ -50,25 +52,54 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
         const int64_t s0 = a.sptr[e], r0 = a.scr[e];   // final list, scratch segment
         const int n = (int)(a.sptr[e + 1] - s0);
         if (n == 0) continue;
-        int n2 = 1;
-        while (n2 < n) n2 <<= 1;
-        for (int t = lane; t < n2; t += 64)
-            key[t] = t < n ? (((unsigned long long)(uint32_t)a.snbr_tmp[r0 + t]) << 32) | (uint32_t)t : ~0ull;
-        __syncthreads();
-        for (int k = 2; k <= n2; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = lane; t < n2; t += 64) {
-                    const int ixj = t ^ j;
-                    if (ixj > t) {
-                        const unsigned long long x = key[t], y = key[ixj];
-                        if ((x > y) == ((t & k) == 0)) {
-                            key[t] = y;
-                            key[ixj] = x;
+        if (n <= kRankMax) {
+            // rank sort: the place of a key is the number of smaller keys (the
+            // keys differ); every lane reads every key by LDS broadcast, which
+            // costs far less LDS bandwidth than the passes of a sorting network
+            unsigned long long kv[kRankMax / 64];
+            int rk[kRankMax / 64];
+#pragma unroll
+            for (int u = 0; u < kRankMax / 64; ++u) {
+                const int t = lane + 64 * u;
+                kv[u] = t < n ? (((unsigned long long)(uint32_t)a.snbr_tmp[r0 + t]) << 32) | (uint32_t)t : ~0ull;
+                rk[u] = 0;
+                if (t < n) key[t] = kv[u];
+            }
+            if (lane == 0 && (n & 1)) key[n] = ~0ull;   // n < cap when odd: pads the last pair
+            __syncthreads();
+            for (int j = 0; j < n; j += 2) {
+                const unsigned long long x = key[j], y = key[j + 1];
+#pragma unroll
+                for (int u = 0; u < kRankMax / 64; ++u)
+                    if (64 * u < n) rk[u] += (int)(x < kv[u]) + (int)(y < kv[u]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kRankMax / 64; ++u)
+                if (lane + 64 * u < n) key[rk[u]] = kv[u];
+            __syncthreads();
+        } else {
+            // bitonic sort of the keys padded to a power of two
+            int n2 = 1;
+            while (n2 < n) n2 <<= 1;
+            for (int t = lane; t < n2; t += 64)
+                key[t] = t < n ? (((unsigned long long)(uint32_t)a.snbr_tmp[r0 + t]) << 32) | (uint32_t)t : ~0ull;
+            __syncthreads();
+            for (int k = 2; k <= n2; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int t = lane; t < n2; t += 64) {
+                        const int ixj = t ^ j;
+                        if (ixj > t) {
+                            const unsigned long long x = key[t], y = key[ixj];
+                            if ((x > y) == ((t & k) == 0)) {
+                                key[t] = y;
+                                key[ixj] = x;
+                            }
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
-            }
+        }
         // the sorted list, and the upper entries (f >= e) appended to the work
         // lists of their class in list order; lower entries get their record
         // from the mirror (link_element, in the CSR rows launch)
