@@ -5,7 +5,7 @@
 // list S(e) this is the union over the elements e containing i (those with
 // S(e) non-empty) of nodes(e) and of nodes(f) for f in S(e).  One wave per
 // row inserts these ids into an open-addressing hash set in LDS, compacts and
-// bitonic-sorts the unique ids and writes them to a row slot of a staging
+// sorts the unique ids and writes them to a row slot of a staging
 // buffer; after the scan of the row lengths a copy kernel packs the slots.
 // A neighbour f met again through another element of the row adds nothing
 // new: a second hash set of element ids lets only the first meeting insert
@@ -21,6 +21,7 @@ namespace {
 constexpr int kEmpty = -1;
 constexpr int kCsrQ = 64;    // elements around a node per batch
 constexpr int kCsrU = 4;     // entries per lane per step
+constexpr int kRankMax = 256;   // longest row sorted by ranks
 
 struct CsrArgs {
     const int32_t *E;
@@ -207,28 +208,53 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
             if (v != kEmpty) buf[basec + __popcll(bb & ((1ull << lane) - 1ull))] = v;
             basec += __popcll(bb);
         }
-        int n2 = 1;
-        while (n2 < n) n2 <<= 1;
-        for (int t = n + lane; t < n2; t += 64) buf[t] = 0x7fffffff;
         wave_sync();
-        for (int k = 2; k <= n2; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = lane; t < n2; t += 64) {
-                    const int ixj = t ^ j;
-                    if (ixj > t) {
-                        const int32_t x = buf[t], y = buf[ixj];
-                        const bool up = (t & k) == 0;
-                        if ((x > y) == up) {
-                            buf[t] = y;
-                            buf[ixj] = x;
+        int32_t *out = a.stage + item * (int64_t)a.cap;
+        if (n <= kRankMax) {
+            // rank sort: the place of an id is the number of smaller ids (the
+            // ids differ), read by LDS broadcast; each id goes straight to
+            // its place in the slot
+            int32_t kv[kRankMax / 64];
+            int rk[kRankMax / 64];
+#pragma unroll
+            for (int u = 0; u < kRankMax / 64; ++u) {
+                const int t = lane + 64 * u;
+                kv[u] = t < n ? buf[t] : 0x7fffffff;
+                rk[u] = 0;
+            }
+            for (int j = 0; j < n; ++j) {
+                const int32_t x = buf[j];
+#pragma unroll
+                for (int u = 0; u < kRankMax / 64; ++u)
+                    if (64 * u < n) rk[u] += (int)(x < kv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kRankMax / 64; ++u)
+                if (lane + 64 * u < n) out[rk[u]] = kv[u];
+        } else {
+            // bitonic sort of the ids padded to a power of two
+            int n2 = 1;
+            while (n2 < n) n2 <<= 1;
+            for (int t = n + lane; t < n2; t += 64) buf[t] = 0x7fffffff;
+            wave_sync();
+            for (int k = 2; k <= n2; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int t = lane; t < n2; t += 64) {
+                        const int ixj = t ^ j;
+                        if (ixj > t) {
+                            const int32_t x = buf[t], y = buf[ixj];
+                            const bool up = (t & k) == 0;
+                            if ((x > y) == up) {
+                                buf[t] = y;
+                                buf[ixj] = x;
+                            }
                         }
                     }
+                    wave_sync();
                 }
-                wave_sync();
             }
+            for (int t = lane; t < n; t += 64) out[t] = buf[t];
         }
-        int32_t *out = a.stage + item * (int64_t)a.cap;
-        for (int t = lane; t < n; t += 64) out[t] = buf[t];
         if (lane == 0) a.nlen[i] = n;   // the longest row comes from the scan of nlen
         wave_sync();
     }
