@@ -917,7 +917,7 @@ struct DiagArgs {
 // of S(e) in that order, kDiagU of them with their loads in flight at once,
 // then the group sums by shuffles; the grouping fixes the order of the sums,
 // so every path uses these constants.
-constexpr int kDiagG = 16;
+constexpr int kDiagG = 32;
 constexpr int kDiagU = 4;
 
 template <int NK, typename TR>
