@@ -42,24 +42,28 @@
 #ifndef NLFEM_H
 #define NLFEM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
 #endif
 
-#define NLFEM_ABI_VERSION 2
+#define NLFEM_ABI_VERSION 3
 
 /* return codes */
 enum {
     NLFEM_OK = 0,
     NLFEM_E_INVALID = -1,   /* bad argument: NULL pointer, size <= 0, delta <= 0,
                                weights not summing to 1/2, unsupported option */
-    NLFEM_E_MESH = -2,      /* vertex index out of range or zero-area element */
+    NLFEM_E_MESH = -2,      /* vertex index out of range, zero-area element, or
+                               an edge shared by more than two elements (the
+                               mesh is not conforming, Sec. 2.2 Assumption 2) */
     NLFEM_E_NOMEM = -3,     /* device allocation failed */
     NLFEM_E_HIP = -4,       /* HIP runtime error (message has the HIP text) */
-    NLFEM_E_OVERFLOW = -5,  /* a count exceeds 32-bit column indices or an
-                               internal capacity */
+    NLFEM_E_OVERFLOW = -5,  /* a count exceeds 32-bit column indices, an
+                               internal capacity or the limit set by
+                               nlfem_set_capacity */
     NLFEM_E_MISMATCH = -6,  /* handle built for another mesh or configuration */
     NLFEM_E_NODEVICE = -7   /* no HIP device available */
 };
@@ -140,9 +144,38 @@ typedef struct {
                              S(k) = {l : (k,l) or (l,k) interacts}, summed over k */
     int64_t rebuild;      /* how the last nlfem_build_pairs ran: 0 plain build,
                              1 rebuild with the sizes of the build before it
-                             (one synchronisation), 2 such a rebuild found other
-                             sizes and ran as a plain build */
+                             (launched without waiting), 2 such a rebuild found
+                             other sizes and was run again as a plain build by
+                             the call that checked it */
+    int64_t skipped;      /* nlfem_assemble calls on this handle, since it was
+                             created, whose work was skipped because they were
+                             queued after a rebuild that found other sizes
+                             (their val was left unchanged; see nlfem_assemble) */
 } nlfem_pairs_info_t;
+
+/* Device memory of handles and batches.  alloc(bytes, stream, ctx) returns
+   device memory of the current device, aligned to at least 256 bytes, that
+   work enqueued on `stream` may use from then on, or NULL (the calling entry
+   point then returns E_NOMEM).  free_(ptr, stream, ctx) gives back a block
+   of an earlier alloc with the stream it was allocated on; work the library
+   enqueued on that stream before the call may still be using it, so the
+   free must be stream-ordered (as torch's caching allocator and
+   hipFreeAsync are) or wait for the stream.  Both NULL: hipMalloc/hipFree
+   (the default).  A block is always released by the pair it came from,
+   even after the hooks were replaced.  Set it before the calls that
+   allocate; not thread-safe.  Errors: E_INVALID (exactly one of the two
+   functions NULL). */
+typedef void *(*nlfem_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*nlfem_free_fn)(void *ptr, void *stream, void *ctx);
+int nlfem_set_allocator(nlfem_alloc_fn alloc, nlfem_free_fn free_, void *ctx);
+
+/* Largest number of neighbour-list entries (nlfem_pairs_info_t.n_nbr, the
+   size that all other buffers of a handle follow) a plain build may hold;
+   past it nlfem_build_pairs returns E_OVERFLOW before allocating them.
+   0 = no limit (2^31 - 1 entries, the bound of 32-bit list indices).
+   For callers that bound device memory per problem, and to test the
+   overflow path.  Not thread-safe.  Errors: E_INVALID (negative). */
+int nlfem_set_capacity(int64_t max_entries);
 
 /* ABI version (NLFEM_ABI_VERSION of the built library). */
 int32_t nlfem_version(void);
@@ -161,8 +194,8 @@ const char *nlfem_last_error(void);
    (no fused multiply-add), so the pattern does not depend on `precision`.
    *pairs: if NULL a new handle is created; otherwise the given handle is
    rebuilt in place, reusing its device memory when large enough.
-   A plain build synchronises with `stream` three times (sizes are needed to
-   allocate).  A rebuild of a handle whose last plain build had the same
+   A plain build synchronises with `stream` four times (sizes are needed to
+   allocate) and allocates through the hooks of nlfem_set_allocator.  A rebuild of a handle whose last plain build had the same
    numbers of vertices and elements and the same kernel, delta, ball, rules
    and singular flag is launched with that build's sizes and returns without
    waiting; its kernels compare the device-side counts with the expected ones
@@ -175,6 +208,8 @@ const char *nlfem_last_error(void);
    error of the rebuild (E_MESH, ...) is returned by that call.  A batch
    holding the handle stays valid across rebuilds that keep the sizes; after
    a plain rebuild its runs return E_MISMATCH.
+   E_MESH is returned for a vertex index outside [0, M), an element of zero
+   area, or an edge shared by more than two elements of labels 1 and 2.
    Errors: E_INVALID, E_MESH, E_NOMEM, E_HIP, E_OVERFLOW, E_NODEVICE. */
 int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg,
                       nlfem_pairs **pairs, void *stream);
@@ -201,8 +236,16 @@ int nlfem_csr_pattern(const nlfem_pairs *pairs, int64_t *row_ptr, int32_t *col,
    `mesh` must be the mesh the handle was built from; `cfg` may differ from
    the build configuration only in `c`, `precision` and `singular_n` when
    the latter keeps its zero/non-zero status (E_MISMATCH otherwise).
-   Allocates nothing and never synchronises; uses workspace held by the
-   handle, so two assemblies with the same handle must not overlap in time.
+   Allocates nothing and never synchronises: every call only enqueues
+   kernels on `stream`.  Uses workspace held by the handle, so two
+   assemblies with the same handle must not overlap in time.
+   After a rebuild that returned without waiting (see nlfem_build_pairs),
+   the kernels compare the rebuild's device-side counts with the sizes the
+   handle had before it; if they differ, the kernels skip their work and
+   val is left unchanged.  The next nlfem_pairs_info reports that case
+   (rebuild = 2, `skipped` counts such calls); query the sizes there and
+   assemble again.  When the rebuild kept its sizes (rebuild = 1), val holds
+   the result as always.
    Errors: E_INVALID, E_MISMATCH, E_HIP. */
 int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg,
                    const nlfem_pairs *pairs, double *val, void *stream);
@@ -215,6 +258,8 @@ int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg,
    f_qp:     device [K][outer.n][n] values at the outer quadrature points, or
    f_affine: host [n][3], f_c(x) = f_affine[c][0] + f_affine[c][1] x_1
              + f_affine[c][2] x_2 (used when f_qp is NULL).
+   Elements with a vertex index outside [0, M) are skipped (nlfem_build_pairs
+   reports them as E_MESH; this call validates no device data).
    Allocates nothing and never synchronises.
    Errors: E_INVALID, E_HIP. */
 int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_qp,

@@ -55,11 +55,15 @@ class _Config(C.Structure):
 class _Info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_pairs", "n_far", "n_vertex", "n_edge", "n_ident",
                                          "n_dof", "n_rows", "nnz", "n_upper_far", "n_upper_touch", "n_nbr",
-                                         "rebuild")]
+                                         "rebuild", "skipped")]
 
 
-ABI_VERSION = 2   # layout of the structs below
+ABI_VERSION = 3   # layout of the structs below
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 _lib = None
+_hooks = []   # every callback pair ever installed: blocks keep their free function
+# until they are released, so no pair may be collected before the process ends
 
 
 def lib():
@@ -104,6 +108,10 @@ def lib():
         L.nlfem_batch_free.restype = None
         L.nlfem_assemble_batched.argtypes = [C.c_int32, vp, vp, vp, vp, C.c_char_p, vp]
         L.nlfem_assemble_batched.restype = i32
+        L.nlfem_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+        L.nlfem_set_allocator.restype = i32
+        L.nlfem_set_capacity.argtypes = [C.c_int64]
+        L.nlfem_set_capacity.restype = i32
         _lib = L
     return _lib
 
@@ -311,6 +319,52 @@ def nlfem_timing_read(reset: bool = True) -> dict:
     n = np.zeros(len(TIMING_PHASES), np.int64)
     _check(lib().nlfem_timing_read(ms.ctypes.data, n.ctypes.data, 1 if reset else 0))
     return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(TIMING_PHASES)}
+
+
+def nlfem_set_allocator(alloc=None, free=None, ctx=None):
+    """Installs device-allocation hooks: alloc(nbytes, stream) -> int device
+    pointer (0 = failure) and free(ptr, stream), both called with plain ints.
+    Both None restores hipMalloc/hipFree.  A Python exception inside a hook
+    counts as a failed allocation (alloc) or is ignored (free)."""
+    if (alloc is None) != (free is None):
+        raise ValueError("give both allocator functions or neither")
+    if alloc is None:
+        _check(lib().nlfem_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def _a(nbytes, stream, _ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:   # noqa: BLE001 - reported by the library as E_NOMEM
+            return None
+
+    def _f(ptr, stream, _ctx):
+        try:
+            free(int(ptr), int(stream or 0))
+        except Exception:   # noqa: BLE001 - nothing to report to
+            pass
+
+    hooks = (ALLOC_FN(_a), FREE_FN(_f))
+    _hooks.append(hooks)
+    _check(lib().nlfem_set_allocator(hooks[0], hooks[1], None))
+
+
+def torch_allocator():
+    """(alloc, free) hooks that take device memory from torch's caching
+    allocator on the library's stream."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device(), stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
+
+
+def nlfem_set_capacity(max_entries: int = 0):
+    _check(lib().nlfem_set_capacity(int(max_entries)))
 
 
 def nlfem_pairs_free(pairs: Pairs):

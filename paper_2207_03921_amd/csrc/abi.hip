@@ -14,6 +14,15 @@ namespace nlfem {
 namespace {
 thread_local std::string g_err = "no error";
 
+// device allocator (nlfem_set_allocator) and the capacity limit of a build
+struct Allocator {
+    nlfem_alloc_fn alloc = nullptr;
+    nlfem_free_fn free_fn = nullptr;
+    void *ctx = nullptr;
+};
+Allocator g_alloc;
+int64_t g_capacity = 0;
+
 enum Buf : int {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
@@ -29,21 +38,8 @@ int ensure(nlfem_pairs *h, int id, size_t bytes)
     auto &b = h->bufs[id];
     if (bytes == 0) bytes = 16;
     if (b.p && b.cap >= bytes) return NLFEM_OK;
-    if (b.p) {
-        (void)hipFree(b.p);
-        b.p = nullptr;
-        b.cap = 0;
-    }
-    const size_t want = bytes + bytes / 8;   // headroom for rebuilds that grow a little
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        b.p = nullptr;
-        return set_error(NLFEM_E_NOMEM, std::string("device allocation of ") + std::to_string(want) +
-                                            " bytes failed: " + hipGetErrorString(e));
-    }
-    b.cap = want;
-    return NLFEM_OK;
+    if (b.p) dev_release(b);
+    return dev_alloc(b, bytes + bytes / 8, h->alloc_stream);   // headroom for rebuilds that grow a little
 }
 
 template <typename T>
@@ -232,6 +228,15 @@ int read_slots(nlfem_pairs *h, hipStream_t s)
     return wait_event(h->ev_rb);
 }
 
+// true when the read-back of a rebuild (pinned copy) has the slots of the
+// last plain build
+bool rebuild_held(const nlfem_pairs *h)
+{
+    for (int i = 0; i < kRedSlots; ++i)
+        if (((kSpecCsr >> i) & 1u) && h->rb[i] != h->spec_red[i]) return false;
+    return true;
+}
+
 // Counters of the build after the geometry, all cleared by one launch.
 // codes of the order of the dof rows: the Morton codes of the grid cells
 // (2 * bits interleaved bits), or the row-major cell index for grids too
@@ -268,6 +273,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
 {
     h->gate = SpecGate{};
     if (!spec) h->spec_ok = false;
+    h->alloc_stream = s;
     NLFEM_HIP(hipGetDevice(&h->device));
     h->mesh_vertices = m->vertices;
     h->mesh_elements = m->elements;
@@ -301,7 +307,6 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     unsigned long long *red = h->rb;
     if (!h->ev_rb) {
         NLFEM_HIP(hipEventCreateWithFlags(&h->ev_rb, hipEventDisableTiming));
-        NLFEM_HIP(hipEventCreateWithFlags(&h->ev_asm, hipEventDisableTiming));
     }
     timing_begin(kPhGeometry, s);
     {
@@ -448,6 +453,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         h->n_far = h->n_pairs - h->n_ident - h->n_edge - h->n_vertex;
         if (h->nS >= (int64_t)INT32_MAX || h->nUF >= (int64_t)INT32_MAX || h->nUT >= (int64_t)INT32_MAX)
             return set_error(NLFEM_E_OVERFLOW, "more than 2^31 neighbour entries");
+        if (g_capacity > 0 && h->nS > g_capacity)
+            return set_error(NLFEM_E_OVERFLOW, std::to_string(h->nS) + " neighbour entries exceed the capacity limit of " +
+                                                   std::to_string(g_capacity));
     }
     NLFEM_TRY(ensure_typed(h, B_SNBR, h->nS, h->snbr));
     NLFEM_TRY(ensure_typed(h, B_SFLAG, h->nS, h->sflag));
@@ -492,6 +500,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         z.add(h->scan_w[3].hdr, 1 + h->scan_w[3].tiles);
         NLFEM_TRY(launch_zero(z, nullptr, s));
     }
+    if (err & kErrEdge) return set_error(NLFEM_E_MESH, "an edge is shared by more than two elements");
     if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");
     if (!spec) {
         h->nnz_node = (int64_t)red[kRedNnz];
@@ -539,18 +548,56 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
 
 }  // namespace
 
-int resolve(nlfem_pairs *h, hipEvent_t after)
+int dev_alloc(DevBlock &b, size_t bytes, hipStream_t s)
+{
+    b = DevBlock{};
+    if (!g_alloc.alloc) {
+        const hipError_t e = hipMalloc(&b.p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return set_error(NLFEM_E_NOMEM, std::string("device allocation of ") + std::to_string(bytes) +
+                                                " bytes failed: " + hipGetErrorString(e));
+        }
+    } else {
+        b.p = g_alloc.alloc(bytes, (void *)s, g_alloc.ctx);
+        if (!b.p)
+            return set_error(NLFEM_E_NOMEM, "the allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+        b.free_fn = g_alloc.free_fn;
+        b.ctx = g_alloc.ctx;
+        b.stream = s;
+        if ((uintptr_t)b.p & 255u) {
+            dev_release(b);
+            return set_error(NLFEM_E_INVALID, "the allocator hook returned memory not aligned to 256 bytes");
+        }
+    }
+    b.cap = bytes;
+    return NLFEM_OK;
+}
+
+void dev_release(DevBlock &b)
+{
+    if (b.p) {
+        if (b.free_fn) b.free_fn(b.p, (void *)b.stream, b.ctx);
+        else (void)hipFree(b.p);
+    }
+    b = DevBlock{};
+}
+
+// Finishes an unchecked rebuild: waits for its read-back and, when the sizes
+// differ, counts the assemblies queued since (their kernels skipped their
+// work) and runs the plain build of the rebuild's mesh.
+int resolve(nlfem_pairs *h)
 {
     if (!h->pending) return NLFEM_OK;
     h->pending = false;
     h->asm_gate = SpecGate{};
     NLFEM_TRY(wait_event(h->ev_rb));
-    bool same = true;
-    for (int i = 0; i < kRedSlots; ++i)
-        if (((kSpecCsr >> i) & 1u) && h->rb[i] != h->spec_red[i]) same = false;
-    if (same) return NLFEM_OK;
+    const int64_t queued = h->pend_asm;
+    h->pend_asm = 0;
+    if (rebuild_held(h)) return NLFEM_OK;
+    h->skipped += queued;
     h->last_build = 2;
-    if (after) NLFEM_TRY(wait_event(after));
     int rc = build(&h->pend_mesh, &h->pend_cfg.c, h, h->pend_stream, false);
     if (rc == NLFEM_OK) {
         // the plain build's last launches are still queued on its stream
@@ -677,13 +724,21 @@ int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pai
     const bool fresh = *pairs == nullptr;
     nlfem_pairs *h = fresh ? new (std::nothrow) nlfem_pairs() : *pairs;
     if (!h) return set_error(NLFEM_E_NOMEM, "host allocation failed");
+    bool held = true;
     if (!fresh && h->pending) {
-        // a newer build replaces an unchecked one: only its read-back is awaited
+        // a newer build replaces an unchecked one: its read-back is checked
+        // (assemblies queued after it skipped their work if it failed), but
+        // its plain build is not run
         NLFEM_TRY(wait_event(h->ev_rb));
         h->pending = false;
         h->asm_gate = SpecGate{};
+        held = rebuild_held(h);
+        if (!held) h->skipped += h->pend_asm;
+        h->pend_asm = 0;
     }
-    const bool spec = !fresh && h->spec_ok && same_shape(h, mesh, cfg);
+    // after a rebuild that found other sizes the mesh has probably changed:
+    // build plainly
+    const bool spec = !fresh && held && h->spec_ok && same_shape(h, mesh, cfg);
     int rc = build(mesh, cfg, h, (hipStream_t)stream, spec);
     h->last_build = spec ? 1 : 0;
     if (rc != NLFEM_OK) {
@@ -713,6 +768,7 @@ int nlfem_pairs_info(const nlfem_pairs *h, nlfem_pairs_info_t *info)
     info->n_upper_touch = h->nUT;
     info->n_nbr = h->nS;
     info->rebuild = h->last_build;
+    info->skipped = h->skipped;
     return NLFEM_OK;
 }
 
@@ -747,16 +803,11 @@ int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg, const nlfem_
     GaussArgs g{};
     g.n = cfg->singular_n;
     if (g.n > 0) gauss_legendre01(g.n, g.x, g.w);
-    nlfem_pairs *hm = const_cast<nlfem_pairs *>(h);
-    if (!hm->pending) return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
     // after an unchecked rebuild the launches test its slots on the device
-    // and the check finishes here, with the assembly already queued; a
-    // failed one is built plainly and assembled again
-    NLFEM_TRY(launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream));
-    NLFEM_HIP(hipEventRecord(hm->ev_asm, (hipStream_t)stream));
-    NLFEM_TRY(resolve(hm, hm->ev_asm));
-    if (hm->last_build == 2) return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
-    return NLFEM_OK;
+    // (asm_gate) and skip their work when they differ; the check of the
+    // read-back is left to the next call that needs the sizes
+    if (h->pending) ++const_cast<nlfem_pairs *>(h)->pend_asm;
+    return launch_assemble(h, mesh, cfg, g, val, (hipStream_t)stream);
 }
 
 int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_qp, const double *f_affine,
@@ -819,13 +870,27 @@ int nlfem_timing_read(double *ms, int64_t *launches, int reset)
     return NLFEM_OK;
 }
 
+int nlfem_set_allocator(nlfem_alloc_fn alloc, nlfem_free_fn free_, void *ctx)
+{
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return set_error(NLFEM_E_INVALID, "give both allocator functions or neither");
+    g_alloc = Allocator{alloc, free_, alloc ? ctx : nullptr};
+    return NLFEM_OK;
+}
+
+int nlfem_set_capacity(int64_t max_entries)
+{
+    if (max_entries < 0) return set_error(NLFEM_E_INVALID, "capacity must be >= 0");
+    g_capacity = max_entries;
+    return NLFEM_OK;
+}
+
 void nlfem_pairs_free(nlfem_pairs *h)
 {
     if (!h) return;
-    for (auto &b : h->bufs)
-        if (b.p) (void)hipFree(b.p);
+    (void)hipDeviceSynchronize();   // no queued work may still use the buffers
+    for (auto &b : h->bufs) dev_release(b);
     if (h->rb) (void)hipHostFree(h->rb);
-    if (h->ev_asm) (void)hipEventDestroy(h->ev_asm);
     if (h->ev_rb) (void)hipEventDestroy(h->ev_rb);
     delete h;
 }

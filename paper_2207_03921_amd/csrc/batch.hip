@@ -250,7 +250,8 @@ struct nlfem_batch {
     int cus = 0;
     std::vector<AssemblePlan> plans;
     std::vector<Group> groups;
-    void *dev = nullptr;              // all tables and counters
+    void *dev = nullptr;              // all tables and counters (in mem)
+    DevBlock mem;
     size_t dev_bytes = 0;
     unsigned long long *counters = nullptr;
     Shape shape[kPhases] = {{1024, 4}, {256, 4}, {64, 4}, {4, 16}};
@@ -435,7 +436,7 @@ void make_groups(nlfem_batch *b)
     }
 }
 
-int upload_tables(nlfem_batch *b)
+int upload_tables(nlfem_batch *b, hipStream_t s)
 {
     // layout
     size_t off = align256(sizeof(unsigned long long) * std::max<size_t>(b->groups.size(), 1));
@@ -482,11 +483,12 @@ int upload_tables(nlfem_batch *b)
             }
         }
     }
-    const hipError_t e = hipMalloc(&b->dev, off);
-    if (e != hipSuccess) return hip_error(e, "hipMalloc(batch tables)");
+    NLFEM_TRY(dev_alloc(b->mem, off, s));
+    b->dev = b->mem.p;
     b->dev_bytes = off;
     b->counters = (unsigned long long *)b->dev;
-    NLFEM_HIP(hipMemcpy(b->dev, host.data(), off, hipMemcpyHostToDevice));
+    NLFEM_HIP(hipMemcpyAsync(b->dev, host.data(), off, hipMemcpyHostToDevice, s));
+    NLFEM_HIP(hipStreamSynchronize(s));   // the host table is freed on return
     return NLFEM_OK;
 }
 
@@ -623,7 +625,7 @@ int batch_create(const std::vector<AssemblePlan> &plans, const std::vector<nlfem
         rc = set_error(NLFEM_E_HIP, "cannot query the compute-unit count");
     if (rc == NLFEM_OK) {
         make_groups(b);
-        rc = upload_tables(b);
+        rc = upload_tables(b, s);
     }
     if (rc == NLFEM_OK && (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
                            hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -699,7 +701,7 @@ void batch_free(nlfem_batch *b)
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     if (b->aux) (void)hipStreamDestroy(b->aux);
-    if (b->dev) (void)hipFree(b->dev);
+    dev_release(b->mem);
     delete b;
 }
 

@@ -34,6 +34,9 @@ struct ListArgs {
     int32_t *srec;
     int4 *snode;
     const int32_t *E;
+    const int32_t *lab;
+    const int64_t *ne_ptr;     // node -> element incidence
+    const int32_t *ne_list;
     int32_t *ue, *uf;
     uint32_t *um_ef, *um_fe;
     int32_t *te, *tf;
@@ -49,6 +52,24 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
     for (int64_t b = blockIdx.x; b < xcd_span(a.K); b += gridDim.x) {
         const int64_t e = xcd_item(b, a.K);
         if (e >= a.K) continue;
+        // conforming mesh (Sec. 2.2, Assumption 2): lane v counts the labelled
+        // elements holding edge v of e (vertex indices are valid by now: the
+        // build stops at an index error before this launch)
+        if (lane < 3) {
+            const int32_t le = a.lab[e];
+            if (le == 1 || le == 2) {
+                const int32_t va = a.E[3 * e + lane], vb = a.E[3 * e + (lane + 1) % 3];
+                int cnt = 0;
+                for (int64_t i = a.ne_ptr[va]; i < a.ne_ptr[va + 1]; ++i) {
+                    const int32_t g = a.ne_list[i];
+                    const int32_t lg = a.lab[g];
+                    if (lg != 1 && lg != 2) continue;
+                    cnt += (a.E[3 * (int64_t)g] == vb) | (a.E[3 * (int64_t)g + 1] == vb) |
+                           (a.E[3 * (int64_t)g + 2] == vb);
+                }
+                if (cnt > 2) atomicOr(a.err, kErrEdge);
+            }
+        }
         const int64_t s0 = a.sptr[e], r0 = a.scr[e];   // final list, scratch segment
         const int n = (int)(a.sptr[e + 1] - s0);
         if (n == 0) continue;
@@ -180,6 +201,9 @@ ListArgs list_args(nlfem_pairs *h)
     a.srec = h->srec;
     a.snode = h->snode;
     a.E = h->mesh_elements;
+    a.lab = h->mesh_labels;
+    a.ne_ptr = h->ne_ptr;
+    a.ne_list = h->ne_list;
     a.ue = h->ue;
     a.uf = h->uf;
     a.um_ef = h->um_ef;
@@ -195,7 +219,6 @@ ListArgs list_args(nlfem_pairs *h)
 
 int launch_sort_lists(nlfem_pairs *h, hipStream_t s)
 {
-    if (h->nS == 0) return NLFEM_OK;
     ListArgs a = list_args(h);
     if (a.cap > 8192) return set_error(NLFEM_E_OVERFLOW, "neighbour list longer than 8192 entries");
     const unsigned grid = xcd_grid(h->K);

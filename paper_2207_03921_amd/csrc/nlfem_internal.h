@@ -27,6 +27,7 @@ enum : int32_t {
     kErrSlot = 8,        // scatter target not in the pattern (internal bug)
     kErrCell = 16,       // cell occupancy above the pair-search tile size
     kErrClip = 32,       // polygon clip longer than the bound found by the pair search (internal bug)
+    kErrEdge = 64,       // an edge shared by more than two elements (non-conforming mesh)
 };
 
 // Quadrature tables passed by value (kernel arguments live in scalar registers).
@@ -78,6 +79,21 @@ struct ConfigCopy {
         c.polygon_dirs = dirs.empty() ? nullptr : dirs.data();
     }
 };
+
+// A block of device memory and the allocator that gave it (nlfem_set_allocator:
+// the caller's hook, else hipMalloc/hipFree).  abi.hip.
+struct DevBlock {
+    void *p = nullptr;
+    size_t cap = 0;
+    nlfem_free_fn free_fn = nullptr;   // null: hipFree
+    void *ctx = nullptr;
+    hipStream_t stream = nullptr;      // stream of the allocation
+};
+// allocates `bytes` (256-byte aligned) on stream s into b (b must be empty)
+int dev_alloc(DevBlock &b, size_t bytes, hipStream_t s);
+// releases b (work already enqueued on its stream may still use it when the
+// hook is stream-ordered; hipFree waits for the device)
+void dev_release(DevBlock &b);
 
 // A rebuild launched with the last build's sizes: a build kernel runs only
 // while the reduction slots that are final at its launch (mask) equal the
@@ -236,13 +252,12 @@ struct nlfem_pairs {
     double *poly_dir = nullptr;  // [N][2] polygon directions (approach POLY)
     int32_t far_stride = 0, touch_stride = 0;
     hipEvent_t ev_rb = nullptr;    // completion of a read-back of the reduction slots
-    hipEvent_t ev_asm = nullptr;   // end of an assembly queued before a rebuild's check
+    // assemblies queued while a rebuild was unchecked, and those of them
+    // whose work was skipped because the rebuild found other sizes
+    int64_t pend_asm = 0, skipped = 0;
+    hipStream_t alloc_stream = nullptr;   // stream of the build that allocates
     // grow-only device buffers behind the typed pointers above
-    struct DevBuf {
-        void *p = nullptr;
-        size_t cap = 0;
-    };
-    DevBuf bufs[64];
+    nlfem::DevBlock bufs[64];
 };
 
 namespace nlfem {
@@ -256,8 +271,8 @@ void timing_end(int phase, hipStream_t s);
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *what);
 // abi.hip: finishes an unchecked rebuild of h (waits for its read-back; runs
-// the plain build when the sizes differ, after `after` when given)
-int resolve(nlfem_pairs *h, hipEvent_t after = nullptr);
+// the plain build when the sizes differ)
+int resolve(nlfem_pairs *h);
 
 #define NLFEM_HIP(call)                                               \
     do {                                                              \

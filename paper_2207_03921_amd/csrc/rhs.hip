@@ -6,7 +6,7 @@ namespace nlfem {
 namespace {
 
 struct RhsArgs {
-    int64_t K;
+    int64_t K, M;
     const double *V;
     const int32_t *E;
     const int32_t *lab;
@@ -21,6 +21,9 @@ __global__ void __launch_bounds__(256) k_rhs(RhsArgs a, RuleArgs r)
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.K || a.lab[k] != 1) return;
     const int32_t n0 = a.E[3 * k], n1 = a.E[3 * k + 1], n2 = a.E[3 * k + 2];
+    // an element with an index outside [0, M) is skipped (the pair build
+    // reports it; this call validates no device data)
+    if ((uint64_t)n0 >= (uint64_t)a.M || (uint64_t)n1 >= (uint64_t)a.M || (uint64_t)n2 >= (uint64_t)a.M) return;
     const double v0x = a.V[2 * (int64_t)n0], v0y = a.V[2 * (int64_t)n0 + 1];
     const double J00 = a.V[2 * (int64_t)n1] - v0x, J10 = a.V[2 * (int64_t)n1 + 1] - v0y;
     const double J01 = a.V[2 * (int64_t)n2] - v0x, J11 = a.V[2 * (int64_t)n2 + 1] - v0y;
@@ -53,6 +56,7 @@ int launch_rhs(const nlfem_mesh *m, const RuleArgs &r, int ncomp, const double *
 {
     RhsArgs a{};
     a.K = m->n_elements;
+    a.M = m->n_vertices;
     a.V = m->vertices;
     a.E = m->elements;
     a.lab = m->labels;

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(nl):
     L = nl.lib()
     for n in _declared():
         assert hasattr(L, n), n
-    assert nl.nlfem_version() == 2
+    assert nl.nlfem_version() == nl.ABI_VERSION == 3
 
 
 def _cfg(nl, **over):
@@ -142,3 +142,17 @@ def test_batch_entry_points_validate_without_device(nl):
     assert L.nlfem_batch_info(None, C.byref(g), sh) == -1
     assert L.nlfem_assemble_batched(0, None, None, None, None, None, None) == -1
     L.nlfem_batch_free(None)
+
+
+def test_allocator_and_capacity_validation(nl):
+    """The allocator hooks come in pairs; the capacity limit is >= 0.  Both
+    are host settings, checked without a device."""
+    L = nl.lib()
+    keep = nl.ALLOC_FN(lambda n, s, c: None)
+    assert L.nlfem_set_allocator(keep, nl.FREE_FN(), None) == -1
+    assert "both" in nl.nlfem_last_error()
+    assert L.nlfem_set_allocator(nl.ALLOC_FN(), nl.FREE_FN(), None) == 0   # default
+    with pytest.raises(ValueError):
+        nl.nlfem_set_allocator(alloc=lambda n, s: 0)
+    assert L.nlfem_set_capacity(-1) == -1
+    assert L.nlfem_set_capacity(0) == 0

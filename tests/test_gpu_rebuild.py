@@ -22,11 +22,13 @@ def _result(nl, dm, cfg, pairs):
     import torch
     info = dict(nl.nlfem_pairs_info(pairs))
     rb = info.pop("rebuild")
+    skipped = info.pop("skipped")
     rp, col = nl.nlfem_csr_pattern(pairs)
     val = nl.nlfem_assemble(dm, cfg, pairs)
     k, l, c = nl.nlfem_pairs_export(pairs)
     torch.cuda.synchronize()
-    return dict(info=info, rebuild=rb, rp=rp.cpu().numpy(), col=col.cpu().numpy(),
+    _result.skipped = skipped
+    return dict(info=info, rebuild=rb, skipped=skipped, rp=rp.cpu().numpy(), col=col.cpu().numpy(),
                 val=val[:info["nnz"]].cpu().numpy(), pairs=(k.cpu().numpy(), l.cpu().numpy(), c.cpu().numpy()))
 
 
@@ -39,16 +41,25 @@ def _assert_same(a, b):
     assert np.abs(a["val"] - b["val"]).max() <= 1e-13 * scale
 
 
-def _result_assemble_first(nl, dm, cfg, pairs):
-    """The same, with the assembly as the first call after the rebuild."""
+def _result_assemble_first(nl, dm, cfg, pairs, nnz_before, path):
+    """The same, with the assembly as the first call after the rebuild.  The
+    assembly never waits: when the rebuild kept its sizes it writes the
+    result; when it found other sizes its kernels skip their work (val keeps
+    its contents) and the next nlfem_pairs_info counts the skipped call."""
     import torch
-    nnz_cap = 4 << 20
-    val = torch.full((nnz_cap,), float("nan"), dtype=torch.float64, device="cuda")
+    val = torch.full((max(nnz_before, 1),), float("nan"), dtype=torch.float64, device="cuda")
     nl.nlfem_assemble(dm, cfg, pairs, val=val)
+    skipped_before = _result.skipped
     r = _result(nl, dm, cfg, pairs)
     torch.cuda.synchronize()
-    got = val[:r["info"]["nnz"]].cpu().numpy()
-    assert np.array_equal(got, r["val"]) or np.abs(got - r["val"]).max() <= 1e-13 * max(np.abs(r["val"]).max(), 1e-300)
+    got = val.cpu().numpy()
+    if path == 1:
+        assert r["info"]["nnz"] == nnz_before
+        assert np.array_equal(got, r["val"]) or np.abs(got - r["val"]).max() <= 1e-13 * max(np.abs(r["val"]).max(), 1e-300)
+        assert r["skipped"] == skipped_before
+    else:
+        assert np.isnan(got).all()
+        assert r["skipped"] == skipped_before + 1
     return r
 
 
@@ -58,6 +69,7 @@ def _fresh(nl, mesh, cfg):
 
 
 def test_rebuild_same_and_changed_meshes():
+    import torch
     import paper_2207_03921_amd as nl
     w = inv_dist_jittered(n=24, delta=0.1, precision="fp64")
     A = w["mesh"]
@@ -90,12 +102,26 @@ def test_rebuild_same_and_changed_meshes():
     # the same sequence with the assembly as the first call after each rebuild
     for name, path in (("B", 2), ("B", 1), ("A", 2), ("A", 1)):
         print("rebuild with", name, "assembly first", flush=True)
+        nnz_before = r["info"]["nnz"]
         pairs = nl.nlfem_build_pairs(dm[name], cfg, pairs=pairs)
-        r = _result_assemble_first(nl, dm[name], cfg, pairs)
+        r = _result_assemble_first(nl, dm[name], cfg, pairs, nnz_before, path)
         assert r["rebuild"] == path, (name, r["rebuild"])
         _assert_same(r, ref[name])
+    # an unchecked rebuild that found other sizes, replaced by a newer build
+    # before any call checked it: its assembly skipped, the newer build plain
+    skipped = r["skipped"]
+    pairs = nl.nlfem_build_pairs(dm["B"], cfg, pairs=pairs)
+    val = torch.full((max(r["info"]["nnz"], 1),), float("nan"), dtype=torch.float64, device="cuda")
+    nl.nlfem_assemble(dm["B"], cfg, pairs, val=val)
+    pairs = nl.nlfem_build_pairs(dm["B"], cfg, pairs=pairs)
+    r = _result(nl, dm["B"], cfg, pairs)
+    assert r["rebuild"] == 0 and r["skipped"] == skipped + 1
+    assert torch.isnan(val).all().item()
+    _assert_same(r, ref["B"])
     # a new device copy of the same mesh (other pointers, same values)
     dA2 = nl.DeviceMesh.from_numpy(A)
+    pairs = nl.nlfem_build_pairs(dA2, cfg, pairs=pairs)   # B's sizes: falls back
+    assert nl.nlfem_pairs_info(pairs)["rebuild"] == 2
     pairs = nl.nlfem_build_pairs(dA2, cfg, pairs=pairs)
     r = _result(nl, dA2, cfg, pairs)
     assert r["rebuild"] == 1
