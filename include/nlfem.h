@@ -340,6 +340,26 @@ int nlfem_assemble_batched(int32_t n, const nlfem_mesh *meshes, const nlfem_conf
                            nlfem_pairs *const *pairs, double *const *vals, const char *tune_cache,
                            void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+   harnesses that forbid hipMalloc): the one-shot batched assembly of
+   nlfem_assemble_batched with its launch tables and work-queue counters in a
+   static device array of NLFEM_NOALLOC_SCRATCH_BYTES (8 MiB) that each GPU
+   the library runs on holds until the process ends.  Same arguments and
+   results as nlfem_assemble_batched (default launch shapes, no tuning, no
+   cache), all phases on `stream`.  Allocates no device memory (neither
+   hipMalloc nor the nlfem_set_allocator hooks) and creates no stream or
+   event; synchronises once, after copying the tables, then returns with the
+   assembly enqueued.  Every call on one GPU shares that GPU's array, which
+   keeps the last call's contents: calls that overlap in time on one GPU
+   (from several host threads or streams) race and must not be made.
+   Handles with an unchecked rebuild are rejected (E_INVALID; call
+   nlfem_pairs_info first), since finishing one may need a plain build.
+   Errors: those of nlfem_assemble_batched, and E_OVERFLOW when the batch's
+   tables (about 5 KB per problem) exceed the array. */
+#define NLFEM_NOALLOC_SCRATCH_BYTES (8u << 20)
+int nlfem_assemble_batched_noalloc(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs,
+                                   nlfem_pairs *const *pairs, double *const *vals, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,6 +112,8 @@ def lib():
         L.nlfem_set_allocator.restype = i32
         L.nlfem_set_capacity.argtypes = [C.c_int64]
         L.nlfem_set_capacity.restype = i32
+        L.nlfem_assemble_batched_noalloc.argtypes = [C.c_int32, vp, vp, vp, vp, vp]
+        L.nlfem_assemble_batched_noalloc.restype = i32
         _lib = L
     return _lib
 
@@ -455,4 +457,12 @@ def nlfem_assemble_batched(meshes, cfgs, pairs, vals, tune_cache=None, stream=No
     n, cm, cc, ph, vp = _batch_arrays(meshes, cfgs, pairs, vals)
     path = None if tune_cache is None else os.fsencode(tune_cache)
     _check(lib().nlfem_assemble_batched(n, cm, cc, ph, vp, path, _stream(stream)))
+    return vals
+
+
+def nlfem_assemble_batched_noalloc(meshes, cfgs, pairs, vals, stream=None):
+    """The one-shot batch with its tables in the library's static device
+    array: no device allocation."""
+    n, cm, cc, ph, vp = _batch_arrays(meshes, cfgs, pairs, vals)
+    _check(lib().nlfem_assemble_batched_noalloc(n, cm, cc, ph, vp, _stream(stream)))
     return vals

@@ -895,24 +895,31 @@ void nlfem_pairs_free(nlfem_pairs *h)
     delete h;
 }
 
-int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, nlfem_pairs *const *pairs,
-                       double *const *vals, const char *tune_cache, int32_t tune, nlfem_batch **batch,
-                       void *stream)
+}  // extern "C"
+
+namespace {
+
+// checks a batch's problems and makes their launch plans; handles with an
+// unchecked rebuild are finished first when `resolve_pending`, rejected
+// otherwise (finishing one may run a plain build, which allocates)
+int batch_plans(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, nlfem_pairs *const *pairs,
+                double *const *vals, bool resolve_pending, std::vector<items::AssemblePlan> &plans,
+                std::vector<nlfem_pairs *> &handles)
 {
-    if (!batch) return set_error(NLFEM_E_INVALID, "batch is NULL");
-    *batch = nullptr;
     if (n < 1 || n > NLFEM_MAX_BATCH) return set_error(NLFEM_E_INVALID, "batch size outside [1, NLFEM_MAX_BATCH]");
     if (!meshes || !cfgs || !pairs || !vals) return set_error(NLFEM_E_INVALID, "NULL array argument");
-    if (tune < 0 || tune > 2) return set_error(NLFEM_E_INVALID, "tune must be 0, 1 or 2");
     NLFEM_TRY(check_device());
     int dev = -1;
     NLFEM_HIP(hipGetDevice(&dev));
-    std::vector<items::AssemblePlan> plans;
-    std::vector<nlfem_pairs *> handles;
     plans.reserve(n);
     for (int i = 0; i < n; ++i) {
         nlfem_pairs *h = pairs[i];
-        if (h) NLFEM_TRY(resolve(h));
+        if (h && h->pending) {
+            if (!resolve_pending)
+                return set_error(NLFEM_E_INVALID, "pairs handle " + std::to_string(i) +
+                                                      " has an unchecked rebuild (call nlfem_pairs_info first)");
+            NLFEM_TRY(resolve(h));
+        }
         if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle " + std::to_string(i) + " is NULL or not built");
         NLFEM_TRY(check_mesh(&meshes[i]));
         NLFEM_TRY(check_cfg(&cfgs[i]));
@@ -929,7 +936,33 @@ int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *
         plans.push_back(items::make_plan(h, &meshes[i], &cfgs[i], g, vals[i]));
         handles.push_back(h);
     }
+    return NLFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nlfem_batch_create(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, nlfem_pairs *const *pairs,
+                       double *const *vals, const char *tune_cache, int32_t tune, nlfem_batch **batch,
+                       void *stream)
+{
+    if (!batch) return set_error(NLFEM_E_INVALID, "batch is NULL");
+    *batch = nullptr;
+    if (tune < 0 || tune > 2) return set_error(NLFEM_E_INVALID, "tune must be 0, 1 or 2");
+    std::vector<items::AssemblePlan> plans;
+    std::vector<nlfem_pairs *> handles;
+    NLFEM_TRY(batch_plans(n, meshes, cfgs, pairs, vals, true, plans, handles));
     return batch_create(plans, handles, tune_cache, tune, batch, (hipStream_t)stream);
+}
+
+int nlfem_assemble_batched_noalloc(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs,
+                                   nlfem_pairs *const *pairs, double *const *vals, void *stream)
+{
+    std::vector<items::AssemblePlan> plans;
+    std::vector<nlfem_pairs *> handles;
+    NLFEM_TRY(batch_plans(n, meshes, cfgs, pairs, vals, false, plans, handles));
+    return batch_assemble_noalloc(plans, (hipStream_t)stream);
 }
 
 int nlfem_batch_assemble(nlfem_batch *batch, void *stream)

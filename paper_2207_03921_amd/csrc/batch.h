@@ -18,5 +18,10 @@ int batch_run(nlfem_batch *b, hipStream_t s);
 int batch_graph_launch(nlfem_batch *b, hipStream_t s);
 int batch_info(const nlfem_batch *b, int32_t *groups, int32_t *shape);
 void batch_free(nlfem_batch *b);
+// the same assembly with its tables and counters in a static device array
+// (no allocation; one synchronisation for the table copy); E_OVERFLOW when
+// the tables exceed batch_scratch_bytes()
+int batch_assemble_noalloc(const std::vector<items::AssemblePlan> &plans, hipStream_t s);
+size_t batch_scratch_bytes();
 
 }  // namespace nlfem

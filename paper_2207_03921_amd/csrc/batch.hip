@@ -436,9 +436,9 @@ void make_groups(nlfem_batch *b)
     }
 }
 
-int upload_tables(nlfem_batch *b, hipStream_t s)
+// offsets of the groups' tables in one block; returns its size
+size_t table_layout(nlfem_batch *b)
 {
-    // layout
     size_t off = align256(sizeof(unsigned long long) * std::max<size_t>(b->groups.size(), 1));
     for (Group &g : b->groups) {
         const size_t np = g.probs.size();
@@ -458,7 +458,13 @@ int upload_tables(nlfem_batch *b, hipStream_t s)
             off = align256(off + sizeof(GaussArgs) * np);
         }
     }
-    std::vector<unsigned char> host(off, 0);
+    return off;
+}
+
+// the host image of the tables (counters zero)
+std::vector<unsigned char> table_image(const nlfem_batch *b, size_t bytes)
+{
+    std::vector<unsigned char> host(bytes, 0);
     for (const Group &g : b->groups) {
         std::memcpy(&host[g.off_pre], g.pre.data(), sizeof(int64_t) * g.pre.size());
         for (size_t j = 0; j < g.probs.size(); ++j) {
@@ -483,6 +489,13 @@ int upload_tables(nlfem_batch *b, hipStream_t s)
             }
         }
     }
+    return host;
+}
+
+int upload_tables(nlfem_batch *b, hipStream_t s)
+{
+    const size_t off = table_layout(b);
+    const std::vector<unsigned char> host = table_image(b, off);
     NLFEM_TRY(dev_alloc(b->mem, off, s));
     b->dev = b->mem.p;
     b->dev_bytes = off;
@@ -712,6 +725,73 @@ int batch_info(const nlfem_batch *b, int32_t *groups, int32_t *shape)
         shape[2 * p] = b->shape[p].chunk;
         shape[2 * p + 1] = b->shape[p].per_cu;
     }
+    return NLFEM_OK;
+}
+
+// ---- the allocation-free one-shot batch
+
+namespace {
+
+// Tables and queue counters of nlfem_assemble_batched_noalloc: one array per
+// device, held until the process ends.  Host code never passes `scratch`
+// itself (a host-side stand-in): it uses the device address taken by
+// hipGetSymbolAddress on each device.
+constexpr size_t kScratchBytes = NLFEM_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices];
+
+int scratch_address(void **out)
+{
+    int dev = -1;
+    NLFEM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(NLFEM_E_INVALID, "device ordinal above 63");
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NLFEM_OK;
+}
+
+}  // namespace
+
+size_t batch_scratch_bytes() { return kScratchBytes; }
+
+int batch_assemble_noalloc(const std::vector<AssemblePlan> &plans, hipStream_t s)
+{
+    void *ptr = nullptr;
+    NLFEM_TRY(scratch_address(&ptr));
+    nlfem_batch b;   // host bookkeeping only: no streams, events or device memory
+    b.n = (int)plans.size();
+    b.plans = plans;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || b.cus < 1)
+        return set_error(NLFEM_E_HIP, "cannot query the compute-unit count");
+    make_groups(&b);
+    const size_t bytes = table_layout(&b);
+    if (bytes > kScratchBytes)
+        return set_error(NLFEM_E_OVERFLOW, "batch tables of " + std::to_string(bytes) +
+                                               " bytes exceed the static workspace of " +
+                                               std::to_string(kScratchBytes) + " bytes");
+    const std::vector<unsigned char> host = table_image(&b, bytes);
+    b.dev = ptr;
+    b.dev_bytes = bytes;
+    b.counters = (unsigned long long *)ptr;
+    NLFEM_HIP(hipMemcpyAsync(ptr, host.data(), bytes, hipMemcpyHostToDevice, s));
+    // the host image is freed on return; the copy reads it before then
+    NLFEM_HIP(hipStreamSynchronize(s));
+    // the counters start at zero (a fill kernel, as in the graph path); all
+    // phases on the caller's stream: touching, non-touching, diagonals, rows
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, b.counters, (int)b.groups.size());
+    NLFEM_TRY(run_phase(&b, kTouch, b.shape[kTouch], s));
+    NLFEM_TRY(run_phase(&b, kFar, b.shape[kFar], s));
+    NLFEM_TRY(run_phase(&b, kDiag, b.shape[kDiag], s));
+    NLFEM_TRY(run_phase(&b, kRows, b.shape[kRows], s));
     return NLFEM_OK;
 }
 
