@@ -275,6 +275,9 @@ int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_q
      5 touching pairs (one kernel)                6 row gather (one kernel)
      7 load vector           8 per-element sums of the non-touching
                                diagonal blocks (one kernel)
+   nlfem_batch_assemble records its phases too (4, 5, 8, 6: one pair of
+   events around the launches of each phase, the touching phase on the
+   batch's second stream); replays of its HIP graph are not timed.
    Enabling creates events (host allocation); nlfem_assemble then still
    allocates no device memory.  Not thread-safe.
    Errors: E_INVALID (mask outside [0, 2^NLFEM_TIMING_PHASES)), E_HIP. */

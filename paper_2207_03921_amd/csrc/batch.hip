@@ -362,18 +362,27 @@ int run_phase(const nlfem_batch *b, Phase ph, const Shape &sh, hipStream_t s)
 }
 
 // far pairs then element diagonals on s; touching pairs on the batch's
-// second stream beside them; rows after the join
-int run_all(const nlfem_batch *b, hipStream_t s)
+// second stream beside them; rows after the join.  `timed`: HIP events of
+// the per-phase timing around each phase on its stream (not while capturing)
+int run_all(const nlfem_batch *b, hipStream_t s, bool timed)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, b->counters, (int)b->groups.size());
     NLFEM_HIP(hipEventRecord(b->ev_fork, s));
     NLFEM_HIP(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
+    if (timed) timing_begin(kPhTouch, b->aux);
     NLFEM_TRY(run_phase(b, kTouch, b->shape[kTouch], b->aux));
+    if (timed) timing_end(kPhTouch, b->aux);
     NLFEM_HIP(hipEventRecord(b->ev_join, b->aux));
+    if (timed) timing_begin(kPhFar, s);
     NLFEM_TRY(run_phase(b, kFar, b->shape[kFar], s));
+    if (timed) timing_end(kPhFar, s);
+    if (timed) timing_begin(kPhDiag, s);
     NLFEM_TRY(run_phase(b, kDiag, b->shape[kDiag], s));
+    if (timed) timing_end(kPhDiag, s);
     NLFEM_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
+    if (timed) timing_begin(kPhRows, s);
     NLFEM_TRY(run_phase(b, kRows, b->shape[kRows], s));
+    if (timed) timing_end(kPhRows, s);
     return NLFEM_OK;
 }
 
@@ -680,7 +689,7 @@ int check_handles(nlfem_batch *b)
 int batch_run(nlfem_batch *b, hipStream_t s)
 {
     NLFEM_TRY(check_handles(b));
-    return run_all(b, s);
+    return run_all(b, s, true);
 }
 
 int batch_graph_launch(nlfem_batch *b, hipStream_t s)
@@ -689,7 +698,7 @@ int batch_graph_launch(nlfem_batch *b, hipStream_t s)
     if (!b->exec) {
         if (!b->capture) NLFEM_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
         NLFEM_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-        const int rc = run_all(b, b->capture);
+        const int rc = run_all(b, b->capture, false);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->capture, &g);
         if (rc != NLFEM_OK) {

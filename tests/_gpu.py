@@ -55,3 +55,16 @@ def rel_frob(A, B):
     nb = np.sqrt((B.multiply(B)).sum()) if sp.issparse(B) else np.linalg.norm(B)
     nd = np.sqrt((d.multiply(d)).sum()) if sp.issparse(d) else np.linalg.norm(d)
     return float(nd / nb)
+
+
+def entrywise(G, A):
+    """Largest entry error of a row relative to the row's largest entry, over
+    all rows: catches an error in small (far-field) entries that the
+    Frobenius norm of the whole matrix would hide under the diagonal."""
+    D = abs(G - A).tocsr()
+    Aa = abs(A).tocsr()
+    dmax = np.asarray(D.max(axis=1).todense()).ravel()
+    amax = np.asarray(Aa.max(axis=1).todense()).ravel()
+    rows = amax > 0
+    assert np.all(dmax[~rows] == 0)
+    return float((dmax[rows] / amax[rows]).max()) if rows.any() else 0.0

@@ -15,7 +15,7 @@ import pytest
 
 from inputs import square_mesh, gauss7, paper7, collapsed
 from inputs.workloads import batched, inv_dist_jittered, peridynamic, c_frac
-from _gpu import make_config, to_sparse, rel_frob
+from _gpu import make_config, to_sparse, rel_frob, entrywise
 
 pytestmark = pytest.mark.gpu
 
@@ -152,7 +152,8 @@ def test_assemble_batched_one_shot():
 def test_batch_full_size_64_problems(oracle_lib, precision):
     """The 64-problem workload (h from 1/32 to 1/160, delta/h in 2..5, half
     constant, half 1/|z|): every problem bit-identical to its single
-    assembly, two problems sampled against the oracle."""
+    assembly, eight problems (both kernels, small to large meshes) sampled
+    against the oracle, row by row and entry by entry."""
     import torch
     import paper_2207_03921_amd as nl
     ws = batched(64, precision=precision)
@@ -162,7 +163,7 @@ def test_batch_full_size_64_problems(oracle_lib, precision):
                               [p["val"] for p in probs], tune=0)
     nl.nlfem_batch_launch_graph(b)
     _assert_same(probs)
-    for i in (1, 2):   # one 1/|z| and one constant-kernel member
+    for i in (1, 2, 13, 22, 35, 44, 57, 62):   # 1/|z| (odd) and constant-kernel (even) members
         w = ws[i]
         P = oracle_lib.Problem(w["mesh"], w)
         dof = np.flatnonzero(P.isdof())
@@ -174,5 +175,7 @@ def test_batch_full_size_64_problems(oracle_lib, precision):
         A = to_sparse(rp, col, val, nv)
         Gs, As = G[rows], A[rows]
         assert np.array_equal(Gs.indptr, As.indptr) and np.array_equal(Gs.indices, As.indices)
-        assert rel_frob(Gs, As) <= (1e-12 if precision == "fp64" else 1e-5)
+        tol = 1e-12 if precision == "fp64" else 1e-5
+        assert rel_frob(Gs, As) <= tol
+        assert entrywise(Gs, As) <= tol
     nl.nlfem_batch_free(b)

@@ -11,7 +11,7 @@ import pytest
 from inputs import square_mesh, gauss7, paper7, collapsed, centroid1
 from inputs.meshes import Mesh
 from inputs.workloads import small_constant, inv_dist_jittered, peridynamic, constant_polygon, c_frac
-from _gpu import gpu_run, to_sparse, rel_frob, f_affine_of
+from _gpu import gpu_run, to_sparse, rel_frob, entrywise, f_affine_of
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +66,39 @@ def _cases():
     }
 
 
+def _fan_mesh(nseg=72, r=0.1):
+    """A node of valence nseg: nseg Omega triangles around the origin, closed
+    by a ring of 2 nseg Omega_D triangles out to radius 2r (only the centre
+    is a degree of freedom)."""
+    ang = 2 * np.pi * np.arange(nseg) / nseg
+    inner = np.stack([r * np.cos(ang), r * np.sin(ang)], 1)
+    outer = np.stack([2 * r * np.cos(ang + np.pi / nseg), 2 * r * np.sin(ang + np.pi / nseg)], 1)
+    V = np.vstack([[[0.0, 0.0]], inner, outer])
+    E, L = [], []
+    for i in range(nseg):
+        j = (i + 1) % nseg
+        E.append([0, 1 + i, 1 + j])
+        L.append(1)
+        E.append([1 + i, 1 + nseg + i, 1 + j])
+        E.append([1 + j, 1 + nseg + i, 1 + nseg + j])
+        L += [2, 2]
+    return Mesh(V, np.array(E, np.int32), np.array(L, np.int32), r, 1, 1)
+
+
+def _long_path_cases():
+    """Meshes whose lists and rows exceed the short-list kernels' sizes: a
+    horizon of 9-10 mesh sizes (neighbour lists above 256 entries: bitonic
+    sort; CSR rows above 256 columns: bitonic row sort), and a node of
+    valence 72 (more than one batch of 64 elements in the row gather, and
+    more than 256 touching entries queued in one batch: the queue is flushed
+    before the batch ends)."""
+    return {
+        "invdist_delta_10h": _w("inv_dist", square_mesh(8, delta=1.25, jitter=0.1, seed=17), 1.25),
+        "peri_delta_9h": _w("peridynamic", square_mesh(6, delta=1.5, jitter=0.1, seed=18), 1.5),
+        "invdist_fan72": _w("inv_dist", _fan_mesh(72), 0.3),
+    }
+
+
 def _ignored_labels_case():
     mesh = square_mesh(12, delta=0.2, jitter=0.1, seed=10)
     lab = mesh.labels.copy()
@@ -88,6 +121,8 @@ def _compare_full(oracle_lib, w, precision):
     G = to_sparse(g["row_ptr"], g["col"], g["val"], n)
     err = rel_frob(G, A)
     assert err <= TOL[precision], err
+    ew = entrywise(G, A)
+    assert ew <= TOL[precision], ew
     b = P.rhs(f_affine=f_affine_of(w))
     assert np.abs(g["b"] - b).max() <= 1e-13 * max(1.0, np.abs(b).max())
     info = g["info"]
@@ -98,6 +133,27 @@ def _compare_full(oracle_lib, w, precision):
     assert info["nnz"] == len(col)
     assert info["n_dof"] == int(P.isdof().sum())
     return err
+
+
+@pytest.mark.parametrize("name", list(_long_path_cases()))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_long_lists_and_rows(oracle_lib, name, precision):
+    w = _long_path_cases()[name]
+    mesh = w["mesh"]
+    print(f"case {name} {precision} K={mesh.n_elements}", flush=True)
+    P = oracle_lib.Problem(mesh, w)
+    k, l, c = P.pairs()
+    rp, col = P.pattern(k, l)
+    seg = np.bincount(np.concatenate([k, l]), minlength=mesh.n_elements)   # >= |S(e)|
+    if name == "invdist_fan72":
+        centre_elems = np.flatnonzero((mesh.elements == 0).any(axis=1))
+        assert len(centre_elems) > 64                                    # two element batches
+        touch_centre = np.isin(k, centre_elems) & (c != 0)
+        assert touch_centre.sum() > 2 * 256                              # touching queue flushed
+    else:
+        assert np.diff(rp).max() > 256 * P.n                             # bitonic row sort
+        assert (seg // 2).max() > 256                                    # bitonic list sort
+    _compare_full(oracle_lib, w, precision)
 
 
 @pytest.mark.parametrize("name", list(_cases()))
@@ -222,7 +278,7 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
     print(f"full {name} {precision} K={mesh.n_elements}", flush=True)
     P = oracle_lib.Problem(mesh, w)
     g = gpu_run(mesh, w, precision=precision)
-    rows = _sample_rows(P, n_rows=16 if name == "poly32_h256" else 48)
+    rows = _sample_rows(P, n_rows=48)
     if precision == "fp64":
         gk, gl, gc = g["pairs"]
         if name == "poly32_h256":
@@ -236,6 +292,16 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
         else:
             k, l, c = P.pairs()
         assert np.array_equal(gk, k) and np.array_equal(gl, l) and np.array_equal(gc, c)
+    elif name == "poly32_h256":
+        # the mixed form decides inclusion in FP64 too: the same pairs meet the
+        # sampled rows' elements
+        gk, gl, gc = g["pairs"]
+        rowsel = np.zeros(mesh.n_vertices, bool)
+        rowsel[rows] = True
+        emask = rowsel[mesh.elements].any(axis=1)
+        k, l, c = P.pairs(elem_mask=emask)
+        keep = emask[gk] | emask[gl]
+        assert np.array_equal(gk[keep], k) and np.array_equal(gl[keep], l) and np.array_equal(gc[keep], c)
     rp, col, val = P.assemble_rows(rows)
     n = P.n
     G = to_sparse(g["row_ptr"], g["col"], g["val"], n * mesh.n_vertices)
@@ -245,6 +311,8 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
     assert np.array_equal(Gs.indptr, As.indptr) and np.array_equal(Gs.indices, As.indices)
     err = rel_frob(Gs, As)
     assert err <= TOL[precision], err
+    ew = entrywise(Gs, As)
+    assert ew <= TOL[precision], ew
     # invariants on the whole GPU matrix
     dofm = np.repeat(P.isdof(), n)
     B = G[dofm][:, dofm]
