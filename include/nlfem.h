@@ -78,8 +78,13 @@ enum {
 /* ball approximations 1_{B(x)}(y) for the Euclidean ball of radius delta */
 enum {
     NLFEM_A_NOCAPS_BARY = 0,     /* T_l counts for x iff |x - bary(T_l)| <= delta */
-    NLFEM_A_APPROXCAPS_POLY = 1  /* regular polygon inscribed in the circle,
+    NLFEM_A_APPROXCAPS_POLY = 1, /* regular polygon inscribed in the circle,
                                     T_l n polygon retriangulated (Sec. 2.4.1) */
+    NLFEM_A_INF_BALL = 2         /* the infinity-norm ball {y : |x - y|_inf <= delta}
+                                    (Def. 2.5): the square with corners
+                                    x + delta (+-1, +-1), T_l n square clipped and
+                                    retriangulated like the polygon, which is exact
+                                    here; polygon_n and polygon_dirs are unused */
 };
 
 /* arithmetic of the quadrature of non-touching pairs */

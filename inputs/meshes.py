@@ -46,27 +46,29 @@ class Mesh:
         return int(self.elements.shape[0])
 
 
-def layer_cells(n: int, delta: float) -> int:
+def layer_cells(n: int, delta: float, side: float = 1.0) -> int:
     """Number of whole cells needed for a layer of width >= delta."""
-    h = 1.0 / n
+    h = side / n
     return int(math.ceil(delta / h - 1e-9))
 
 
 def square_mesh(n: int, delta: float | None = None, m: int | None = None,
                 jitter: float = 0.0, seed: int = 0,
-                neumann: bool = False) -> Mesh:
+                neumann: bool = False, side: float = 1.0) -> Mesh:
     """Uniform right-isosceles mesh of [0,1]^2 plus an interaction layer.
 
     ``n`` cells per side of Omega; the layer width is ``m`` cells (derived
     from ``delta`` when not given).  ``jitter`` is the relative amplitude a
     of the seeded node perturbation.  With ``neumann=True`` every element is
     labelled Omega (the pure-interaction case, base domain = Omega).
+    ``side`` scales the geometry: Omega = [0, side]^2 and h = side / n (the
+    numerical section's square is side = 0.5).
     """
     if m is None:
         if delta is None:
             raise ValueError("give delta or m")
-        m = layer_cells(n, delta)
-    h = 1.0 / n
+        m = layer_cells(n, delta, side)
+    h = side / n
     N = n + 2 * m
     ii, jj = np.meshgrid(np.arange(N + 1), np.arange(N + 1), indexing="ij")
     ii = ii.reshape(-1)

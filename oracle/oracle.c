@@ -33,7 +33,7 @@
 #endif
 
 enum { ORC_K_CONSTANT = 0, ORC_K_INV_DIST = 1, ORC_K_PERIDYNAMIC = 2 };
-enum { ORC_A_BARY = 0, ORC_A_POLY = 1 };
+enum { ORC_A_BARY = 0, ORC_A_POLY = 1, ORC_A_INF = 2 };
 enum { ORC_FAR = 0, ORC_VERTEX = 1, ORC_EDGE = 2, ORC_IDENT = 3 };
 
 typedef struct {
@@ -236,8 +236,12 @@ static int chi_bary(const orc_cfg *cf, const double x[2], const elem_t *l)
 /* Regular N-gon inscribed in the circle of radius delta around x, vertices
  * q_j = x + delta * dir_j (CCW).  Sutherland-Hodgman clip of T_l against its
  * N edges.  A point v is inside edge j iff cross(q_{j+1} - q_j, v - q_j) >= 0;
- * the crossing point of segment a -> b is a + t (b - a), t = d_a/(d_a - d_b). */
+ * the crossing point of segment a -> b is a + t (b - a), t = d_a/(d_a - d_b).
+ * The infinity-norm ball (Def. 2.5) {y : |x - y|_inf <= delta} is the square
+ * with corners x + delta (+-1, +-1), taken counter-clockwise from (+1, +1):
+ * the same clip against its 4 edges is exact. */
 #define MAXPOLY 80
+static const double SQUARE_CORNERS[4][2] = {{1.0, 1.0}, {-1.0, 1.0}, {-1.0, -1.0}, {1.0, -1.0}};
 static int clip_triangle(const orc_cfg *cf, const double x[2], const elem_t *l, double out[][2])
 {
     double buf[2][MAXPOLY][2];
@@ -247,13 +251,15 @@ static int clip_triangle(const orc_cfg *cf, const double x[2], const elem_t *l, 
         buf[0][a][1] = l->v[a][1];
     }
     int cur = 0;
-    const int N = cf->polygon_n;
+    const int square = cf->approach == ORC_A_INF;
+    const int N = square ? 4 : cf->polygon_n;
+    const double *dirs = square ? &SQUARE_CORNERS[0][0] : cf->polygon_dirs;
     for (int j = 0; j < N && cnt > 0; ++j) {
         int j1 = (j + 1) % N;
-        double qa0 = x[0] + cf->delta * cf->polygon_dirs[2 * j + 0];
-        double qa1 = x[1] + cf->delta * cf->polygon_dirs[2 * j + 1];
-        double qb0 = x[0] + cf->delta * cf->polygon_dirs[2 * j1 + 0];
-        double qb1 = x[1] + cf->delta * cf->polygon_dirs[2 * j1 + 1];
+        double qa0 = x[0] + cf->delta * dirs[2 * j + 0];
+        double qa1 = x[1] + cf->delta * dirs[2 * j + 1];
+        double qb0 = x[0] + cf->delta * dirs[2 * j1 + 0];
+        double qb1 = x[1] + cf->delta * dirs[2 * j1 + 1];
         double e0 = qb0 - qa0, e1 = qb1 - qa1;
         int nxt = 1 - cur, m = 0;
         for (int i = 0; i < cnt; ++i) {

@@ -112,7 +112,8 @@ int check_cfg(const nlfem_config *c)
         return set_error(NLFEM_E_INVALID, "unknown kernel");
     if (!is_finite(c->c)) return set_error(NLFEM_E_INVALID, "kernel constant must be finite");
     if (!(c->delta > 0.0) || !is_finite(c->delta)) return set_error(NLFEM_E_INVALID, "delta must be positive");
-    if (c->approach != NLFEM_A_NOCAPS_BARY && c->approach != NLFEM_A_APPROXCAPS_POLY)
+    if (c->approach != NLFEM_A_NOCAPS_BARY && c->approach != NLFEM_A_APPROXCAPS_POLY &&
+        c->approach != NLFEM_A_INF_BALL)
         return set_error(NLFEM_E_INVALID, "unknown ball approach");
     if (c->precision != NLFEM_P_FP64 && c->precision != NLFEM_P_MIXED)
         return set_error(NLFEM_E_INVALID, "unknown precision");
@@ -169,20 +170,29 @@ RuleArgs make_rules(const nlfem_config *c)
 PolyArgs make_poly(const nlfem_config *c)
 {
     PolyArgs p{};
-    if (c->approach != NLFEM_A_APPROXCAPS_POLY) return p;
-    p.N = c->polygon_n;
-    double rmin = 1e300;
-    for (int j = 0; j < p.N; ++j) {
-        p.dir[j][0] = c->polygon_dirs[2 * j];
-        p.dir[j][1] = c->polygon_dirs[2 * j + 1];
+    if (!clipped_ball(c->approach)) return p;
+    if (c->approach == NLFEM_A_INF_BALL) {
+        // Def. 2.5: corners x + delta (+-1, +-1), counter-clockwise from (+1, +1)
+        static const double sq[4][2] = {{1.0, 1.0}, {-1.0, 1.0}, {-1.0, -1.0}, {1.0, -1.0}};
+        p.N = 4;
+        std::memcpy(p.dir, sq, sizeof sq);
+    } else {
+        p.N = c->polygon_n;
+        for (int j = 0; j < p.N; ++j) {
+            p.dir[j][0] = c->polygon_dirs[2 * j];
+            p.dir[j][1] = c->polygon_dirs[2 * j + 1];
+        }
     }
+    double rmin = 1e300, rmax = 0.0;
     for (int j = 0; j < p.N; ++j) {
         const int j1 = (j + 1) % p.N;
         const double ex = p.dir[j1][0] - p.dir[j][0], ey = p.dir[j1][1] - p.dir[j][1];
         const double cr = p.dir[j][0] * p.dir[j1][1] - p.dir[j][1] * p.dir[j1][0];
         rmin = std::min(rmin, cr / std::sqrt(ex * ex + ey * ey));
+        rmax = std::max(rmax, std::sqrt(p.dir[j][0] * p.dir[j][0] + p.dir[j][1] * p.dir[j][1]));
     }
     p.r_in = c->delta * rmin;
+    p.r_out = c->delta * rmax;
     return p;
 }
 
@@ -330,7 +340,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         const bool any = x1 >= x0 && y1 >= y0;
 
         // uniform grid over the barycentres -------------------------------
-        double far = h->delta + rq + (h->approach == NLFEM_A_APPROXCAPS_POLY ? rv : 0.0);
+        // a clipped ball reaches its farthest vertex and any part of T_l
+        const bool clip = clipped_ball(h->approach);
+        double far = (clip ? h->poly.r_out : h->delta) + rq + (clip ? rv : 0.0);
         far = far * (1.0 + 1e-9) + 1e-300;
         h->far_reach = far;
         double reach = std::max(far, h->singular ? 2.0 * rv * (1.0 + 1e-9) : 0.0);
@@ -390,7 +402,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_NELIST, 3 * K, h->ne_list));
     NLFEM_TRY(ensure_typed(h, B_NEFILL, M, h->ne_fill));
     NLFEM_TRY(ensure_typed(h, B_DOFL, M, h->dof_list));
-    if (h->approach == NLFEM_A_APPROXCAPS_POLY) {
+    if (clipped_ball(h->approach)) {
         // h->poly lives as long as the handle, so the copy may run asynchronously
         NLFEM_TRY(ensure_typed(h, B_POLYDIR, 2 * kMaxPoly, h->poly_dir));
         NLFEM_HIP(hipMemcpyAsync(h->poly_dir, h->poly.dir, sizeof(double) * 2 * h->poly.N, hipMemcpyHostToDevice, s));
@@ -625,7 +637,7 @@ bool same_shape(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c
     if (std::memcmp(r.pxi, h->rules.pxi, sizeof r.pxi) || std::memcmp(r.pw, h->rules.pw, sizeof r.pw) ||
         std::memcmp(r.qxi, h->rules.qxi, sizeof r.qxi) || std::memcmp(r.qw, h->rules.qw, sizeof r.qw))
         return false;
-    if (c->approach == NLFEM_A_APPROXCAPS_POLY) {
+    if (clipped_ball(c->approach)) {
         const PolyArgs p = make_poly(c);
         if (p.N != h->poly.N || std::memcmp(p.dir, h->poly.dir, sizeof p.dir)) return false;
     }

@@ -185,7 +185,7 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     p.kernel = h->kernel;
     p.nc = h->ncomp;
     p.fp32 = cfg->precision == NLFEM_P_MIXED;
-    p.poly = h->approach == NLFEM_A_APPROXCAPS_POLY;
+    p.poly = clipped_ball(h->approach);
     p.gauss = g;
     // far records
     FarArgs &a = p.far;

@@ -41,9 +41,17 @@ struct RuleArgs {
 
 struct PolyArgs {
     int32_t N;
-    double r_in;                   // inscribed radius delta cos(pi/N)
+    double r_in;                   // inscribed radius (delta cos(pi/N) for the N-gon)
+    double r_out;                  // largest distance of a polygon vertex from the centre
     double dir[kMaxPoly][2];
 };
+
+// the ball approaches clipped as polygons around each outer point: the
+// inscribed N-gon and the infinity-norm square
+inline bool clipped_ball(int approach)
+{
+    return approach == NLFEM_A_APPROXCAPS_POLY || approach == NLFEM_A_INF_BALL;
+}
 
 struct GaussArgs {
     int32_t n;

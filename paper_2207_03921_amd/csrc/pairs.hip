@@ -707,14 +707,14 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     a.gr = h->gr;
     a.P = h->rules.P;
     a.singular = h->singular;
-    a.poly = h->approach == NLFEM_A_APPROXCAPS_POLY;
+    a.poly = clipped_ball(h->approach);
     a.delta = h->delta;
     a.delta2 = h->delta * h->delta;
     // conservative reach of a non-touching interaction between barycentres
     a.reach2 = h->far_reach * h->far_reach;
     const double rin = h->poly.r_in * (1.0 - 1e-12);
     a.rin2 = rin * rin;
-    const double out = h->delta * (1.0 + 1e-12);
+    const double out = h->poly.r_out * (1.0 + 1e-12);   // the farthest polygon vertex
     a.out2 = out * out;
     a.lcnt = h->lcnt;
     a.maxClip = h->red + 10;

@@ -63,6 +63,13 @@ def _cases():
                                rule=gauss7(), inner=collapsed(2), approach="poly"),
         "invdist_p7_q1": _w("inv_dist", square_mesh(10, delta=0.2, jitter=0.15, seed=16), 0.2,
                             rule=gauss7(), inner=centroid1()),
+        # infinity-norm ball (Def. 2.5): the square clipped exactly
+        "const_inf_h16": _w("constant", square_mesh(16, delta=0.1), 0.1, approach="inf",
+                            c=3.0 / (4.0 * 0.1 ** 4)),
+        "const_inf_paper7_jit": _w("constant", square_mesh(10, delta=0.15, jitter=0.2, seed=19), 0.15,
+                                   rule=paper7(), approach="inf", c=3.0 / (4.0 * 0.15 ** 4)),
+        "invdist_inf": _w("inv_dist", square_mesh(12, delta=0.15, jitter=0.2, seed=20), 0.15, approach="inf"),
+        "peri_inf": _w("peridynamic", square_mesh(10, delta=0.25, jitter=0.1, seed=21), 0.25, approach="inf"),
     }
 
 
@@ -270,10 +277,18 @@ def _sample_rows(P, n_rows=48, seed=0):
     return np.unique(np.concatenate([pick, dof[:2], dof[-2:]]))
 
 
-@pytest.mark.parametrize("name", ["invdist_h64", "peri_h128", "poly32_h256"])
+def _inf_h96():
+    """Constant kernel 3/(4 delta^4) on the infinity-norm ball, h = 1/96,
+    delta = 0.05 (about 44k triangles)."""
+    return _w("constant", square_mesh(96, delta=0.05, jitter=0.1, seed=23), 0.05, approach="inf",
+              c=3.0 / (4.0 * 0.05 ** 4), precision="mixed")
+
+
+@pytest.mark.parametrize("name", ["invdist_h64", "peri_h128", "poly32_h256", "inf_h96"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_parity_full_size_sampled(oracle_lib, name, precision):
-    w = {"invdist_h64": inv_dist_jittered, "peri_h128": peridynamic, "poly32_h256": constant_polygon}[name]()
+    w = {"invdist_h64": inv_dist_jittered, "peri_h128": peridynamic, "poly32_h256": constant_polygon,
+         "inf_h96": _inf_h96}[name]()
     mesh = w["mesh"]
     print(f"full {name} {precision} K={mesh.n_elements}", flush=True)
     P = oracle_lib.Problem(mesh, w)
@@ -281,7 +296,7 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
     rows = _sample_rows(P, n_rows=48)
     if precision == "fp64":
         gk, gl, gc = g["pairs"]
-        if name == "poly32_h256":
+        if name in ("poly32_h256", "inf_h96"):
             # all pairs that meet the sampled rows' elements
             rowsel = np.zeros(mesh.n_vertices, bool)
             rowsel[rows] = True
@@ -292,7 +307,7 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
         else:
             k, l, c = P.pairs()
         assert np.array_equal(gk, k) and np.array_equal(gl, l) and np.array_equal(gc, c)
-    elif name == "poly32_h256":
+    elif name in ("poly32_h256", "inf_h96"):
         # the mixed form decides inclusion in FP64 too: the same pairs meet the
         # sampled rows' elements
         gk, gl, gc = g["pairs"]
