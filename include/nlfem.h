@@ -72,7 +72,11 @@ enum {
 enum {
     NLFEM_K_CONSTANT = 0,    /* Psi = c                       (s = -1)    */
     NLFEM_K_INV_DIST = 1,    /* Psi = c / |x - y|             (s = -1/2)  */
-    NLFEM_K_PERIDYNAMIC = 2  /* Psi = c (x-y)(x-y)^T / |x-y|^3, 2 components */
+    NLFEM_K_PERIDYNAMIC = 2, /* Psi = c (x-y)(x-y)^T / |x-y|^3, 2 components */
+    NLFEM_K_FRAC_HALF = 3    /* Psi = c / |x - y|^3           (s = 1/2: the
+                                fractional-type kernel of Sec. 3.1, constant
+                                c_{1/2,delta} = 1 / (pi delta)); needs
+                                singular_n > 0 */
 };
 
 /* ball approximations 1_{B(x)}(y) for the Euclidean ball of radius delta */
@@ -129,7 +133,8 @@ typedef struct {
                                   regularising transforms on touching pairs
                                   (Sec. 2.4.2); 0 = touching pairs use the
                                   product rule like all others.  Required > 0
-                                  for INV_DIST and PERIDYNAMIC.  0..32. */
+                                  for INV_DIST, PERIDYNAMIC and FRAC_HALF.
+                                  0..32. */
     int32_t precision;         /* NLFEM_P_* */
 } nlfem_config;
 

@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KERNELS = {"constant": 0, "inv_dist": 1, "peridynamic": 2}
+KERNELS = {"constant": 0, "inv_dist": 1, "peridynamic": 2, "frac_half": 3}
 APPROACHES = {"bary": 0, "poly": 1, "inf": 2}   # inf: the square of Def. 2.5
 FAR, VERTEX, EDGE, IDENT = 0, 1, 2, 3
 

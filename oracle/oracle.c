@@ -32,7 +32,7 @@
 #include <omp.h>
 #endif
 
-enum { ORC_K_CONSTANT = 0, ORC_K_INV_DIST = 1, ORC_K_PERIDYNAMIC = 2 };
+enum { ORC_K_CONSTANT = 0, ORC_K_INV_DIST = 1, ORC_K_PERIDYNAMIC = 2, ORC_K_FRAC_HALF = 3 };
 enum { ORC_A_BARY = 0, ORC_A_POLY = 1, ORC_A_INF = 2 };
 enum { ORC_FAR = 0, ORC_VERTEX = 1, ORC_EDGE = 2, ORC_IDENT = 3 };
 
@@ -130,6 +130,7 @@ static void phihat(const double xi[2], double phi[3])
 /*   constant:    c                       (s = -1, Sec. 3.1)           */
 /*   inv_dist:    c / |x - y|             (s = -1/2, Sec. 3.1)         */
 /*   peridynamic: c (x-y)(x-y)^T / |x-y|^3 (Sec. 3.2)                  */
+/*   frac_half:   c / |x - y|^3           (s = 1/2, Sec. 3.1)          */
 
 static void kernel(const orc_cfg *cf, const double x[2], const double y[2], double *out)
 {
@@ -141,6 +142,9 @@ static void kernel(const orc_cfg *cf, const double x[2], const double y[2], doub
         break;
     case ORC_K_INV_DIST:
         out[0] = cf->c / r;
+        break;
+    case ORC_K_FRAC_HALF:
+        out[0] = cf->c / (r * r * r);
         break;
     default: {
         double r3 = r * r * r;

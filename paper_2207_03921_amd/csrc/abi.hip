@@ -108,7 +108,7 @@ int check_mesh(const nlfem_mesh *m)
 int check_cfg(const nlfem_config *c)
 {
     if (!c) return set_error(NLFEM_E_INVALID, "config is NULL");
-    if (c->kernel < NLFEM_K_CONSTANT || c->kernel > NLFEM_K_PERIDYNAMIC)
+    if (c->kernel < NLFEM_K_CONSTANT || c->kernel > NLFEM_K_FRAC_HALF)
         return set_error(NLFEM_E_INVALID, "unknown kernel");
     if (!is_finite(c->c)) return set_error(NLFEM_E_INVALID, "kernel constant must be finite");
     if (!(c->delta > 0.0) || !is_finite(c->delta)) return set_error(NLFEM_E_INVALID, "delta must be positive");
@@ -827,7 +827,7 @@ int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_q
 {
     NLFEM_TRY(check_mesh(mesh));
     if (!cfg) return set_error(NLFEM_E_INVALID, "config is NULL");
-    if (cfg->kernel < NLFEM_K_CONSTANT || cfg->kernel > NLFEM_K_PERIDYNAMIC)
+    if (cfg->kernel < NLFEM_K_CONSTANT || cfg->kernel > NLFEM_K_FRAC_HALF)
         return set_error(NLFEM_E_INVALID, "unknown kernel");
     NLFEM_TRY(check_rule(cfg->outer, "outer"));
     if (!b) return set_error(NLFEM_E_INVALID, "b is NULL");

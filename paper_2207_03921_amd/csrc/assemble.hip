@@ -279,6 +279,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         switch (p.kernel) {
         case NLFEM_K_CONSTANT: touch_dispatch<NLFEM_K_CONSTANT>(p, s); break;
         case NLFEM_K_INV_DIST: touch_dispatch<NLFEM_K_INV_DIST>(p, s); break;
+        case NLFEM_K_FRAC_HALF: touch_dispatch<NLFEM_K_FRAC_HALF>(p, s); break;
         default: touch_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
         }
         timing_end(kPhTouch, s);
@@ -288,6 +289,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         switch (p.kernel) {
         case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(p, s); break;
         case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(p, s); break;
+        case NLFEM_K_FRAC_HALF: far_dispatch<NLFEM_K_FRAC_HALF>(p, s); break;
         default: far_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
         }
         timing_end(kPhFar, s);

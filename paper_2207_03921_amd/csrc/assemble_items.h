@@ -63,7 +63,8 @@ template <int KER>
 struct Ker {
     static constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
     static constexpr int NK = NC == 1 ? 1 : 3;   // stored values of a symmetric NC x NC block
-    static constexpr int D = KER == NLFEM_K_CONSTANT ? 2 : 1;   // homogeneity degree of the integrand
+    // homogeneity degree of the integrand: 2 + the degree of Psi
+    static constexpr int D = KER == NLFEM_K_CONSTANT ? 2 : KER == NLFEM_K_FRAC_HALF ? -1 : 1;
 };
 
 // kernel values; for two components the symmetric block (k00, k01, k11)
@@ -74,6 +75,9 @@ __device__ inline void kernel_eval(T zx, T zy, T c, T *k)
         k[0] = c;
     } else if (KER == NLFEM_K_INV_DIST) {
         k[0] = c * rsq(zx * zx + zy * zy);
+    } else if (KER == NLFEM_K_FRAC_HALF) {
+        const T r = rsq(zx * zx + zy * zy);
+        k[0] = c * r * r * r;
     } else {
         const T r = rsq(zx * zx + zy * zy);
         const T s = c * r * r * r;

@@ -319,11 +319,13 @@ void launch_group(const nlfem_batch *b, const Group &g, const Shape &sh, hipStre
     case kFar:
         if (g.kernel == NLFEM_K_CONSTANT) far_group_k<NLFEM_K_CONSTANT>(b, g, q, sh, s);
         else if (g.kernel == NLFEM_K_INV_DIST) far_group_k<NLFEM_K_INV_DIST>(b, g, q, sh, s);
+        else if (g.kernel == NLFEM_K_FRAC_HALF) far_group_k<NLFEM_K_FRAC_HALF>(b, g, q, sh, s);
         else far_group_k<NLFEM_K_PERIDYNAMIC>(b, g, q, sh, s);
         break;
     case kTouch:
         if (g.kernel == NLFEM_K_CONSTANT) touch_group<NLFEM_K_CONSTANT>(b, g, q, sh, s);
         else if (g.kernel == NLFEM_K_INV_DIST) touch_group<NLFEM_K_INV_DIST>(b, g, q, sh, s);
+        else if (g.kernel == NLFEM_K_FRAC_HALF) touch_group<NLFEM_K_FRAC_HALF>(b, g, q, sh, s);
         else touch_group<NLFEM_K_PERIDYNAMIC>(b, g, q, sh, s);
         break;
     case kDiag: {

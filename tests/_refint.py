@@ -158,3 +158,105 @@ class PairIntegral:
 
         res, _ = quad_vec(f1, 0.0, 1.0, epsrel=epsrel, epsabs=epsabs)
         return self.union, detJ * res
+
+
+class PolarPairIntegral:
+    """The same local matrix by a second route that also covers the
+    hypersingular kernel c |z|^-3 (s = 1/2, Sec. 3.1): for every outer point
+    x the inner integral is taken in polar coordinates y = x + r e(theta).
+    Along a ray the basis differences are affine in r,
+        a_u(x, y) = A_u(x) - r g_u . e,
+    with A_u = phi^k_u(x) - phi^l_u(x) (phi^l extended affinely to x) and g_u
+    the gradient of T_l's basis, so the r-integral over the ray's chord
+    [r1, r2] of T_l is closed-form:
+        int (A_a - r ga)(A_b - r gb) r^(1 - alpha) dr
+    (terms r^p with p = -2, -1, 0 for alpha = 3; log for p = -1).  theta is
+    integrated by 40-point Gauss-Legendre between the directions of T_l's
+    vertices, x by scipy's adaptive quad_vec.  For x inside T_l (identical
+    pairs) A = 0 and r1 = 0."""
+
+    def __init__(self, Vk, Vl, nodes_k, nodes_l, kernel, c):
+        base = PairIntegral(Vk, Vl, nodes_k, nodes_l, "constant", c)
+        self.Vk, self.Vl, self.Gk, self.Gl = base.Vk, base.Vl, base.Gk, base.Gl
+        self.Nl, self.Cl = base.Nl, base.Cl
+        self.union, self.ink, self.inl = base.union, base.ink, base.inl
+        self.identical = sorted(nodes_k) == sorted(nodes_l)
+        self.alpha = {"constant": 0, "inv_dist": 1, "peridynamic": 1, "frac_half": 3}[kernel]
+        self.ncomp = 2 if kernel == "peridynamic" else 1
+        self.c = c
+
+    @staticmethod
+    def _ipow(p, r1, r2):
+        if p == -1:
+            return np.log(r2 / r1)
+        return (r2 ** (p + 1) - r1 ** (p + 1)) / (p + 1)
+
+    def _theta_nodes(self, x):
+        ang = np.arctan2(self.Vl[:, 1] - x[1], self.Vl[:, 0] - x[0])
+        if self.identical:
+            cuts = np.sort(np.mod(ang, 2 * np.pi))
+            cuts = np.concatenate([cuts, [cuts[0] + 2 * np.pi]])
+        else:
+            ref = np.arctan2(*(self.Vl.mean(axis=0) - x)[::-1])
+            rel = np.mod(ang - ref + np.pi, 2 * np.pi) - np.pi
+            cuts = ref + np.sort(rel)
+        th, wt = [], []
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            th.append(0.5 * (hi - lo) * _GX + 0.5 * (hi + lo))
+            wt.append(0.5 * (hi - lo) * _GW)
+        return np.concatenate(th), np.concatenate(wt)
+
+    def inner(self, x):
+        pk = _phi(self.Vk, self.Gk, x)
+        pl = _phi(self.Vl, self.Gl, x)
+        nu = len(self.union)
+        A = np.zeros(nu)
+        Gr = np.zeros((nu, 2))
+        for u in range(nu):
+            fx = pk[self.ink[u]] if self.ink[u] >= 0 else 0.0
+            py = pl[self.inl[u]] if self.inl[u] >= 0 else 0.0
+            A[u] = fx - py
+            if self.inl[u] >= 0:
+                Gr[u] = self.Gl[self.inl[u]]
+        th, wt = self._theta_nodes(x)
+        e = np.stack([np.cos(th), np.sin(th)], axis=1)            # (T, 2)
+        ne = e @ self.Nl.T                                         # (T, 3)
+        gap = self.Cl - self.Nl @ x                                # (3,)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = gap[None, :] / ne
+        r2 = np.min(np.where(ne > 0, t, np.inf), axis=1)
+        r1 = np.max(np.where(ne < 0, t, 0.0), axis=1)
+        r1 = np.maximum(r1, 0.0)
+        keep = r2 > r1
+        th, wt, e, r1, r2 = th[keep], wt[keep], e[keep], r1[keep], r2[keep]
+        ge = e @ Gr.T                                              # (T, nu): g_u . e
+        p0 = 1 - self.alpha
+        if self.identical:
+            assert np.abs(A).max() < 1e-12
+            I0 = I1 = np.zeros_like(r1)
+        else:
+            I0 = self._ipow(p0, r1, r2)
+        I1 = self._ipow(p0 + 1, r1, r2) if not self.identical else I1
+        I2 = self._ipow(p0 + 2, r1, r2)
+        n = self.ncomp
+        out = np.zeros((nu, n, nu, n))
+        for cc in range(n):
+            for dd in range(n):
+                kw = wt if n == 1 else wt * e[:, cc] * e[:, dd]
+                S0 = np.sum(kw * I0)
+                S1 = (kw * I1) @ ge
+                S2 = (ge * (kw * I2)[:, None]).T @ ge
+                out[:, cc, :, dd] += np.outer(A, A) * S0 - (np.outer(A, S1) + np.outer(S1, A)) + S2
+        return self.c * out.reshape(n * nu, n * nu)
+
+    def local(self, epsrel=1e-10, epsabs=0.0):
+        J = np.array([self.Vk[1] - self.Vk[0], self.Vk[2] - self.Vk[0]]).T
+        detJ = abs(np.linalg.det(J))
+
+        def f1(x1):
+            r, _ = quad_vec(lambda x2: self.inner(self.Vk[0] + J @ np.array([x1, x2])), 0.0, 1.0 - x1,
+                            epsrel=epsrel, epsabs=epsabs)
+            return r
+
+        res, _ = quad_vec(f1, 0.0, 1.0, epsrel=epsrel, epsabs=epsabs)
+        return self.union, detJ * res

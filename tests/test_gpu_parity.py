@@ -24,6 +24,8 @@ def _w(kernel, mesh, delta, rule=None, inner=None, singular_n=None, approach="ba
         c = c_frac(-1.0, delta)
     elif kernel == "inv_dist":
         c = c_frac(-0.5, delta)
+    elif kernel == "frac_half":
+        c = c_frac(0.5, delta)
     else:
         c = 6.0 / (np.pi * delta ** 3)
     if singular_n is None:
@@ -70,6 +72,12 @@ def _cases():
                                    rule=paper7(), approach="inf", c=3.0 / (4.0 * 0.15 ** 4)),
         "invdist_inf": _w("inv_dist", square_mesh(12, delta=0.15, jitter=0.2, seed=20), 0.15, approach="inf"),
         "peri_inf": _w("peridynamic", square_mesh(10, delta=0.25, jitter=0.1, seed=21), 0.25, approach="inf"),
+        # fractional-type kernel c/|z|^3 (s = 1/2, Sec. 3.1): hypersingular
+        # touching pairs through the transforms with d = -1
+        "frac_h16": _w("frac_half", square_mesh(16, delta=0.15, jitter=0.2, seed=24), 0.15),
+        "frac_poly": _w("frac_half", square_mesh(12, delta=0.15, jitter=0.15, seed=25), 0.15, approach="poly"),
+        "frac_inf_paper7": _w("frac_half", square_mesh(10, delta=0.2, jitter=0.1, seed=26), 0.2, approach="inf",
+                              rule=paper7()),
     }
 
 
