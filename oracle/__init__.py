@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 KERNELS = {"constant": 0, "inv_dist": 1, "peridynamic": 2, "frac_half": 3}
-APPROACHES = {"bary": 0, "poly": 1, "inf": 2}   # inf: the square of Def. 2.5
+APPROACHES = {"bary": 0, "poly": 1, "inf": 2, "nocaps": 3, "approxcaps": 4}   # Def. 2.5, 2.3, 2.4
 FAR, VERTEX, EDGE, IDENT = 0, 1, 2, 3
 
 

@@ -33,7 +33,7 @@
 #endif
 
 enum { ORC_K_CONSTANT = 0, ORC_K_INV_DIST = 1, ORC_K_PERIDYNAMIC = 2, ORC_K_FRAC_HALF = 3 };
-enum { ORC_A_BARY = 0, ORC_A_POLY = 1, ORC_A_INF = 2 };
+enum { ORC_A_BARY = 0, ORC_A_POLY = 1, ORC_A_INF = 2, ORC_A_NOCAPS = 3, ORC_A_APPROXCAPS = 4 };
 enum { ORC_FAR = 0, ORC_VERTEX = 1, ORC_EDGE = 2, ORC_IDENT = 3 };
 
 typedef struct {
@@ -304,10 +304,145 @@ static double shoelace(const double (*p)[2], int cnt)
     return 0.5 * s;
 }
 
+/* The ball approximations of Def. 2.3 and 2.4 restricted to T_l.
+ * nocaps: the convex hull of all crossings of the circle |y - x| = delta
+ * with element edges.  Between two consecutive crossings (by angle) the arc
+ * runs inside a single element, so the hull's chord between them lies in
+ * that element, no vertex lies in the cut-off cap, and
+ *   T_l n B^ncp(x) = conv(vertices of T_l in the closed disc
+ *                         u crossings of the edges of T_l with the circle).
+ * approxcaps adds, for every arc of the circle inside T_l, its midpoint (the
+ * cap centre).  The region is convex; its boundary is walked counter-
+ * clockwise: along each edge v_i -> v_i+1 the vertex v_i if inside, then
+ * the crossings in order of the edge parameter t, from the roots of
+ *   |v_i - x + t e|^2 = delta^2:  A t^2 + 2 B t + C = 0,
+ *   A = e.e, B = (v_i - x).e, C = |v_i - x|^2 - delta^2, D = B^2 - A C;
+ * leaving the disc (inside -> outside) t = (-B + sqrt D)/A, entering
+ * t = (-B - sqrt D)/A (clamped to [0, 1]), and two crossings on an edge
+ * with both ends outside iff D > 0 and 0 < -B < A.  With approxcaps the cap
+ * centre follows every leaving crossing: the arc from it to the next
+ * entering crossing lies inside T_l, and its midpoint is one of the two
+ * points x +- delta m/|m| on the circle, m = u1 + u2 (u1, u2 the two
+ * crossings minus x; u1 turned by +90 degrees when m = 0): the one deeper
+ * inside T_l, i.e. with the larger smallest edge function
+ * cross(v_i+1 - v_i, y - v_i) (ties to +; this also settles the degenerate
+ * arc of a circle through a vertex, where the two crossings meet).  All
+ * vertices inside: the triangle
+ * itself.  No crossing otherwise: empty (also when the circle lies inside
+ * T_l).  Returns the point count (<= 12). */
+#define MAXCAPS 12
+static int caps_polygon(const orc_cfg *cf, const double x[2], const elem_t *l, double out[][2])
+{
+    const double d2 = cf->delta * cf->delta;
+    const double sa = (l->v[1][0] - l->v[0][0]) * (l->v[2][1] - l->v[0][1]) -
+                      (l->v[2][0] - l->v[0][0]) * (l->v[1][1] - l->v[0][1]);
+    const int ord[3] = {0, sa >= 0.0 ? 1 : 2, sa >= 0.0 ? 2 : 1};
+    double P[3][2];
+    int in[3];
+    for (int i = 0; i < 3; ++i) {
+        P[i][0] = l->v[ord[i]][0];
+        P[i][1] = l->v[ord[i]][1];
+        const double dx = P[i][0] - x[0], dy = P[i][1] - x[1];
+        in[i] = dx * dx + dy * dy <= d2;
+    }
+    if (in[0] && in[1] && in[2]) {   /* the triangle itself, in stored order */
+        for (int i = 0; i < 3; ++i) {
+            out[i][0] = l->v[i][0];
+            out[i][1] = l->v[i][1];
+        }
+        return 3;
+    }
+    double pt[MAXCAPS][2];
+    int kind[MAXCAPS];   /* 0 vertex, 1 entering, 2 leaving */
+    int n = 0, ncross = 0;
+    for (int i = 0; i < 3; ++i) {
+        const int i1 = (i + 1) % 3;
+        if (in[i]) {
+            pt[n][0] = P[i][0];
+            pt[n][1] = P[i][1];
+            kind[n++] = 0;
+        }
+        const double ex = P[i1][0] - P[i][0], ey = P[i1][1] - P[i][1];
+        const double ax = P[i][0] - x[0], ay = P[i][1] - x[1];
+        const double A = ex * ex + ey * ey;
+        const double B = ax * ex + ay * ey;
+        const double C = ax * ax + ay * ay - d2;
+        const double D = B * B - A * C;
+        const double sq = sqrt(D > 0.0 ? D : 0.0);
+        double t[2];
+        int k[2], m = 0;
+        if (in[i] && !in[i1]) {
+            t[0] = (-B + sq) / A;
+            k[0] = 2;
+            m = 1;
+        } else if (!in[i] && in[i1]) {
+            t[0] = (-B - sq) / A;
+            k[0] = 1;
+            m = 1;
+        } else if (!in[i] && !in[i1] && D > 0.0 && -B > 0.0 && -B < A) {
+            t[0] = (-B - sq) / A;
+            t[1] = (-B + sq) / A;
+            k[0] = 1;
+            k[1] = 2;
+            m = 2;
+        }
+        for (int c = 0; c < m; ++c) {
+            const double tc = t[c] < 0.0 ? 0.0 : (t[c] > 1.0 ? 1.0 : t[c]);
+            pt[n][0] = P[i][0] + tc * ex;
+            pt[n][1] = P[i][1] + tc * ey;
+            kind[n++] = k[c];
+            ++ncross;
+        }
+    }
+    if (ncross == 0) return 0;
+    int cnt = 0;
+    for (int j = 0; j < n; ++j) {
+        out[cnt][0] = pt[j][0];
+        out[cnt][1] = pt[j][1];
+        ++cnt;
+        if (cf->approach != ORC_A_APPROXCAPS || kind[j] != 2) continue;
+        int jn = (j + 1) % n;
+        while (kind[jn] != 1) jn = (jn + 1) % n;
+        const double u1x = pt[j][0] - x[0], u1y = pt[j][1] - x[1];
+        const double u2x = pt[jn][0] - x[0], u2y = pt[jn][1] - x[1];
+        double mx = u1x + u2x, my = u1y + u2y;
+        if (mx == 0.0 && my == 0.0) {
+            mx = -u1y;
+            my = u1x;
+        }
+        const double mn = sqrt(mx * mx + my * my);
+        const double ux = cf->delta * (mx / mn), uy = cf->delta * (my / mn);
+        double cand[2][2] = {{x[0] + ux, x[1] + uy}, {x[0] - ux, x[1] - uy}};
+        double depth[2];
+        for (int c = 0; c < 2; ++c) {
+            depth[c] = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                const int i1 = (i + 1) % 3;
+                const double f = (P[i1][0] - P[i][0]) * (cand[c][1] - P[i][1]) -
+                                 (P[i1][1] - P[i][1]) * (cand[c][0] - P[i][0]);
+                if (i == 0 || f < depth[c]) depth[c] = f;
+            }
+        }
+        const int pick = depth[0] >= depth[1] ? 0 : 1;
+        out[cnt][0] = cand[pick][0];
+        out[cnt][1] = cand[pick][1];
+        ++cnt;
+    }
+    return cnt;
+}
+
+static int is_caps(const orc_cfg *cf) { return cf->approach == ORC_A_NOCAPS || cf->approach == ORC_A_APPROXCAPS; }
+
+/* the polygon of T_l n B(x) for the clipped balls (N-gon, square, caps) */
+static int ball_polygon(const orc_cfg *cf, const double x[2], const elem_t *l, double out[][2])
+{
+    return is_caps(cf) ? caps_polygon(cf, x, l, out) : clip_triangle(cf, x, l, out);
+}
+
 static int chi_poly(const orc_cfg *cf, const double x[2], const elem_t *l)
 {
     double out[MAXPOLY][2];
-    int cnt = clip_triangle(cf, x, l, out);
+    int cnt = ball_polygon(cf, x, l, out);
     if (cnt < 3) return 0;
     return fabs(shoelace((const double (*)[2])out, cnt)) > 0.0;
 }
@@ -654,7 +789,7 @@ static int inner_samples(const orc_cfg *cf, const double x[2], const elem_t *l,
         return cnt;
     }
     double poly[MAXPOLY][2];
-    int nv = clip_triangle(cf, x, l, poly);
+    int nv = ball_polygon(cf, x, l, poly);
     if (nv < 3) return 0;
     if (!(fabs(shoelace((const double (*)[2])poly, nv)) > 0.0)) return 0;
     int whole = nv == 3;
@@ -781,7 +916,7 @@ double orc_clip_area(const orc_cfg *cf, const double *x, const orc_mesh *m, int3
     elem_t l;
     double poly[MAXPOLY][2];
     load_elem(m, ll, &l);
-    int cnt = clip_triangle(cf, x, &l, poly);
+    int cnt = ball_polygon(cf, x, &l, poly);
     *cnt_out = cnt;
     if (cnt < 3) return 0.0;
     return shoelace((const double (*)[2])poly, cnt);

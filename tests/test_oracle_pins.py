@@ -715,3 +715,117 @@ def test_inf_ball_convergence_rates_table7(oracle_lib):
         assert abs(got - row[3]) <= 0.05, (rates, [r[3] for r in rows[1:3]])
     for e, row in zip(errs, rows):
         assert 1.5 <= e / row[2] <= 1.8
+
+
+# ----------------------------------------------------------------------
+# the paper's ball approximations (Def. 2.3 nocaps, Def. 2.4 approxcaps)
+
+def _global_hull_area(mesh, x, delta, caps):
+    """Area of the convex hull of the crossings of the circle |y - x| = delta
+    with ALL mesh edges (Def. 2.3), plus the arc midpoints between
+    consecutive crossings (Def. 2.4): the points lie on the circle, so the
+    area is delta^2/2 sum sin(angle gaps).  Written from the definitions,
+    over the whole mesh, with no per-element construction."""
+    V, E = mesh.vertices, mesh.elements
+    edges = {tuple(sorted((int(e[i]), int(e[(i + 1) % 3])))) for e in E for i in range(3)}
+    ang = []
+    for a, b in edges:
+        p, d = V[a], V[b] - V[a]
+        f = p - x
+        A, B, C = d @ d, f @ d, f @ f - delta ** 2
+        D = B * B - A * C
+        if D <= 0:
+            continue
+        for t in ((-B - math.sqrt(D)) / A, (-B + math.sqrt(D)) / A):
+            if 0.0 <= t <= 1.0:
+                y = f + t * d
+                ang.append(math.atan2(y[1], y[0]) % (2 * math.pi))
+    ang = np.unique(np.round(np.sort(ang), 13))
+    if caps:
+        nxt = np.concatenate([ang[1:], [ang[0] + 2 * math.pi]])
+        ang = np.sort(np.concatenate([ang, 0.5 * (ang + nxt)]))
+    gaps = np.diff(np.concatenate([ang, [ang[0] + 2 * math.pi]]))
+    return 0.5 * delta ** 2 * np.sin(gaps).sum()
+
+
+@pytest.mark.parametrize("approach", ["nocaps", "approxcaps"])
+def test_caps_balls_are_the_global_hull(oracle_lib, approach):
+    """The per-element polygons T_l n B(x) of the oracle add up to the area of
+    the hull of Def. 2.3 (resp. 2.4) over the whole mesh, and their area gap
+    to the disc is O(h^2) (Sec. 2.2): factor >= 3 per halving of h."""
+    delta = 0.13
+    rng = np.random.default_rng(5)
+    gaps = []
+    for n in (10, 20, 40):
+        mesh = square_mesh(n, delta=delta, jitter=0.2, seed=31)
+        P = oracle_lib.Problem(mesh, cfg("constant", delta=delta, approach=approach))
+        worst = 0.0
+        for x in rng.uniform(0.2, 0.8, size=(3, 2)):
+            near = np.flatnonzero(np.linalg.norm(mesh.vertices[mesh.elements].mean(axis=1) - x, axis=1)
+                                  < delta + 2 * mesh.h)
+            tot = sum(abs(P.clip_area(x, l)[0]) for l in near)
+            assert abs(tot - _global_hull_area(mesh, x, delta, approach == "approxcaps")) < 1e-15
+            worst = max(worst, math.pi * delta ** 2 - tot)
+        gaps.append(worst)
+    assert gaps[0] / gaps[1] >= 3.0 and gaps[1] / gaps[2] >= 3.0, gaps
+
+
+def _manufactured_l2(oracle_lib, mesh, c_cfg, u, f_affine=None, f_point=None):
+    """Solve the nonlocal Dirichlet problem (Sec. 3, eq.
+    inhomogeneousDirichletData) with g = u on Omega_D and return
+    ||u_h - u||_L2(Omega) by the degree-5 rule."""
+    import scipy.sparse.linalg as spla
+    P = oracle_lib.Problem(mesh, c_cfg)
+    rp, col, val = P.assemble()
+    M = mesh.n_vertices
+    A = sp.csr_matrix((val, col, rp), shape=(M, M))
+    V, E = mesh.vertices, mesh.elements
+    v0 = V[E[:, 0]]
+    J = np.stack([V[E[:, 1]] - v0, V[E[:, 2]] - v0], axis=2)
+    if f_point is not None:
+        X = v0[:, None, :] + np.einsum("kij,pj->kpi", J, c_cfg["outer"].xi)
+        b = P.rhs(f_qp=f_point(X)[..., None])
+    else:
+        b = P.rhs(f_affine=f_affine)
+    dof = P.isdof()
+    U = u(V)
+    Uh = U.copy()
+    Uh[dof] = spla.spsolve(A[dof][:, dof].tocsc(), b[dof] - A[dof][:, ~dof] @ U[~dof])
+    g = gauss7()
+    Xg = v0[:, None, :] + np.einsum("kij,pj->kpi", J, g.xi)
+    lam = np.stack([1 - g.xi[:, 0] - g.xi[:, 1], g.xi[:, 0], g.xi[:, 1]], 1)
+    eh = np.einsum("kv,pv->kp", Uh[E], lam) - u(Xg)
+    det = np.abs(J[:, 0, 0] * J[:, 1, 1] - J[:, 0, 1] * J[:, 1, 0])
+    om = mesh.labels == 1
+    return math.sqrt((det[om, None] * g.w[None, :] * eh[om] ** 2).sum()), int(dof.sum())
+
+
+def test_fractional_approxcaps_convergence_table2(oracle_lib):
+    """Table 2 (golden fixture): s = 1/2, delta = 0.2, approximate caps, the
+    cubic manufactured solution (reproduced by the exact operator, Sec. 3.1)
+    on Omega = (0, 0.5)^2 with h = 0.5/5, 0.5/10, 0.5/20 (element diameters
+    1.41e-1, 7.07e-2, 3.54e-2; 16, 81, 361 dofs as printed): the L2 error
+    decreases at the printed rates 2.13 and 2.01 (within 0.05).  The errors
+    here are about 2.0 times the printed ones at every level (the reported
+    norm and the meshes are not specified further), so the rates are what is
+    pinned; nocaps and the 32-gon give other errors with the same rates."""
+    rows = [list(map(float, l.split())) for l in open(os.path.join(GOLDEN, "table2_fractional_rates.txt"))
+            if l.strip() and not l.startswith("#")]
+    delta = 0.2
+
+    def u(X):
+        return X[..., 0] ** 2 * X[..., 1] + X[..., 1] ** 2
+
+    errs = []
+    for i, n in enumerate((5, 10, 20)):
+        mesh = square_mesh(n, delta=delta, side=0.5)
+        c = cfg("frac_half", c=1.0 / (math.pi * delta), delta=delta, approach="approxcaps", rule=paper7(),
+                singular_n=5)
+        e, ndof = _manufactured_l2(oracle_lib, mesh, c, u, f_affine=[(-2.0, 0.0, -2.0)])
+        assert ndof == int(rows[i][1])
+        errs.append(e)
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    for got, row in zip(rates, rows[1:]):
+        assert abs(got - row[3]) <= 0.05, rates
+    for e, row in zip(errs, rows):
+        assert 1.9 <= e / row[2] <= 2.2, errs
