@@ -84,11 +84,19 @@ enum {
     NLFEM_A_NOCAPS_BARY = 0,     /* T_l counts for x iff |x - bary(T_l)| <= delta */
     NLFEM_A_APPROXCAPS_POLY = 1, /* regular polygon inscribed in the circle,
                                     T_l n polygon retriangulated (Sec. 2.4.1) */
-    NLFEM_A_INF_BALL = 2         /* the infinity-norm ball {y : |x - y|_inf <= delta}
+    NLFEM_A_INF_BALL = 2,        /* the infinity-norm ball {y : |x - y|_inf <= delta}
                                     (Def. 2.5): the square with corners
                                     x + delta (+-1, +-1), T_l n square clipped and
                                     retriangulated like the polygon, which is exact
                                     here; polygon_n and polygon_dirs are unused */
+    NLFEM_A_NOCAPS = 3,          /* Def. 2.3: the convex hull of the crossings of
+                                    the circle |y - x| = delta with the element
+                                    edges; on T_l the hull of its vertices in the
+                                    disc and its edge crossings, retriangulated
+                                    (Sec. 2.4.1) */
+    NLFEM_A_APPROXCAPS = 4       /* Def. 2.4: as NOCAPS plus the centre of every
+                                    circular cap (midpoint of each arc inside an
+                                    element) */
 };
 
 /* arithmetic of the quadrature of non-touching pairs */

@@ -21,12 +21,13 @@ NLFEM_OK = 0
 ERRORS = {-1: "E_INVALID", -2: "E_MESH", -3: "E_NOMEM", -4: "E_HIP", -5: "E_OVERFLOW",
           -6: "E_MISMATCH", -7: "E_NODEVICE"}
 K_CONSTANT, K_INV_DIST, K_PERIDYNAMIC, K_FRAC_HALF = 0, 1, 2, 3
-A_NOCAPS_BARY, A_APPROXCAPS_POLY, A_INF_BALL = 0, 1, 2
+A_NOCAPS_BARY, A_APPROXCAPS_POLY, A_INF_BALL, A_NOCAPS, A_APPROXCAPS = 0, 1, 2, 3, 4
 P_FP64, P_MIXED = 0, 1
 C_FAR, C_VERTEX, C_EDGE, C_IDENT = 0, 1, 2, 3
 
 KERNELS = {"constant": K_CONSTANT, "inv_dist": K_INV_DIST, "peridynamic": K_PERIDYNAMIC, "frac_half": K_FRAC_HALF}
-APPROACHES = {"bary": A_NOCAPS_BARY, "poly": A_APPROXCAPS_POLY, "inf": A_INF_BALL}
+APPROACHES = {"bary": A_NOCAPS_BARY, "poly": A_APPROXCAPS_POLY, "inf": A_INF_BALL, "nocaps": A_NOCAPS,
+              "approxcaps": A_APPROXCAPS}
 PRECISIONS = {"fp64": P_FP64, "mixed": P_MIXED}
 
 

@@ -112,8 +112,7 @@ int check_cfg(const nlfem_config *c)
         return set_error(NLFEM_E_INVALID, "unknown kernel");
     if (!is_finite(c->c)) return set_error(NLFEM_E_INVALID, "kernel constant must be finite");
     if (!(c->delta > 0.0) || !is_finite(c->delta)) return set_error(NLFEM_E_INVALID, "delta must be positive");
-    if (c->approach != NLFEM_A_NOCAPS_BARY && c->approach != NLFEM_A_APPROXCAPS_POLY &&
-        c->approach != NLFEM_A_INF_BALL)
+    if (c->approach < NLFEM_A_NOCAPS_BARY || c->approach > NLFEM_A_APPROXCAPS)
         return set_error(NLFEM_E_INVALID, "unknown ball approach");
     if (c->precision != NLFEM_P_FP64 && c->precision != NLFEM_P_MIXED)
         return set_error(NLFEM_E_INVALID, "unknown precision");
@@ -171,6 +170,12 @@ PolyArgs make_poly(const nlfem_config *c)
 {
     PolyArgs p{};
     if (!clipped_ball(c->approach)) return p;
+    if (c->approach == NLFEM_A_NOCAPS || c->approach == NLFEM_A_APPROXCAPS) {
+        // polygons inside the disc, built from its crossings with the element
+        p.N = 0;
+        p.r_in = p.r_out = c->delta;
+        return p;
+    }
     if (c->approach == NLFEM_A_INF_BALL) {
         // Def. 2.5: corners x + delta (+-1, +-1), counter-clockwise from (+1, +1)
         static const double sq[4][2] = {{1.0, 1.0}, {-1.0, 1.0}, {-1.0, -1.0}, {1.0, -1.0}};
@@ -405,7 +410,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     if (clipped_ball(h->approach)) {
         // h->poly lives as long as the handle, so the copy may run asynchronously
         NLFEM_TRY(ensure_typed(h, B_POLYDIR, 2 * kMaxPoly, h->poly_dir));
-        NLFEM_HIP(hipMemcpyAsync(h->poly_dir, h->poly.dir, sizeof(double) * 2 * h->poly.N, hipMemcpyHostToDevice, s));
+        if (h->poly.N > 0)
+            NLFEM_HIP(hipMemcpyAsync(h->poly_dir, h->poly.dir, sizeof(double) * 2 * h->poly.N, hipMemcpyHostToDevice,
+                                     s));
     }
     if (!spec) {
         // every counter of the rest of the build starts at zero

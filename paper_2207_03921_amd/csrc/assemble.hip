@@ -207,6 +207,7 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     a.V = m->vertices;
     a.dir = h->poly_dir;
     a.N = h->poly.N;
+    a.caps = caps_mode(h->approach);
     a.delta = h->delta;
     a.cap = kMaxPoly + 4;
     a.err = h->err;

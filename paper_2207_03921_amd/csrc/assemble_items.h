@@ -39,6 +39,7 @@
 // meets it twice and adds L each time.
 #pragma once
 
+#include "caps.h"
 #include "nlfem_internal.h"
 
 namespace nlfem {
@@ -168,6 +169,7 @@ struct FarArgs {
     const double *V;
     const double *dir;       // [N][2]
     int32_t N;
+    int32_t caps;            // 1 nocaps, 2 approximate caps (caps.h): polygons from the circle's crossings
     double delta;
     int32_t cap;             // clip buffer length per lane
     int32_t *err;
@@ -360,7 +362,17 @@ __device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, do
         vy[k] = a.V[2 * (int64_t)n + 1];
     }
     int cur = 0;
-    const int cnt = clip_polygon(xo_x, xo_y, vx, vy, a.dir, a.N, a.delta, buf, a.cap, lane, &cur, ovf);
+    int cnt;
+    if (a.caps) {
+        double px[kMaxCaps], py[kMaxCaps];
+        cnt = caps_polygon(xo_x, xo_y, vx, vy, a.delta, a.caps == 2, px, py);
+        for (int i = 0; i < cnt; ++i) {
+            cb(buf, a.cap, lane, 0, 0, i) = px[i];
+            cb(buf, a.cap, lane, 0, 1, i) = py[i];
+        }
+    } else {
+        cnt = clip_polygon(xo_x, xo_y, vx, vy, a.dir, a.N, a.delta, buf, a.cap, lane, &cur, ovf);
+    }
     if (cnt < 3) return;
     const double deti = Ji.x * Ji.w - Ji.y * Ji.z;
     const int Q = inner_b ? r.PB : r.PA;

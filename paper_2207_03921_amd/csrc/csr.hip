@@ -40,6 +40,7 @@ struct CsrArgs {
     // mirror links, run by the link_blocks workgroups after the row_blocks
     // workgroups of the rows
     int64_t K, link_blocks, row_blocks;
+    int32_t wpb;             // waves (rows) per workgroup: fewer when the hash tables are large
     const int32_t *snbr;     // sorted neighbour lists
     int32_t *srec;
 };
@@ -106,9 +107,9 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
     if ((int64_t)blockIdx.x >= a.row_blocks) {
         // the links share the launch: both are latency-bound and independent,
         // and the shorter link items fill the tail of the rows
-        const int64_t ng = (a.K + kWavesPerRowBlock - 1) / kWavesPerRowBlock;
+        const int64_t ng = (a.K + a.wpb - 1) / a.wpb;
         for (int64_t b = blockIdx.x - a.row_blocks; b < xcd_span(ng); b += a.link_blocks) {
-            const int64_t e = xcd_item(b, ng) * kWavesPerRowBlock + w;
+            const int64_t e = xcd_item(b, ng) * a.wpb + w;
             if (e < a.K) link_element(a, e, lane);
         }
         return;
@@ -123,9 +124,9 @@ __global__ void __launch_bounds__(64 * kWavesPerRowBlock) k_csr_rows(CsrArgs a)
     int32_t *pre = pre_w[w];
     const int32_t mask = a.hcap - 1;
     const int64_t nrows = (int64_t)*a.nrows;
-    const int64_t ngroups = (nrows + kWavesPerRowBlock - 1) / kWavesPerRowBlock;
+    const int64_t ngroups = (nrows + a.wpb - 1) / a.wpb;
     for (int64_t b = blockIdx.x; b < xcd_span(ngroups); b += a.row_blocks) {
-        const int64_t item = xcd_item(b, ngroups) * kWavesPerRowBlock + w;
+        const int64_t item = xcd_item(b, ngroups) * a.wpb + w;
         if (item >= nrows) continue;
         const int64_t i = a.rows[item];
         for (int t = lane; t < a.hcap; t += 64) {
@@ -372,13 +373,18 @@ int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool lin
               h->err, h->gate};
     // with links: the last workgroups set the mirror records (once per build)
     a.K = h->K;
-    a.link_blocks = links && h->nS > 0 ? xcd_grid((h->K + kWavesPerRowBlock - 1) / kWavesPerRowBlock) : 0;
-    a.row_blocks = xcd_grid((h->M + kWavesPerRowBlock - 1) / kWavesPerRowBlock);
+    // each wave holds two hash tables of hcap ids; at most 128 KB of LDS per
+    // workgroup (gfx950 has 160 KB per CU): fewer rows per workgroup for
+    // long rows (horizons of many mesh sizes)
+    const size_t per_wave = sizeof(int32_t) * 2 * (size_t)h->hcap;
+    a.wpb = kWavesPerRowBlock;
+    while (a.wpb > 1 && per_wave * a.wpb > ((size_t)128 << 10)) a.wpb >>= 1;
+    a.link_blocks = links && h->nS > 0 ? xcd_grid((h->K + a.wpb - 1) / a.wpb) : 0;
+    a.row_blocks = xcd_grid((h->M + a.wpb - 1) / a.wpb);
     a.snbr = h->snbr;
     a.srec = h->srec;
-    const size_t lds = sizeof(int32_t) * 2 * (size_t)h->hcap * kWavesPerRowBlock;
-    hipLaunchKernelGGL(k_csr_rows, dim3((unsigned)(a.row_blocks + a.link_blocks)), dim3(64 * kWavesPerRowBlock), lds,
-                       s, a);
+    const size_t lds = per_wave * a.wpb;
+    hipLaunchKernelGGL(k_csr_rows, dim3((unsigned)(a.row_blocks + a.link_blocks)), dim3(64 * a.wpb), lds, s, a);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }

@@ -48,9 +48,12 @@ struct PolyArgs {
 
 // the ball approaches clipped as polygons around each outer point: the
 // inscribed N-gon and the infinity-norm square
+// (and the paper's nocaps / approximate caps, whose polygons are built from
+// the circle's crossings with the element instead: caps.h)
 inline bool clipped_ball(int approach)
 {
-    return approach == NLFEM_A_APPROXCAPS_POLY || approach == NLFEM_A_INF_BALL;
+    return approach == NLFEM_A_APPROXCAPS_POLY || approach == NLFEM_A_INF_BALL || approach == NLFEM_A_NOCAPS ||
+           approach == NLFEM_A_APPROXCAPS;
 }
 
 struct GaussArgs {

@@ -24,6 +24,7 @@
 //   x (vertex j = x + delta dir_j), nonzero shoelace area; the clip is only
 //   run when cheap bounds cannot decide (vertices well inside the inscribed
 //   circle: whole; triangle well outside the circumscribed circle: empty).
+#include "caps.h"
 #include "nlfem_internal.h"
 
 #pragma clang fp contract(off)
@@ -47,6 +48,7 @@ struct PairArgs {
     const int32_t *cell_elems;
     int32_t gnx, gny, gr, P;
     int32_t singular, poly;
+    int32_t caps;                  // 1 nocaps, 2 approximate caps (caps.h), 0 polygon clip
     double delta, delta2, reach2, rin2, out2;
     int64_t *lcnt;          // [kLsLast][K1] per-element counts
     unsigned long long *maxClip;   // bound on the vertex count of any straddling clip
@@ -177,7 +179,13 @@ __device__ inline uint32_t poly_quick(double x, double y, const double2 v[3], co
     double d0 = (v[0].x - x) * (v[0].x - x) + (v[0].y - y) * (v[0].y - y);
     double d1 = (v[1].x - x) * (v[1].x - x) + (v[1].y - y) * (v[1].y - y);
     double d2 = (v[2].x - x) * (v[2].x - x) + (v[2].y - y) * (v[2].y - y);
-    if (d0 < a.rin2 && d1 < a.rin2 && d2 < a.rin2) return kWhole;
+    // caps: whole exactly when every vertex lies in the closed disc (the
+    // construction's own test)
+    if (a.caps) {
+        if (d0 <= a.delta2 && d1 <= a.delta2 && d2 <= a.delta2) return kWhole;
+    } else if (d0 < a.rin2 && d1 < a.rin2 && d2 < a.rin2) {
+        return kWhole;
+    }
     if (point_triangle_dist2(x, y, v) > a.out2) return kOut;
     return kUnsure;
 }
@@ -185,6 +193,18 @@ __device__ inline uint32_t poly_quick(double x, double y, const double2 v[3], co
 __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], const PolyArgs &pg,
                                        const PairArgs &a, int *maxcnt)
 {
+    if (a.caps) {
+        const double vx[3] = {v[0].x, v[1].x, v[2].x}, vy[3] = {v[0].y, v[1].y, v[2].y};
+        double px[kMaxCaps], py[kMaxCaps];
+        const int n = caps_polygon(x, y, vx, vy, a.delta, a.caps == 2, px, py);
+        if (n < 3) return kOut;
+        if (n == 3 && px[0] == vx[0] && py[0] == vy[0] && px[1] == vx[1] && py[1] == vy[1] && px[2] == vx[2] &&
+            py[2] == vy[2])
+            return kWhole;
+        if (!(fabs(caps_area(px, py, n)) > 0.0)) return kOut;
+        *maxcnt = max(*maxcnt, n);
+        return kStraddle;
+    }
     const double C = fmax(fabs(x), fabs(y)) + a.delta;
     const double m_out = 1e-9 * C, m_in = 1e-5 * C;   // margins as distances
     const int N = pg.N;
@@ -708,6 +728,7 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     a.P = h->rules.P;
     a.singular = h->singular;
     a.poly = clipped_ball(h->approach);
+    a.caps = caps_mode(h->approach);
     a.delta = h->delta;
     a.delta2 = h->delta * h->delta;
     // conservative reach of a non-touching interaction between barycentres

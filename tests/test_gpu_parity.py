@@ -78,6 +78,17 @@ def _cases():
         "frac_poly": _w("frac_half", square_mesh(12, delta=0.15, jitter=0.15, seed=25), 0.15, approach="poly"),
         "frac_inf_paper7": _w("frac_half", square_mesh(10, delta=0.2, jitter=0.1, seed=26), 0.2, approach="inf",
                               rule=paper7()),
+        # the paper's balls (Def. 2.3 nocaps, Def. 2.4 approximate caps); the
+        # uniform meshes with the vertex rule put points exactly on circles
+        "const_nocaps_h16": _w("constant", square_mesh(16, delta=0.1, jitter=0.1, seed=27), 0.1, approach="nocaps"),
+        "const_nocaps_uniform_paper7": _w("constant", square_mesh(12, delta=0.25), 0.25, approach="nocaps",
+                                          rule=paper7()),
+        "invdist_approxcaps": _w("inv_dist", square_mesh(12, delta=0.15, jitter=0.2, seed=28), 0.15,
+                                 approach="approxcaps"),
+        "frac_approxcaps_table2": _w("frac_half", square_mesh(10, delta=0.2, side=0.5), 0.2, approach="approxcaps",
+                                     rule=paper7()),
+        "peri_approxcaps": _w("peridynamic", square_mesh(10, delta=0.25, jitter=0.1, seed=29), 0.25,
+                              approach="approxcaps"),
     }
 
 
@@ -111,6 +122,9 @@ def _long_path_cases():
         "invdist_delta_10h": _w("inv_dist", square_mesh(8, delta=1.25, jitter=0.1, seed=17), 1.25),
         "peri_delta_9h": _w("peridynamic", square_mesh(6, delta=1.5, jitter=0.1, seed=18), 1.5),
         "invdist_fan72": _w("inv_dist", _fan_mesh(72), 0.3),
+        # 16 mesh sizes: hash tables of 8192 ids, two rows per workgroup in
+        # the symbolic pass
+        "invdist_delta_16h": _w("inv_dist", square_mesh(6, delta=16.0 / 6.0, jitter=0.1, seed=32), 16.0 / 6.0),
     }
 
 
@@ -168,6 +182,8 @@ def test_parity_long_lists_and_rows(oracle_lib, name, precision):
     else:
         assert np.diff(rp).max() > 256 * P.n                             # bitonic row sort
         assert (seg // 2).max() > 256                                    # bitonic list sort
+    if name == "invdist_delta_16h":
+        assert (seg // 2).max() > 1100                                   # hash tables of 8192 ids
     _compare_full(oracle_lib, w, precision)
 
 
@@ -285,6 +301,13 @@ def _sample_rows(P, n_rows=48, seed=0):
     return np.unique(np.concatenate([pick, dof[:2], dof[-2:]]))
 
 
+def _approxcaps_h128():
+    """1/|z| kernel on the approximate-caps ball (Def. 2.4), h = 1/128,
+    delta = 0.03 (about 37k triangles)."""
+    return _w("inv_dist", square_mesh(128, delta=0.03, jitter=0.15, seed=30), 0.03, approach="approxcaps",
+              precision="mixed")
+
+
 def _inf_h96():
     """Constant kernel 3/(4 delta^4) on the infinity-norm ball, h = 1/96,
     delta = 0.05 (about 44k triangles)."""
@@ -292,11 +315,11 @@ def _inf_h96():
               c=3.0 / (4.0 * 0.05 ** 4), precision="mixed")
 
 
-@pytest.mark.parametrize("name", ["invdist_h64", "peri_h128", "poly32_h256", "inf_h96"])
+@pytest.mark.parametrize("name", ["invdist_h64", "peri_h128", "poly32_h256", "inf_h96", "approxcaps_h128"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_parity_full_size_sampled(oracle_lib, name, precision):
     w = {"invdist_h64": inv_dist_jittered, "peri_h128": peridynamic, "poly32_h256": constant_polygon,
-         "inf_h96": _inf_h96}[name]()
+         "inf_h96": _inf_h96, "approxcaps_h128": _approxcaps_h128}[name]()
     mesh = w["mesh"]
     print(f"full {name} {precision} K={mesh.n_elements}", flush=True)
     P = oracle_lib.Problem(mesh, w)
@@ -304,7 +327,7 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
     rows = _sample_rows(P, n_rows=48)
     if precision == "fp64":
         gk, gl, gc = g["pairs"]
-        if name in ("poly32_h256", "inf_h96"):
+        if name in ("poly32_h256", "inf_h96", "approxcaps_h128"):
             # all pairs that meet the sampled rows' elements
             rowsel = np.zeros(mesh.n_vertices, bool)
             rowsel[rows] = True
@@ -315,7 +338,7 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
         else:
             k, l, c = P.pairs()
         assert np.array_equal(gk, k) and np.array_equal(gl, l) and np.array_equal(gc, c)
-    elif name in ("poly32_h256", "inf_h96"):
+    elif name in ("poly32_h256", "inf_h96", "approxcaps_h128"):
         # the mixed form decides inclusion in FP64 too: the same pairs meet the
         # sampled rows' elements
         gk, gl, gc = g["pairs"]

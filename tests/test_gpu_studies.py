@@ -1,0 +1,109 @@
+"""The paper's convergence studies with matrices assembled on the GPU
+(MI355X only): Table 2 (s = 1/2 kernel, approximate caps, Sec. 3.1) and
+Table 7 (infinity-norm ball, Sec. 3.3).  The GPU matrix is solved with scipy
+for the manufactured solution; the rates must match the printed ones (and
+the errors the oracle's, to the assembly tolerance)."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from inputs import square_mesh, gauss7, paper7
+from _gpu import make_config
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    return [list(map(float, l.split())) for l in open(os.path.join(GOLDEN, name))
+            if l.strip() and not l.startswith("#")]
+
+
+def _solve_l2(mesh, w, u, f_affine=None, f_point=None):
+    import torch
+    import paper_2207_03921_amd as nl
+    cfg = make_config(w)
+    dm = nl.DeviceMesh.from_numpy(mesh)
+    pairs = nl.nlfem_build_pairs(dm, cfg)
+    rp, col = nl.nlfem_csr_pattern(pairs)
+    val = nl.nlfem_assemble(dm, cfg, pairs)
+    V, E = mesh.vertices, mesh.elements
+    v0 = V[E[:, 0]]
+    J = np.stack([V[E[:, 1]] - v0, V[E[:, 2]] - v0], axis=2)
+    if f_point is not None:
+        X = v0[:, None, :] + np.einsum("kij,pj->kpi", J, w["outer"].xi)
+        b = nl.nlfem_rhs(dm, cfg, f_qp=torch.as_tensor(np.ascontiguousarray(f_point(X)[..., None]), device="cuda"))
+    else:
+        b = nl.nlfem_rhs(dm, cfg, f_affine=f_affine)
+    torch.cuda.synchronize()
+    nnz = col.shape[0]
+    M = mesh.n_vertices
+    A = sp.csr_matrix((val[:nnz].cpu().numpy(), col.cpu().numpy(), rp.cpu().numpy()), shape=(M, M))
+    b = b.cpu().numpy()
+    nl.nlfem_pairs_free(pairs)
+    dof = np.zeros(M, bool)
+    dof[E[mesh.labels == 1].reshape(-1)] = True
+    dof[E[mesh.labels == 2].reshape(-1)] = False
+    U = u(V)
+    Uh = U.copy()
+    Uh[dof] = spla.spsolve(A[dof][:, dof].tocsc(), b[dof] - A[dof][:, ~dof] @ U[~dof])
+    g = gauss7()
+    Xg = v0[:, None, :] + np.einsum("kij,pj->kpi", J, g.xi)
+    lam = np.stack([1 - g.xi[:, 0] - g.xi[:, 1], g.xi[:, 0], g.xi[:, 1]], 1)
+    eh = np.einsum("kv,pv->kp", Uh[E], lam) - u(Xg)
+    det = np.abs(J[:, 0, 0] * J[:, 1, 1] - J[:, 0, 1] * J[:, 1, 0])
+    om = mesh.labels == 1
+    return math.sqrt((det[om, None] * g.w[None, :] * eh[om] ** 2).sum()), int(dof.sum())
+
+
+def _w(mesh, kernel, c, delta, approach, singular_n):
+    r = paper7()
+    return dict(mesh=mesh, kernel=kernel, c=c, delta=delta, approach=approach, outer=r, inner=r,
+                singular_n=singular_n, precision="fp64")
+
+
+def test_table2_fractional_approxcaps():
+    rows = _rows("table2_fractional_rates.txt")
+    delta = 0.2
+
+    def u(X):
+        return X[..., 0] ** 2 * X[..., 1] + X[..., 1] ** 2
+
+    errs = []
+    for i, n in enumerate((5, 10, 20, 40)):
+        print("table 2, n =", n, flush=True)
+        mesh = square_mesh(n, delta=delta, side=0.5)
+        e, ndof = _solve_l2(mesh, _w(mesh, "frac_half", 1.0 / (math.pi * delta), delta, "approxcaps", 5), u,
+                            f_affine=[(-2.0, 0.0, -2.0)])
+        assert float(f"{ndof:.2e}") == rows[i][1]   # dofs as printed (3 digits)
+        errs.append(e)
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    print("errors", errs, "rates", rates)
+    for got, row in zip(rates, rows[1:]):
+        assert abs(got - row[3]) <= 0.06, rates
+    for e, row in zip(errs, rows):
+        assert 1.9 <= e / row[2] <= 2.2, errs
+
+
+def test_table7_infinity_ball():
+    rows = _rows("table7_inf_ball_rates.txt")
+
+    def u(X):
+        return np.sin(4 * np.pi * X[..., 0]) * np.sin(4 * np.pi * X[..., 1])
+
+    errs = []
+    for n in (5, 10, 20, 40):
+        print("table 7, n =", n, flush=True)
+        delta = 1.0 / n          # two cells of 0.5/n
+        mesh = square_mesh(n, m=2, side=0.5)
+        e, _ = _solve_l2(mesh, _w(mesh, "constant", 3.0 / (4.0 * delta ** 4), delta, "inf", 0), u,
+                         f_point=lambda X: 32 * np.pi ** 2 * u(X))
+        errs.append(e)
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    print("errors", errs, "rates", rates)
+    for got, row in zip(rates, rows[1:]):
+        assert abs(got - row[3]) <= 0.05, rates
