@@ -54,7 +54,7 @@ class _Cfg(C.Structure):
                 ("P", C.c_int32), ("pxi", C.c_void_p), ("pw", C.c_void_p),
                 ("Q", C.c_int32), ("qxi", C.c_void_p), ("qw", C.c_void_p),
                 ("singular_n", C.c_int32), ("gl_x", C.c_void_p),
-                ("gl_w", C.c_void_p)]
+                ("gl_w", C.c_void_p), ("dg", C.c_int32)]
 
 
 _lib = None
@@ -109,6 +109,8 @@ class Problem:
         self.E = np.ascontiguousarray(mesh.elements, dtype=np.int32)
         self.lab = np.ascontiguousarray(mesh.labels, dtype=np.int32)
         self.n = int(cfg.get("ncomp", 1))
+        # discontinuous P1: unknowns 3 k + local vertex of every element
+        self.dg = cfg.get("ansatz", "cg") == "dg"
         outer, inner = cfg["outer"], cfg["inner"]
         self.pxi = np.ascontiguousarray(outer.xi, dtype=np.float64)
         self.pw = np.ascontiguousarray(outer.w, dtype=np.float64)
@@ -128,7 +130,19 @@ class Problem:
                        pn, _ptr(self.pdirs),
                        self.pw.shape[0], _ptr(self.pxi), _ptr(self.pw),
                        self.qw.shape[0], _ptr(self.qxi), _ptr(self.qw),
-                       ns, _ptr(self.glx), _ptr(self.glw))
+                       ns, _ptr(self.glx), _ptr(self.glw), 1 if self.dg else 0)
+
+    @property
+    def n_unknowns(self):
+        """Scalar unknowns per component: vertices (CG) or 3 per element (DG)."""
+        return 3 * self.E.shape[0] if self.dg else self.V.shape[0]
+
+    def unknowns_of(self, k):
+        """Unknown ids of the vertices of elements k ([len(k), 3])."""
+        k = np.asarray(k)
+        if self.dg:
+            return (3 * k.astype(np.int64))[:, None] + np.arange(3)[None, :]
+        return self.E[k]
 
     # -- pairs -------------------------------------------------------
     def pairs(self, elem_mask=None):
@@ -168,6 +182,9 @@ class Problem:
 
     # -- degrees of freedom and pattern --------------------------------
     def isdof(self):
+        if self.dg:
+            # the three unknowns of every Omega element
+            return np.repeat(self.lab == 1, 3)
         M = self.V.shape[0]
         in_omega = np.zeros(M, bool)
         in_dir = np.zeros(M, bool)
@@ -177,7 +194,7 @@ class Problem:
 
     def pattern(self, k, l, rowsel=None):
         """CSR pattern (row_ptr int64 [nM+1], col int32) of the listed pairs."""
-        M = self.V.shape[0]
+        M = self.n_unknowns
         n = self.n
         isdof = self.isdof()
         if rowsel is not None:
@@ -185,7 +202,7 @@ class Problem:
         keys = []
         chunk = 1 << 18
         for s in range(0, len(k), chunk):
-            nodes = np.concatenate([self.E[k[s:s + chunk]], self.E[l[s:s + chunk]]], axis=1)
+            nodes = np.concatenate([self.unknowns_of(k[s:s + chunk]), self.unknowns_of(l[s:s + chunk])], axis=1)
             rows = np.repeat(nodes, 6, axis=1).reshape(-1)
             cols = np.tile(nodes, (1, 6)).reshape(-1)
             ok = isdof[rows]
@@ -226,11 +243,12 @@ class Problem:
         return row_ptr, col, val
 
     def assemble_rows(self, rows):
-        """Rows of the matrix for the given node ids only (sampled check)."""
-        M = self.V.shape[0]
+        """Rows of the matrix for the given node (DG: unknown) ids only
+        (sampled check)."""
+        M = self.n_unknowns
         rowsel = np.zeros(M, bool)
         rowsel[np.asarray(rows)] = True
-        elem_mask = rowsel[self.E].any(axis=1)
+        elem_mask = rowsel[self.unknowns_of(np.arange(self.E.shape[0]))].any(axis=1)
         pairs = self.pairs(elem_mask=elem_mask)
         return self.assemble(pairs=pairs, rowsel=rowsel)
 
@@ -250,7 +268,7 @@ class Problem:
 
     def rhs(self, f_const=None, f_affine=None, f_qp=None):
         n = self.n
-        b = np.zeros(n * self.V.shape[0], np.float64)
+        b = np.zeros(n * self.n_unknowns, np.float64)
         if f_qp is not None:
             fq = np.ascontiguousarray(f_qp, dtype=np.float64)
             aff = None

@@ -55,6 +55,8 @@ typedef struct {
     int32_t singular_n;       /* 0 = product rule on touching pairs too */
     const double *gl_x;       /* [singular_n] Gauss-Legendre nodes on [0,1] */
     const double *gl_w;       /* [singular_n] weights on [0,1] */
+    int32_t dg;               /* 1: discontinuous P1 (three unknowns per element,
+                                 numbered 3k + local vertex), 0: continuous */
 } orc_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -94,6 +96,20 @@ static void load_elem_ordered(const orc_mesh *m, const int32_t order[3], elem_t 
     e->J[1][0] = e->v[1][1] - e->v[0][1];
     e->J[1][1] = e->v[2][1] - e->v[0][1];
     e->absdet = fabs(e->J[0][0] * e->J[1][1] - e->J[0][1] * e->J[1][0]);
+}
+
+/* Discontinuous ansatz (Sec. 1 and 2.3: nlfem assembles CG or DG spaces):
+ * every element carries its own three basis functions, so the union of a
+ * pair's unknowns never merges vertices of different elements.  The node
+ * ids of a loaded element become 3 kk + (stored position of the vertex). */
+static void dg_ids(const orc_mesh *m, int64_t kk, elem_t *e)
+{
+    for (int a = 0; a < 3; ++a) {
+        int slot = 0;
+        for (int s = 0; s < 3; ++s)
+            if (m->elements[3 * kk + s] == e->node[a]) slot = s;
+        e->node[a] = (int32_t)(3 * kk + slot);
+    }
 }
 
 static void to_phys(const elem_t *e, const double xi[2], double x[2])
@@ -865,6 +881,10 @@ static int local_matrix(const orc_mesh *m, const orc_cfg *cf, int64_t kk, int64_
         touch_frames(m, kk, ll, cls, ok, ol);
         load_elem_ordered(m, ok, &k);
         load_elem_ordered(m, ol, &l);
+        if (cf->dg) {
+            dg_ids(m, kk, &k);
+            dg_ids(m, ll, &l);
+        }
         make_union(&k, &l, &u);
         memset(L, 0, sizeof(double) * (size_t)(u.nu * n) * (size_t)(u.nu * n));
         const int ns = cf->singular_n;
@@ -884,6 +904,10 @@ static int local_matrix(const orc_mesh *m, const orc_cfg *cf, int64_t kk, int64_
         /* Alg. 1, second branch: quadrature for kernel truncations */
         load_elem(m, kk, &k);
         load_elem(m, ll, &l);
+        if (cf->dg) {
+            dg_ids(m, kk, &k);
+            dg_ids(m, ll, &l);
+        }
         make_union(&k, &l, &u);
         memset(L, 0, sizeof(double) * (size_t)(u.nu * n) * (size_t)(u.nu * n));
         double *eta = (double *)malloc(sizeof(double) * 2 * (size_t)MAXPOLY * (size_t)cf->Q);
@@ -985,11 +1009,13 @@ int orc_assemble(const orc_mesh *m, const orc_cfg *cf, int64_t npairs, const int
 int orc_rhs(const orc_mesh *m, const orc_cfg *cf, const double *fqp, const double *aff, double *b)
 {
     const int n = cf->ncomp;
-    memset(b, 0, sizeof(double) * (size_t)(n * m->n_vertices));
+    const int64_t nunk = cf->dg ? 3 * m->n_elements : m->n_vertices;
+    memset(b, 0, sizeof(double) * (size_t)(n * nunk));
     for (int64_t kk = 0; kk < m->n_elements; ++kk) {
         if (m->labels[kk] != 1) continue;
         elem_t k;
         load_elem(m, kk, &k);
+        if (cf->dg) dg_ids(m, kk, &k);
         for (int p = 0; p < cf->P; ++p) {
             double x[2], ph[3];
             to_phys(&k, &cf->pxi[2 * p], x);

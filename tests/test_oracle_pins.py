@@ -829,3 +829,46 @@ def test_fractional_approxcaps_convergence_table2(oracle_lib):
         assert abs(got - row[3]) <= 0.05, rates
     for e, row in zip(errs, rows):
         assert 1.9 <= e / row[2] <= 2.2, errs
+
+
+# ----------------------------------------------------------------------
+# discontinuous P1 ansatz (three unknowns per element)
+
+@pytest.mark.parametrize("kernel,singular_n", [("constant", 0), ("inv_dist", 5), ("peridynamic", 5),
+                                                ("constant", 4)])
+def test_dg_matrix_restricts_to_the_cg_matrix(oracle_lib, kernel, singular_n):
+    """A continuous P1 function is a DG function with equal values at shared
+    vertices: with P the injection (node, component) -> (3k + a, component)
+    over all elements k holding the node, P^T A_DG P = A_CG on the CG degrees
+    of freedom (every DG sample and weight is the CG one; the transforms of
+    touching pairs included).  The DG matrix is symmetric with zero row
+    sums (constants: the sum of all DG basis functions is 1)."""
+    mesh = square_mesh(8, delta=0.3, jitter=0.2, seed=3)
+    c_cg = cfg(kernel, c=1.5, delta=0.3, singular_n=singular_n)
+    Pc = oracle_lib.Problem(mesh, c_cg)
+    Pd = oracle_lib.Problem(mesh, dict(c_cg, ansatz="dg"))
+    n = Pc.n
+    rc, cc, vc = Pc.assemble()
+    rd, cd, vd = Pd.assemble()
+    Nc, Nd = n * Pc.n_unknowns, n * Pd.n_unknowns
+    Ac = sp.csr_matrix((vc, cc, rc), shape=(Nc, Nc))
+    Ad = sp.csr_matrix((vd, cd, rd), shape=(Nd, Nd))
+    E = mesh.elements
+    r = [n * (3 * k + a) + c for k in range(E.shape[0]) for a in range(3) for c in range(n)]
+    q = [n * E[k, a] + c for k in range(E.shape[0]) for a in range(3) for c in range(n)]
+    P = sp.csr_matrix((np.ones(len(r)), (r, q)), shape=(Nd, Nc))
+    dof = np.repeat(Pc.isdof(), n)
+    assert abs((P.T @ Ad @ P - Ac).tocsr()[dof]).max() <= 1e-14 * abs(Ac[dof]).max()
+    dd = np.repeat(Pd.isdof(), n)
+    B = Ad[dd][:, dd]
+    assert abs(B - B.T).max() <= 1e-14 * abs(B).max()
+    if n == 1:
+        assert np.abs(Ad @ np.ones(Nd))[dd].max() <= 1e-13 * abs(Ad).max()
+    # rows of Omega_D elements are empty; the load vector has one entry per
+    # DG unknown: sum over an element's three entries = int_T f
+    assert np.all(np.diff(rd)[np.repeat(~Pd.isdof(), n)] == 0)
+    b = Pd.rhs(f_const=[-4.0] * n)
+    area = 0.5 * np.abs(np.cross(mesh.vertices[E[:, 1]] - mesh.vertices[E[:, 0]],
+                                 mesh.vertices[E[:, 2]] - mesh.vertices[E[:, 0]]))
+    bs = b.reshape(-1, 3, n).sum(axis=1)[:, 0]
+    assert np.abs(bs - np.where(mesh.labels == 1, -4.0 * area, 0.0)).max() < 1e-15
