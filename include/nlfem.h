@@ -32,7 +32,10 @@
  *    of the discretisation).
  *  - The matrix is returned in CSR form (Sec. 1: the Python front end returns
  *    CSR) over n*M rows and n*M columns, n = 1 (scalar) or 2
- *    (peridynamics); row/column n*node + component.  Rows of nodes that are
+ *    (peridynamics); row/column n*node + component.  With the
+ *    discontinuous ansatz (cfg.ansatz = NLFEM_ANSATZ_DG) over n*3K rows and
+ *    columns, row/column n*(3k + a) + component; rows of elements outside
+ *    Omega are empty.  Rows of nodes that are
  *    not degrees of freedom are empty.  Column indices ascend within a row;
  *    the pattern holds every entry touched by some interacting element pair,
  *    including numerically zero ones.  Splitting the columns into degrees of
@@ -49,7 +52,7 @@
 extern "C" {
 #endif
 
-#define NLFEM_ABI_VERSION 3
+#define NLFEM_ABI_VERSION 4
 
 /* return codes */
 enum {
@@ -107,6 +110,16 @@ enum {
                            and the global sums stay FP64 */
 };
 
+/* ansatz spaces (Sec. 1, 2.3) */
+enum {
+    NLFEM_ANSATZ_CG = 0,   /* continuous P1: unknown n*node + component */
+    NLFEM_ANSATZ_DG = 1    /* discontinuous P1: three basis functions per
+                              element, unknown n*(3k + a) + component for
+                              vertex a (stored order) of element k; rows for
+                              the elements of Omega; kernels with s < 1/2
+                              only (not NLFEM_K_FRAC_HALF) */
+};
+
 /* pair classes (Sec. 2.3: intersecting pairs are vertex touching, edge
    touching or identical) */
 enum { NLFEM_C_FAR = 0, NLFEM_C_VERTEX = 1, NLFEM_C_EDGE = 2, NLFEM_C_IDENT = 3 };
@@ -144,6 +157,7 @@ typedef struct {
                                   for INV_DIST, PERIDYNAMIC and FRAC_HALF.
                                   0..32. */
     int32_t precision;         /* NLFEM_P_* */
+    int32_t ansatz;            /* NLFEM_ANSATZ_* */
 } nlfem_config;
 
 typedef struct nlfem_pairs nlfem_pairs;   /* opaque, library-owned */
@@ -153,8 +167,8 @@ typedef struct {
                              at least one of them 1 */
     int64_t n_far;        /* ... of class NLFEM_C_FAR */
     int64_t n_vertex, n_edge, n_ident;   /* ... touching classes */
-    int64_t n_dof;        /* degree-of-freedom nodes */
-    int64_t n_rows;       /* n * n_dof non-empty matrix rows */
+    int64_t n_dof;        /* degree-of-freedom nodes (DG: 3 x Omega elements) */
+    int64_t n_rows;       /* n * n_dof matrix rows that may hold entries */
     int64_t nnz;          /* stored entries of the CSR matrix */
     int64_t n_upper_far;  /* unordered non-touching pairs processed by assemble */
     int64_t n_upper_touch;/* unordered touching pairs processed by assemble */
@@ -241,8 +255,8 @@ int nlfem_pairs_info(const nlfem_pairs *pairs, nlfem_pairs_info_t *info);
 int nlfem_pairs_export(const nlfem_pairs *pairs, int32_t *k, int32_t *l,
                        int8_t *cls, void *stream);
 
-/* CSR pattern: row_ptr[n*M + 1] (int64) and col[nnz] (int32), device arrays
-   owned by the caller.  Errors: E_INVALID, E_HIP. */
+/* CSR pattern: row_ptr[n*M + 1] (DG: [n*3K + 1]) (int64) and col[nnz]
+   (int32), device arrays owned by the caller.  Errors: E_INVALID, E_HIP. */
 int nlfem_csr_pattern(const nlfem_pairs *pairs, int64_t *row_ptr, int32_t *col,
                       void *stream);
 
@@ -268,9 +282,11 @@ int nlfem_csr_pattern(const nlfem_pairs *pairs, int64_t *row_ptr, int32_t *col,
 int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg,
                    const nlfem_pairs *pairs, double *val, void *stream);
 
-/* Load vector b[n*M] (device, FP64):
+/* Load vector b[n*M] (DG: b[n*3K]) (device, FP64):
      b_(n i + c) = sum over Omega elements T containing node i of
                    |J_T| sum_p d_p f_c(x_p) phi^_(i)(xi_p)
+   (DG: b_(n(3k + a) + c) = |J_k| sum_p d_p f_c(x_p) phi^_a(xi_p) for the
+   elements of Omega, 0 for the others)
    with the outer rule of `cfg` (Sec. 3, right-hand side (f, v)).  Entries
    of nodes that are not degrees of freedom are returned too.
    f_qp:     device [K][outer.n][n] values at the outer quadrature points, or
@@ -318,7 +334,7 @@ typedef struct nlfem_batch nlfem_batch;   /* opaque, library-owned */
 #define NLFEM_MAX_BATCH 4096
 
 /* Fixes a batch of n problems: meshes[n], cfgs[n] (each as accepted by
-   nlfem_assemble for pairs[i]), pairs[n] (distinct built handles) and
+   nlfem_assemble for pairs[i]; continuous ansatz only), pairs[n] (distinct built handles) and
    vals[n] (device output arrays, nnz of pairs[i] entries, owned by the
    caller).  All of them must stay valid and unchanged while the batch is
    used; the handles' workspaces are used by the batch.

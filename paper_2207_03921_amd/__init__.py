@@ -29,6 +29,7 @@ KERNELS = {"constant": K_CONSTANT, "inv_dist": K_INV_DIST, "peridynamic": K_PERI
 APPROACHES = {"bary": A_NOCAPS_BARY, "poly": A_APPROXCAPS_POLY, "inf": A_INF_BALL, "nocaps": A_NOCAPS,
               "approxcaps": A_APPROXCAPS}
 PRECISIONS = {"fp64": P_FP64, "mixed": P_MIXED}
+ANSATZ = {"cg": 0, "dg": 1}
 
 
 class NlfemError(RuntimeError):
@@ -50,7 +51,7 @@ class _Config(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("c", C.c_double), ("delta", C.c_double),
                 ("approach", C.c_int32), ("polygon_n", C.c_int32), ("polygon_dirs", C.c_void_p),
                 ("outer", _Rule), ("inner", _Rule), ("singular_n", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("ansatz", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -59,7 +60,7 @@ class _Info(C.Structure):
                                          "rebuild", "skipped")]
 
 
-ABI_VERSION = 3   # layout of the structs below
+ABI_VERSION = 4   # layout of the structs below
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 _lib = None
@@ -181,6 +182,7 @@ class Config:
     polygon_dirs: np.ndarray | None = None
     singular_n: int = 0
     precision: str = "fp64"
+    ansatz: str = "cg"
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -191,7 +193,7 @@ class Config:
         # reused while no field was rebound and every table is already a
         # contiguous float64 array (the struct then points at the caller's
         # arrays, so changes made in place are seen)
-        key = (self.kernel, self.c, self.delta, self.approach, self.singular_n, self.precision,
+        key = (self.kernel, self.c, self.delta, self.approach, self.singular_n, self.precision, self.ansatz,
                id(self.outer_xi), id(self.outer_w), id(self.inner_xi), id(self.inner_w), id(self.polygon_dirs))
         cached = self.__dict__.get("_cs")
         if cached is not None and cached[0] == key:
@@ -206,7 +208,7 @@ class Config:
                      None if dirs is None else dirs.ctypes.data,
                      _Rule(ow.shape[0], oxi.ctypes.data, ow.ctypes.data),
                      _Rule(iw.shape[0], ixi.ctypes.data, iw.ctypes.data),
-                     int(self.singular_n), PRECISIONS[self.precision])
+                     int(self.singular_n), PRECISIONS[self.precision], ANSATZ[self.ansatz])
         src = (self.outer_xi, self.outer_w, self.inner_xi, self.inner_w)
         if all(a is b for a, b in zip(arrs, src)) and (dirs is None or dirs is self.polygon_dirs):
             self.__dict__["_cs"] = (key, cs)
@@ -216,10 +218,12 @@ class Config:
 class Pairs:
     """Owner of an nlfem_pairs handle."""
 
-    def __init__(self, ptr: C.c_void_p, ncomp: int, n_vertices: int):
+    def __init__(self, ptr: C.c_void_p, ncomp: int, n_vertices: int, n_unknowns: int | None = None):
         self.ptr = ptr
         self.ncomp = ncomp
         self.n_vertices = n_vertices
+        # scalar unknowns per component: vertices (continuous) or 3 per element
+        self.n_unknowns = n_vertices if n_unknowns is None else n_unknowns
 
     def __del__(self):
         if getattr(self, "ptr", None) and self.ptr.value and _lib is not None:
@@ -239,12 +243,14 @@ def nlfem_build_pairs(mesh: DeviceMesh, cfg: Config, pairs: Pairs | None = None,
     cm, cc = mesh.c_struct(), cfg.c_struct()
     h = C.c_void_p(None if pairs is None else pairs.ptr.value)
     _check(lib().nlfem_build_pairs(C.byref(cm), C.byref(cc), C.byref(h), _stream(stream)))
+    nunk = 3 * int(mesh.elements.shape[0]) if cfg.ansatz == "dg" else int(mesh.vertices.shape[0])
     if pairs is not None:
         pairs.ptr = h
         pairs.ncomp = cfg.ncomp
         pairs.n_vertices = int(mesh.vertices.shape[0])
+        pairs.n_unknowns = nunk
         return pairs
-    return Pairs(h, cfg.ncomp, int(mesh.vertices.shape[0]))
+    return Pairs(h, cfg.ncomp, int(mesh.vertices.shape[0]), nunk)
 
 
 def nlfem_pairs_info(pairs: Pairs) -> dict:
@@ -267,7 +273,7 @@ def nlfem_pairs_export(pairs: Pairs, stream=None):
 def nlfem_csr_pattern(pairs: Pairs, stream=None):
     import torch
     info = nlfem_pairs_info(pairs)
-    rp = torch.empty(pairs.ncomp * pairs.n_vertices + 1, dtype=torch.int64, device="cuda")
+    rp = torch.empty(pairs.ncomp * pairs.n_unknowns + 1, dtype=torch.int64, device="cuda")
     col = torch.empty(max(info["nnz"], 1), dtype=torch.int32, device="cuda")
     _check(lib().nlfem_csr_pattern(pairs.ptr, C.c_void_p(rp.data_ptr()), C.c_void_p(col.data_ptr()),
                                    _stream(stream)))
@@ -289,7 +295,8 @@ def nlfem_rhs(mesh: DeviceMesh, cfg: Config, f_qp=None, f_affine=None, b=None, s
     import torch
     n = cfg.ncomp
     if b is None:
-        b = torch.empty(n * mesh.vertices.shape[0], dtype=torch.float64, device="cuda")
+        nunk = 3 * mesh.elements.shape[0] if cfg.ansatz == "dg" else mesh.vertices.shape[0]
+        b = torch.empty(n * nunk, dtype=torch.float64, device="cuda")
     cm, cc = mesh.c_struct(), cfg.c_struct()
     fq = None if f_qp is None else C.c_void_p(_dev_ptr(f_qp, torch.float64, "f_qp"))
     aff = None
@@ -383,7 +390,7 @@ def assemble(mesh: DeviceMesh, cfg: Config, f_affine=None, stream=None):
     rp, col = nlfem_csr_pattern(pairs, stream=stream)
     val = nlfem_assemble(mesh, cfg, pairs, stream=stream)
     nnz = col.shape[0]
-    N = cfg.ncomp * mesh.vertices.shape[0]
+    N = cfg.ncomp * (3 * mesh.elements.shape[0] if cfg.ansatz == "dg" else mesh.vertices.shape[0])
     A = torch.sparse_csr_tensor(rp, col, val[:nnz], size=(N, N))
     if f_affine is None:
         f_affine = [(0.0, 0.0, 0.0)] * cfg.ncomp

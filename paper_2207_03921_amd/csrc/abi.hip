@@ -28,7 +28,7 @@ enum Buf : int {
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
     B_SNBR, B_SFLAG, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
     B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_SPEC,
-    B_NCODE, B_CODECNT, B_CODESTART, B_CODEFILL, B_CAND, B_SCROFF, B_LAST
+    B_NCODE, B_CODECNT, B_CODESTART, B_CODEFILL, B_CAND, B_SCROFF, B_DGCNT, B_DGPTR, B_LAST
 };
 static_assert(B_LAST <= (int)(sizeof(nlfem_pairs::bufs) / sizeof(nlfem_pairs::bufs[0])), "too few buffer slots");
 
@@ -118,6 +118,12 @@ int check_cfg(const nlfem_config *c)
         return set_error(NLFEM_E_INVALID, "unknown precision");
     if (c->singular_n < 0 || c->singular_n > kMaxGauss)
         return set_error(NLFEM_E_INVALID, "singular_n must be in [0, 32]");
+    if (c->ansatz != NLFEM_ANSATZ_CG && c->ansatz != NLFEM_ANSATZ_DG)
+        return set_error(NLFEM_E_INVALID, "unknown ansatz");
+    if (c->ansatz == NLFEM_ANSATZ_DG && c->kernel == NLFEM_K_FRAC_HALF)
+        return set_error(NLFEM_E_INVALID,
+                         "the discontinuous ansatz needs a kernel with s < 1/2 (c/|z|^3 is not integrable across a "
+                         "shared edge for discontinuous functions)");
     if (c->kernel != NLFEM_K_CONSTANT && c->singular_n == 0)
         return set_error(NLFEM_E_INVALID, "singular kernels need singular_n > 0 on touching pairs");
     NLFEM_TRY(check_rule(c->outer, "outer"));
@@ -276,6 +282,44 @@ ZeroList build_counters(nlfem_pairs *h)
     return z;
 }
 
+// Rest of a plain build for the discontinuous ansatz, after the lists: the
+// mirror links, the element blocks of every row block and their prefix sums
+// (the pattern follows from the sorted lists, so there is no symbolic pass),
+// and the assembly's workspace.
+int build_dg_rest(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
+{
+    const int64_t K = h->K;
+    unsigned long long *red = h->rb;
+    NLFEM_TRY(ensure_typed(h, B_DGCNT, K, h->dg_cnt));
+    NLFEM_TRY(ensure_typed(h, B_DGPTR, K + 1, h->dg_ptr));
+    timing_begin(kPhCsr, s);
+    NLFEM_TRY(launch_csr_rows(h, m, s, true, false));
+    NLFEM_TRY(launch_dg_counts(h, s));
+    NLFEM_TRY(exclusive_scan(h->dg_cnt, h->dg_ptr, K, h->scan_w[3], s, (int64_t *)(h->red + kRedNnz),
+                             (int64_t *)(h->red + kRedMaxRow), h->gate));
+    timing_end(kPhCsr, s);
+    NLFEM_TRY(read_slots(h, s));
+    const int32_t err = (int32_t)(red[kRedErr] & 0xffffffffull);
+    if (err & kErrEdge) return set_error(NLFEM_E_MESH, "an edge is shared by more than two elements");
+    if (err) return set_error(NLFEM_E_OVERFLOW, "internal capacity exceeded during the pair search");
+    const int64_t blocks = (int64_t)red[kRedNnz];
+    if (9 * blocks * h->ncomp * h->ncomp >= (int64_t)INT32_MAX * 64)
+        return set_error(NLFEM_E_OVERFLOW, "matrix too large");
+    h->nnz_node = 9 * blocks;   // nnz = nnz_node * n^2
+    h->n_dof = 3 * (int64_t)red[kRedDgDofs];
+    h->max_row = 3 * (int64_t)red[kRedMaxRow];
+    h->far_stride = far_record_stride(h->ncomp);
+    h->touch_stride = touch_record_stride(h->ncomp, true);
+    double *far_rec = nullptr;
+    NLFEM_TRY(ensure_typed(h, B_FARREC, h->nUF * h->far_stride, far_rec));
+    h->far_rec = far_rec;
+    NLFEM_TRY(ensure_typed(h, B_TOUCHREC, h->nUT * h->touch_stride, h->touch_rec));
+    NLFEM_TRY(ensure_typed(h, B_DSUM, K * 6 * (h->ncomp == 1 ? 1 : 3), h->dsum));
+    h->spec_ok = false;   // rebuilds of the discontinuous ansatz are plain builds
+    ++h->generation;
+    return NLFEM_OK;
+}
+
 // Builds the pair structures.  The plain build reads the reduction slots
 // back three times to size buffers and launches.  A speculative rebuild
 // (spec: same sizes and configuration as the handle's last build) launches
@@ -299,6 +343,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->ncomp = ncomp_of(cfg->kernel);
     h->approach = cfg->approach;
     h->singular = cfg->singular_n > 0;
+    h->dg = cfg->ansatz == NLFEM_ANSATZ_DG;
     h->delta = cfg->delta;
     h->rules = make_rules(cfg);
     h->poly = make_poly(cfg);
@@ -386,7 +431,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     {
         // the four scans of a build (cleared with the counters)
         const int64_t tiles[4] = {scan_tiles(M) + scan_tiles(ncell) + scan_tiles(ncode), scan_tiles(K),
-                                  scan_tiles(K, kLsLast), scan_tiles(M)};
+                                  scan_tiles(K, kLsLast), scan_tiles(std::max(M, K))};
         int64_t words = 0;
         for (int c = 0; c < 4; ++c) words += 1 + tiles[c];
         NLFEM_TRY(ensure_typed(h, B_SCAN, words, h->scan_tmp));
@@ -490,6 +535,8 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(launch_sort_lists(h, s));
     timing_end(kPhLists, s);
 
+    if (h->dg) return build_dg_rest(h, m, s);
+
     // CSR pattern -------------------------------------------------------------
     int hcap = 64;
     while (hcap < 4 * (h->max_S + 8) && hcap < 16384) hcap <<= 1;
@@ -535,7 +582,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
 
     // workspace of the assembly: one result record per unordered pair
     h->far_stride = far_record_stride(h->ncomp);
-    h->touch_stride = touch_record_stride(h->ncomp);
+    h->touch_stride = touch_record_stride(h->ncomp, false);
     double *far_rec = nullptr;
     NLFEM_TRY(ensure_typed(h, B_FARREC, h->nUF * h->far_stride, far_rec));
     h->far_rec = far_rec;
@@ -639,6 +686,7 @@ bool same_shape(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c
     if (h->M != m->n_vertices || h->K != m->n_elements) return false;
     if (h->kernel != c->kernel || h->approach != c->approach || h->delta != c->delta) return false;
     if (h->singular != (c->singular_n > 0)) return false;
+    if (h->dg != (c->ansatz == NLFEM_ANSATZ_DG)) return false;
     const RuleArgs r = make_rules(c);
     if (r.P != h->rules.P || r.Q != h->rules.Q) return false;
     if (std::memcmp(r.pxi, h->rules.pxi, sizeof r.pxi) || std::memcmp(r.pw, h->rules.pw, sizeof r.pw) ||
@@ -757,7 +805,7 @@ int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pai
     }
     // after a rebuild that found other sizes the mesh has probably changed:
     // build plainly
-    const bool spec = !fresh && held && h->spec_ok && same_shape(h, mesh, cfg);
+    const bool spec = !fresh && held && h->spec_ok && same_shape(h, mesh, cfg) && cfg->ansatz == NLFEM_ANSATZ_CG;
     int rc = build(mesh, cfg, h, (hipStream_t)stream, spec);
     h->last_build = spec ? 1 : 0;
     if (rc != NLFEM_OK) {
@@ -804,6 +852,7 @@ int nlfem_csr_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, void
     if (h) NLFEM_TRY(resolve(const_cast<nlfem_pairs *>(h)));
     if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle is NULL or not built");
     if (!row_ptr || (h->nnz_node > 0 && !col)) return set_error(NLFEM_E_INVALID, "NULL output array");
+    if (h->dg) return launch_dg_pattern(h, row_ptr, col, (hipStream_t)stream);
     return launch_pattern(h, row_ptr, col, (hipStream_t)stream);
 }
 
@@ -845,7 +894,10 @@ int nlfem_rhs(const nlfem_mesh *mesh, const nlfem_config *cfg, const double *f_q
             if (!is_finite(f_affine[t])) return set_error(NLFEM_E_INVALID, "f_affine not finite");
     NLFEM_TRY(check_device());
     timing_begin(kPhRhs, (hipStream_t)stream);
-    const int rc = launch_rhs(mesh, make_rules(cfg), nc, f_qp, f_affine, b, (hipStream_t)stream);
+    if (cfg->ansatz != NLFEM_ANSATZ_CG && cfg->ansatz != NLFEM_ANSATZ_DG)
+        return set_error(NLFEM_E_INVALID, "unknown ansatz");
+    const int rc = launch_rhs(mesh, make_rules(cfg), nc, f_qp, f_affine, b, (hipStream_t)stream,
+                              cfg->ansatz == NLFEM_ANSATZ_DG);
     timing_end(kPhRhs, (hipStream_t)stream);
     return rc;
 }
@@ -947,6 +999,7 @@ int batch_plans(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, n
             return set_error(NLFEM_E_MISMATCH, "problem " + std::to_string(i) +
                                                    ": mesh or configuration differs from the one its pairs were built for");
         if (dev != h->device) return set_error(NLFEM_E_MISMATCH, "current device differs from a build device");
+        if (h->dg) return set_error(NLFEM_E_INVALID, "batches take problems of the continuous ansatz");
         for (int j = 0; j < i; ++j)
             if (pairs[j] == h) return set_error(NLFEM_E_INVALID, "a pairs handle appears twice (shared workspace)");
         GaussArgs g{};

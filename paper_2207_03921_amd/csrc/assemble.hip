@@ -266,12 +266,25 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
 }  // namespace items
 
 int far_record_stride(int ncomp) { return ncomp == 1 ? 21 : 63; }
-int touch_record_stride(int ncomp) { return (5 * ncomp) * (5 * ncomp + 1) / 2; }
+// packed symmetric local matrices over the union of the pair's unknowns:
+// at most 5 nodes (continuous) or 6 unknowns (discontinuous) per component
+int touch_record_stride(int ncomp, bool dg)
+{
+    const int d = (dg ? 6 : 5) * ncomp;
+    return d * (d + 1) / 2;
+}
 
 int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
                     double *val, hipStream_t s)
 {
-    const AssemblePlan p = make_plan(h, m, cfg, g, val);
+    AssemblePlan p = make_plan(h, m, cfg, g, val);
+    if (h->dg) {
+        // discontinuous ansatz: the identical pairs by the reduced transforms
+        // here, edge and vertex pairs by the 4D transforms of dg.hip
+        p.touch[1].n = 0;
+        p.touch[2].n = 0;
+        NLFEM_TRY(launch_dg_assemble_rest(h, m, cfg, g, val, s));
+    }
     const bool has_touch = p.touch[0].n + p.touch[1].n + p.touch[2].n > 0;
     // one stream: a second stream for the touching pairs costs more in the
     // two cross-queue waits than their overlap with the far records gains
@@ -308,6 +321,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
             else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, p.diag);
         }
         timing_end(kPhDiag, s);
+        if (h->dg) return launch_dg_rows(h, cfg, val, s);
         const size_t lds = row_lds_bytes(p.rows.maxlen, nc, p.rows.hcap);
         const unsigned grid = xcd_grid(p.rows.nrows);
         timing_begin(kPhRows, s);

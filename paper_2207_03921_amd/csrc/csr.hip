@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(64) k_export(int64_t K, const int64_t *sptr, c
 
 }  // namespace
 
-int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool links)
+int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool links, bool rows)
 {
     CsrArgs a{m->elements, h->dof_list, h->red + kRedDofs, h->ne_ptr, h->ne_list,
               h->loff + (int64_t)kLsS * (h->K + 1), h->snode, h->hcap, csr_slot(h->hcap), h->csr_stage, h->nlen,
@@ -380,7 +380,9 @@ int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool lin
     a.wpb = kWavesPerRowBlock;
     while (a.wpb > 1 && per_wave * a.wpb > ((size_t)128 << 10)) a.wpb >>= 1;
     a.link_blocks = links && h->nS > 0 ? xcd_grid((h->K + a.wpb - 1) / a.wpb) : 0;
-    a.row_blocks = xcd_grid((h->M + a.wpb - 1) / a.wpb);
+    a.row_blocks = rows ? xcd_grid((h->M + a.wpb - 1) / a.wpb) : 0;   // links only: rows of the
+                                                                        // discontinuous ansatz come from dg.hip
+    if (a.row_blocks + a.link_blocks == 0) return NLFEM_OK;
     a.snbr = h->snbr;
     a.srec = h->srec;
     const size_t lds = per_wave * a.wpb;

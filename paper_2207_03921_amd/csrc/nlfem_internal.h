@@ -62,11 +62,12 @@ struct GaussArgs {
 };
 
 // Slots of the reduction buffer (u64 each), read back in one copy:
-//   0-3 bounding-box keys, 4-5 radii, 6 candidate total, 7 unused, 8 dof count, 9 longest
+//   0-3 bounding-box keys, 4-5 radii, 6 candidate total, 7 elements of Omega
+//   (discontinuous ansatz), 8 dof count, 9 longest
 //   CSR row, 10 polygon clip bound, 11 CSR nnz, 12-17 totals of the
 //   per-element pair counts, 18 error bits (int32), 19-24 largest
 //   per-element pair counts (19: largest |S(e)|)
-enum { kRedCounts = 6, kRedCand = 6, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
+enum { kRedCounts = 6, kRedCand = 6, kRedDgDofs = 7, kRedDofs = 8, kRedMaxRow = 9, kRedClip = 10, kRedNnz = 11,
        kRedTot = 12, kRedErr = 18, kRedSegMax = 19, kRedSlots = 32 };
 
 // Deep copy of a configuration (its host tables), for a build that may have
@@ -166,6 +167,7 @@ struct nlfem_pairs {
     int64_t M = 0, K = 0;
     int32_t ncomp = 1;
     int32_t kernel = 0, approach = 0, singular = 0;
+    int32_t dg = 0;              // discontinuous ansatz
     double delta = 0.0;
     nlfem::RuleArgs rules{};
     nlfem::PolyArgs poly{};
@@ -262,6 +264,9 @@ struct nlfem_pairs {
     double *dsum = nullptr;      // [K][6 * NK] summed element-diagonal blocks of the far pairs
     double *poly_dir = nullptr;  // [N][2] polygon directions (approach POLY)
     int32_t far_stride = 0, touch_stride = 0;
+    // discontinuous ansatz: element blocks of each row block and their prefix
+    int64_t *dg_cnt = nullptr;   // [K]
+    int64_t *dg_ptr = nullptr;   // [K + 1]
     hipEvent_t ev_rb = nullptr;    // completion of a read-back of the reduction slots
     // assemblies queued while a rebuild was unchecked, and those of them
     // whose work was skipped because the rebuild found other sizes
@@ -377,18 +382,24 @@ int launch_sort_lists(nlfem_pairs *h, hipStream_t s);
 inline int32_t csr_slot(int32_t hcap) { return hcap / 4 * 3; }
 // -> nlen, stage, max row; with links also the mirror records of the lower
 // neighbour-list entries (after the list sort)
-int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool links);
+int launch_csr_rows(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, bool links, bool rows = true);
 // stage -> ncol; with slots_out (pinned host) also copies the reduction slots
 int launch_csr_pack(nlfem_pairs *h, hipStream_t s, unsigned long long *slots_out = nullptr);
 int launch_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
 int launch_export(const nlfem_pairs *h, int32_t *k, int32_t *l, int8_t *cls, hipStream_t s);
 // assemble.hip
 int far_record_stride(int ncomp);     // values per non-touching pair record
-int touch_record_stride(int ncomp);   // values per touching pair record
+int touch_record_stride(int ncomp, bool dg);   // values per touching pair record
+// dg.hip: discontinuous ansatz
+int launch_dg_counts(nlfem_pairs *h, hipStream_t s);
+int launch_dg_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
+int launch_dg_assemble_rest(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
+                            double *val, hipStream_t s);
+int launch_dg_rows(const nlfem_pairs *h, const nlfem_config *cfg, double *val, hipStream_t s);
 int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg,
                     const GaussArgs &g, double *val, hipStream_t s);
 // rhs.hip
 int launch_rhs(const nlfem_mesh *m, const RuleArgs &r, int ncomp, const double *f_qp,
-               const double *f_affine, double *b, hipStream_t s);
+               const double *f_affine, double *b, hipStream_t s, bool dg = false);
 
 }  // namespace nlfem

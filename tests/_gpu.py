@@ -11,7 +11,8 @@ def make_config(w, **over):
     d = dict(kernel=w["kernel"], c=float(w["c"]), delta=float(w["delta"]),
              outer_xi=w["outer"].xi, outer_w=w["outer"].w, inner_xi=w["inner"].xi,
              inner_w=w["inner"].w, approach=w.get("approach", "bary"),
-             singular_n=int(w.get("singular_n", 0)), precision=w.get("precision", "fp64"))
+             singular_n=int(w.get("singular_n", 0)), precision=w.get("precision", "fp64"),
+             ansatz=w.get("ansatz", "cg"))
     if d["approach"] == "poly":
         d["polygon_dirs"] = polygon_dirs(int(w.get("polygon_n", 32)))
     d.update(over)

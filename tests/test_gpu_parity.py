@@ -145,7 +145,7 @@ def _compare_full(oracle_lib, w, precision):
     gk, gl, gc = g["pairs"]
     assert np.array_equal(gk, k) and np.array_equal(gl, l) and np.array_equal(gc, c), "pair list"
     assert np.array_equal(g["row_ptr"], rp) and np.array_equal(g["col"], col), "CSR pattern"
-    n = P.n * mesh.n_vertices
+    n = P.n * P.n_unknowns
     A = to_sparse(rp, col, val, n)
     G = to_sparse(g["row_ptr"], g["col"], g["val"], n)
     err = rel_frob(G, A)
@@ -185,6 +185,40 @@ def test_parity_long_lists_and_rows(oracle_lib, name, precision):
     if name == "invdist_delta_16h":
         assert (seg // 2).max() > 1100                                   # hash tables of 8192 ids
     _compare_full(oracle_lib, w, precision)
+
+
+def _dg_cases():
+    """Discontinuous P1 ansatz (three unknowns per element): far pairs of
+    every ball, touching pairs of singular kernels by the 4D transforms."""
+    return {
+        "dg_const_bary": _w("constant", square_mesh(10, delta=0.2, jitter=0.2, seed=33), 0.2, ansatz="dg"),
+        "dg_invdist": _w("inv_dist", square_mesh(10, delta=0.2, jitter=0.2, seed=34), 0.2, ansatz="dg"),
+        "dg_peri": _w("peridynamic", square_mesh(8, delta=0.3, jitter=0.1, seed=35), 0.3, ansatz="dg"),
+        "dg_const_poly": _w("constant", square_mesh(10, delta=0.15, jitter=0.1, seed=36), 0.15, approach="poly",
+                            ansatz="dg"),
+        "dg_invdist_approxcaps": _w("inv_dist", square_mesh(10, delta=0.2, jitter=0.15, seed=37), 0.2,
+                                    approach="approxcaps", ansatz="dg", rule=paper7()),
+        "dg_const_duffy": _w("constant", square_mesh(8, delta=0.25, jitter=0.2, seed=38), 0.25, singular_n=4,
+                             ansatz="dg"),
+    }
+
+
+@pytest.mark.parametrize("name", list(_dg_cases()))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_dg(oracle_lib, name, precision):
+    w = _dg_cases()[name]
+    print(f"case {name} {precision}", flush=True)
+    _compare_full(oracle_lib, w, precision)
+
+
+def test_dg_rejects_fractional_kernel():
+    import paper_2207_03921_amd as nl
+    from _gpu import make_config
+    mesh = square_mesh(6, delta=0.3)
+    w = _w("frac_half", mesh, 0.3, ansatz="dg")
+    with pytest.raises(nl.NlfemError) as e:
+        nl.nlfem_build_pairs(nl.DeviceMesh.from_numpy(mesh), make_config(w))
+    assert e.value.code == -1 and "discontinuous" in str(e.value)
 
 
 @pytest.mark.parametrize("name", list(_cases()))
