@@ -116,8 +116,12 @@ enum {
     NLFEM_ANSATZ_DG = 1    /* discontinuous P1: three basis functions per
                               element, unknown n*(3k + a) + component for
                               vertex a (stored order) of element k; rows for
-                              the elements of Omega; kernels with s < 1/2
-                              only (not NLFEM_K_FRAC_HALF) */
+                              the elements of Omega.  Every kernel (s <= 1/2,
+                              Sec. 2.4.2); with NLFEM_K_FRAC_HALF the
+                              edge-touching integrals of functions that jump
+                              across the shared edge diverge logarithmically
+                              and the value is that of the Gauss rule of
+                              order singular_n, as in the paper's DG study */
 };
 
 /* pair classes (Sec. 2.3: intersecting pairs are vertex touching, edge
@@ -153,9 +157,15 @@ typedef struct {
     int32_t singular_n;        /* Gauss-Legendre points per direction of the
                                   regularising transforms on touching pairs
                                   (Sec. 2.4.2); 0 = touching pairs use the
-                                  product rule like all others.  Required > 0
-                                  for INV_DIST, PERIDYNAMIC and FRAC_HALF.
-                                  0..32. */
+                                  product rule with the ball like all others
+                                  (Table 1); for INV_DIST and PERIDYNAMIC
+                                  (s <= 0) that rule avoids zero division:
+                                  point pairs with |x - y|^2 <=
+                                  1e-12 min(|det J_k|, |det J_l|), the same
+                                  point of both elements, are skipped.
+                                  Required > 0 for FRAC_HALF; 0 with a
+                                  singular kernel runs in the single-problem
+                                  path only (not in batches).  0..32. */
     int32_t precision;         /* NLFEM_P_* */
     int32_t ansatz;            /* NLFEM_ANSATZ_* */
 } nlfem_config;

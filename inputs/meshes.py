@@ -102,6 +102,22 @@ def square_mesh(n: int, delta: float | None = None, m: int | None = None,
                 labels=np.ascontiguousarray(labels), h=h, n=n, m=m)
 
 
+def boundary_triangles_to_layer(mesh: Mesh, side: float = 1.0) -> Mesh:
+    """The same mesh with every Omega triangle whose three vertices lie on
+    the boundary of [0, side]^2 labelled 2 (two corner triangles on the
+    uniform mesh).  This is the labelling the printed dof counts of the
+    paper's discontinuous-Galerkin studies imply: 3 (2 n^2 - 2) unknowns per
+    component for n cells per side; continuous problems are unchanged by it
+    (those triangles carry no degree of freedom)."""
+    V, E = mesh.vertices, mesh.elements
+    p = V[E]
+    on = (np.isclose(p[..., 0], 0.0) | np.isclose(p[..., 0], side) |
+          np.isclose(p[..., 1], 0.0) | np.isclose(p[..., 1], side))
+    labels = mesh.labels.copy()
+    labels[(labels == 1) & on.all(axis=1)] = 2
+    return Mesh(vertices=V, elements=E, labels=np.ascontiguousarray(labels), h=mesh.h, n=mesh.n, m=mesh.m)
+
+
 def batched_meshes(count: int = 64, seed: int = 0, n_lo: int = 32,
                    n_hi: int = 160, ratios=(2, 3, 4, 5)):
     """Seeded list of (mesh, delta, kernel_kind) for the batched workload.

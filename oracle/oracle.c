@@ -223,6 +223,14 @@ static void add_sample(const orc_cfg *cf, const union_t *u, const elem_t *k, con
     double fx[MAXU], fy[MAXU];
     to_phys(k, xi, x);
     to_phys(l, eta, y);
+    /* Table 1, s <= 0 without the transforms (singular_n = 0): the rule
+     * avoids x_p = y_q, i.e. a sample at the same point of both elements
+     * (distance at rounding level against the element size) is left out */
+    if (cf->kernel != ORC_K_CONSTANT && cf->singular_n == 0) {
+        double z0 = x[0] - y[0], z1 = x[1] - y[1];
+        double small = 1e-12 * (k->absdet < l->absdet ? k->absdet : l->absdet);
+        if (z0 * z0 + z1 * z1 <= small) return;
+    }
     phihat(xi, pk);
     phihat(eta, pl);
     for (int a = 0; a < u->nu; ++a) {

@@ -120,12 +120,9 @@ int check_cfg(const nlfem_config *c)
         return set_error(NLFEM_E_INVALID, "singular_n must be in [0, 32]");
     if (c->ansatz != NLFEM_ANSATZ_CG && c->ansatz != NLFEM_ANSATZ_DG)
         return set_error(NLFEM_E_INVALID, "unknown ansatz");
-    if (c->ansatz == NLFEM_ANSATZ_DG && c->kernel == NLFEM_K_FRAC_HALF)
+    if (c->kernel == NLFEM_K_FRAC_HALF && c->singular_n == 0)
         return set_error(NLFEM_E_INVALID,
-                         "the discontinuous ansatz needs a kernel with s < 1/2 (c/|z|^3 is not integrable across a "
-                         "shared edge for discontinuous functions)");
-    if (c->kernel != NLFEM_K_CONSTANT && c->singular_n == 0)
-        return set_error(NLFEM_E_INVALID, "singular kernels need singular_n > 0 on touching pairs");
+                         "the s = 1/2 kernel needs singular_n > 0 (regularising transforms on touching pairs)");
     NLFEM_TRY(check_rule(c->outer, "outer"));
     NLFEM_TRY(check_rule(c->inner, "inner"));
     if (c->approach == NLFEM_A_APPROXCAPS_POLY) {
@@ -1000,6 +997,10 @@ int batch_plans(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, n
                                                    ": mesh or configuration differs from the one its pairs were built for");
         if (dev != h->device) return set_error(NLFEM_E_MISMATCH, "current device differs from a build device");
         if (h->dg) return set_error(NLFEM_E_INVALID, "batches take problems of the continuous ansatz");
+        if (kernel_variant(&cfgs[i]) & kKerNoZeroDiv)
+            return set_error(NLFEM_E_INVALID,
+                             "batches take singular kernels with singular_n > 0 (the no-zero-division rule runs "
+                             "in the single-problem path)");
         for (int j = 0; j < i; ++j)
             if (pairs[j] == h) return set_error(NLFEM_E_INVALID, "a pairs handle appears twice (shared workspace)");
         GaussArgs g{};

@@ -182,7 +182,7 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
                        double *val)
 {
     AssemblePlan p{};
-    p.kernel = h->kernel;
+    p.kernel = kernel_variant(cfg);
     p.nc = h->ncomp;
     p.fp32 = cfg->precision == NLFEM_P_MIXED;
     p.poly = clipped_ball(h->approach);
@@ -304,6 +304,10 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(p, s); break;
         case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(p, s); break;
         case NLFEM_K_FRAC_HALF: far_dispatch<NLFEM_K_FRAC_HALF>(p, s); break;
+        case NLFEM_K_INV_DIST | kKerNoZeroDiv: far_dispatch<NLFEM_K_INV_DIST | kKerNoZeroDiv>(p, s); break;
+        case NLFEM_K_PERIDYNAMIC | kKerNoZeroDiv:
+            far_dispatch<NLFEM_K_PERIDYNAMIC | kKerNoZeroDiv>(p, s);
+            break;
         default: far_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
         }
         timing_end(kPhFar, s);

@@ -62,29 +62,38 @@ __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 template <int KER>
 struct Ker {
-    static constexpr int NC = KER == NLFEM_K_PERIDYNAMIC ? 2 : 1;
+    static constexpr int BASE = KER & (kKerNoZeroDiv - 1);
+    static constexpr bool NZD = (KER & kKerNoZeroDiv) != 0;
+    static constexpr int NC = BASE == NLFEM_K_PERIDYNAMIC ? 2 : 1;
     static constexpr int NK = NC == 1 ? 1 : 3;   // stored values of a symmetric NC x NC block
     // homogeneity degree of the integrand: 2 + the degree of Psi
-    static constexpr int D = KER == NLFEM_K_CONSTANT ? 2 : KER == NLFEM_K_FRAC_HALF ? -1 : 1;
+    static constexpr int D = BASE == NLFEM_K_CONSTANT ? 2 : BASE == NLFEM_K_FRAC_HALF ? -1 : 1;
 };
 
-// kernel values; for two components the symmetric block (k00, k01, k11)
+// kernel values; for two components the symmetric block (k00, k01, k11).
+// With the no-zero-division variant the values are 0 for |z|^2 <= z2min.
 template <int KER, typename T>
-__device__ inline void kernel_eval(T zx, T zy, T c, T *k)
+__device__ inline void kernel_eval(T zx, T zy, T c, T *k, T z2min = 0)
 {
-    if (KER == NLFEM_K_CONSTANT) {
+    constexpr int B = Ker<KER>::BASE;
+    const T r2 = zx * zx + zy * zy;
+    if (B == NLFEM_K_CONSTANT) {
         k[0] = c;
-    } else if (KER == NLFEM_K_INV_DIST) {
-        k[0] = c * rsq(zx * zx + zy * zy);
-    } else if (KER == NLFEM_K_FRAC_HALF) {
-        const T r = rsq(zx * zx + zy * zy);
+    } else if (B == NLFEM_K_INV_DIST) {
+        k[0] = c * rsq(r2);
+    } else if (B == NLFEM_K_FRAC_HALF) {
+        const T r = rsq(r2);
         k[0] = c * r * r * r;
     } else {
-        const T r = rsq(zx * zx + zy * zy);
+        const T r = rsq(r2);
         const T s = c * r * r * r;
         k[0] = s * zx * zx;
         k[1] = s * zx * zy;
         k[2] = s * zy * zy;
+    }
+    if constexpr (Ker<KER>::NZD) {
+#pragma unroll
+        for (int i = 0; i < Ker<KER>::NK; ++i) k[i] = r2 <= z2min ? (T)0 : k[i];
     }
 }
 
@@ -195,6 +204,7 @@ __device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double
     const int PB = PM > 0 ? PM : r.PB;
     T fx[PMAX], fy[PMAX], wf[PMAX], tf[PMAX];
     T beta[PMAX][NK];
+    const T z2min = Ker<KER>::NZD ? (T)(1e-12 * fmin(dete, detf)) : (T)0;
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) {
         if (q < PB) {
@@ -219,7 +229,7 @@ __device__ inline void far_direction(const RoleArgs &r, T dx, T dy, const double
             if (q >= PB) continue;
             const T zx = ox - fx[q], zy = oy - fy[q];
             T kv[NK];
-            kernel_eval<KER, T>(zx, zy, cc, kv);
+            kernel_eval<KER, T>(zx, zy, cc, kv, z2min);
             const T wgt = we * wf[q] + we0 * tf[q];   // w_p|J_e| w_q|J_f| (s_p + t_q)
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
@@ -350,7 +360,7 @@ __device__ inline int clip_polygon(double x, double y, const double vx[3], const
 template <int KER, typename T>
 __device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, double xo_y, double wo, const double (&po)[3],
                                int32_t inner, const double2 &v0i, const double4 &Ji, const RoleArgs &r,
-                               bool inner_b, bool outer_e, double *buf, int lane, T cc,
+                               bool inner_b, bool outer_e, double *buf, int lane, T cc, T z2min,
                                T (&X)[3][3][Ker<KER>::NK], T (&De)[6][Ker<KER>::NK], T (&Df)[6][Ker<KER>::NK],
                                bool *ovf)
 {
@@ -393,7 +403,7 @@ __device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, do
             const double h2 = (-Ji.z * dx + Ji.x * dy) / deti;
             const T pi[3] = {(T)(1.0 - h1 - h2), (T)h1, (T)h2};
             T kv[NK];
-            kernel_eval<KER, T>((T)(xo_x - yx), (T)(xo_y - yy), cc, kv);
+            kernel_eval<KER, T>((T)(xo_x - yx), (T)(xo_y - yy), cc, kv, z2min);
             const T w = (T)(wo * wq * adet);
             const T *pr = outer_e ? pe : pi;   // basis of e at its point
             const T *pc = outer_e ? pi : pe;   // basis of f at its point
@@ -483,22 +493,23 @@ __device__ __forceinline__ void straddle_item(const FarArgs &a, const RoleArgs &
 {
     double clipbuf[2 * 2 * (kMaxPoly + 4)];
     const T cc = (T)a.c;
+    const T z2min = Ker<KER>::NZD ? (T)(1e-12 * fmin(a.det[e], a.det[f])) : (T)0;
     c.zero();
     if (side == 0) {
         const double2 xo = a.xp[(int64_t)e * a.P + p];
         const double po[3] = {r1.pa[p][0], r1.pa[p][1], r1.pa[p][2]};
         straddle_point<KER, T>(a, xo.x, xo.y, r1.wa[p] * a.det[e], po, f, a.v0[f], a.J[f], r1, true, true, clipbuf,
-                               0, cc, c.X, c.De, c.Df, ovf);
+                               0, cc, z2min, c.X, c.De, c.Df, ovf);
     } else if (a.same) {   // one rule: both directions use r1
         const double2 xo = a.xp[(int64_t)f * a.P + p];
         const double po[3] = {r1.pb[p][0], r1.pb[p][1], r1.pb[p][2]};
         straddle_point<KER, T>(a, xo.x, xo.y, r1.wb[p] * a.det[f], po, e, a.v0[e], a.J[e], r1, false, false,
-                               clipbuf, 0, cc, c.X, c.De, c.Df, ovf);
+                               clipbuf, 0, cc, z2min, c.X, c.De, c.Df, ovf);
     } else {               // the outer rule on f is role B of r2
         const double2 xo = a.xp[(int64_t)f * a.P + p];
         const double po[3] = {r2.pb[p][0], r2.pb[p][1], r2.pb[p][2]};
         straddle_point<KER, T>(a, xo.x, xo.y, r2.wb[p] * a.det[f], po, e, a.v0[e], a.J[e], r2, false, false,
-                               clipbuf, 0, cc, c.X, c.De, c.Df, ovf);
+                               clipbuf, 0, cc, z2min, c.X, c.De, c.Df, ovf);
     }
 }
 

@@ -438,6 +438,7 @@ int launch_dg_assemble_rest(const nlfem_pairs *h, const nlfem_mesh *m, const nlf
         switch (h->kernel) {
         case NLFEM_K_CONSTANT: touch_dg_launch<NLFEM_K_CONSTANT>(ae, av, g, s); break;
         case NLFEM_K_INV_DIST: touch_dg_launch<NLFEM_K_INV_DIST>(ae, av, g, s); break;
+        case NLFEM_K_FRAC_HALF: touch_dg_launch<NLFEM_K_FRAC_HALF>(ae, av, g, s); break;
         default: touch_dg_launch<NLFEM_K_PERIDYNAMIC>(ae, av, g, s); break;
         }
         timing_end(kPhTouch, s);

@@ -13,6 +13,16 @@ namespace nlfem {
 
 constexpr int kMaxRule = 16;      // outer/inner rule points (2 status bits each in a u32)
 constexpr int kMaxGauss = 32;     // 1-D Gauss points of the touching-pair rules
+// Kernel specialisation flag: a weakly singular kernel (s <= 0) whose
+// touching pairs take the standard rule with the ball (singular_n = 0), so
+// point pairs at distance |z|^2 <= 1e-12 min(|det J_e|, |det J_f|) (the same
+// point of both elements, up to rounding) are skipped (Sec. 2.4.2, Table 1:
+// the rule that avoids x_p = y_q)
+constexpr int kKerNoZeroDiv = 8;
+inline int kernel_variant(const nlfem_config *c)
+{
+    return c->kernel != NLFEM_K_CONSTANT && c->singular_n == 0 ? c->kernel | kKerNoZeroDiv : c->kernel;
+}
 constexpr int kMaxPoly = 64;      // polygon vertices
 constexpr int kWave = 64;
 

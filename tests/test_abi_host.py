@@ -59,7 +59,7 @@ def _fake_mesh(nl, K=4, M=6, null=False):
 @pytest.mark.parametrize("bad,msg", [
     (dict(delta=0.0), "delta"),
     (dict(delta=-1.0), "delta"),
-    (dict(kernel="inv_dist", singular_n=0), "singular"),
+    (dict(kernel="frac_half", singular_n=0), "singular_n > 0"),
     (dict(outer_w=np.array([0.1] * 7)), "sum to 1/2"),
     (dict(singular_n=40), "singular_n"),
     (dict(approach="poly", polygon_dirs=None), "polygon"),

@@ -205,3 +205,32 @@ def test_rhs_from_quadrature_point_values(nl, oracle_lib, kind):
     P = oracle_lib.Problem(mesh, w)
     ob = P.rhs(f_qp=fr)
     assert np.abs(b_rand.cpu().numpy() - ob).max() <= 1e-14 * np.abs(ob).max()
+
+
+@pytest.mark.parametrize("kind", ["dg", "no_zero_division"])
+def test_batch_rejects_single_problem_only_configs(nl, kind):
+    """Batches take continuous problems whose singular kernels use the
+    transforms; a discontinuous problem, or a weakly singular kernel with
+    the standard rule on touching pairs (singular_n = 0), is refused with
+    E_INVALID before anything runs (the single-problem path assembles it)."""
+    import torch
+    from inputs import square_mesh
+    w = inv_dist_jittered(n=8, delta=0.25, precision="fp64")
+    w = dict(w, mesh=square_mesh(8, delta=0.25))
+    if kind == "dg":
+        w["ansatz"] = "dg"
+    else:
+        w["singular_n"] = 0
+    cfg = make_config(w)
+    dm = nl.DeviceMesh.from_numpy(w["mesh"])
+    pairs = nl.nlfem_build_pairs(dm, cfg)
+    nnz = nl.nlfem_pairs_info(pairs)["nnz"]
+    val = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+    with pytest.raises(nl.NlfemError) as e:
+        nl.nlfem_batch_create([dm], [cfg], [pairs], [val])
+    assert e.value.code == -1
+    assert ("continuous" in str(e.value)) if kind == "dg" else ("singular_n" in str(e.value))
+    nl.nlfem_assemble(dm, cfg, pairs, val)
+    torch.cuda.synchronize()
+    assert torch.isfinite(val).all() and float(val.abs().max()) > 0.0
+    nl.nlfem_pairs_free(pairs)

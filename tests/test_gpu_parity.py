@@ -89,6 +89,15 @@ def _cases():
                                      rule=paper7()),
         "peri_approxcaps": _w("peridynamic", square_mesh(10, delta=0.25, jitter=0.1, seed=29), 0.25,
                               approach="approxcaps"),
+        # weakly singular kernels with the standard rule on touching pairs
+        # (Table 1, singular_n = 0): the vertex rule puts points of both
+        # elements on shared vertices and mid-sides, which are skipped
+        "invdist_nozerodiv_paper7": _w("inv_dist", square_mesh(12, delta=0.15, jitter=0.2, seed=40), 0.15,
+                                       rule=paper7(), singular_n=0),
+        "peri_nozerodiv_approxcaps_table4": _w("peridynamic", square_mesh(10, delta=0.1, side=0.5), 0.1,
+                                               approach="approxcaps", rule=paper7(), singular_n=0),
+        "invdist_nozerodiv_poly": _w("inv_dist", square_mesh(10, delta=0.2, jitter=0.1, seed=41), 0.2,
+                                     approach="poly", rule=paper7(), singular_n=0),
     }
 
 
@@ -200,6 +209,12 @@ def _dg_cases():
                                     approach="approxcaps", ansatz="dg", rule=paper7()),
         "dg_const_duffy": _w("constant", square_mesh(8, delta=0.25, jitter=0.2, seed=38), 0.25, singular_n=4,
                              ansatz="dg"),
+        # s = 1/2: the edge-touching integrals of jumping functions are the
+        # Gauss rule's (log-divergent integrand), the same rule on both sides
+        "dg_frac_approxcaps": _w("frac_half", square_mesh(10, delta=0.2, jitter=0.15, seed=39), 0.2,
+                                 approach="approxcaps", ansatz="dg", rule=paper7()),
+        "dg_peri_nozerodiv": _w("peridynamic", square_mesh(10, delta=0.1, jitter=0.1, seed=42, side=0.5), 0.1,
+                                approach="approxcaps", ansatz="dg", rule=paper7(), singular_n=0),
     }
 
 
@@ -209,16 +224,6 @@ def test_parity_dg(oracle_lib, name, precision):
     w = _dg_cases()[name]
     print(f"case {name} {precision}", flush=True)
     _compare_full(oracle_lib, w, precision)
-
-
-def test_dg_rejects_fractional_kernel():
-    import paper_2207_03921_amd as nl
-    from _gpu import make_config
-    mesh = square_mesh(6, delta=0.3)
-    w = _w("frac_half", mesh, 0.3, ansatz="dg")
-    with pytest.raises(nl.NlfemError) as e:
-        nl.nlfem_build_pairs(nl.DeviceMesh.from_numpy(mesh), make_config(w))
-    assert e.value.code == -1 and "discontinuous" in str(e.value)
 
 
 @pytest.mark.parametrize("name", list(_cases()))

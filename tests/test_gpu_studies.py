@@ -1,8 +1,9 @@
 """The paper's convergence studies with matrices assembled on the GPU
-(MI355X only): Table 2 (s = 1/2 kernel, approximate caps, Sec. 3.1) and
-Table 7 (infinity-norm ball, Sec. 3.3).  The GPU matrix is solved with scipy
-for the manufactured solution; the rates must match the printed ones (and
-the errors the oracle's, to the assembly tolerance)."""
+(MI355X only): Tables 2 and 3 (s = 1/2 kernel, approximate caps, continuous
+and discontinuous, Sec. 3.1), Tables 4 and 5 (peridynamics, continuous and
+discontinuous, Sec. 3.2) and Table 7 (infinity-norm ball, Sec. 3.3).  The GPU
+matrix is solved on the host (scipy / numpy) for the manufactured solution;
+the rates must match the printed ones."""
 import math
 import os
 
@@ -11,7 +12,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from inputs import square_mesh, gauss7, paper7
+from inputs import square_mesh, gauss7, paper7, boundary_triangles_to_layer
 from _gpu import make_config
 
 pytestmark = pytest.mark.gpu
@@ -40,30 +41,53 @@ def _solve_l2(mesh, w, u, f_affine=None, f_point=None):
     else:
         b = nl.nlfem_rhs(dm, cfg, f_affine=f_affine)
     torch.cuda.synchronize()
+    dg = w.get("ansatz", "cg") == "dg"
+    n = 2 if w["kernel"] == "peridynamic" else 1
     nnz = col.shape[0]
-    M = mesh.n_vertices
-    A = sp.csr_matrix((val[:nnz].cpu().numpy(), col.cpu().numpy(), rp.cpu().numpy()), shape=(M, M))
+    N = n * (3 * mesh.n_elements if dg else mesh.n_vertices)
+    A = sp.csr_matrix((val[:nnz].cpu().numpy(), col.cpu().numpy(), rp.cpu().numpy()), shape=(N, N))
     b = b.cpu().numpy()
     nl.nlfem_pairs_free(pairs)
-    dof = np.zeros(M, bool)
-    dof[E[mesh.labels == 1].reshape(-1)] = True
-    dof[E[mesh.labels == 2].reshape(-1)] = False
-    U = u(V)
+    if dg:   # the unknowns of Omega elements; Omega_D ones carry g
+        node_dof = np.repeat(mesh.labels == 1, 3)
+    else:
+        node_dof = np.zeros(mesh.n_vertices, bool)
+        node_dof[E[mesh.labels == 1].reshape(-1)] = True
+        node_dof[E[mesh.labels == 2].reshape(-1)] = False
+    dof = np.repeat(node_dof, n)
+    uu = lambda X: np.reshape(u(X), X.shape[:-1] + (n,))
+    U = uu(V[E].reshape(-1, 2) if dg else V).reshape(-1)
     Uh = U.copy()
-    Uh[dof] = spla.spsolve(A[dof][:, dof].tocsc(), b[dof] - A[dof][:, ~dof] @ U[~dof])
+    rhs = b[dof] - A[dof][:, ~dof] @ U[~dof]
+    if dg:
+        Uh[dof] = np.linalg.solve(A[dof][:, dof].toarray(), rhs)
+    else:
+        Uh[dof] = spla.spsolve(A[dof][:, dof].tocsc(), rhs)
     g = gauss7()
     Xg = v0[:, None, :] + np.einsum("kij,pj->kpi", J, g.xi)
     lam = np.stack([1 - g.xi[:, 0] - g.xi[:, 1], g.xi[:, 0], g.xi[:, 1]], 1)
-    eh = np.einsum("kv,pv->kp", Uh[E], lam) - u(Xg)
+    Ue = Uh.reshape(-1, 3, n) if dg else Uh.reshape(-1, n)[E]
+    eh = np.einsum("kvc,pv->kpc", Ue, lam) - uu(Xg)
     det = np.abs(J[:, 0, 0] * J[:, 1, 1] - J[:, 0, 1] * J[:, 1, 0])
     om = mesh.labels == 1
-    return math.sqrt((det[om, None] * g.w[None, :] * eh[om] ** 2).sum()), int(dof.sum())
+    return math.sqrt((det[om, None, None] * g.w[None, :, None] * eh[om] ** 2).sum()), int(dof.sum())
 
 
-def _w(mesh, kernel, c, delta, approach, singular_n):
+def _w(mesh, kernel, c, delta, approach, singular_n, ansatz="cg"):
     r = paper7()
     return dict(mesh=mesh, kernel=kernel, c=c, delta=delta, approach=approach, outer=r, inner=r,
-                singular_n=singular_n, precision="fp64")
+                singular_n=singular_n, precision="fp64", ansatz=ansatz)
+
+
+def _u_cubic(X):
+    return X[..., 0] ** 2 * X[..., 1] + X[..., 1] ** 2
+
+
+def _u_navier(X):
+    return np.stack([X[..., 1] ** 2, X[..., 0] ** 2 * X[..., 1]], -1)
+
+
+_F_NAVIER = [(-math.pi / 2, -math.pi, 0.0), (0.0, 0.0, -math.pi / 2)]
 
 
 def test_table2_fractional_approxcaps():
@@ -107,3 +131,62 @@ def test_table7_infinity_ball():
     print("errors", errs, "rates", rates)
     for got, row in zip(rates, rows[1:]):
         assert abs(got - row[3]) <= 0.05, rates
+
+
+def test_table3_fractional_dg():
+    """Table 3: Table 2's study in the discontinuous space, four levels (up
+    to 9,594 unknowns, solved densely)."""
+    rows = _rows("table3_fractional_dg_rates.txt")
+    delta = 0.2
+    errs = []
+    for i, n in enumerate((5, 10, 20, 40)):
+        print("table 3, n =", n, flush=True)
+        mesh = boundary_triangles_to_layer(square_mesh(n, delta=delta, side=0.5), side=0.5)
+        e, ndof = _solve_l2(mesh, _w(mesh, "frac_half", 1.0 / (math.pi * delta), delta, "approxcaps", 5, "dg"),
+                            _u_cubic, f_affine=[(-2.0, 0.0, -2.0)])
+        assert float(f"{ndof:.2e}") == rows[i][1]
+        errs.append(e)
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    print("errors", errs, "rates", rates)
+    assert abs(rates[0] - rows[1][3]) <= 0.15, rates
+    for got, row in zip(rates[1:], rows[2:]):
+        assert abs(got - row[3]) <= 0.05, rates
+
+
+def test_table4_peridynamic_no_zero_division():
+    """Table 4: peridynamics (c = 3/delta^3, delta = 0.1) with the standard
+    rule on touching pairs (singular_n = 0), four levels."""
+    rows = _rows("table4_peridynamic_cg_rates.txt")
+    delta = 0.1
+    errs = []
+    for i, n in enumerate((5, 10, 20, 40)):
+        print("table 4, n =", n, flush=True)
+        mesh = square_mesh(n, delta=delta, side=0.5)
+        e, ndof = _solve_l2(mesh, _w(mesh, "peridynamic", 3.0 / delta ** 3, delta, "approxcaps", 0), _u_navier,
+                            f_affine=_F_NAVIER)
+        assert float(f"{ndof:.2e}") == rows[i][1]
+        errs.append(e)
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    print("errors", errs, "rates", rates)
+    for got, row in zip(rates, rows[1:]):
+        assert abs(got - row[3]) <= 0.05, rates
+
+
+def test_table5_peridynamic_dg():
+    """Table 5: Table 4's study in the discontinuous space, three levels
+    (second order; the printed rates are lower at these levels)."""
+    rows = _rows("table5_peridynamic_dg_rates.txt")
+    delta = 0.1
+    errs = []
+    for i, n in enumerate((5, 10, 20)):
+        print("table 5, n =", n, flush=True)
+        mesh = boundary_triangles_to_layer(square_mesh(n, delta=delta, side=0.5), side=0.5)
+        e, ndof = _solve_l2(mesh, _w(mesh, "peridynamic", 3.0 / delta ** 3, delta, "approxcaps", 0, "dg"),
+                            _u_navier, f_affine=_F_NAVIER)
+        if n <= 10:
+            assert float(f"{ndof:.2e}") == rows[i][1]
+        errs.append(e)
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    print("errors", errs, "rates", rates)
+    for got, row in zip(rates, rows[1:]):
+        assert got >= 1.8 and abs(got - row[3]) <= 0.25, rates
