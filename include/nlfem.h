@@ -52,16 +52,17 @@
 extern "C" {
 #endif
 
-#define NLFEM_ABI_VERSION 4
+#define NLFEM_ABI_VERSION 5
 
 /* return codes */
 enum {
     NLFEM_OK = 0,
     NLFEM_E_INVALID = -1,   /* bad argument: NULL pointer, size <= 0, delta <= 0,
                                weights not summing to 1/2, unsupported option */
-    NLFEM_E_MESH = -2,      /* vertex index out of range, zero-area element, or
+    NLFEM_E_MESH = -2,      /* vertex index out of range, zero-area element,
                                an edge shared by more than two elements (the
-                               mesh is not conforming, Sec. 2.2 Assumption 2) */
+                               mesh is not conforming, Sec. 2.2 Assumption 2),
+                               or a material id outside the material table */
     NLFEM_E_NOMEM = -3,     /* device allocation failed */
     NLFEM_E_HIP = -4,       /* HIP runtime error (message has the HIP text) */
     NLFEM_E_OVERFLOW = -5,  /* a count exceeds 32-bit column indices, an
@@ -134,6 +135,11 @@ typedef struct {
     const double *vertices;    /* device, [M][2] */
     const int32_t *elements;   /* device, [K][3] vertex indices in [0, M) */
     const int32_t *labels;     /* device, [K]: 1 Omega, 2 Omega_D, other = ignored */
+    const int32_t *materials;  /* device, [K] material ids in [0, n_materials)
+                                  of the configuration's material table, or
+                                  NULL (all 0); read only when the table is
+                                  given (Sec. 1: kernels that depend on
+                                  element labels, for interface problems) */
 } nlfem_mesh;
 
 /* quadrature rule on the reference triangle {xi >= 0, xi_1 + xi_2 <= 1}
@@ -168,6 +174,21 @@ typedef struct {
                                   path only (not in batches).  0..32. */
     int32_t precision;         /* NLFEM_P_* */
     int32_t ansatz;            /* NLFEM_ANSATZ_* */
+    int32_t n_materials;       /* 0 (no table) or 1..4 */
+    const double *material_c;  /* host, [n_materials][n_materials]: the
+                                  kernel becomes
+                                    Psi(x, y) = material_c[m(x)][m(y)] Psi0(x, y)
+                                  with Psi0 the kernel above and m(x) the
+                                  material of the element holding x (Sec. 1
+                                  and 2.1: label-dependent and non-symmetric
+                                  kernels).  A non-symmetric table gives a
+                                  non-symmetric matrix; it needs a kernel with
+                                  s <= 0 (not FRAC_HALF: the difference of the
+                                  two directions is not integrable on touching
+                                  pairs) and runs in the single-problem path
+                                  (not in batches).  Row i, column j of the
+                                  matrix is a(phi_j, phi_i): test function in
+                                  the row, trial function in the column. */
 } nlfem_config;
 
 typedef struct nlfem_pairs nlfem_pairs;   /* opaque, library-owned */

@@ -36,6 +36,7 @@ class Mesh:
     h: float
     n: int                 # cells per side of Omega
     m: int                 # layer width in cells
+    materials: np.ndarray | None = None   # int32 [K] material ids of a label-dependent kernel
 
     @property
     def n_vertices(self) -> int:
@@ -115,7 +116,8 @@ def boundary_triangles_to_layer(mesh: Mesh, side: float = 1.0) -> Mesh:
           np.isclose(p[..., 1], 0.0) | np.isclose(p[..., 1], side))
     labels = mesh.labels.copy()
     labels[(labels == 1) & on.all(axis=1)] = 2
-    return Mesh(vertices=V, elements=E, labels=np.ascontiguousarray(labels), h=mesh.h, n=mesh.n, m=mesh.m)
+    return Mesh(vertices=V, elements=E, labels=np.ascontiguousarray(labels), h=mesh.h, n=mesh.n, m=mesh.m,
+                materials=mesh.materials)
 
 
 def batched_meshes(count: int = 64, seed: int = 0, n_lo: int = 32,

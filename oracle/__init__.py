@@ -43,7 +43,7 @@ def build(force: bool = True) -> str:
 class _Mesh(C.Structure):
     _fields_ = [("n_vertices", C.c_int64), ("n_elements", C.c_int64),
                 ("vertices", C.c_void_p), ("elements", C.c_void_p),
-                ("labels", C.c_void_p)]
+                ("labels", C.c_void_p), ("materials", C.c_void_p)]
 
 
 class _Cfg(C.Structure):
@@ -54,7 +54,8 @@ class _Cfg(C.Structure):
                 ("P", C.c_int32), ("pxi", C.c_void_p), ("pw", C.c_void_p),
                 ("Q", C.c_int32), ("qxi", C.c_void_p), ("qw", C.c_void_p),
                 ("singular_n", C.c_int32), ("gl_x", C.c_void_p),
-                ("gl_w", C.c_void_p), ("dg", C.c_int32)]
+                ("gl_w", C.c_void_p), ("dg", C.c_int32),
+                ("n_materials", C.c_int32), ("material_c", C.c_void_p)]
 
 
 _lib = None
@@ -123,14 +124,24 @@ class Problem:
             self.glx = self.glw = np.zeros(1)
         pn = int(cfg.get("polygon_n", 32))
         self.pdirs = polygon_dirs(pn)
+        # label-dependent kernel: material ids per element and the table
+        # material_c[m(x)][m(y)] that scales the kernel
+        mat = getattr(mesh, "materials", None)
+        self.mat = None if mat is None else np.ascontiguousarray(mat, dtype=np.int32)
+        mc = cfg.get("material_c")
+        self.mc = None if mc is None else np.ascontiguousarray(mc, dtype=np.float64)
+        if self.mc is not None and self.mat is None:
+            raise ValueError("a material table needs mesh.materials")
         self.cm = _Mesh(self.V.shape[0], self.E.shape[0], _ptr(self.V),
-                        _ptr(self.E), _ptr(self.lab))
+                        _ptr(self.E), _ptr(self.lab), None if self.mat is None else _ptr(self.mat))
         self.cc = _Cfg(KERNELS[cfg["kernel"]], self.n, float(cfg["c"]),
                        float(cfg["delta"]), APPROACHES[cfg.get("approach", "bary")],
                        pn, _ptr(self.pdirs),
                        self.pw.shape[0], _ptr(self.pxi), _ptr(self.pw),
                        self.qw.shape[0], _ptr(self.qxi), _ptr(self.qw),
-                       ns, _ptr(self.glx), _ptr(self.glw), 1 if self.dg else 0)
+                       ns, _ptr(self.glx), _ptr(self.glw), 1 if self.dg else 0,
+                       0 if self.mc is None else self.mc.shape[0],
+                       None if self.mc is None else _ptr(self.mc))
 
     @property
     def n_unknowns(self):

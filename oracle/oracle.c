@@ -41,6 +41,7 @@ typedef struct {
     const double *vertices;   /* [M][2] */
     const int32_t *elements;  /* [K][3] */
     const int32_t *labels;    /* [K]    1 = Omega, 2 = Omega_D, else ignored */
+    const int32_t *materials; /* [K]    material ids (NULL: all 0) */
 } orc_mesh;
 
 typedef struct {
@@ -57,6 +58,11 @@ typedef struct {
     const double *gl_w;       /* [singular_n] weights on [0,1] */
     int32_t dg;               /* 1: discontinuous P1 (three unknowns per element,
                                  numbered 3k + local vertex), 0: continuous */
+    int32_t n_materials;      /* 0: no table */
+    const double *material_c; /* [n][n]: Psi(x, y) = material_c[m(x)][m(y)] Psi0(x, y),
+                                 m(x) the material of the element holding x
+                                 (Sec. 1 and 2.1: label-dependent, possibly
+                                 non-symmetric kernels) */
 } orc_cfg;
 
 /* ------------------------------------------------------------------ */
@@ -67,7 +73,13 @@ typedef struct {
     double v[3][2];
     double J[2][2];
     double absdet;
+    int32_t mat;   /* material id (0 without a table) */
 } elem_t;
+
+static int32_t material_of(const orc_mesh *m, int64_t k)
+{
+    return m->materials ? m->materials[k] : 0;
+}
 
 static void load_elem(const orc_mesh *m, int64_t k, elem_t *e)
 {
@@ -239,6 +251,15 @@ static void add_sample(const orc_cfg *cf, const union_t *u, const elem_t *k, con
     }
     kernel(cf, x, y, Kxy);
     kernel(cf, y, x, Kyx);
+    if (cf->n_materials > 0) {
+        /* x in T_k, y in T_l */
+        const double cxy = cf->material_c[k->mat * cf->n_materials + l->mat];
+        const double cyx = cf->material_c[l->mat * cf->n_materials + k->mat];
+        for (int i = 0; i < n * n; ++i) {
+            Kxy[i] *= cxy;
+            Kyx[i] *= cyx;
+        }
+    }
     for (int a = 0; a < u->nu; ++a)
         for (int c = 0; c < n; ++c)
             for (int b = 0; b < u->nu; ++b)
@@ -889,6 +910,8 @@ static int local_matrix(const orc_mesh *m, const orc_cfg *cf, int64_t kk, int64_
         touch_frames(m, kk, ll, cls, ok, ol);
         load_elem_ordered(m, ok, &k);
         load_elem_ordered(m, ol, &l);
+        k.mat = material_of(m, kk);
+        l.mat = material_of(m, ll);
         if (cf->dg) {
             dg_ids(m, kk, &k);
             dg_ids(m, ll, &l);
@@ -912,6 +935,8 @@ static int local_matrix(const orc_mesh *m, const orc_cfg *cf, int64_t kk, int64_
         /* Alg. 1, second branch: quadrature for kernel truncations */
         load_elem(m, kk, &k);
         load_elem(m, ll, &l);
+        k.mat = material_of(m, kk);
+        l.mat = material_of(m, ll);
         if (cf->dg) {
             dg_ids(m, kk, &k);
             dg_ids(m, ll, &l);

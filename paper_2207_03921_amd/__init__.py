@@ -40,7 +40,8 @@ class NlfemError(RuntimeError):
 
 class _Mesh(C.Structure):
     _fields_ = [("n_vertices", C.c_int64), ("n_elements", C.c_int64),
-                ("vertices", C.c_void_p), ("elements", C.c_void_p), ("labels", C.c_void_p)]
+                ("vertices", C.c_void_p), ("elements", C.c_void_p), ("labels", C.c_void_p),
+                ("materials", C.c_void_p)]
 
 
 class _Rule(C.Structure):
@@ -51,7 +52,8 @@ class _Config(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("c", C.c_double), ("delta", C.c_double),
                 ("approach", C.c_int32), ("polygon_n", C.c_int32), ("polygon_dirs", C.c_void_p),
                 ("outer", _Rule), ("inner", _Rule), ("singular_n", C.c_int32),
-                ("precision", C.c_int32), ("ansatz", C.c_int32)]
+                ("precision", C.c_int32), ("ansatz", C.c_int32), ("n_materials", C.c_int32),
+                ("material_c", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -60,7 +62,7 @@ class _Info(C.Structure):
                                          "rebuild", "skipped")]
 
 
-ABI_VERSION = 4   # layout of the structs below
+ABI_VERSION = 5   # layout of the structs below
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 _lib = None
@@ -148,24 +150,28 @@ def _dev_ptr(t, dtype, name):
 @dataclass
 class DeviceMesh:
     """Device copies of a mesh (vertices float64 [M,2], elements int32 [K,3],
-    labels int32 [K])."""
+    labels int32 [K], optional materials int32 [K])."""
     vertices: object
     elements: object
     labels: object
+    materials: object = None
 
     @classmethod
     def from_numpy(cls, mesh, device="cuda"):
         import torch
+        mat = getattr(mesh, "materials", None)
         return cls(torch.as_tensor(np.ascontiguousarray(mesh.vertices, np.float64), device=device),
                    torch.as_tensor(np.ascontiguousarray(mesh.elements, np.int32), device=device),
-                   torch.as_tensor(np.ascontiguousarray(mesh.labels, np.int32), device=device))
+                   torch.as_tensor(np.ascontiguousarray(mesh.labels, np.int32), device=device),
+                   None if mat is None else torch.as_tensor(np.ascontiguousarray(mat, np.int32), device=device))
 
     def c_struct(self):
         import torch
         return _Mesh(self.vertices.shape[0], self.elements.shape[0],
                      _dev_ptr(self.vertices, torch.float64, "vertices"),
                      _dev_ptr(self.elements, torch.int32, "elements"),
-                     _dev_ptr(self.labels, torch.int32, "labels"))
+                     _dev_ptr(self.labels, torch.int32, "labels"),
+                     None if self.materials is None else _dev_ptr(self.materials, torch.int32, "materials"))
 
 
 @dataclass
@@ -183,6 +189,7 @@ class Config:
     singular_n: int = 0
     precision: str = "fp64"
     ansatz: str = "cg"
+    material_c: np.ndarray | None = None   # [n][n]: Psi(x, y) = material_c[m(x)][m(y)] Psi0
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -194,23 +201,27 @@ class Config:
         # contiguous float64 array (the struct then points at the caller's
         # arrays, so changes made in place are seen)
         key = (self.kernel, self.c, self.delta, self.approach, self.singular_n, self.precision, self.ansatz,
-               id(self.outer_xi), id(self.outer_w), id(self.inner_xi), id(self.inner_w), id(self.polygon_dirs))
+               id(self.outer_xi), id(self.outer_w), id(self.inner_xi), id(self.inner_w), id(self.polygon_dirs),
+               id(self.material_c))
         cached = self.__dict__.get("_cs")
         if cached is not None and cached[0] == key:
             return cached[1]
         arrs = [np.ascontiguousarray(a, np.float64) for a in
                 (self.outer_xi, self.outer_w, self.inner_xi, self.inner_w)]
         dirs = None if self.polygon_dirs is None else np.ascontiguousarray(self.polygon_dirs, np.float64)
-        self._keep = arrs + [dirs]
+        mc = None if self.material_c is None else np.ascontiguousarray(self.material_c, np.float64)
+        self._keep = arrs + [dirs, mc]
         oxi, ow, ixi, iw = arrs
         cs = _Config(KERNELS[self.kernel], float(self.c), float(self.delta),
                      APPROACHES[self.approach], 0 if dirs is None else dirs.shape[0],
                      None if dirs is None else dirs.ctypes.data,
                      _Rule(ow.shape[0], oxi.ctypes.data, ow.ctypes.data),
                      _Rule(iw.shape[0], ixi.ctypes.data, iw.ctypes.data),
-                     int(self.singular_n), PRECISIONS[self.precision], ANSATZ[self.ansatz])
+                     int(self.singular_n), PRECISIONS[self.precision], ANSATZ[self.ansatz],
+                     0 if mc is None else mc.shape[0], None if mc is None else mc.ctypes.data)
         src = (self.outer_xi, self.outer_w, self.inner_xi, self.inner_w)
-        if all(a is b for a, b in zip(arrs, src)) and (dirs is None or dirs is self.polygon_dirs):
+        if all(a is b for a, b in zip(arrs, src)) and (dirs is None or dirs is self.polygon_dirs) and \
+                (mc is None or mc is self.material_c):
             self.__dict__["_cs"] = (key, cs)
         return cs
 

@@ -125,6 +125,16 @@ int check_cfg(const nlfem_config *c)
                          "the s = 1/2 kernel needs singular_n > 0 (regularising transforms on touching pairs)");
     NLFEM_TRY(check_rule(c->outer, "outer"));
     NLFEM_TRY(check_rule(c->inner, "inner"));
+    if (c->n_materials < 0 || c->n_materials > kMaxMaterials)
+        return set_error(NLFEM_E_INVALID, "n_materials must be in [0, 4]");
+    if (c->n_materials > 0) {
+        if (!c->material_c) return set_error(NLFEM_E_INVALID, "material_c is NULL");
+        for (int i = 0; i < c->n_materials * c->n_materials; ++i)
+            if (!is_finite(c->material_c[i])) return set_error(NLFEM_E_INVALID, "material_c not finite");
+        if (c->kernel == NLFEM_K_FRAC_HALF && material_nonsymmetric(c))
+            return set_error(NLFEM_E_INVALID,
+                             "a non-symmetric material table needs a kernel with s <= 0 (not the s = 1/2 kernel)");
+    }
     if (c->approach == NLFEM_A_APPROXCAPS_POLY) {
         if (c->polygon_n < 3 || c->polygon_n > kMaxPoly)
             return set_error(NLFEM_E_INVALID, "polygon_n must be in [3, 64]");
@@ -341,6 +351,9 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     h->approach = cfg->approach;
     h->singular = cfg->singular_n > 0;
     h->dg = cfg->ansatz == NLFEM_ANSATZ_DG;
+    h->materials = cfg->n_materials;
+    h->mesh_materials = cfg->n_materials > 0 ? m->materials : nullptr;
+    h->nonsym = cfg->n_materials > 0 && material_nonsymmetric(cfg);
     h->delta = cfg->delta;
     h->rules = make_rules(cfg);
     h->poly = make_poly(cfg);
@@ -381,6 +394,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
         err = (int32_t)(red[kRedErr] & 0xffffffffull);
         if (err & kErrIndex) return set_error(NLFEM_E_MESH, "element vertex index out of range");
         if (err & kErrArea) return set_error(NLFEM_E_MESH, "element with zero area");
+        if (err & kErrMaterial) return set_error(NLFEM_E_MESH, "element material outside the material table");
         const double x0 = key_to_double(red[0]), y0 = key_to_double(red[1]);
         const double x1 = key_to_double(red[2]), y1 = key_to_double(red[3]);
         const double rq = key_to_double(red[4]), rv = key_to_double(red[5]);
@@ -579,7 +593,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
 
     // workspace of the assembly: one result record per unordered pair
     h->far_stride = far_record_stride(h->ncomp);
-    h->touch_stride = touch_record_stride(h->ncomp, false);
+    h->touch_stride = touch_record_stride(h->ncomp, h->nonsym != 0);
     double *far_rec = nullptr;
     NLFEM_TRY(ensure_typed(h, B_FARREC, h->nUF * h->far_stride, far_rec));
     h->far_rec = far_rec;
@@ -684,6 +698,8 @@ bool same_shape(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c
     if (h->kernel != c->kernel || h->approach != c->approach || h->delta != c->delta) return false;
     if (h->singular != (c->singular_n > 0)) return false;
     if (h->dg != (c->ansatz == NLFEM_ANSATZ_DG)) return false;
+    if (h->materials != c->n_materials) return false;
+    if (h->nonsym != (c->n_materials > 0 && material_nonsymmetric(c))) return false;
     const RuleArgs r = make_rules(c);
     if (r.P != h->rules.P || r.Q != h->rules.Q) return false;
     if (std::memcmp(r.pxi, h->rules.pxi, sizeof r.pxi) || std::memcmp(r.pw, h->rules.pw, sizeof r.pw) ||
@@ -700,6 +716,7 @@ bool same_build(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *c
 {
     if (h->mesh_vertices != m->vertices || h->mesh_elements != m->elements || h->mesh_labels != m->labels)
         return false;
+    if (c->n_materials > 0 && h->mesh_materials != m->materials) return false;
     return same_shape(h, m, c);
 }
 
@@ -784,6 +801,8 @@ int nlfem_build_pairs(const nlfem_mesh *mesh, const nlfem_config *cfg, nlfem_pai
     if (!pairs) return set_error(NLFEM_E_INVALID, "pairs is NULL");
     NLFEM_TRY(check_mesh(mesh));
     NLFEM_TRY(check_cfg(cfg));
+    if (cfg->n_materials > 0 && !mesh->materials)
+        return set_error(NLFEM_E_INVALID, "mesh materials are NULL with a material table");
     NLFEM_TRY(check_device());
     const bool fresh = *pairs == nullptr;
     nlfem_pairs *h = fresh ? new (std::nothrow) nlfem_pairs() : *pairs;
@@ -859,6 +878,8 @@ int nlfem_assemble(const nlfem_mesh *mesh, const nlfem_config *cfg, const nlfem_
     if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle is NULL or not built");
     NLFEM_TRY(check_mesh(mesh));
     NLFEM_TRY(check_cfg(cfg));
+    if (cfg->n_materials > 0 && !mesh->materials)
+        return set_error(NLFEM_E_INVALID, "mesh materials are NULL with a material table");
     if (h->nnz_node > 0 && !val) return set_error(NLFEM_E_INVALID, "val is NULL");
     if (!same_build(h, mesh, cfg))
         return set_error(NLFEM_E_MISMATCH, "mesh or configuration differs from the one the pairs were built for");
@@ -991,6 +1012,12 @@ int batch_plans(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs, n
         if (!h || h->K == 0) return set_error(NLFEM_E_INVALID, "pairs handle " + std::to_string(i) + " is NULL or not built");
         NLFEM_TRY(check_mesh(&meshes[i]));
         NLFEM_TRY(check_cfg(&cfgs[i]));
+        if (cfgs[i].n_materials > 0 && !meshes[i].materials)
+            return set_error(NLFEM_E_INVALID, "mesh materials are NULL with a material table");
+        if (material_nonsymmetric(&cfgs[i]))
+            return set_error(NLFEM_E_INVALID,
+                             "batches take symmetric material tables (a non-symmetric one runs in the "
+                             "single-problem path)");
         if (h->nnz_node > 0 && !vals[i]) return set_error(NLFEM_E_INVALID, "val " + std::to_string(i) + " is NULL");
         if (!same_build(h, &meshes[i], &cfgs[i]))
             return set_error(NLFEM_E_MISMATCH, "problem " + std::to_string(i) +

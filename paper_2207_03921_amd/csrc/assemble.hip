@@ -258,8 +258,10 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     r.val = val;
     r.err = h->err;
     r.gate = h->asm_gate;
+    r.mat = material_args(m->materials, cfg);
+    r.nonsym = h->nonsym;
     p.diag = DiagArgs{h->K,        r.sptr,   h->snbr, h->sflag, h->srec, h->far_rec, h->far_stride,
-                      h->nUF,      h->dsum,  h->err,  h->asm_gate};
+                      h->nUF,      h->dsum,  h->err,  h->asm_gate, r.mat};
     return p;
 }
 
@@ -278,9 +280,10 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
                     double *val, hipStream_t s)
 {
     AssemblePlan p = make_plan(h, m, cfg, g, val);
-    if (h->dg) {
-        // discontinuous ansatz: the identical pairs by the reduced transforms
-        // here, edge and vertex pairs by the 4D transforms of dg.hip
+    if (h->dg || h->nonsym) {
+        // discontinuous ansatz or non-symmetric material table: the identical
+        // pairs by the reduced transforms here, edge and vertex pairs by the
+        // 4D transforms of dg.hip
         p.touch[1].n = 0;
         p.touch[2].n = 0;
         NLFEM_TRY(launch_dg_assemble_rest(h, m, cfg, g, val, s));
@@ -325,7 +328,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
             else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, p.diag);
         }
         timing_end(kPhDiag, s);
-        if (h->dg) return launch_dg_rows(h, cfg, val, s);
+        if (h->dg) return launch_dg_rows(h, m, cfg, val, s);
         const size_t lds = row_lds_bytes(p.rows.maxlen, nc, p.rows.hcap);
         const unsigned grid = xcd_grid(p.rows.nrows);
         timing_begin(kPhRows, s);

@@ -937,6 +937,7 @@ struct DiagArgs {
     double *dsum;
     int32_t *err;
     SpecGate gate;
+    MatArgs mat;   // label-dependent kernel: e's block of pair (e, f) scaled by c[m(e)][m(f)]
 };
 
 // D_e of element e by the kDiagG lanes sub = 0..kDiagG-1 of an aligned lane
@@ -974,8 +975,14 @@ __device__ __forceinline__ void diag_item(const DiagArgs &a, int64_t e, int sub)
                 continue;
             }
             const TR *r = (const TR *)a.far_rec + (int64_t)u[k] * a.far_stride + (f[k] >= e ? 9 : 15) * NK;
+            if (a.mat.n == 0) {
 #pragma unroll
-            for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
+                for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
+            } else {
+                const double cf = a.mat.coef((int32_t)e, f[k]);
+#pragma unroll
+                for (int i = 0; i < 6 * NK; ++i) acc[i] += cf * (double)r[i];
+            }
         }
     }
 #pragma unroll
@@ -1022,6 +1029,12 @@ struct RowArgs {
     double *val;
     int32_t *err;
     SpecGate gate;
+    // label-dependent kernel: the block (rows e, columns f) of a
+    // non-touching pair scaled by c[m(f)][m(e)]; touching records by
+    // c[m(e)][m(f)] (a symmetric table), or, with a non-symmetric table, edge
+    // and vertex records in the discontinuous form folded per column
+    MatArgs mat;
+    int32_t nonsym;
 };
 
 constexpr int kRowQ = 64;   // elements around a node per batch (one per lane)
@@ -1100,7 +1113,7 @@ __device__ inline Frame frame_of(int cls, int32_t a0, int32_t a1, int32_t a2, in
 template <int NC>
 __device__ inline bool add_touch(double *acc, const int32_t *hk, const int32_t *hv, int32_t mask, int32_t i,
                                  int cls, int32_t e, int32_t f, int32_t e0, int32_t e1, int32_t e2,
-                                 int32_t f0, int32_t f1, int32_t f2, const double *L)
+                                 int32_t f0, int32_t f1, int32_t f2, const double *L, double scale)
 {
     constexpr int NN = NC * NC;
     const bool first = e <= f;
@@ -1112,7 +1125,7 @@ __device__ inline bool add_touch(double *acc, const int32_t *hk, const int32_t *
         if (nodes[c] == i) rr = c;
     const bool ine = e0 == i || e1 == i || e2 == i;
     const bool inf = f0 == i || f1 == i || f2 == i;
-    const double factor = (cls == 3 || (ine && inf)) ? 1.0 : 2.0;
+    const double factor = ((cls == 3 || (ine && inf)) ? 1.0 : 2.0) * scale;
     const int D = fr.nu * NC;
     bool ok = true;
 #pragma unroll
@@ -1128,6 +1141,52 @@ __device__ inline bool add_touch(double *acc, const int32_t *hk, const int32_t *
 #pragma unroll
             for (int dd = 0; dd < NC; ++dd)
                 atomicAdd(&acc[pc * NN + cc * NC + dd], factor * L[sym_index(rr * NC + cc, c * NC + dd, D)]);
+    }
+    return ok;
+}
+
+// Row i's share of an edge or vertex touching pair in the discontinuous form
+// (non-symmetric material table): L is the packed symmetric 6n x 6n matrix
+// over [stored vertices of the smaller element p | of the larger q] with the
+// plain kernel; the pair's continuous matrix is P^T L S P with P folding the
+// six slots onto their nodes and S scaling the columns of p by c[m(p)][m(q)]
+// and those of q by c[m(q)][m(p)] (the element holding x first).  Row i is the
+// sum of the rows of its slots; factor as in add_touch.
+template <int NC>
+__device__ inline bool add_touch_dg(double *acc, const int32_t *hk, const int32_t *hv, int32_t mask, int32_t i,
+                                    int32_t e, int32_t f, int32_t e0, int32_t e1, int32_t e2, int32_t f0,
+                                    int32_t f1, int32_t f2, const double *L, double cpq, double cqp)
+{
+    constexpr int NN = NC * NC;
+    constexpr int D = 6 * NC;
+    const bool first = e < f;
+    const int32_t nd[6] = {first ? e0 : f0, first ? e1 : f1, first ? e2 : f2,
+                           first ? f0 : e0, first ? f1 : e1, first ? f2 : e2};
+    int rp = -1, rq = -1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (nd[c] == i) rp = c;
+        if (nd[3 + c] == i) rq = 3 + c;
+    }
+    const double factor = rp >= 0 && rq >= 0 ? 1.0 : 2.0;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const int pc = hpos(hk, hv, mask, nd[c]);
+        if (pc < 0) {
+            ok = false;
+            continue;
+        }
+        const double sc = factor * (c < 3 ? cpq : cqp);
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc)
+#pragma unroll
+            for (int dd = 0; dd < NC; ++dd) {
+                double v = 0.0;
+                if (rp >= 0) v += L[sym_index(rp * NC + cc, c * NC + dd, D)];
+                if (rq >= 0) v += L[sym_index(rq * NC + cc, c * NC + dd, D)];
+                atomicAdd(&acc[pc * NN + cc * NC + dd], sc * v);
+            }
     }
     return ok;
 }
@@ -1161,9 +1220,19 @@ __device__ inline bool flush_touch(const RowArgs &a, RowShared &sh, int ntouch, 
             continue;
         }
         const double *L = a.touch_rec + (int64_t)u * a.touch_stride;
-        if (!add_touch<NC>(acc, hk, hv, mask, (int32_t)i, cls, sh.qe[q], sn.x, sh.qn[q][0], sh.qn[q][1],
-                           sh.qn[q][2], sn.y, sn.z, sn.w, L))
-            ok = false;
+        const int32_t e = sh.qe[q], f = sn.x;
+        if (a.nonsym && cls != 3) {
+            const int32_t p = min(e, f), r = max(e, f);
+            if (!add_touch_dg<NC>(acc, hk, hv, mask, (int32_t)i, e, f, sh.qn[q][0], sh.qn[q][1], sh.qn[q][2], sn.y,
+                                  sn.z, sn.w, L, a.mat.coef(p, r), a.mat.coef(r, p)))
+                ok = false;
+        } else {
+            // identical pairs and symmetric tables: one coefficient per pair
+            const double scale = a.mat.n == 0 ? 1.0 : a.mat.coef(e, f);
+            if (!add_touch<NC>(acc, hk, hv, mask, (int32_t)i, cls, e, f, sh.qn[q][0], sh.qn[q][1], sh.qn[q][2],
+                               sn.y, sn.z, sn.w, L, scale))
+                ok = false;
+        }
     }
     return ok;
 }
@@ -1333,6 +1402,12 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                             double xs[NK];
 #pragma unroll
                             for (int kk = 0; kk < NK; ++kk) xs[kk] = (double)xv[k][b][kk];
+                            if (a.mat.n) {
+                                // rows e, columns f: the element of the column holds x
+                                const double cf = a.mat.coef(f, e);
+#pragma unroll
+                                for (int kk = 0; kk < NK; ++kk) xs[kk] *= cf;
+                            }
                             add_sym_block<NC>(acc, px, xs);
                         }
                     }

@@ -145,6 +145,10 @@ struct DgRowArgs {
     int32_t touch_stride;
     double *val;
     SpecGate gate;
+    // label-dependent kernel: the columns of the element holding x are scaled
+    // by c[m(x's element)][m(y's element)] (far blocks (e, f): c[m(f)][m(e)];
+    // e's own block: the diagonal sums carry c[m(e)][m(f)] already)
+    MatArgs mat;
 };
 
 template <int NC, typename TR>
@@ -174,10 +178,11 @@ __global__ void __launch_bounds__(64) k_dg_rows(DgRowArgs a)
             if (cls == 0 || cls == 3 || u < 0) continue;
             const double *L = a.touch_rec + (int64_t)u * a.touch_stride;
             const int oe = (int32_t)e < a.snbr[t] ? 0 : BW;
+            const double w = a.mat.n == 0 ? 2.0 : 2.0 * a.mat.coef((int32_t)e, a.snbr[t]);
 #pragma unroll
             for (int r = 0; r < BW; ++r)
 #pragma unroll
-                for (int s = 0; s < BW; ++s) self[r][s] += 2.0 * L[sym_index(oe + r, oe + s, 2 * BW)];
+                for (int s = 0; s < BW; ++s) self[r][s] += w * L[sym_index(oe + r, oe + s, 2 * BW)];
         }
 #pragma unroll
         for (int r = 0; r < BW; ++r)
@@ -214,6 +219,8 @@ __global__ void __launch_bounds__(64) k_dg_rows(DgRowArgs a)
                             for (int d = 0; d < NC; ++d)
                                 blk[NC * p + c][NC * q + d] += ds[sym_index(p, q, 3) * NK + (NC == 1 ? 0 : c + d)];
             }
+            // coefficient of the columns of f (f holds x): c[m(f)][m(e)]
+            const double cfe = a.mat.n == 0 ? 1.0 : a.mat.coef(f, (int32_t)e);
             if (u >= 0 && cls == 0) {
                 // far record: rows of e are the rows of X (e first) or its
                 // columns (f first); the self pair stores X + X^T
@@ -227,7 +234,7 @@ __global__ void __launch_bounds__(64) k_dg_rows(DgRowArgs a)
                         for (int c = 0; c < NC; ++c)
 #pragma unroll
                             for (int d = 0; d < NC; ++d)
-                                blk[NC * p + c][NC * q + d] += (double)rec[xi * NK + (NC == 1 ? 0 : c + d)];
+                                blk[NC * p + c][NC * q + d] += cfe * (double)rec[xi * NK + (NC == 1 ? 0 : c + d)];
                     }
             } else if (u >= 0) {
                 const double *L = a.touch_rec + (int64_t)u * a.touch_stride;
@@ -236,7 +243,7 @@ __global__ void __launch_bounds__(64) k_dg_rows(DgRowArgs a)
 #pragma unroll
                     for (int r = 0; r < BW; ++r)
 #pragma unroll
-                        for (int s = 0; s < BW; ++s) blk[r][s] += L[sym_index(r, s, BW)];
+                        for (int s = 0; s < BW; ++s) blk[r][s] += cfe * L[sym_index(r, s, BW)];
                 } else {
                     // edge / vertex: [first element | second element] unknowns;
                     // both ordered pairs give the same matrix
@@ -244,7 +251,7 @@ __global__ void __launch_bounds__(64) k_dg_rows(DgRowArgs a)
 #pragma unroll
                     for (int r = 0; r < BW; ++r)
 #pragma unroll
-                        for (int s = 0; s < BW; ++s) blk[r][s] += 2.0 * L[sym_index(oe + r, of + s, 2 * BW)];
+                        for (int s = 0; s < BW; ++s) blk[r][s] += 2.0 * cfe * L[sym_index(oe + r, of + s, 2 * BW)];
                 }
             }
 #pragma unroll
@@ -446,12 +453,12 @@ int launch_dg_assemble_rest(const nlfem_pairs *h, const nlfem_mesh *m, const nlf
     return NLFEM_OK;
 }
 
-int launch_dg_rows(const nlfem_pairs *h, const nlfem_config *cfg, double *val, hipStream_t s)
+int launch_dg_rows(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, double *val, hipStream_t s)
 {
     if (h->nnz_node == 0) return NLFEM_OK;
     DgRowArgs a{h->K,           h->dg_ptr,        h->loff + (int64_t)kLsS * (h->K + 1), h->snbr, h->sflag,
                 h->srec,        h->far_rec,       h->far_stride, h->dsum, h->touch_rec, h->touch_stride, val,
-                h->asm_gate};
+                h->asm_gate,    material_args(m->materials, cfg)};
     const unsigned grid = xcd_grid(h->K);
     const bool fp32 = cfg->precision == NLFEM_P_MIXED;
     timing_begin(kPhRows, s);

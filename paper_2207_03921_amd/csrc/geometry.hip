@@ -46,6 +46,8 @@ struct GeoArgs {
     uint32_t *node_flags;
     int32_t *err;
     unsigned long long *red;
+    const int32_t *mat;   // material ids, checked against nmat when a table is given
+    int32_t nmat;
 };
 
 __global__ void __launch_bounds__(256) k_geometry(GeoArgs a, RuleArgs r)
@@ -67,6 +69,7 @@ __global__ void __launch_bounds__(256) k_geometry(GeoArgs a, RuleArgs r)
         const double d = fabs(J00 * J11 - J01 * J10);
         const bool active = lab == 1 || lab == 2;
         if (ok && active && !(d > 0.0)) atomicOr(a.err, kErrArea);
+        if (active && a.nmat > 0 && (unsigned)a.mat[k] >= (unsigned)a.nmat) atomicOr(a.err, kErrMaterial);
         a.v0[k] = make_double2(v0x, v0y);
         a.J[k] = make_double4(J00, J01, J10, J11);
         a.det[k] = d;
@@ -164,8 +167,9 @@ double key_to_double(unsigned long long key)
 
 int launch_geometry(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s, const ZeroList &later)
 {
-    GeoArgs a{h->K, h->M, m->vertices, m->elements, m->labels, h->v0, h->J, h->det,
-              h->bary, h->xp, h->node_flags, h->err, h->red};
+    GeoArgs a{h->K,        h->M,     m->vertices, m->elements, m->labels,
+              h->v0,       h->J,     h->det,      h->bary,     h->xp,
+              h->node_flags, h->err, h->red,      h->materials > 0 ? m->materials : nullptr, h->materials};
     ZeroList z = later;
     z.add(h->node_flags, h->M);
     NLFEM_TRY(launch_zero(z, h->red, s));   // also clears err (a reduction slot)

@@ -38,7 +38,38 @@ enum : int32_t {
     kErrCell = 16,       // cell occupancy above the pair-search tile size
     kErrClip = 32,       // polygon clip longer than the bound found by the pair search (internal bug)
     kErrEdge = 64,       // an edge shared by more than two elements (non-conforming mesh)
+    kErrMaterial = 128,  // material id outside the configuration's table
 };
+
+// Material table of a label-dependent kernel: Psi(x, y) = c[m(x)][m(y)] Psi0
+// (n = 0: no table, every coefficient 1).  Passed by value.
+constexpr int kMaxMaterials = 4;
+struct MatArgs {
+    const int32_t *mat = nullptr;   // [K] material of each element
+    int32_t n = 0;
+    double c[kMaxMaterials * kMaxMaterials] = {};
+    // coefficient of the ordered element pair (material of x's element first)
+    __device__ double coef(int32_t ex, int32_t ey) const { return n == 0 ? 1.0 : c[mat[ex] * n + mat[ey]]; }
+};
+inline MatArgs material_args(const int32_t *mat, const nlfem_config *cfg)
+{
+    MatArgs m;
+    if (cfg->n_materials > 0) {
+        m.mat = mat;
+        m.n = cfg->n_materials;
+        for (int i = 0; i < m.n * m.n; ++i) m.c[i] = cfg->material_c[i];
+    }
+    return m;
+}
+// true when some c[a][b] != c[b][a]
+inline bool material_nonsymmetric(const nlfem_config *cfg)
+{
+    const int n = cfg->n_materials;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < a; ++b)
+            if (cfg->material_c[a * n + b] != cfg->material_c[b * n + a]) return true;
+    return false;
+}
 
 // Quadrature tables passed by value (kernel arguments live in scalar registers).
 struct RuleArgs {
@@ -174,10 +205,15 @@ struct nlfem_pairs {
     const double *mesh_vertices = nullptr;
     const int32_t *mesh_elements = nullptr;
     const int32_t *mesh_labels = nullptr;
+    const int32_t *mesh_materials = nullptr;   // validated by the build when a table is given
     int64_t M = 0, K = 0;
     int32_t ncomp = 1;
     int32_t kernel = 0, approach = 0, singular = 0;
     int32_t dg = 0;              // discontinuous ansatz
+    // material table given at build / non-symmetric: edge and vertex touching
+    // pairs then take the 4D transforms over the pair's six element unknowns
+    // (the records of the discontinuous path), scaled per column in the rows
+    int32_t materials = 0, nonsym = 0;
     double delta = 0.0;
     nlfem::RuleArgs rules{};
     nlfem::PolyArgs poly{};
@@ -405,7 +441,7 @@ int launch_dg_counts(nlfem_pairs *h, hipStream_t s);
 int launch_dg_pattern(const nlfem_pairs *h, int64_t *row_ptr, int32_t *col, hipStream_t s);
 int launch_dg_assemble_rest(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
                             double *val, hipStream_t s);
-int launch_dg_rows(const nlfem_pairs *h, const nlfem_config *cfg, double *val, hipStream_t s);
+int launch_dg_rows(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, double *val, hipStream_t s);
 int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg,
                     const GaussArgs &g, double *val, hipStream_t s);
 // rhs.hip

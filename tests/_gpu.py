@@ -12,7 +12,7 @@ def make_config(w, **over):
              outer_xi=w["outer"].xi, outer_w=w["outer"].w, inner_xi=w["inner"].xi,
              inner_w=w["inner"].w, approach=w.get("approach", "bary"),
              singular_n=int(w.get("singular_n", 0)), precision=w.get("precision", "fp64"),
-             ansatz=w.get("ansatz", "cg"))
+             ansatz=w.get("ansatz", "cg"), material_c=w.get("material_c"))
     if d["approach"] == "poly":
         d["polygon_dirs"] = polygon_dirs(int(w.get("polygon_n", 32)))
     d.update(over)

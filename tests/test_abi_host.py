@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(nl):
     L = nl.lib()
     for n in _declared():
         assert hasattr(L, n), n
-    assert nl.nlfem_version() == nl.ABI_VERSION == 4
+    assert nl.nlfem_version() == nl.ABI_VERSION == 5
 
 
 def _cfg(nl, **over):

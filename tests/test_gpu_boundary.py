@@ -234,3 +234,35 @@ def test_batch_rejects_single_problem_only_configs(nl, kind):
     torch.cuda.synchronize()
     assert torch.isfinite(val).all() and float(val.abs().max()) > 0.0
     nl.nlfem_pairs_free(pairs)
+
+
+def test_batch_material_tables(nl):
+    """A symmetric material table runs in batches, bit-identical to the
+    single-problem assembly; a non-symmetric one is refused there."""
+    import dataclasses
+    import torch
+    from inputs import square_mesh
+    mesh = square_mesh(10, delta=0.2, jitter=0.1, seed=60)
+    bx = mesh.vertices[mesh.elements].mean(axis=1)[:, 0]
+    mesh = dataclasses.replace(mesh, materials=(bx > 0.5).astype(np.int32))
+    w = dict(inv_dist_jittered(n=10, delta=0.2, precision="fp64"), mesh=mesh,
+             material_c=np.array([[1.0, 0.4], [0.4, 2.0]]))
+    cfg = make_config(w)
+    dm = nl.DeviceMesh.from_numpy(mesh)
+    pairs = nl.nlfem_build_pairs(dm, cfg)
+    ref = nl.nlfem_assemble(dm, cfg, pairs)
+    nnz = nl.nlfem_pairs_info(pairs)["nnz"]
+    val = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+    b = nl.nlfem_batch_create([dm], [cfg], [pairs], [val])
+    nl.nlfem_batch_assemble(b)
+    torch.cuda.synchronize()
+    assert _same_values(val.cpu().numpy(), ref[:nnz].cpu().numpy())
+    del b
+    bad = make_config(dict(w, material_c=np.array([[1.0, 0.3], [2.5, 0.7]])))
+    pairs2 = nl.nlfem_build_pairs(dm, bad)
+    with pytest.raises(nl.NlfemError) as e:
+        nl.nlfem_batch_create([dm], [bad], [pairs2], [torch.zeros(nl.nlfem_pairs_info(pairs2)["nnz"],
+                                                                    dtype=torch.float64, device="cuda")])
+    assert e.value.code == -1 and "symmetric" in str(e.value)
+    nl.nlfem_pairs_free(pairs)
+    nl.nlfem_pairs_free(pairs2)

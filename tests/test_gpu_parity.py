@@ -408,3 +408,74 @@ def test_parity_full_size_sampled(oracle_lib, name, precision):
         r = G @ ones
         scale = abs(G) @ ones
         assert np.all(np.abs(r[dofm]) <= (1e-13 if precision == "fp64" else 1e-6) * scale[dofm])
+
+
+_NONSYM = np.array([[1.0, 0.3], [2.5, 0.7]])
+_SYM = np.array([[1.0, 0.4], [0.4, 2.0]])
+
+
+def _mat(mesh, cut=0.45):
+    """Material 1 for elements whose barycentre has x1 > cut, else 0."""
+    import dataclasses
+    bx = mesh.vertices[mesh.elements].mean(axis=1)[:, 0]
+    return dataclasses.replace(mesh, materials=(bx > cut).astype(np.int32))
+
+
+def _material_cases():
+    """Label-dependent kernels C[m(x)][m(y)] Psi0: a symmetric table scales
+    each pair's records; a non-symmetric one scales the columns of each
+    element and takes the touching edge/vertex pairs through the 4D form."""
+    return {
+        "mat_const_bary_nonsym": dict(_w("constant", _mat(square_mesh(10, delta=0.2, jitter=0.2, seed=50)), 0.2),
+                                      material_c=_NONSYM),
+        "mat_invdist_sym": dict(_w("inv_dist", _mat(square_mesh(10, delta=0.2, jitter=0.2, seed=51)), 0.2),
+                                material_c=_SYM),
+        "mat_invdist_nonsym": dict(_w("inv_dist", _mat(square_mesh(10, delta=0.2, jitter=0.2, seed=52)), 0.2),
+                                   material_c=_NONSYM),
+        "mat_peri_nonsym": dict(_w("peridynamic", _mat(square_mesh(8, delta=0.3, jitter=0.1, seed=53)), 0.3),
+                                material_c=_NONSYM),
+        "mat_const_poly_nonsym": dict(_w("constant", _mat(square_mesh(10, delta=0.15, jitter=0.1, seed=54)), 0.15,
+                                         approach="poly"), material_c=_NONSYM),
+        "mat_frac_sym_approxcaps": dict(_w("frac_half", _mat(square_mesh(10, delta=0.2, jitter=0.1, seed=55)),
+                                           0.2, approach="approxcaps", rule=paper7()), material_c=_SYM),
+        "mat_invdist_nozerodiv_nonsym": dict(_w("inv_dist", _mat(square_mesh(10, delta=0.2, jitter=0.1, seed=56)),
+                                                0.2, rule=paper7(), singular_n=0), material_c=_NONSYM),
+        "mat_dg_invdist_nonsym": dict(_w("inv_dist", _mat(square_mesh(10, delta=0.2, jitter=0.2, seed=57)), 0.2,
+                                         ansatz="dg"), material_c=_NONSYM),
+        "mat_dg_peri_sym": dict(_w("peridynamic", _mat(square_mesh(8, delta=0.3, jitter=0.1, seed=58)), 0.3,
+                                   ansatz="dg"), material_c=_SYM),
+    }
+
+
+@pytest.mark.parametrize("name", list(_material_cases()))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_materials(oracle_lib, name, precision):
+    w = _material_cases()[name]
+    print(f"case {name} {precision}", flush=True)
+    _compare_full(oracle_lib, w, precision)
+
+
+def test_material_table_validation():
+    """Tables: 1..4 materials, finite, non-symmetric ones not with the s = 1/2
+    kernel; the mesh needs materials with a table; ids outside the table are
+    E_MESH at the build."""
+    import torch
+    import paper_2207_03921_amd as nl
+    from _gpu import make_config
+    mesh = _mat(square_mesh(6, delta=0.3))
+    dm = nl.DeviceMesh.from_numpy(mesh)
+    w = _w("inv_dist", mesh, 0.3)
+    for table, msg in [(np.ones((5, 5)), "n_materials"), (np.array([[1.0, np.inf], [1.0, 1.0]]), "finite")]:
+        with pytest.raises(nl.NlfemError) as e:
+            nl.nlfem_build_pairs(dm, make_config(dict(w, material_c=table)))
+        assert e.value.code == -1 and msg in str(e.value)
+    with pytest.raises(nl.NlfemError) as e:
+        nl.nlfem_build_pairs(dm, make_config(dict(_w("frac_half", mesh, 0.3), material_c=_NONSYM)))
+    assert e.value.code == -1 and "non-symmetric" in str(e.value)
+    with pytest.raises(nl.NlfemError) as e:
+        nl.nlfem_build_pairs(nl.DeviceMesh(dm.vertices, dm.elements, dm.labels), make_config(dict(w, material_c=_SYM)))
+    assert e.value.code == -1 and "materials" in str(e.value)
+    bad = nl.DeviceMesh(dm.vertices, dm.elements, dm.labels, torch.full_like(dm.labels, 2))
+    with pytest.raises(nl.NlfemError) as e:
+        nl.nlfem_build_pairs(bad, make_config(dict(w, material_c=_SYM)))
+    assert e.value.code == -2 and "material" in str(e.value)

@@ -978,3 +978,106 @@ def test_peridynamic_dg_convergence_table5(oracle_lib):
     rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
     for got, row in zip(rates, rows[1:]):
         assert got >= 1.8 and abs(got - row[3]) <= 0.25, rates
+
+
+# ----------------------------------------------------------------------
+# label-dependent (material) kernels, possibly non-symmetric:
+# Psi(x, y) = C[m(x)][m(y)] Psi0(x - y)
+
+_TABLE = np.array([[1.0, 0.3], [2.5, 0.7]])   # non-symmetric
+
+
+def _two_materials(mesh):
+    """Material 1 for elements whose barycentre has x1 > 0.45, else 0."""
+    import dataclasses
+    bx = mesh.vertices[mesh.elements].mean(axis=1)[:, 0]
+    return dataclasses.replace(mesh, materials=(bx > 0.45).astype(np.int32))
+
+
+@pytest.mark.parametrize("singular_n,rule", [(0, "gauss7"), (4, "paper7")])
+def test_material_kernel_full_ball_closed_form(oracle_lib, singular_n, rule):
+    """Constant kernel c C[m(x)][m(y)] with the ball covering the mesh:
+    a(phi_j, phi_i) = c int int (phi_i(x) - phi_i(y)) (C_xy phi_j(x) - C_yx phi_j(y))
+    over D x D, which with D_a the elements of material a, M^a the P1 mass
+    matrix over D_a and m^a_i = int_{D_a} phi_i is
+      c sum_ab [C_ab |D_b| M^a_ij - C_ba m^a_i m^b_j - C_ab m^b_i m^a_j + C_ba |D_a| M^b_ij]
+    for every degree of freedom i.  A transposed table, a swapped x/y or a
+    missing direction fails it."""
+    mesh = _two_materials(square_mesh(5, m=1, jitter=0.2, seed=4))
+    r = gauss7() if rule == "gauss7" else paper7()
+    c = 3.7
+    P = oracle_lib.Problem(mesh, dict(cfg("constant", c=c, delta=100.0, rule=r, singular_n=singular_n),
+                                      material_c=_TABLE))
+    A = dense(P, *P.assemble())
+    Ms, ms, Ds = [], [], []
+    import dataclasses
+    for a in range(2):
+        sub = dataclasses.replace(mesh, elements=mesh.elements[mesh.materials == a],
+                                  labels=mesh.labels[mesh.materials == a])
+        M, mv = mass_matrix(sub)
+        Ms.append(M)
+        ms.append(mv)
+        Ds.append(mv.sum())
+    C = _TABLE
+    expect = np.zeros_like(A)
+    for a in range(2):
+        for b in range(2):
+            expect += C[a, b] * Ds[b] * Ms[a] - C[b, a] * np.outer(ms[a], ms[b]) \
+                - C[a, b] * np.outer(ms[b], ms[a]) + C[b, a] * Ds[a] * Ms[b]
+    expect *= c
+    dof = P.isdof()
+    assert np.max(np.abs(A[dof] - expect[dof])) < 1e-13 * np.abs(expect).max()
+    # the transposed table gives another matrix (the orientation matters)
+    Pt = oracle_lib.Problem(mesh, dict(cfg("constant", c=c, delta=100.0, rule=r, singular_n=singular_n),
+                                       material_c=_TABLE.T.copy()))
+    At = dense(Pt, *Pt.assemble())
+    assert np.max(np.abs(At[dof] - A[dof])) > 1e-3 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("kernel", ["inv_dist", "peridynamic"])
+def test_material_kernel_null_space_and_symmetry(oracle_lib, kernel):
+    """All elements in Omega (pure interaction problem): a(phi_j, 1) = 0 for a
+    kernel of any table, so every column of the matrix sums to zero; the rows
+    sum to a(1, phi_i) = 2 int int (C_xy - C_yx) Psi0 phi_i(x), which is not
+    zero for a non-symmetric table.  A symmetric table gives a symmetric
+    matrix, and the table c * ones gives c times the plain matrix (touching
+    pairs through the transforms included)."""
+    mesh = _two_materials(square_mesh(6, delta=0.3, jitter=0.2, seed=8, neumann=True))
+    base = cfg(kernel, c=1.3, delta=0.3, singular_n=5)
+    n = base["ncomp"]
+    A = dense(oracle_lib.Problem(mesh, dict(base, material_c=_TABLE)),
+              *oracle_lib.Problem(mesh, dict(base, material_c=_TABLE)).assemble())
+    scale = np.abs(A).max()
+    colsum = A.reshape(A.shape[0], -1, n).sum(axis=0) if n == 1 else \
+        np.stack([A[c::n].sum(axis=0) for c in range(n)])
+    assert np.abs(colsum).max() <= 1e-13 * scale
+    rowsum = A.sum(axis=1) if n == 1 else np.stack([A[:, c::n].sum(axis=1) for c in range(n)])
+    assert np.abs(rowsum).max() > 1e-3 * scale
+    sym = np.array([[1.0, 0.4], [0.4, 2.0]])
+    Ps = oracle_lib.Problem(mesh, dict(base, material_c=sym))
+    As = dense(Ps, *Ps.assemble())
+    assert np.abs(As - As.T).max() <= 1e-14 * np.abs(As).max()
+    P1 = oracle_lib.Problem(mesh, dict(base, material_c=np.full((2, 2), 1.7)))
+    P0 = oracle_lib.Problem(mesh, base)
+    A1, A0 = dense(P1, *P1.assemble()), dense(P0, *P0.assemble())
+    assert np.abs(A1 - 1.7 * A0).max() <= 1e-14 * np.abs(A1).max()
+
+
+def test_material_dg_restricts_to_cg(oracle_lib):
+    """P^T A_DG P = A_CG with a non-symmetric table (the DG edge and vertex
+    pairs by the 4D transforms, the continuous ones too)."""
+    mesh = _two_materials(square_mesh(8, delta=0.3, jitter=0.2, seed=3))
+    c_cg = dict(cfg("inv_dist", c=1.5, delta=0.3, singular_n=5), material_c=_TABLE)
+    Pc = oracle_lib.Problem(mesh, c_cg)
+    Pd = oracle_lib.Problem(mesh, dict(c_cg, ansatz="dg"))
+    rc, cc, vc = Pc.assemble()
+    rd, cd, vd = Pd.assemble()
+    Nc, Nd = Pc.n_unknowns, Pd.n_unknowns
+    Ac = sp.csr_matrix((vc, cc, rc), shape=(Nc, Nc))
+    Ad = sp.csr_matrix((vd, cd, rd), shape=(Nd, Nd))
+    E = mesh.elements
+    r = [3 * k + a for k in range(E.shape[0]) for a in range(3)]
+    q = [E[k, a] for k in range(E.shape[0]) for a in range(3)]
+    P = sp.csr_matrix((np.ones(len(r)), (r, q)), shape=(Nd, Nc))
+    dof = Pc.isdof()
+    assert abs((P.T @ Ad @ P - Ac).tocsr()[dof]).max() <= 1e-14 * abs(Ac[dof]).max()
