@@ -236,20 +236,51 @@ def bench_batched(args):
     bs = [torch.empty(c.ncomp * d.vertices.shape[0], dtype=torch.float64, device="cuda") for c, d in zip(cfgs, dms)]
     cache = os.path.join(ROOT, "paper_2207_03921_amd", "tune_cache.txt")
     batch = nl.nlfem_batch_create(dms, cfgs, pairs, vals, tune_cache=cache, tune=1)
+    # The handles are independent: their rebuilds (and load vectors) run on
+    # several streams at once, the largest problems spread first over the
+    # least loaded stream; events order them against the batched assembly
+    # on the default stream (a rebuild rewrites what the last assembly read).
+    n_str = max(1, args.build_streams)
+    streams = [torch.cuda.Stream() for _ in range(n_str)]
+    load = [0] * n_str
+    lane = [0] * len(ws)
+    for i in sorted(range(len(ws)), key=lambda i: -infos[i]["n_pairs"]):
+        s = min(range(n_str), key=load.__getitem__)
+        lane[i] = s
+        load[s] += infos[i]["n_pairs"]
+    main_stream = torch.cuda.current_stream()
 
-    def step():
-        for d, c, p in zip(dms, cfgs, pairs):
-            nl.nlfem_build_pairs(d, c, pairs=p)
+    def fan_out(work, spread=True):
+        if not spread:   # everything on the default stream
+            for i in range(len(ws)):
+                work(i, main_stream)
+            return
+        ev = torch.cuda.Event()
+        ev.record(main_stream)
+        for s in streams:
+            s.wait_event(ev)
+        for i in range(len(ws)):
+            work(i, streams[lane[i]])
+        for s in streams:
+            e = torch.cuda.Event()
+            e.record(s)
+            main_stream.wait_event(e)
+
+    def rebuilds(spread=True):
+        fan_out(lambda i, s: nl.nlfem_build_pairs(dms[i], cfgs[i], pairs=pairs[i], stream=s), spread)
+
+    def step(spread=True):
+        rebuilds(spread)
         nl.nlfem_batch_assemble(batch)
-        for d, c, a, b in zip(dms, cfgs, affs, bs):
-            nl.nlfem_rhs(d, c, f_affine=a, b=b)
+        fan_out(lambda i, s: nl.nlfem_rhs(dms[i], cfgs[i], f_affine=affs[i], b=bs[i], stream=s), spread)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # one untimed step with every phase timed: the dominant phase
+    # one untimed step with every phase timed, on one stream so that the
+    # phase times are those of the kernels alone: the dominant phase
     _timing_mask_all()
-    step()
+    step(spread=False)
     torch.cuda.synchronize()
     phase_ms = _phases_per_step(1)
     dominant = max(phase_ms, key=phase_ms.get)
@@ -278,7 +309,7 @@ def bench_batched(args):
 
     reps = max(3, args.steps // 2)
     # parts of the step
-    t_build = timed(lambda: [nl.nlfem_build_pairs(d, c, pairs=p) for d, c, p in zip(dms, cfgs, pairs)], reps)
+    t_build = timed(rebuilds, reps)
     for p in pairs:
         nl.nlfem_pairs_info(p)   # finishes the rebuilds' checks
     t_asm = timed(lambda: nl.nlfem_batch_assemble(batch), reps)
@@ -345,7 +376,8 @@ def bench_batched(args):
                    "triangles": int(sum(w["mesh"].n_elements for w in ws)), "ordered_pairs": n_pairs,
                    "touching_pairs": int(sum(i["n_vertex"] + i["n_edge"] + i["n_ident"] for i in infos)),
                    "nnz": int(sum(i["nnz"] for i in infos)), "precision": prec,
-                   "step": "64 rebuilds + batched assembly + 64 load vectors"},
+                   "step": "64 rebuilds + batched assembly + 64 load vectors",
+                   "build_streams": n_str},
         "roofline": roof,
         "phase_ms_per_step": {k: round(v, 4) for k, v in phase_ms.items()},
         "parts_ms": {"rebuilds_64": t_build * 1e3, "batched_assembly": t_asm * 1e3,
@@ -502,6 +534,8 @@ def main():
     ap.add_argument("--workload", default="batched64", choices=WORKLOADS)
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--build-streams", type=int, default=4,
+                    help="streams the batched workload's rebuilds and load vectors are spread over")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (counter calibration)")
     args = ap.parse_args()

@@ -7,10 +7,11 @@ using namespace items;
 namespace {
 
 // record staging through LDS (coalesced stores) where it fits: all but the
-// two-component FP64 records (32 KB per wave)
+// two-component FP64 records (46 KB per wave)
 template <int KER, typename T>
 constexpr bool far_staged() { return !(Ker<KER>::NK == 3 && sizeof(T) == 8); }
 
+// thread per record; consecutive lanes hold consecutive records
 template <int KER, typename T, int PM, bool POLY>
 __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArgs r2)
 {
@@ -21,7 +22,7 @@ __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArg
         far_item<KER, T, PM, POLY>(a, r1, r2, idx);
         return;
     }
-    constexpr int NV = 21 * Ker<KER>::NK;
+    constexpr int NV = Rec<Ker<KER>::NK>::kValues;
     __shared__ T slots[far_staged<KER, T>() ? 4 * 64 * NV : 1];
     const int64_t idx0 = idx - (threadIdx.x & 63);
     if (idx0 >= a.n) return;   // whole waves leave together
@@ -267,7 +268,7 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
 
 }  // namespace items
 
-int far_record_stride(int ncomp) { return ncomp == 1 ? 21 : 63; }
+int far_record_stride(int ncomp) { return ncomp == 1 ? Rec<1>::kValues : Rec<3>::kValues; }
 // packed symmetric local matrices over the union of the pair's unknowns:
 // at most 5 nodes (continuous) or 6 unknowns (discontinuous) per component
 int touch_record_stride(int ncomp, bool dg)

@@ -185,6 +185,24 @@ struct FarArgs {
     SpecGate gate;           // single-problem launches after an unchecked rebuild
 };
 
+// Non-touching pair records (n records, NK values per block entry), stored
+// by use: the row chunks R_loc (row loc of X: e's vertex loc against the
+// vertices of f), the column chunks C_loc (column loc of X: f's vertex loc
+// against the vertices of e), then the element-diagonal blocks [De | Df].
+// Each array is contiguous over the record index, so the rows of e's
+// vertices read the R chunks of e's upper list entries and those of f's
+// vertices the C chunks, each chunk once and only the values used.
+template <int NK>
+struct Rec {
+    static constexpr int kValues = 30 * NK;   // per record
+    __host__ __device__ static int64_t r(int loc, int64_t u, int64_t n) { return ((int64_t)loc * n + u) * 3 * NK; }
+    __host__ __device__ static int64_t c(int loc, int64_t u, int64_t n)
+    {
+        return ((int64_t)(3 + loc) * n + u) * 3 * NK;
+    }
+    __host__ __device__ static int64_t d(int64_t u, int64_t n) { return 18 * NK * n + u * 12 * NK; }
+};
+
 // rule points of the two roles (A on e, B on f)
 struct RoleArgs {
     int32_t PA, PB;
@@ -522,80 +540,84 @@ __device__ inline uint32_t straddle_bits(uint32_t m, int P)
     return b;
 }
 
+// Record idx (Rec layout over a.n records).  Consecutive lanes hold
+// consecutive records, so each chunk store of a wave covers a contiguous
+// range.  The self pair (e, e) stores X + X^T in its R chunks and De + Df.
 template <int KER, typename T>
 __device__ __forceinline__ void far_store(const FarArgs &a, int64_t idx, bool self, const FarAcc<KER, T> &acc)
 {
     constexpr int NK = Ker<KER>::NK;
-    T *out = (T *)a.rec + idx * a.stride;
-    if (self) {
+    using L = Rec<NK>;
+    T *base = (T *)a.rec;
+    const int64_t n = a.n;
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
+    for (int loc = 0; loc < 3; ++loc) {
+        T *r = base + L::r(loc, idx, n);
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+        for (int b = 0; b < 3; ++b)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) out[(3 * i + j) * NK + k] = acc.X[i][j][k] + acc.X[j][i][k];
+            for (int k = 0; k < NK; ++k) r[b * NK + k] = self ? acc.X[loc][b][k] + acc.X[b][loc][k] : acc.X[loc][b][k];
+    }
+    if (!self) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                out[(9 + i) * NK + k] = acc.De[i][k] + acc.Df[i][k];
-                out[(15 + i) * NK + k] = 0;
-            }
-        }
-    } else {
+        for (int loc = 0; loc < 3; ++loc) {
+            T *c = base + L::c(loc, idx, n);
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
+            for (int b = 0; b < 3; ++b)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) out[i * NK + k] = acc.X[i / 3][i % 3][k];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                out[(9 + i) * NK + k] = acc.De[i][k];
-                out[(15 + i) * NK + k] = acc.Df[i][k];
-            }
+                for (int k = 0; k < NK; ++k) c[b * NK + k] = acc.X[b][loc][k];
         }
     }
+    T *d = base + L::d(idx, n);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            d[i * NK + k] = self ? acc.De[i][k] + acc.Df[i][k] : acc.De[i][k];
+            d[(6 + i) * NK + k] = self ? (T)0 : acc.Df[i][k];
+        }
 }
 
-// Records of the pairs idx0 .. idx0 + nvalid - 1 of one wave (lane
-// lane0 + l holds pair idx0 + l), written through LDS so that the wave
-// stores its contiguous block of records with consecutive addresses.  All
-// lanes of the wave call it.
+// Records idx0 .. idx0 + nvalid - 1 of one wave (lane lane0 + l holds record
+// idx0 + l), through LDS: the wave then stores its block of each record
+// array with consecutive lanes at consecutive addresses.  All lanes of the
+// wave call it.  slots: Rec<NK>::kValues values per lane.
 template <int KER, typename T>
 __device__ __forceinline__ void far_store_wave(const FarArgs &a, int64_t idx0, int nvalid, bool self,
                                                const FarAcc<KER, T> &acc, T *slots, int lane0 = 0)
 {
-    constexpr int NK = Ker<KER>::NK, NV = 21 * NK;
+    constexpr int NK = Ker<KER>::NK, NV = Rec<NK>::kValues, W = 3 * NK;
     const int hw = threadIdx.x & 63;
-    const int lane = hw - lane0;   // position of this lane's pair in the run
-    T *sl = slots + lane * NV;
+    const int lane = hw - lane0;   // position of this lane's record in the run
     if (lane >= 0 && lane < nvalid) {
-        if (self) {
+        // [R_0 R_1 R_2 C_0 C_1 C_2 | De Df], the order of the record arrays
+        T *sl = slots + lane * NV;
+#pragma unroll
+        for (int loc = 0; loc < 3; ++loc)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int k = 0; k < NK; ++k) {
+                    sl[loc * W + b * NK + k] = self ? acc.X[loc][b][k] + acc.X[b][loc][k] : acc.X[loc][b][k];
+                    sl[(3 + loc) * W + b * NK + k] = self ? (T)0 : acc.X[b][loc][k];
+                }
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) sl[(3 * i + j) * NK + k] = acc.X[i][j][k] + acc.X[j][i][k];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    sl[(9 + i) * NK + k] = acc.De[i][k] + acc.Df[i][k];
-                    sl[(15 + i) * NK + k] = 0;
-                }
+                sl[6 * W + i * NK + k] = self ? acc.De[i][k] + acc.Df[i][k] : acc.De[i][k];
+                sl[6 * W + (6 + i) * NK + k] = self ? (T)0 : acc.Df[i][k];
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < NK; ++k) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) sl[i * NK + k] = acc.X[i / 3][i % 3][k];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    sl[(9 + i) * NK + k] = acc.De[i][k];
-                    sl[(15 + i) * NK + k] = acc.Df[i][k];
-                }
-            }
-        }
     }
     wave_sync();
-    T *out = (T *)a.rec + idx0 * NV;   // the record stride is NV
-    for (int t = hw; t < nvalid * NV; t += 64) out[t] = slots[t];
+    T *base = (T *)a.rec;
+    const int64_t n = a.n;
+    for (int p = 0; p < 6; ++p) {
+        T *out = base + ((int64_t)p * n + idx0) * W;
+        for (int t = hw; t < nvalid * W; t += 64) out[t] = slots[(t / W) * NV + p * W + t % W];
+    }
+    T *out = base + Rec<NK>::d(idx0, n);
+    for (int t = hw; t < nvalid * 4 * W; t += 64) out[t] = slots[(t / (4 * W)) * NV + 6 * W + t % (4 * W)];
     wave_sync();
 }
 
@@ -974,7 +996,7 @@ __device__ __forceinline__ void diag_item(const DiagArgs &a, int64_t e, int sub)
                 bad = true;
                 continue;
             }
-            const TR *r = (const TR *)a.far_rec + (int64_t)u[k] * a.far_stride + (f[k] >= e ? 9 : 15) * NK;
+            const TR *r = (const TR *)a.far_rec + Rec<NK>::d(u[k], a.n_far) + (f[k] >= e ? 0 : 6) * NK;
             if (a.mat.n == 0) {
 #pragma unroll
                 for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
@@ -1376,13 +1398,12 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                         // self pair stores X + X^T
                         const int32_t e = qe[qq[k]];
                         const int loc = qloc[qq[k]];
-                        const TR *r = (const TR *)a.far_rec + (int64_t)uu[k] * a.far_stride;
+                        const TR *r = (const TR *)a.far_rec + (f >= e ? Rec<NK>::r(loc, uu[k], a.n_far)
+                                                                       : Rec<NK>::c(loc, uu[k], a.n_far));
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) {
-                            const int xi = f >= e ? 3 * loc + b : 3 * b + loc;
+                        for (int b = 0; b < 3; ++b)
 #pragma unroll
-                            for (int kk = 0; kk < NK; ++kk) xv[k][b][kk] = r[xi * NK + kk];
-                        }
+                            for (int kk = 0; kk < NK; ++kk) xv[k][b][kk] = r[b * NK + kk];
                     }
                 }
 #pragma unroll

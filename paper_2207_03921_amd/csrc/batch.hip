@@ -89,16 +89,16 @@ __device__ inline int64_t grab(const QueueArgs &q, unsigned long long *slot)
     return b0;
 }
 
-// records staged through LDS as in the single-problem kernel where it fits
 template <int KER, typename T>
 constexpr bool batch_far_staged() { return !(Ker<KER>::NK == 3 && sizeof(T) == 8); }
 
+// records staged through LDS as in the single-problem kernel where it fits
 template <int KER, typename T, int PM, bool POLY>
 __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *__restrict__ fa, const RoleArgs *__restrict__ r1,
                                                 const RoleArgs *__restrict__ r2)
 {
     constexpr bool STAGED = batch_far_staged<KER, T>() && !POLY;
-    constexpr int NV = 21 * Ker<KER>::NK;
+    constexpr int NV = Rec<Ker<KER>::NK>::kValues;
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
     __shared__ T slots[STAGED ? 4 * 64 * NV : 1];

@@ -139,7 +139,7 @@ struct DgRowArgs {
     const uint8_t *sflag;
     const int32_t *srec;
     const void *far_rec;
-    int32_t far_stride;
+    int64_t n_far;     // records (Rec layout)
     const double *dsum;      // [K][6 NK]
     const double *touch_rec;
     int32_t touch_stride;
@@ -224,18 +224,18 @@ __global__ void __launch_bounds__(64) k_dg_rows(DgRowArgs a)
             if (u >= 0 && cls == 0) {
                 // far record: rows of e are the rows of X (e first) or its
                 // columns (f first); the self pair stores X + X^T
-                const TR *rec = (const TR *)a.far_rec + (int64_t)u * a.far_stride;
 #pragma unroll
-                for (int p = 0; p < 3; ++p)
+                for (int p = 0; p < 3; ++p) {
+                    const TR *rec = (const TR *)a.far_rec + (f >= (int32_t)e ? Rec<NK>::r(p, u, a.n_far)
+                                                                               : Rec<NK>::c(p, u, a.n_far));
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const int xi = f >= (int32_t)e ? 3 * p + q : 3 * q + p;
+                    for (int q = 0; q < 3; ++q)
 #pragma unroll
                         for (int c = 0; c < NC; ++c)
 #pragma unroll
                             for (int d = 0; d < NC; ++d)
-                                blk[NC * p + c][NC * q + d] += cfe * (double)rec[xi * NK + (NC == 1 ? 0 : c + d)];
-                    }
+                                blk[NC * p + c][NC * q + d] += cfe * (double)rec[q * NK + (NC == 1 ? 0 : c + d)];
+                }
             } else if (u >= 0) {
                 const double *L = a.touch_rec + (int64_t)u * a.touch_stride;
                 if (cls == 3) {
@@ -457,7 +457,7 @@ int launch_dg_rows(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config
 {
     if (h->nnz_node == 0) return NLFEM_OK;
     DgRowArgs a{h->K,           h->dg_ptr,        h->loff + (int64_t)kLsS * (h->K + 1), h->snbr, h->sflag,
-                h->srec,        h->far_rec,       h->far_stride, h->dsum, h->touch_rec, h->touch_stride, val,
+                h->srec,        h->far_rec,       h->nUF, h->dsum, h->touch_rec, h->touch_stride, val,
                 h->asm_gate,    material_args(m->materials, cfg)};
     const unsigned grid = xcd_grid(h->K);
     const bool fp32 = cfg->precision == NLFEM_P_MIXED;

@@ -305,7 +305,7 @@ struct nlfem_pairs {
     int32_t *csr_stage = nullptr;   // [n_dof][csr_slot(hcap)] sorted rows before packing
     int64_t max_row = 0;         // longest node row
     // per-pair results of the assembly (workspace held by the handle)
-    void *far_rec = nullptr;     // [nUF][far_stride] FP32 (mixed) or FP64
+    void *far_rec = nullptr;     // nUF records of far_stride values (layout by use: row chunks, column chunks, diagonal blocks), FP32 (mixed) or FP64
     double *touch_rec = nullptr; // [nUT][touch_stride]
     double *dsum = nullptr;      // [K][6 * NK] summed element-diagonal blocks of the far pairs
     double *poly_dir = nullptr;  // [N][2] polygon directions (approach POLY)
