@@ -174,6 +174,7 @@ __device__ inline double corner_sine(const double2 v[3], int a)
 // The distance tests alone: whole if the triangle lies inside the inscribed
 // circle, out if it is farther than delta; kUnsure otherwise.
 constexpr uint32_t kUnsure = 3u;
+template <bool CAPS>
 __device__ inline uint32_t poly_quick(double x, double y, const double2 v[3], const PairArgs &a)
 {
     double d0 = (v[0].x - x) * (v[0].x - x) + (v[0].y - y) * (v[0].y - y);
@@ -181,7 +182,7 @@ __device__ inline uint32_t poly_quick(double x, double y, const double2 v[3], co
     double d2 = (v[2].x - x) * (v[2].x - x) + (v[2].y - y) * (v[2].y - y);
     // caps: whole exactly when every vertex lies in the closed disc (the
     // construction's own test)
-    if (a.caps) {
+    if (CAPS) {
         if (d0 <= a.delta2 && d1 <= a.delta2 && d2 <= a.delta2) return kWhole;
     } else if (d0 < a.rin2 && d1 < a.rin2 && d2 < a.rin2) {
         return kWhole;
@@ -190,10 +191,11 @@ __device__ inline uint32_t poly_quick(double x, double y, const double2 v[3], co
     return kUnsure;
 }
 
+template <bool CAPS>
 __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], const PolyArgs &pg,
                                        const PairArgs &a, int *maxcnt)
 {
-    if (a.caps) {
+    if constexpr (CAPS) {
         const double vx[3] = {v[0].x, v[1].x, v[2].x}, vy[3] = {v[0].y, v[1].y, v[2].y};
         double px[kMaxCaps], py[kMaxCaps];
         const int n = caps_polygon(x, y, vx, vy, a.delta, a.caps == 2, px, py);
@@ -204,43 +206,47 @@ __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], c
         if (!(fabs(caps_area(px, py, n)) > 0.0)) return kOut;
         *maxcnt = max(*maxcnt, n);
         return kStraddle;
+    } else {
+        const double C = fmax(fabs(x), fabs(y)) + a.delta;
+        const double m_out = 1e-9 * C, m_in = 1e-5 * C;   // margins as distances
+        const int N = pg.N;
+        bool all_in = true, sep = false, deep0 = true, deep1 = true, deep2 = true;
+        int near = 0;
+        for (int j = 0; j < N; ++j) {
+            const int j1 = j + 1 == N ? 0 : j + 1;
+            const double qa0 = x + a.delta * a.dir[2 * j];
+            const double qa1 = y + a.delta * a.dir[2 * j + 1];
+            const double qb0 = x + a.delta * a.dir[2 * j1];
+            const double qb1 = y + a.delta * a.dir[2 * j1 + 1];
+            const double e0 = qb0 - qa0, e1 = qb1 - qa1;
+            const double p0 = e0 * (v[0].y - qa1) - e1 * (v[0].x - qa0);
+            const double p1 = e0 * (v[1].y - qa1) - e1 * (v[1].x - qa0);
+            const double p2 = e0 * (v[2].y - qa1) - e1 * (v[2].x - qa0);
+            const double el = sqrt(e0 * e0 + e1 * e1);
+            const double tin = m_in * el, tout = m_out * el;
+            all_in &= p0 >= 0.0 && p1 >= 0.0 && p2 >= 0.0;
+            sep |= p0 < -tout && p1 < -tout && p2 < -tout;
+            deep0 &= p0 > tin;
+            deep1 &= p1 > tin;
+            deep2 &= p2 > tin;
+            near += (p0 < tout || p1 < tout || p2 < tout) ? 1 : 0;
+        }
+        if (all_in) return kWhole;
+        if (sep) return kOut;
+        const bool deep = (deep0 && corner_sine(v, 0) > 1e-3) || (deep1 && corner_sine(v, 1) > 1e-3) ||
+                          (deep2 && corner_sine(v, 2) > 1e-3);
+        const uint32_t st = deep ? kStraddle : clip_status(x, y, v, a.dir, N, a.delta);
+        if (st == kStraddle) *maxcnt = max(*maxcnt, 3 + 2 * near);
+        return st;
     }
-    const double C = fmax(fabs(x), fabs(y)) + a.delta;
-    const double m_out = 1e-9 * C, m_in = 1e-5 * C;   // margins as distances
-    const int N = pg.N;
-    bool all_in = true, sep = false, deep0 = true, deep1 = true, deep2 = true;
-    int near = 0;
-    for (int j = 0; j < N; ++j) {
-        const int j1 = j + 1 == N ? 0 : j + 1;
-        const double qa0 = x + a.delta * a.dir[2 * j];
-        const double qa1 = y + a.delta * a.dir[2 * j + 1];
-        const double qb0 = x + a.delta * a.dir[2 * j1];
-        const double qb1 = y + a.delta * a.dir[2 * j1 + 1];
-        const double e0 = qb0 - qa0, e1 = qb1 - qa1;
-        const double p0 = e0 * (v[0].y - qa1) - e1 * (v[0].x - qa0);
-        const double p1 = e0 * (v[1].y - qa1) - e1 * (v[1].x - qa0);
-        const double p2 = e0 * (v[2].y - qa1) - e1 * (v[2].x - qa0);
-        const double el = sqrt(e0 * e0 + e1 * e1);
-        const double tin = m_in * el, tout = m_out * el;
-        all_in &= p0 >= 0.0 && p1 >= 0.0 && p2 >= 0.0;
-        sep |= p0 < -tout && p1 < -tout && p2 < -tout;
-        deep0 &= p0 > tin;
-        deep1 &= p1 > tin;
-        deep2 &= p2 > tin;
-        near += (p0 < tout || p1 < tout || p2 < tout) ? 1 : 0;
-    }
-    if (all_in) return kWhole;
-    if (sep) return kOut;
-    const bool deep = (deep0 && corner_sine(v, 0) > 1e-3) || (deep1 && corner_sine(v, 1) > 1e-3) ||
-                      (deep2 && corner_sine(v, 2) > 1e-3);
-    const uint32_t st = deep ? kStraddle : clip_status(x, y, v, a.dir, N, a.delta);
-    if (st == kStraddle) *maxcnt = max(*maxcnt, 3 + 2 * near);
-    return st;
 }
 
 // ---- the tile kernel --------------------------------------------------------
 
-template <bool POLY>
+// MODE: 0 barycentre ball, 1 polygon clip (N-gon, square), 2 caps; the caps
+// construction is compiled only into its own kernel (its arrays would
+// otherwise raise the register count of the polygon kernel)
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -248,6 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     const int64_t ncell = (int64_t)a.gnx * a.gny;
     const int64_t cell64 = xcd_item(blockIdx.x, ncell);   // grid.x is a multiple of 8
     if (cell64 >= ncell) return;
+    constexpr bool POLY = MODE > 0, CAPS = MODE == 2;
     const int cell = (int)cell64;
     const int64_t cs = a.cell_start[cell], ce = a.cell_start[cell + 1];
     if (cs >= ce) return;
@@ -421,13 +428,13 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                                     double2 vf[3] = {c_v[j], c_v[kCH + j], c_v[2 * kCH + j]};
                                     for (int p = 0; p < a.P; ++p) {
                                         const double2 x = a.xp[(int64_t)e * a.P + p];
-                                        const uint32_t st = poly_quick(x.x, x.y, vf, a);
+                                        const uint32_t st = poly_quick<CAPS>(x.x, x.y, vf, a);
                                         if (st == kUnsure) pq[atomicAdd(pq_n, 1)] = (lane << 5) | p;
                                         else mef |= st << (2 * p);
                                     }
                                     for (int q = 0; q < a.P; ++q) {
                                         const double2 x = c_xp[q * kCH + j];
-                                        const uint32_t st = poly_quick(x.x, x.y, ve, a);
+                                        const uint32_t st = poly_quick<CAPS>(x.x, x.y, ve, a);
                                         if (st == kUnsure) pq[atomicAdd(pq_n, 1)] = (lane << 5) | 16 | q;
                                         else mfe |= st << (2 * q);
                                     }
@@ -450,11 +457,11 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                             if (!fe_dir) {
                                 const double2 x = a.xp[(int64_t)e * a.P + p];
                                 double2 vf[3] = {c_v[jc], c_v[kCH + jc], c_v[2 * kCH + jc]};
-                                st = poly_status(x.x, x.y, vf, pg, a, &clipmax);
+                                st = poly_status<CAPS>(x.x, x.y, vf, pg, a, &clipmax);
                                 atomicOr(&pm_ef[jl], st << (2 * p));
                             } else {
                                 const double2 x = c_xp[p * kCH + jc];
-                                st = poly_status(x.x, x.y, ve, pg, a, &clipmax);
+                                st = poly_status<CAPS>(x.x, x.y, ve, pg, a, &clipmax);
                                 atomicOr(&pm_fe[jl], st << (2 * p));
                             }
                         }
@@ -748,8 +755,9 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     const size_t lds = sizeof(double2) * (size_t)kCH * (1 + a.P + (a.poly ? 3 : 0)) +
                        sizeof(int64_t) * kTE * kLsLast + sizeof(int32_t) * kCH * 5;
     dim3 grid(xcd_grid(ncell, INT32_MAX));
-    if (a.poly) hipLaunchKernelGGL((k_pairs<true>), grid, dim3(kBlock), lds, s, a, h->poly);
-    else hipLaunchKernelGGL((k_pairs<false>), grid, dim3(kBlock), lds, s, a, h->poly);
+    if (a.caps) hipLaunchKernelGGL((k_pairs<2>), grid, dim3(kBlock), lds, s, a, h->poly);
+    else if (a.poly) hipLaunchKernelGGL((k_pairs<1>), grid, dim3(kBlock), lds, s, a, h->poly);
+    else hipLaunchKernelGGL((k_pairs<0>), grid, dim3(kBlock), lds, s, a, h->poly);
     NLFEM_HIP(hipGetLastError());
     return NLFEM_OK;
 }
