@@ -321,6 +321,34 @@ __device__ inline double &cb(double *buf, int cap, int lane, int b, int c, int i
 }
 
 // returns the vertex count; the polygon is left in buffer *which
+// Edges of the polygon around (x, y) whose pass can change a polygon derived
+// from the triangle (bit j): an edge with every triangle vertex inside by
+// 1e-9 C |e| (C bounds the coordinates) cannot, since every point a pass
+// produces is a convex combination of the vertices up to rounding many
+// orders below that margin, so the plain clip returns its input unchanged
+// there.  Skipping those passes gives the same polygon, bit for bit.
+__device__ inline uint64_t clip_active(double x, double y, const double vx[3], const double vy[3], const double *dir,
+                                       int N, double delta)
+{
+#pragma clang fp contract(off)
+    const double C = fmax(fmax(fmax(fabs(x), fabs(y)), fmax(fabs(vx[0]), fabs(vy[0]))),
+                          fmax(fmax(fabs(vx[1]), fabs(vy[1])), fmax(fabs(vx[2]), fabs(vy[2])))) +
+                     delta;
+    uint64_t act = 0;
+    for (int j = 0; j < N; ++j) {
+        const int j1 = j + 1 == N ? 0 : j + 1;
+        const double qa0 = x + delta * dir[2 * j], qa1 = y + delta * dir[2 * j + 1];
+        const double qb0 = x + delta * dir[2 * j1], qb1 = y + delta * dir[2 * j1 + 1];
+        const double e0 = qb0 - qa0, e1 = qb1 - qa1;
+        const double tol = 1e-9 * C * (fabs(e0) + fabs(e1));
+        const double d0 = e0 * (vy[0] - qa1) - e1 * (vx[0] - qa0);
+        const double d1 = e0 * (vy[1] - qa1) - e1 * (vx[1] - qa0);
+        const double d2 = e0 * (vy[2] - qa1) - e1 * (vx[2] - qa0);
+        if (!(d0 > tol && d1 > tol && d2 > tol)) act |= 1ull << j;
+    }
+    return act;
+}
+
 __device__ inline int clip_polygon(double x, double y, const double vx[3], const double vy[3], const double *dir, int N,
                             double delta, double *buf, int cap, int lane, int *which, bool *ovf)
 {
@@ -329,8 +357,10 @@ __device__ inline int clip_polygon(double x, double y, const double vx[3], const
         cb(buf, cap, lane, 0, 0, k) = vx[k];
         cb(buf, cap, lane, 0, 1, k) = vy[k];
     }
+    const uint64_t act = clip_active(x, y, vx, vy, dir, N, delta);
     int cnt = 3, cur = 0;
-    for (int j = 0; j < N && cnt > 0; ++j) {
+    for (uint64_t rest = act; rest && cnt > 0; rest &= rest - 1) {
+        const int j = __ffsll((unsigned long long)rest) - 1;
         const int j1 = j + 1 == N ? 0 : j + 1;
         const double qa0 = x + delta * dir[2 * j], qa1 = y + delta * dir[2 * j + 1];
         const double qb0 = x + delta * dir[2 * j1], qb1 = y + delta * dir[2 * j1 + 1];
@@ -403,6 +433,7 @@ __device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, do
     }
     if (cnt < 3) return;
     const double deti = Ji.x * Ji.w - Ji.y * Ji.z;
+    const double rdet = 1.0 / deti;
     const int Q = inner_b ? r.PB : r.PA;
     const double s0x = cb(buf, a.cap, lane, cur, 0, 0), s0y = cb(buf, a.cap, lane, cur, 1, 0);
     const T pe[3] = {(T)po[0], (T)po[1], (T)po[2]};
@@ -417,8 +448,8 @@ __device__ __forceinline__ void straddle_point(const FarArgs &a, double xo_x, do
             const double wq = inner_b ? r.wb[q] : r.wa[q];
             const double yx = s0x + (S00 * x1 + S01 * x2), yy = s0y + (S10 * x1 + S11 * x2);
             const double dx = yx - v0i.x, dy = yy - v0i.y;
-            const double h1 = (Ji.w * dx - Ji.y * dy) / deti;
-            const double h2 = (-Ji.z * dx + Ji.x * dy) / deti;
+            const double h1 = (Ji.w * dx - Ji.y * dy) * rdet;
+            const double h2 = (-Ji.z * dx + Ji.x * dy) * rdet;
             const T pi[3] = {(T)(1.0 - h1 - h2), (T)h1, (T)h2};
             T kv[NK];
             kernel_eval<KER, T>((T)(xo_x - yx), (T)(xo_y - yy), cc, kv, z2min);

@@ -85,6 +85,7 @@ struct PolyArgs {
     double r_in;                   // inscribed radius (delta cos(pi/N) for the N-gon)
     double r_out;                  // largest distance of a polygon vertex from the centre
     double dir[kMaxPoly][2];
+    double elen[kMaxPoly];         // delta |dir_{j+1} - dir_j|: edge lengths, for the margins of decisions
 };
 
 // the ball approaches clipped as polygons around each outer point: the

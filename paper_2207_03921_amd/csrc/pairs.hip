@@ -53,6 +53,7 @@ struct PairArgs {
     int64_t *lcnt;          // [kLsLast][K1] per-element counts
     unsigned long long *maxClip;   // bound on the vertex count of any straddling clip
     const double *dir;             // [N][2] polygon directions (device copy)
+    const double *elen;            // [N] polygon edge lengths (device copy)
     const int64_t *scr;     // [K + 1] start of each element's scratch segment
     int32_t *snbr;
     uint8_t *sflag;
@@ -98,8 +99,30 @@ __device__ __noinline__ uint32_t clip_status(double x, double y, const double2 v
         bx[0][a] = v[a].x;
         by[0][a] = v[a].y;
     }
+    // passes that cannot change a polygon derived from the triangle: every
+    // vertex inside edge j by 1e-9 C |e| (C bounds the coordinates), far
+    // above the rounding of any point a pass produces; skipping them gives
+    // the same polygon bit for bit
+    uint64_t act = 0;
+    {
+        const double C = fmax(fmax(fmax(fabs(x), fabs(y)), fmax(fabs(v[0].x), fabs(v[0].y))),
+                              fmax(fmax(fabs(v[1].x), fabs(v[1].y)), fmax(fabs(v[2].x), fabs(v[2].y)))) +
+                         delta;
+        for (int j = 0; j < N; ++j) {
+            const int j1 = j + 1 == N ? 0 : j + 1;
+            const double qa0 = x + delta * dir[2 * j], qa1 = y + delta * dir[2 * j + 1];
+            const double qb0 = x + delta * dir[2 * j1], qb1 = y + delta * dir[2 * j1 + 1];
+            const double e0 = qb0 - qa0, e1 = qb1 - qa1;
+            const double tol = 1e-9 * C * (fabs(e0) + fabs(e1));
+            const double d0 = e0 * (v[0].y - qa1) - e1 * (v[0].x - qa0);
+            const double d1 = e0 * (v[1].y - qa1) - e1 * (v[1].x - qa0);
+            const double d2 = e0 * (v[2].y - qa1) - e1 * (v[2].x - qa0);
+            if (!(d0 > tol && d1 > tol && d2 > tol)) act |= 1ull << j;
+        }
+    }
     int cnt = 3, cur = 0;
-    for (int j = 0; j < N && cnt > 0; ++j) {
+    for (uint64_t rest = act; rest && cnt > 0; rest &= rest - 1) {
+        const int j = __ffsll((unsigned long long)rest) - 1;
         int j1 = j + 1 == N ? 0 : j + 1;
         double qa0 = x + delta * dir[2 * j];
         double qa1 = y + delta * dir[2 * j + 1];
@@ -222,7 +245,8 @@ __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], c
             const double p0 = e0 * (v[0].y - qa1) - e1 * (v[0].x - qa0);
             const double p1 = e0 * (v[1].y - qa1) - e1 * (v[1].x - qa0);
             const double p2 = e0 * (v[2].y - qa1) - e1 * (v[2].x - qa0);
-            const double el = sqrt(e0 * e0 + e1 * e1);
+            // the edge length only scales the margins: the precomputed one
+            const double el = a.elen[j];
             const double tin = m_in * el, tout = m_out * el;
             all_in &= p0 >= 0.0 && p1 >= 0.0 && p2 >= 0.0;
             sep |= p0 < -tout && p1 < -tout && p2 < -tout;
@@ -747,6 +771,7 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     a.lcnt = h->lcnt;
     a.maxClip = h->red + 10;
     a.dir = h->poly_dir;
+    a.elen = h->poly_dir + 2 * kMaxPoly;
     a.scr = h->scr_off;
     a.snbr = h->snbr_tmp;
     a.sflag = h->sflag_tmp;
