@@ -256,8 +256,6 @@ struct nlfem_batch {
     unsigned long long *counters = nullptr;
     Shape shape[kPhases] = {{1024, 4}, {256, 4}, {64, 4}, {4, 16}};
     hipStream_t capture = nullptr;
-    hipStream_t aux = nullptr;            // touching pairs beside the non-touching ones
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<nlfem_pairs *> handles;
@@ -363,25 +361,24 @@ int run_phase(const nlfem_batch *b, Phase ph, const Shape &sh, hipStream_t s)
     return NLFEM_OK;
 }
 
-// far pairs then element diagonals on s; touching pairs on the batch's
-// second stream beside them; rows after the join.  `timed`: HIP events of
-// the per-phase timing around each phase on its stream (not while capturing)
+// touching pairs, far pairs, element diagonals, rows, in that order on s.
+// `timed`: HIP events of the per-phase timing around each phase (not while
+// capturing)
 int run_all(const nlfem_batch *b, hipStream_t s, bool timed)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, b->counters, (int)b->groups.size());
-    NLFEM_HIP(hipEventRecord(b->ev_fork, s));
-    NLFEM_HIP(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
-    if (timed) timing_begin(kPhTouch, b->aux);
-    NLFEM_TRY(run_phase(b, kTouch, b->shape[kTouch], b->aux));
-    if (timed) timing_end(kPhTouch, b->aux);
-    NLFEM_HIP(hipEventRecord(b->ev_join, b->aux));
+    // touching records, then the far records, on one stream: run side by
+    // side the far launch (2 waves per SIMD by registers) left the touching
+    // waves no room and both took longer than one after the other
+    if (timed) timing_begin(kPhTouch, s);
+    NLFEM_TRY(run_phase(b, kTouch, b->shape[kTouch], s));
+    if (timed) timing_end(kPhTouch, s);
     if (timed) timing_begin(kPhFar, s);
     NLFEM_TRY(run_phase(b, kFar, b->shape[kFar], s));
     if (timed) timing_end(kPhFar, s);
     if (timed) timing_begin(kPhDiag, s);
     NLFEM_TRY(run_phase(b, kDiag, b->shape[kDiag], s));
     if (timed) timing_end(kPhDiag, s);
-    NLFEM_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
     if (timed) timing_begin(kPhRows, s);
     NLFEM_TRY(run_phase(b, kRows, b->shape[kRows], s));
     if (timed) timing_end(kPhRows, s);
@@ -651,10 +648,6 @@ int batch_create(const std::vector<AssemblePlan> &plans, const std::vector<nlfem
         make_groups(b);
         rc = upload_tables(b, s);
     }
-    if (rc == NLFEM_OK && (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
-                           hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
-                           hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess))
-        rc = set_error(NLFEM_E_HIP, "cannot create the batch's second stream");
     if (rc == NLFEM_OK && tune_mode != 0) {
         const std::string key = tune_key(b);
         if (tune_mode == 2 || !cache_read(tune_cache, key, b->shape)) {
@@ -722,9 +715,6 @@ void batch_free(nlfem_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->capture) (void)hipStreamDestroy(b->capture);
-    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
-    if (b->aux) (void)hipStreamDestroy(b->aux);
     dev_release(b->mem);
     delete b;
 }
