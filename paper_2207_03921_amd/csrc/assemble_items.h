@@ -1382,6 +1382,9 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
             const int total = __shfl(incl, nq - 1);
             __syncthreads();
             int ntouch = 0;
+            // the element q with pre[q] <= flat < pre[q + 1]: a lane's flat
+            // index only grows, so q advances from where it stopped
+            int qcur = 0;
             for (int base = 0; base < total; base += 64 * kRowU) {
                 int32_t fe[kRowU], uu[kRowU], qq[kRowU], cl[kRowU], nf0[kRowU], nf1[kRowU], nf2[kRowU], tt[kRowU];
                 bool act[kRowU];
@@ -1396,13 +1399,8 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                     cl[k] = 0;
                     qq[k] = 0;
                     if (act[k]) {
-                        // the element q with pre[q] <= flat < pre[q + 1]
-                        int lo = 0, hi = nq;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (pre[mid] <= flat) lo = mid;
-                            else hi = mid;
-                        }
+                        while (qcur + 1 < nq && pre[qcur + 1] <= flat) ++qcur;
+                        const int lo = qcur;
                         qq[k] = lo;
                         const int64_t t = qs[lo] + (flat - pre[lo]);
                         tt[k] = (int32_t)t;
