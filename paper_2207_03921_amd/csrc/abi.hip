@@ -466,14 +466,10 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_DOFL, M, h->dof_list));
     if (clipped_ball(h->approach)) {
         // h->poly lives as long as the handle, so the copy may run asynchronously
-        // [directions | edge lengths]
-        NLFEM_TRY(ensure_typed(h, B_POLYDIR, 3 * kMaxPoly, h->poly_dir));
-        if (h->poly.N > 0) {
+        NLFEM_TRY(ensure_typed(h, B_POLYDIR, 2 * kMaxPoly, h->poly_dir));
+        if (h->poly.N > 0)
             NLFEM_HIP(hipMemcpyAsync(h->poly_dir, h->poly.dir, sizeof(double) * 2 * h->poly.N, hipMemcpyHostToDevice,
                                      s));
-            NLFEM_HIP(hipMemcpyAsync(h->poly_dir + 2 * kMaxPoly, h->poly.elen, sizeof(double) * h->poly.N,
-                                     hipMemcpyHostToDevice, s));
-        }
     }
     if (!spec) {
         // every counter of the rest of the build starts at zero

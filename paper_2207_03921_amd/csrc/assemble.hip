@@ -45,9 +45,15 @@ __global__ void __launch_bounds__(64) k_far_rec_poly(FarArgs a, RoleArgs r1, Rol
     __shared__ int32_t queue[64 * 2 * kMaxRule];
     __shared__ int32_t pe[64], pf[64];
     __shared__ T slots[64 * NV];
+    __shared__ double sdir[2 * kMaxPoly];
     if (gated(a.gate)) return;
+    // the polygon directions in LDS: every clip pass reads them
+    for (int t = threadIdx.x; t < 2 * a.N; t += 64) sdir[t] = a.dir[t];
+    wave_sync();
+    FarArgs al = a;
+    al.dir = sdir;
     const int64_t idx = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    far_wave_poly<KER, T, PM>(a, r1, r2, idx, idx < a.n, queue, pe, pf, slots);
+    far_wave_poly<KER, T, PM>(al, r1, r2, idx, idx < a.n, queue, pe, pf, slots);
 }
 
 // the three classes in one launch: blocks [0, nb[0]) take the vertex class

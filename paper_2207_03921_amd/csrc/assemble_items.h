@@ -335,9 +335,10 @@ __device__ inline uint64_t clip_active(double x, double y, const double vx[3], c
                           fmax(fmax(fabs(vx[1]), fabs(vy[1])), fmax(fabs(vx[2]), fabs(vy[2])))) +
                      delta;
     uint64_t act = 0;
+    // vertex j + 1 of one edge is vertex j of the next (the same values)
+    double qa0 = x + delta * dir[0], qa1 = y + delta * dir[1];
     for (int j = 0; j < N; ++j) {
         const int j1 = j + 1 == N ? 0 : j + 1;
-        const double qa0 = x + delta * dir[2 * j], qa1 = y + delta * dir[2 * j + 1];
         const double qb0 = x + delta * dir[2 * j1], qb1 = y + delta * dir[2 * j1 + 1];
         const double e0 = qb0 - qa0, e1 = qb1 - qa1;
         const double tol = 1e-9 * C * (fabs(e0) + fabs(e1));
@@ -345,6 +346,8 @@ __device__ inline uint64_t clip_active(double x, double y, const double vx[3], c
         const double d1 = e0 * (vy[1] - qa1) - e1 * (vx[1] - qa0);
         const double d2 = e0 * (vy[2] - qa1) - e1 * (vx[2] - qa0);
         if (!(d0 > tol && d1 > tol && d2 > tol)) act |= 1ull << j;
+        qa0 = qb0;
+        qa1 = qb1;
     }
     return act;
 }

@@ -102,9 +102,11 @@ __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *__rest
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
     __shared__ T slots[STAGED ? 4 * 64 * NV : 1];
+    __shared__ double sdir[POLY ? 4 : 1][POLY ? 2 * kMaxPoly : 1];   // the wave's problem's polygon
     int64_t *pre = (int64_t *)dyn;
     const int64_t total = load_prefix(q, pre);
     const int lane = threadIdx.x & 63;
+    int staged = -1;   // problem whose polygon the wave's sdir holds
     for (;;) {
         const int64_t b0 = grab(q, &slot);
         if (b0 >= total) break;
@@ -130,6 +132,19 @@ __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *__rest
                     }
                     far_store_wave<KER, T>(a, it - lane + r.lane0 - base, __popcll(r.mask), self, acc,
                                            slots + (threadIdx.x >> 6) * 64 * NV, r.lane0);
+                } else if (POLY) {
+                    double *sd = sdir[POLY ? threadIdx.x >> 6 : 0];
+                    if (r.p != staged) {
+                        wave_sync();
+                        for (int t = lane; t < 2 * fa[r.p].N; t += 64) sd[t] = fa[r.p].dir[t];
+                        wave_sync();
+                        staged = r.p;
+                    }
+                    if (mine) {
+                        FarArgs al = fa[r.p];
+                        al.dir = sd;
+                        far_item<KER, T, PM, POLY>(al, r1[r.p], r2[r.p], it - base);
+                    }
                 } else if (mine) {
                     far_item<KER, T, PM, POLY>(fa[r.p], r1[r.p], r2[r.p], it - base);
                 }

@@ -53,7 +53,6 @@ struct PairArgs {
     int64_t *lcnt;          // [kLsLast][K1] per-element counts
     unsigned long long *maxClip;   // bound on the vertex count of any straddling clip
     const double *dir;             // [N][2] polygon directions (device copy)
-    const double *elen;            // [N] polygon edge lengths (device copy)
     const int64_t *scr;     // [K + 1] start of each element's scratch segment
     int32_t *snbr;
     uint8_t *sflag;
@@ -235,18 +234,20 @@ __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], c
         const int N = pg.N;
         bool all_in = true, sep = false, deep0 = true, deep1 = true, deep2 = true;
         int near = 0;
+        // the directions and edge lengths from the kernel arguments (scalar
+        // loads: j is uniform); vertex j + 1 of one edge is vertex j of the next
+        double qa0 = x + a.delta * pg.dir[0][0];
+        double qa1 = y + a.delta * pg.dir[0][1];
         for (int j = 0; j < N; ++j) {
             const int j1 = j + 1 == N ? 0 : j + 1;
-            const double qa0 = x + a.delta * a.dir[2 * j];
-            const double qa1 = y + a.delta * a.dir[2 * j + 1];
-            const double qb0 = x + a.delta * a.dir[2 * j1];
-            const double qb1 = y + a.delta * a.dir[2 * j1 + 1];
+            const double qb0 = x + a.delta * pg.dir[j1][0];
+            const double qb1 = y + a.delta * pg.dir[j1][1];
             const double e0 = qb0 - qa0, e1 = qb1 - qa1;
             const double p0 = e0 * (v[0].y - qa1) - e1 * (v[0].x - qa0);
             const double p1 = e0 * (v[1].y - qa1) - e1 * (v[1].x - qa0);
             const double p2 = e0 * (v[2].y - qa1) - e1 * (v[2].x - qa0);
             // the edge length only scales the margins: the precomputed one
-            const double el = a.elen[j];
+            const double el = pg.elen[j];
             const double tin = m_in * el, tout = m_out * el;
             all_in &= p0 >= 0.0 && p1 >= 0.0 && p2 >= 0.0;
             sep |= p0 < -tout && p1 < -tout && p2 < -tout;
@@ -254,6 +255,8 @@ __device__ inline uint32_t poly_status(double x, double y, const double2 v[3], c
             deep1 &= p1 > tin;
             deep2 &= p2 > tin;
             near += (p0 < tout || p1 < tout || p2 < tout) ? 1 : 0;
+            qa0 = qb0;
+            qa1 = qb1;
         }
         if (all_in) return kWhole;
         if (sep) return kOut;
@@ -771,7 +774,6 @@ int launch_pairs(nlfem_pairs *h, const nlfem_mesh *m, hipStream_t s)
     a.lcnt = h->lcnt;
     a.maxClip = h->red + 10;
     a.dir = h->poly_dir;
-    a.elen = h->poly_dir + 2 * kMaxPoly;
     a.scr = h->scr_off;
     a.snbr = h->snbr_tmp;
     a.sflag = h->sflag_tmp;
