@@ -301,7 +301,6 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     // items and the statuses they decide
     __shared__ int32_t pq_all[POLY ? kBlock / 64 : 1][POLY ? 64 * 2 * kMaxRule : 1];
     __shared__ uint32_t pm_all[POLY ? kBlock / 64 : 1][2][64];
-    __shared__ int pq_cnt[kBlock / 64];
     // per wave: the chunk positions of the candidates that can interact with
     // the wave's current element, in chunk order
     __shared__ int16_t cand_all[kBlock / 64][kCH];
@@ -342,9 +341,6 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
     int clipmax = 0;
     int32_t *pq = pq_all[POLY ? wv : 0];
     uint32_t *pm_ef = pm_all[POLY ? wv : 0][0], *pm_fe = pm_all[POLY ? wv : 0][1];
-    int *pq_n = &pq_cnt[wv];
-    if (lane == 0) *pq_n = 0;
-    wave_sync();
     // the cell's elements in tiles of kTE
     for (int64_t t0 = cs; t0 < ce; t0 += kTE) {
         const int ne = (int)min((int64_t)kTE, ce - t0);
@@ -425,6 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                     uint32_t mef = 0, mfe = 0;
                     int32_t f = -1;
                     uint8_t flags = 0;
+                    bool need = false;   // polygon ball: the point tests of this lane's candidate run
                     if (valid) {
                         f = c_id[j];
                         const int32_t lab_f = c_lab[j];
@@ -450,31 +447,48 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                                         if (dx * dx + dy * dy <= a.delta2) mfe |= kWhole << (2 * q);
                                     }
                                 } else {
-                                    // distance tests now; the unsure (point, triangle) items go to
-                                    // the wave's queue and are decided below by all lanes at once
-                                    double2 vf[3] = {c_v[j], c_v[kCH + j], c_v[2 * kCH + j]};
-                                    for (int p = 0; p < a.P; ++p) {
-                                        const double2 x = a.xp[(int64_t)e * a.P + p];
-                                        const uint32_t st = poly_quick<CAPS>(x.x, x.y, vf, a);
-                                        if (st == kUnsure) pq[atomicAdd(pq_n, 1)] = (lane << 5) | p;
-                                        else mef |= st << (2 * p);
-                                    }
-                                    for (int q = 0; q < a.P; ++q) {
-                                        const double2 x = c_xp[q * kCH + j];
-                                        const uint32_t st = poly_quick<CAPS>(x.x, x.y, ve, a);
-                                        if (st == kUnsure) pq[atomicAdd(pq_n, 1)] = (lane << 5) | 16 | q;
-                                        else mfe |= st << (2 * q);
-                                    }
+                                    need = true;
                                 }
                             }
                         }
                     }
                     if (POLY) {
+                        // distance tests by all lanes in step (one point per step), the
+                        // unsure (point, triangle) items appended to the wave's queue by
+                        // ballot positions, then decided by all lanes at once
+                        int nq = 0;
+                        {
+                            const int jn = need ? j : 0;
+                            const double2 vf[3] = {c_v[jn], c_v[kCH + jn], c_v[2 * kCH + jn]};
+                            for (int p = 0; p < a.P; ++p) {
+                                uint32_t st = kOut;
+                                if (need) {
+                                    const double2 x = a.xp[(int64_t)e * a.P + p];
+                                    st = poly_quick<CAPS>(x.x, x.y, vf, a);
+                                }
+                                const bool u = st == kUnsure;
+                                const unsigned long long m = __ballot(u);
+                                if (u) pq[nq + __popcll(m & lt)] = (lane << 5) | p;
+                                else mef |= st << (2 * p);
+                                nq += __popcll(m);
+                            }
+                            for (int q = 0; q < a.P; ++q) {
+                                uint32_t st = kOut;
+                                if (need) {
+                                    const double2 x = c_xp[q * kCH + jn];
+                                    st = poly_quick<CAPS>(x.x, x.y, ve, a);
+                                }
+                                const bool u = st == kUnsure;
+                                const unsigned long long m = __ballot(u);
+                                if (u) pq[nq + __popcll(m & lt)] = (lane << 5) | 16 | q;
+                                else mfe |= st << (2 * q);
+                                nq += __popcll(m);
+                            }
+                        }
                         // decide the queued items, one per lane
                         wave_sync();
                         pm_ef[lane] = 0u;
                         pm_fe[lane] = 0u;
-                        const int nq = *pq_n;
                         wave_sync();
                         for (int it = lane; it < nq; it += 64) {
                             const int code = pq[it];
@@ -495,8 +509,6 @@ __global__ void __launch_bounds__(kBlock) k_pairs(PairArgs a, PolyArgs pg)
                         wave_sync();
                         mef |= pm_ef[lane];
                         mfe |= pm_fe[lane];
-                        wave_sync();
-                        if (lane == 0) *pq_n = 0;
                         wave_sync();
                     }
                     if (valid) {
