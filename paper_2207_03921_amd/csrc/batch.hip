@@ -433,6 +433,14 @@ void make_groups(nlfem_batch *b)
                 } else if (ph == kTouch) {
                     g.kernel = p.kernel;
                     g.cls = cls;
+                } else if (ph == kRows) {
+                    // rows grouped by the power of two of their LDS need: each
+                    // launch reserves its own problems' size (the largest of a
+                    // single group would cap the resident waves of the others)
+                    const size_t need = row_lds_bytes(p.rows.maxlen, p.nc, p.rows.hcap);
+                    int c2 = 0;
+                    while (((size_t)1024 << c2) < need) ++c2;
+                    g.cls = c2;
                 }
                 char key[96];
                 std::snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d", ph, g.kernel, g.cls, g.nc, (int)g.fp32,
