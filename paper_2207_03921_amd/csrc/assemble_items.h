@@ -1250,7 +1250,7 @@ __device__ inline bool add_touch_dg(double *acc, const int32_t *hk, const int32_
 // LDS of one row gather besides the dynamic part (accumulator, hash table)
 // touching entries of a row are queued and then handled by all lanes at once
 // (they take a longer path than the non-touching ones)
-constexpr int kRowTouchCap = 512;
+constexpr int kRowTouchCap = 320;
 
 struct RowShared {
     int64_t qs[kRowQ];
