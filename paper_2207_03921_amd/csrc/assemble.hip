@@ -7,7 +7,7 @@ using namespace items;
 namespace {
 
 // record staging through LDS (coalesced stores) where it fits: all but the
-// two-component FP64 records (46 KB per wave)
+// two-component FP64 records (28 KB per wave)
 template <int KER, typename T>
 constexpr bool far_staged() { return !(Ker<KER>::NK == 3 && sizeof(T) == 8); }
 
@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArg
         far_item<KER, T, PM, POLY>(a, r1, r2, idx);
         return;
     }
-    constexpr int NV = Rec<Ker<KER>::NK>::kValues;
+    constexpr int NV = kFarStage<Ker<KER>::NK>;
     __shared__ T slots[far_staged<KER, T>() ? 4 * 64 * NV : 1];
     const int64_t idx0 = idx - (threadIdx.x & 63);
     if (idx0 >= a.n) return;   // whole waves leave together

@@ -615,17 +615,24 @@ __device__ __forceinline__ void far_store(const FarArgs &a, int64_t idx, bool se
 // Records idx0 .. idx0 + nvalid - 1 of one wave (lane lane0 + l holds record
 // idx0 + l), through LDS: the wave then stores its block of each record
 // array with consecutive lanes at consecutive addresses.  All lanes of the
-// wave call it.  slots: Rec<NK>::kValues values per lane.
+// wave call it.  slots: kFarStage<NK> values per lane; the six chunk arrays
+// and the diagonal blocks pass through it one after the other (a smaller
+// buffer leaves LDS for more resident waves).
+template <int NK>
+constexpr int kFarStage = 18 * NK;
 template <int KER, typename T>
 __device__ __forceinline__ void far_store_wave(const FarArgs &a, int64_t idx0, int nvalid, bool self,
                                                const FarAcc<KER, T> &acc, T *slots, int lane0 = 0)
 {
-    constexpr int NK = Ker<KER>::NK, NV = Rec<NK>::kValues, W = 3 * NK;
+    constexpr int NK = Ker<KER>::NK, NS = kFarStage<NK>, W = 3 * NK;
     const int hw = threadIdx.x & 63;
     const int lane = hw - lane0;   // position of this lane's record in the run
-    if (lane >= 0 && lane < nvalid) {
-        // [R_0 R_1 R_2 C_0 C_1 C_2 | De Df], the order of the record arrays
-        T *sl = slots + lane * NV;
+    const bool mine = lane >= 0 && lane < nvalid;
+    T *sl = slots + lane * NS;
+    T *base = (T *)a.rec;
+    const int64_t n = a.n;
+    if (mine) {
+        // [R_0 R_1 R_2 C_0 C_1 C_2], the order of the record arrays
 #pragma unroll
         for (int loc = 0; loc < 3; ++loc)
 #pragma unroll
@@ -635,23 +642,26 @@ __device__ __forceinline__ void far_store_wave(const FarArgs &a, int64_t idx0, i
                     sl[loc * W + b * NK + k] = self ? acc.X[loc][b][k] + acc.X[b][loc][k] : acc.X[loc][b][k];
                     sl[(3 + loc) * W + b * NK + k] = self ? (T)0 : acc.X[b][loc][k];
                 }
+    }
+    wave_sync();
+    for (int p = 0; p < 6; ++p) {
+        T *out = base + ((int64_t)p * n + idx0) * W;
+        for (int t = hw; t < nvalid * W; t += 64) out[t] = slots[(t / W) * NS + p * W + t % W];
+    }
+    wave_sync();
+    if (mine) {
+        // [De | Df]
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
-                sl[6 * W + i * NK + k] = self ? acc.De[i][k] + acc.Df[i][k] : acc.De[i][k];
-                sl[6 * W + (6 + i) * NK + k] = self ? (T)0 : acc.Df[i][k];
+                sl[i * NK + k] = self ? acc.De[i][k] + acc.Df[i][k] : acc.De[i][k];
+                sl[(6 + i) * NK + k] = self ? (T)0 : acc.Df[i][k];
             }
     }
     wave_sync();
-    T *base = (T *)a.rec;
-    const int64_t n = a.n;
-    for (int p = 0; p < 6; ++p) {
-        T *out = base + ((int64_t)p * n + idx0) * W;
-        for (int t = hw; t < nvalid * W; t += 64) out[t] = slots[(t / W) * NV + p * W + t % W];
-    }
     T *out = base + Rec<NK>::d(idx0, n);
-    for (int t = hw; t < nvalid * 4 * W; t += 64) out[t] = slots[(t / (4 * W)) * NV + 6 * W + t % (4 * W)];
+    for (int t = hw; t < nvalid * 4 * W; t += 64) out[t] = slots[(t / (4 * W)) * NS + t % (4 * W)];
     wave_sync();
 }
 

@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *__rest
                                                 const RoleArgs *__restrict__ r2)
 {
     constexpr bool STAGED = batch_far_staged<KER, T>() && !POLY;
-    constexpr int NV = Rec<Ker<KER>::NK>::kValues;
+    constexpr int NV = kFarStage<Ker<KER>::NK>;
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
     __shared__ T slots[STAGED ? 4 * 64 * NV : 1];
