@@ -188,10 +188,11 @@ struct FarArgs {
 // Non-touching pair records (n records, NK values per block entry), stored
 // by use: the row chunks R_loc (row loc of X: e's vertex loc against the
 // vertices of f), the column chunks C_loc (column loc of X: f's vertex loc
-// against the vertices of e), then the element-diagonal blocks [De | Df].
+// against the vertices of e), then the element-diagonal blocks De and Df.
 // Each array is contiguous over the record index, so the rows of e's
 // vertices read the R chunks of e's upper list entries and those of f's
-// vertices the C chunks, each chunk once and only the values used.
+// vertices the C chunks, each chunk once and only the values used; the
+// diagonal sums read De of the upper entries and Df of the lower ones.
 template <int NK>
 struct Rec {
     static constexpr int kValues = 30 * NK;   // per record
@@ -200,7 +201,11 @@ struct Rec {
     {
         return ((int64_t)(3 + loc) * n + u) * 3 * NK;
     }
-    __host__ __device__ static int64_t d(int64_t u, int64_t n) { return 18 * NK * n + u * 12 * NK; }
+    // De (second = false) or Df (second = true) of record u: 6 NK values
+    __host__ __device__ static int64_t d(int64_t u, int64_t n, bool second)
+    {
+        return (second ? 24 : 18) * NK * n + u * 6 * NK;
+    }
 };
 
 // rule points of the two roles (A on e, B on f)
@@ -602,13 +607,13 @@ __device__ __forceinline__ void far_store(const FarArgs &a, int64_t idx, bool se
                 for (int k = 0; k < NK; ++k) c[b * NK + k] = acc.X[b][loc][k];
         }
     }
-    T *d = base + L::d(idx, n);
+    T *de = base + L::d(idx, n, false), *df = base + L::d(idx, n, true);
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-            d[i * NK + k] = self ? acc.De[i][k] + acc.Df[i][k] : acc.De[i][k];
-            d[(6 + i) * NK + k] = self ? (T)0 : acc.Df[i][k];
+            de[i * NK + k] = self ? acc.De[i][k] + acc.Df[i][k] : acc.De[i][k];
+            df[i * NK + k] = self ? (T)0 : acc.Df[i][k];
         }
 }
 
@@ -660,8 +665,10 @@ __device__ __forceinline__ void far_store_wave(const FarArgs &a, int64_t idx0, i
             }
     }
     wave_sync();
-    T *out = base + Rec<NK>::d(idx0, n);
-    for (int t = hw; t < nvalid * 4 * W; t += 64) out[t] = slots[(t / (4 * W)) * NS + t % (4 * W)];
+    for (int h = 0; h < 2; ++h) {
+        T *out = base + Rec<NK>::d(idx0, n, h == 1);
+        for (int t = hw; t < nvalid * 2 * W; t += 64) out[t] = slots[(t / (2 * W)) * NS + h * 2 * W + t % (2 * W)];
+    }
     wave_sync();
 }
 
@@ -1040,7 +1047,7 @@ __device__ __forceinline__ void diag_item(const DiagArgs &a, int64_t e, int sub)
                 bad = true;
                 continue;
             }
-            const TR *r = (const TR *)a.far_rec + Rec<NK>::d(u[k], a.n_far) + (f[k] >= e ? 0 : 6) * NK;
+            const TR *r = (const TR *)a.far_rec + Rec<NK>::d(u[k], a.n_far, f[k] < e);
             if (a.mat.n == 0) {
 #pragma unroll
                 for (int i = 0; i < 6 * NK; ++i) acc[i] += (double)r[i];
