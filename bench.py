@@ -541,7 +541,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build runs on a single GPU; "
-              "how the path would shard is described in DESIGN.md.", file=sys.stderr)
+              "independent problems shard across GPUs with no communication, a single mesh by row ownership with a halo.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched64":
         bench_batched(args)
