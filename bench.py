@@ -540,8 +540,8 @@ def main():
                     help="after the run, copy a buffer of this size once (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build runs on a single GPU; "
-              "independent problems shard across GPUs with no communication, a single mesh by row ownership with a halo.", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}); independent problems shard across GPUs "
+              "with no communication, a single mesh by row ownership with a halo.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched64":
         bench_batched(args)
