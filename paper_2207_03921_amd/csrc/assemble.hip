@@ -97,26 +97,28 @@ __global__ void __launch_bounds__(256) k_touch_rec(TouchLaunch L, GaussArgs g)
     touch_block<KER, 3>(L.t[0], gv, b - L.nb[1]);
 }
 
-template <int NK, typename TR>
+template <int NK, typename TR, bool MOM = false>
 __global__ void __launch_bounds__(256) k_elem_diag(DiagArgs a)
 {
     if (gated(a.gate)) return;
-    constexpr int per = 256 / kDiagG;   // elements per workgroup
-    const int64_t e = xcd_item(blockIdx.x, (a.K + per - 1) / per) * per + threadIdx.x / kDiagG;
+    constexpr int G = diag_group<MOM>();
+    constexpr int per = 256 / G;   // elements per workgroup
+    const int64_t e = xcd_item(blockIdx.x, (a.K + per - 1) / per) * per + threadIdx.x / G;
     if (e >= a.K) return;   // whole lane groups leave together
-    diag_item<NK, TR>(a, e, threadIdx.x % kDiagG);
+    diag_item<NK, TR, MOM>(a, e, threadIdx.x % G);
 }
 
-template <int NC, typename TR>
+template <int NC, typename TR, bool MOM = false>
 __global__ void __launch_bounds__(64) k_rows(RowArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ RowShared sh;
+    __shared__ double mq[MOM ? kRowMom : 1];
     if (gated(a.gate)) return;
     for (int64_t b = blockIdx.x; b < xcd_span(a.nrows); b += gridDim.x) {
         const int64_t item = xcd_item(b, a.nrows);
         if (item >= a.nrows) continue;
-        row_item<NC, TR>(a, a.rows[item], smem, sh);
+        row_item<NC, TR, MOM>(a, a.rows[item], smem, sh, mq);
     }
 }
 
@@ -183,6 +185,36 @@ RoleArgs roles(const RuleArgs &r, bool a_outer, bool b_outer)
         }
     }
     return o;
+}
+
+MomArgs moment_args(const nlfem_pairs *h, const nlfem_config *cfg)
+{
+    MomArgs m;
+    if (cfg->kernel != NLFEM_K_CONSTANT || h->approach != NLFEM_A_NOCAPS_BARY || h->ncomp != 1 || h->dg ||
+        h->rules.P > kMomP)
+        return m;
+    const RuleArgs &r = h->rules;
+    m.on = 1;
+    m.P = r.P;
+    m.m_ef = h->um_ef;
+    m.m_fe = h->um_fe;
+    m.det = h->det;
+    m.c = cfg->c;
+    for (int p = 0; p < r.P; ++p) {
+        m.wo[p] = r.pw[p];
+        for (int a = 0; a < 3; ++a) {
+            m.mo[p][a] = r.pw[p] * r.pphi[p][a];
+            for (int b = a; b < 3; ++b) m.qo[p][sym_index(a, b, 3)] = r.pw[p] * r.pphi[p][a] * r.pphi[p][b];
+        }
+    }
+    for (int q = 0; q < r.Q; ++q) {
+        m.wi += r.qw[q];
+        for (int a = 0; a < 3; ++a) {
+            m.mi[a] += r.qw[q] * r.qphi[q][a];
+            for (int b = a; b < 3; ++b) m.qi[sym_index(a, b, 3)] += r.qw[q] * r.qphi[q][a] * r.qphi[q][b];
+        }
+    }
+    return m;
 }
 
 AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
@@ -267,8 +299,11 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     r.gate = h->asm_gate;
     r.mat = material_args(m->materials, cfg);
     r.nonsym = h->nonsym;
+    r.mom = moment_args(h, cfg);
     p.diag = DiagArgs{h->K,        r.sptr,   h->snbr, h->sflag, h->srec, h->far_rec, h->far_stride,
-                      h->nUF,      h->dsum,  h->err,  h->asm_gate, r.mat};
+                      h->nUF,      h->dsum,  h->err,  h->asm_gate, r.mat, r.mom};
+    // the moment form needs no far records
+    p.mom = r.mom.on != 0;
     return p;
 }
 
@@ -308,7 +343,7 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         }
         timing_end(kPhTouch, s);
     }
-    if (p.far.n > 0) {
+    if (p.far.n > 0 && !p.mom) {
         timing_begin(kPhFar, s);
         switch (p.kernel) {
         case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(p, s); break;
@@ -326,8 +361,12 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         const int nc = p.nc;
         const bool fp32 = p.fp32;
         timing_begin(kPhDiag, s);
-        const unsigned dg = xcd_grid((h->K + 256 / kDiagG - 1) / (256 / kDiagG), INT32_MAX);
-        if (nc == 1) {
+        const int per = 256 / (p.mom ? diag_group<true>() : diag_group<false>());
+        const unsigned dg = xcd_grid((h->K + per - 1) / per, INT32_MAX);
+        if (nc == 1 && p.mom) {
+            if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float, true>), dim3(dg), dim3(256), 0, s, p.diag);
+            else hipLaunchKernelGGL((k_elem_diag<1, double, true>), dim3(dg), dim3(256), 0, s, p.diag);
+        } else if (nc == 1) {
             if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float>), dim3(dg), dim3(256), 0, s, p.diag);
             else hipLaunchKernelGGL((k_elem_diag<1, double>), dim3(dg), dim3(256), 0, s, p.diag);
         } else {
@@ -339,7 +378,10 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
         const size_t lds = row_lds_bytes(p.rows.maxlen, nc, p.rows.hcap);
         const unsigned grid = xcd_grid(p.rows.nrows);
         timing_begin(kPhRows, s);
-        if (nc == 1) {
+        if (nc == 1 && p.mom) {
+            if (fp32) hipLaunchKernelGGL((k_rows<1, float, true>), dim3(grid), dim3(64), lds, s, p.rows);
+            else hipLaunchKernelGGL((k_rows<1, double, true>), dim3(grid), dim3(64), lds, s, p.rows);
+        } else if (nc == 1) {
             if (fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(64), lds, s, p.rows);
             else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(64), lds, s, p.rows);
         } else {

@@ -208,6 +208,55 @@ struct Rec {
     }
 };
 
+// Constant kernel under the barycentre ball (scalar, continuous ansatz): a
+// point pair of a non-touching pair counts iff the status bit of its outer
+// point says so, and the kernel value does not depend on the points, so the
+// double sums behind X, De and Df (Sec. 2.3, the four terms of the bilinear
+// form; Sec. 2.4.1) factor into sums over one element's rule.  With, for a
+// status mask m, M_O(m)_a = sum over the outer points p set in m of
+// w_p phi_a(x_p), T_O(m) = sum of their w_p, Q_O(m)_ab = sum of their
+// w_p phi_a phi_b, the same sums over every inner point M_I, W_I, Q_I, and
+// me / mf the masks of e's / f's outer points against the other element:
+//   row a of e against vertex b of f:  -c |J_e| |J_f| (M_O(me)_a M_I,b + M_I,a M_O(mf)_b)
+//   e's element-diagonal block:         c |J_e| |J_f| (Q_O(me) W_I + Q_I T_O(mf))
+// (both directions of the pair; the self pair takes me = mf, which gives
+// X + X^T and De + Df).  The row gather and the diagonal sums evaluate these
+// from the masks and determinants, so such problems form no far records.
+constexpr int kMomP = 8;   // outer points of the moment form (two nibbles of status bits)
+struct MomArgs {
+    int32_t on = 0;
+    int32_t P = 0;                                     // outer points: status fields per mask
+    const uint32_t *m_ef = nullptr, *m_fe = nullptr;   // masks of the unordered pairs (first, second element)
+    const double *det = nullptr;                       // |det J| per element
+    double c = 0.0;
+    double mo[kMaxRule][3] = {};                       // w_p phi_a(x_p), outer rule
+    double mi[3] = {};                                 // M_I
+    double wo[kMaxRule] = {};                          // w_p, outer rule
+    double qo[kMaxRule][6] = {};                       // w_p phi_a phi_b (a <= b, packed), outer rule
+    double qi[6] = {};                                 // Q_I
+    double wi = 0.0;                                   // W_I
+};
+
+// status bit "whole" of outer point p as 0.0 / 1.0
+__device__ __forceinline__ double whole_bit(uint32_t m, int p) { return (double)((m >> (2 * p)) & 1u); }
+
+// the "whole" bits of outer points 4n .. 4n+3 as a 4-bit index
+__device__ __forceinline__ uint32_t whole_nibble(uint32_t m, int n)
+{
+    uint32_t x = (m >> (8 * n)) & 0x55u;
+    x = (x | (x >> 1)) & 0x33u;
+    return (x | (x >> 2)) & 0x0fu;
+}
+
+// masks of the entry f in e's list (record u): e's outer points, then f's
+__device__ __forceinline__ void entry_masks(const MomArgs &m, int64_t u, int32_t e, int32_t f, uint32_t &me,
+                                            uint32_t &mf)
+{
+    const uint32_t x0 = m.m_ef[u], x1 = m.m_fe[u];
+    me = f >= e ? x0 : x1;
+    mf = f > e ? x1 : x0;
+}
+
 // rule points of the two roles (A on e, B on f)
 struct RoleArgs {
     int32_t PA, PB;
@@ -1011,6 +1060,7 @@ struct DiagArgs {
     int32_t *err;
     SpecGate gate;
     MatArgs mat;   // label-dependent kernel: e's block of pair (e, f) scaled by c[m(e)][m(f)]
+    MomArgs mom;   // mom.on: the blocks from the masks, no records
 };
 
 // D_e of element e by the kDiagG lanes sub = 0..kDiagG-1 of an aligned lane
@@ -1020,10 +1070,90 @@ struct DiagArgs {
 // so every path uses these constants.
 constexpr int kDiagG = 32;
 constexpr int kDiagU = 4;
+// the moment form reads 16 bytes per entry and reduces more values: groups
+// of 8 lanes, each with more entries
+constexpr int kDiagGMom = 8;
+template <bool MOM>
+constexpr int diag_group() { return MOM ? kDiagGMom : kDiagG; }
 
-template <int NK, typename TR>
+// The same from the masks (a.mom.on, scalar): per outer point p the lanes sum
+// A_p = coef(e, f) |J_f| over the entries whose me has p set, and
+// B = coef(e, f) |J_f| T_O(mf); the group reduces them, and
+// D_e = c |J_e| (W_I sum_p A_p w_p phi(x_p) phi(x_p)^T + Q_I B).
+__device__ __forceinline__ void diag_item_mom(const DiagArgs &a, int64_t e, int sub)
+{
+    constexpr int G = kDiagGMom;
+    const MomArgs &m = a.mom;
+    double A[kMomP], B = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMomP; ++p) A[p] = 0.0;
+    bool bad = false;
+    const int64_t s0 = a.sptr[e], s1 = a.sptr[e + 1];
+    for (int64_t t0 = s0 + sub; t0 < s1; t0 += G * kDiagU) {
+        int32_t u[kDiagU], f[kDiagU];
+        bool use[kDiagU];
+#pragma unroll
+        for (int k = 0; k < kDiagU; ++k) {
+            const int64_t t = t0 + (int64_t)k * G;
+            use[k] = t < s1 && ((a.sflag[t] >> 2) & 3) == 0;
+            u[k] = use[k] ? a.srec[t] : 0;
+            f[k] = use[k] ? a.snbr[t] : 0;
+        }
+        uint32_t me[kDiagU], mf[kDiagU];
+        double w[kDiagU];
+#pragma unroll
+        for (int k = 0; k < kDiagU; ++k) {
+            me[k] = mf[k] = 0u;
+            w[k] = 0.0;
+            if (!use[k]) continue;
+            if (u[k] < 0 || u[k] >= a.n_far) {
+                bad = true;
+                continue;
+            }
+            entry_masks(m, u[k], (int32_t)e, f[k], me[k], mf[k]);
+            w[k] = m.det[f[k]];
+            if (a.mat.n) w[k] *= a.mat.coef((int32_t)e, f[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kDiagU; ++k) {
+            double to = 0.0;
+#pragma unroll
+            for (int p = 0; p < kMomP; ++p) {
+                if (p < m.P) {
+                    A[p] = fma(w[k], whole_bit(me[k], p), A[p]);
+                    to = fma(whole_bit(mf[k], p), m.wo[p], to);
+                }
+            }
+            B = fma(w[k], to, B);
+        }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int p = 0; p < kMomP; ++p)
+            if (p < m.P) A[p] += __shfl_xor(A[p], o, G);
+        B += __shfl_xor(B, o, G);
+    }
+    if (bad) atomicOr(a.err, kErrSlot);
+    const double ce = m.c * m.det[e];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double q = 0.0;
+#pragma unroll
+        for (int p = 0; p < kMomP; ++p)
+            if (p < m.P) q = fma(A[p], m.qo[p][i], q);
+        if (i % G == sub) a.dsum[e * 6 + i] = ce * (m.wi * q + m.qi[i] * B);
+    }
+}
+
+template <int NK, typename TR, bool MOM = false>
 __device__ __forceinline__ void diag_item(const DiagArgs &a, int64_t e, int sub)
 {
+    static_assert(!MOM || NK == 1, "the moment form is scalar");
+    if constexpr (MOM) {
+        diag_item_mom(a, e, sub);
+        return;
+    }
     constexpr int G = kDiagG;
     double acc[6 * NK];
 #pragma unroll
@@ -1108,6 +1238,7 @@ struct RowArgs {
     // and vertex records in the discontinuous form folded per column
     MatArgs mat;
     int32_t nonsym;
+    MomArgs mom;   // mom.on: far entries from the masks (row_item<1, TR, true>), no records
 };
 
 constexpr int kRowQ = 64;   // elements around a node per batch (one per lane)
@@ -1275,6 +1406,11 @@ struct RowShared {
     int32_t tt[kRowTouchCap];   // queued touching entries: list index and element slot
     uint8_t tq[kRowTouchCap];
 };
+// moment form, LDS of kRowMom doubles beside RowShared: the sums M_O over
+// the set bits of each 4-bit index of the two nibbles of a mask,
+// [nibble][index][a], then M_I
+constexpr int kRowMomLut = 2 * 16 * 3;
+constexpr int kRowMom = kRowMomLut + 3;
 
 // adds the queued touching entries of row i (element slots of the current batch)
 template <int NC>
@@ -1318,9 +1454,11 @@ inline size_t row_lds_bytes(int64_t maxlen, int nc, int hcap)
 
 // row of dof node i by the 64 lanes of a one-wave workgroup; smem holds
 // row_lds_bytes(a.maxlen, NC, a.hcap) bytes
-template <int NC, typename TR>
-__device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned char *smem, RowShared &sh)
+template <int NC, typename TR, bool MOM = false>
+__device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned char *smem, RowShared &sh,
+                                         double *mq = nullptr)
 {
+    static_assert(!MOM || NC == 1, "the moment form is scalar");
     constexpr int NN = NC * NC;
     constexpr int NK = NC == 1 ? 1 : 3;
     double *acc = (double *)smem;                              // [maxlen * NN]
@@ -1336,6 +1474,19 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
         const int64_t s = a.nptr[i];
         const int len = (int)(a.nptr[i + 1] - s);
         if (len == 0) return;
+        if constexpr (MOM) {
+            for (int t = lane; t < kRowMom; t += 64) {
+                const int n = t / 48, idx = (t / 3) % 16, b = t % 3;
+                double v = 0.0;
+                if (t >= kRowMomLut) {
+                    v = a.mom.mi[t - kRowMomLut];
+                } else {
+                    for (int j = 0; j < 4; ++j)
+                        if (((idx >> j) & 1) && 4 * n + j < a.mom.P) v += a.mom.mo[4 * n + j][b];
+                }
+                mq[t] = v;
+            }
+        }
         for (int t = lane; t < a.hcap; t += 64) hk[t] = -1;
         for (int t = lane; t < len * NN; t += 64) acc[t] = 0.0;
         __syncthreads();
@@ -1408,7 +1559,9 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
             for (int base = 0; base < total; base += 64 * kRowU) {
                 int32_t fe[kRowU], uu[kRowU], qq[kRowU], cl[kRowU], nf0[kRowU], nf1[kRowU], nf2[kRowU], tt[kRowU];
                 bool act[kRowU];
-                TR xv[kRowU][3][NK];
+                TR xv[MOM ? 1 : kRowU][3][NK];
+                uint32_t me[MOM ? kRowU : 1], mf[MOM ? kRowU : 1];
+                double dv[MOM ? kRowU : 1];
 #pragma unroll
                 for (int k = 0; k < kRowU; ++k) {
                     const int flat = base + k * 64 + lane;
@@ -1443,16 +1596,21 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                     }
                     const int32_t f = fe[k];
                     if (cl[k] == 0) {
-                        // row loc of X (e first) or column loc (e second); the
-                        // self pair stores X + X^T
                         const int32_t e = qe[qq[k]];
-                        const int loc = qloc[qq[k]];
-                        const TR *r = (const TR *)a.far_rec + (f >= e ? Rec<NK>::r(loc, uu[k], a.n_far)
-                                                                       : Rec<NK>::c(loc, uu[k], a.n_far));
+                        if constexpr (MOM) {
+                            entry_masks(a.mom, uu[k], e, f, me[k], mf[k]);
+                            dv[k] = a.mom.det[f] * a.mom.det[e];
+                        } else {
+                            // row loc of X (e first) or column loc (e second);
+                            // the self pair stores X + X^T
+                            const int loc = qloc[qq[k]];
+                            const TR *r = (const TR *)a.far_rec + (f >= e ? Rec<NK>::r(loc, uu[k], a.n_far)
+                                                                           : Rec<NK>::c(loc, uu[k], a.n_far));
 #pragma unroll
-                        for (int b = 0; b < 3; ++b)
+                            for (int b = 0; b < 3; ++b)
 #pragma unroll
-                            for (int kk = 0; kk < NK; ++kk) xv[k][b][kk] = r[b * NK + kk];
+                                for (int kk = 0; kk < NK; ++kk) xv[k][b][kk] = r[b * NK + kk];
+                        }
                     }
                 }
 #pragma unroll
@@ -1462,6 +1620,23 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                     const int32_t e = qe[q], f = fe[k];
                     if (cl[k] == 0) {
                         const int32_t nb[3] = {nf0[k], nf1[k], nf2[k]};
+                        double xm[3];
+                        if constexpr (MOM) {
+                            // -c |J_e| |J_f| (M_O(me)_loc M_I + M_I,loc M_O(mf))
+                            const int loc = qloc[q];
+                            // M_O of each mask from the two nibble sums
+                            const double *lut = mq;
+                            const int e0 = (int)whole_nibble(me[k], 0) * 3, e1 = 48 + (int)whole_nibble(me[k], 1) * 3;
+                            const int f0 = (int)whole_nibble(mf[k], 0) * 3, f1 = 48 + (int)whole_nibble(mf[k], 1) * 3;
+                            const double ol = lut[e0 + loc] + lut[e1 + loc];
+                            double ob[3];
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) ob[b] = lut[f0 + b] + lut[f1 + b];
+                            const double il = mq[kRowMomLut + loc];
+                            const double sc = -a.mom.c * dv[k];
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) xm[b] = sc * (ol * a.mom.mi[b] + il * ob[b]);
+                        }
 #pragma unroll
                         for (int b = 0; b < 3; ++b) {
                             const int px = f == e ? qp[q][b] : hpos(hk, hv, mask, nb[b]);
@@ -1471,7 +1646,7 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
                             }
                             double xs[NK];
 #pragma unroll
-                            for (int kk = 0; kk < NK; ++kk) xs[kk] = (double)xv[k][b][kk];
+                            for (int kk = 0; kk < NK; ++kk) xs[kk] = MOM ? xm[b] : (double)xv[MOM ? 0 : k][b][kk];
                             if (a.mat.n) {
                                 // rows e, columns f: the element of the column holds x
                                 const double cf = a.mat.coef(f, e);
@@ -1526,6 +1701,7 @@ __device__ __forceinline__ void row_item(const RowArgs &a, int64_t i, unsigned c
 struct AssemblePlan {
     int kernel, nc;
     bool fp32, poly, seven;          // seven: both rules have 7 points
+    bool mom;                        // moment form (MomArgs): no far-record launch
     FarArgs far;                     // far.n == 0: no non-touching pairs
     RoleArgs r1, r2;
     TouchArgs touch[3];              // identical, edge, vertex classes
@@ -1535,6 +1711,7 @@ struct AssemblePlan {
 };
 
 RoleArgs roles(const RuleArgs &r, bool a_outer, bool b_outer);
+MomArgs moment_args(const nlfem_pairs *h, const nlfem_config *cfg);
 AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
                        double *val);
 

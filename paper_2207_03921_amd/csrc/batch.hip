@@ -189,14 +189,15 @@ __global__ void __launch_bounds__(256) kb_touch(QueueArgs q, const TouchArgs *__
     }
 }
 
-template <int NK, typename TR>
+template <int NK, typename TR, bool MOM = false>
 __global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *__restrict__ da)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ unsigned long long slot;
     int64_t *pre = (int64_t *)dyn;
     const int64_t total = load_prefix(q, pre);
-    const int group = threadIdx.x / kDiagG, sub = threadIdx.x % kDiagG, groups = blockDim.x / kDiagG;
+    constexpr int G = diag_group<MOM>();
+    const int group = threadIdx.x / G, sub = threadIdx.x % G, groups = blockDim.x / G;
     for (;;) {
         const int64_t b0 = grab(q, &slot);
         if (b0 >= total) break;
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *__re
             unsigned long long todo = __ballot(it < b1);
             while (todo) {
                 const Run r = next_run(p, &todo);   // whole lane groups
-                if (p == r.p) diag_item<NK, TR>(da[r.p], it - pre[r.p], sub);
+                if (p == r.p) diag_item<NK, TR, MOM>(da[r.p], it - pre[r.p], sub);
             }
         }
     }
@@ -216,11 +217,12 @@ __global__ void __launch_bounds__(256) kb_diag(QueueArgs q, const DiagArgs *__re
 // Rows cost about the same each, so they are spread statically, one per
 // workgroup of one wave, with the XCD-aware order of the single-problem
 // kernel over the rows of all problems of the group (no queue).
-template <int NC, typename TR>
+template <int NC, typename TR, bool MOM = false>
 __global__ void __launch_bounds__(64) kb_rows(QueueArgs q, const RowArgs *__restrict__ ra, size_t pre_bytes)
 {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ RowShared sh;
+    __shared__ double mq[MOM ? kRowMom : 1];
     int64_t *pre = (int64_t *)dyn;
     unsigned char *rowmem = dyn + pre_bytes;
     const int64_t total = load_prefix(q, pre);
@@ -230,7 +232,7 @@ __global__ void __launch_bounds__(64) kb_rows(QueueArgs q, const RowArgs *__rest
         // one row per workgroup of one wave: the problem is uniform
         const int p = __builtin_amdgcn_readfirstlane(find_prob(pre, q.nprob, it));
         const RowArgs &a = ra[p];
-        row_item<NC, TR>(a, a.rows[it - pre[p]], rowmem, sh);
+        row_item<NC, TR, MOM>(a, a.rows[it - pre[p]], rowmem, sh, mq);
     }
 }
 
@@ -251,6 +253,7 @@ struct Group {
     Phase phase;
     int kernel = 0, cls = 0, nc = 1;
     bool fp32 = false, poly = false, seven = false;
+    bool mom = false;           // kDiag, kRows: moment form (no far records)
     std::vector<int> probs;
     std::vector<int64_t> pre;   // host copy
     size_t off_pre = 0, off_args = 0, off_r1 = 0, off_r2 = 0;
@@ -344,7 +347,10 @@ void launch_group(const nlfem_batch *b, const Group &g, const Shape &sh, hipStre
     case kDiag: {
         const dim3 grid((unsigned)(b->cus * sh.per_cu)), block(256);
         const DiagArgs *da = dptr<DiagArgs>(b, g.off_args);
-        if (g.nc == 1) {
+        if (g.nc == 1 && g.mom) {
+            if (g.fp32) hipLaunchKernelGGL((kb_diag<1, float, true>), grid, block, pre_lds, s, q, da);
+            else hipLaunchKernelGGL((kb_diag<1, double, true>), grid, block, pre_lds, s, q, da);
+        } else if (g.nc == 1) {
             if (g.fp32) hipLaunchKernelGGL((kb_diag<1, float>), grid, block, pre_lds, s, q, da);
             else hipLaunchKernelGGL((kb_diag<1, double>), grid, block, pre_lds, s, q, da);
         } else {
@@ -357,7 +363,10 @@ void launch_group(const nlfem_batch *b, const Group &g, const Shape &sh, hipStre
         const dim3 grid(xcd_grid(g.pre.back())), block(64);
         const RowArgs *ra = dptr<RowArgs>(b, g.off_args);
         const size_t lds = pre_lds + g.row_lds;
-        if (g.nc == 1) {
+        if (g.nc == 1 && g.mom) {
+            if (g.fp32) hipLaunchKernelGGL((kb_rows<1, float, true>), grid, block, lds, s, q, ra, pre_lds);
+            else hipLaunchKernelGGL((kb_rows<1, double, true>), grid, block, lds, s, q, ra, pre_lds);
+        } else if (g.nc == 1) {
             if (g.fp32) hipLaunchKernelGGL((kb_rows<1, float>), grid, block, lds, s, q, ra, pre_lds);
             else hipLaunchKernelGGL((kb_rows<1, double>), grid, block, lds, s, q, ra, pre_lds);
         } else {
@@ -405,7 +414,7 @@ int run_all(const nlfem_batch *b, hipStream_t s, bool timed)
 int64_t items_of(const AssemblePlan &p, Phase ph, int cls)
 {
     switch (ph) {
-    case kFar: return p.far.n;
+    case kFar: return p.mom ? 0 : p.far.n;
     case kTouch: return p.touch[cls == 3 ? 0 : cls == 2 ? 1 : 2].n;
     case kDiag: return p.rows.nrows > 0 ? p.diag.K : 0;
     default: return p.rows.nrows;
@@ -441,10 +450,13 @@ void make_groups(nlfem_batch *b)
                     int c2 = 0;
                     while (((size_t)1024 << c2) < need) ++c2;
                     g.cls = c2;
+                    g.mom = p.mom;
+                } else if (ph == kDiag) {
+                    g.mom = p.mom;
                 }
                 char key[96];
-                std::snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d", ph, g.kernel, g.cls, g.nc, (int)g.fp32,
-                              (int)g.poly, (int)g.seven);
+                std::snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d", ph, g.kernel, g.cls, g.nc, (int)g.fp32,
+                              (int)g.poly, (int)g.seven, (int)g.mom);
                 auto it = index.find(key);
                 if (it == index.end()) {
                     it = index.emplace(key, (int)b->groups.size()).first;
