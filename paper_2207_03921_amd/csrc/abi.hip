@@ -26,7 +26,7 @@ int64_t g_capacity = 0;
 enum Buf : int {
     B_V0, B_J, B_DET, B_BARY, B_XP, B_FLAGS, B_ERR, B_RED, B_NEPTR, B_NELIST, B_NEFILL,
     B_CELLCNT, B_CELLSTART, B_CELLFILL, B_CELLELEMS, B_CELLOF, B_LCNT, B_LOFF, B_SCAN,
-    B_SNBR, B_SFLAG, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UMEF, B_UMFE, B_TE, B_TF,
+    B_SNBR, B_SFLAG, B_SREC, B_SNBRT, B_SFLAGT, B_SMASKT, B_UE, B_UF, B_UM, B_TE, B_TF,
     B_NLEN, B_NPTR, B_NCOL, B_FARREC, B_TOUCHREC, B_DSUM, B_DOFL, B_POLYDIR, B_CSRSTAGE, B_SNODE, B_SPEC,
     B_NCODE, B_CODECNT, B_CODESTART, B_CODEFILL, B_CAND, B_SCROFF, B_DGCNT, B_DGPTR, B_LAST
 };
@@ -539,8 +539,7 @@ int build(const nlfem_mesh *m, const nlfem_config *cfg, nlfem_pairs *h, hipStrea
     NLFEM_TRY(ensure_typed(h, B_SNODE, h->nS, h->snode));
     NLFEM_TRY(ensure_typed(h, B_UE, h->nUF, h->ue));
     NLFEM_TRY(ensure_typed(h, B_UF, h->nUF, h->uf));
-    NLFEM_TRY(ensure_typed(h, B_UMEF, h->nUF, h->um_ef));
-    NLFEM_TRY(ensure_typed(h, B_UMFE, h->nUF, h->um_fe));
+    NLFEM_TRY(ensure_typed(h, B_UM, h->nUF, h->um));
     NLFEM_TRY(ensure_typed(h, B_TE, h->nUT, h->te));
     NLFEM_TRY(ensure_typed(h, B_TF, h->nUT, h->tf));
     timing_begin(kPhLists, s);

@@ -32,7 +32,8 @@ __global__ void __launch_bounds__(256) k_far_rec(FarArgs a, RoleArgs r1, RoleArg
     if (idx < a.n) {
         const int32_t e = a.ue[idx], f = a.uf[idx];
         self = e == f;
-        far_whole<KER, T, PM>(a, r1, r2, e, f, a.m_ef[idx], a.m_fe[idx], acc);
+        const uint2 mm = a.m[idx];
+        far_whole<KER, T, PM>(a, r1, r2, e, f, mm.x, mm.y, acc);
     }
     far_store_wave<KER, T>(a, idx0, nvalid, self, acc, slots + (threadIdx.x >> 6) * 64 * NV);
 }
@@ -196,8 +197,7 @@ MomArgs moment_args(const nlfem_pairs *h, const nlfem_config *cfg)
     const RuleArgs &r = h->rules;
     m.on = 1;
     m.P = r.P;
-    m.m_ef = h->um_ef;
-    m.m_fe = h->um_fe;
+    m.m = h->um;
     m.det = h->det;
     m.c = cfg->c;
     for (int p = 0; p < r.P; ++p) {
@@ -231,8 +231,7 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
     a.n = h->nUF;
     a.ue = h->ue;
     a.uf = h->uf;
-    a.m_ef = h->um_ef;
-    a.m_fe = h->um_fe;
+    a.m = h->um;
     a.v0 = h->v0;
     a.J = h->J;
     a.det = h->det;

@@ -163,7 +163,7 @@ __device__ inline double2 vtx(const double *V, int32_t n) { return make_double2(
 struct FarArgs {
     int64_t n;
     const int32_t *ue, *uf;
-    const uint32_t *m_ef, *m_fe;
+    const uint2 *m;          // status masks (e's outer points vs f, f's vs e)
     const double2 *v0;
     const double4 *J;
     const double *det;
@@ -226,7 +226,7 @@ constexpr int kMomP = 8;   // outer points of the moment form (two nibbles of st
 struct MomArgs {
     int32_t on = 0;
     int32_t P = 0;                                     // outer points: status fields per mask
-    const uint32_t *m_ef = nullptr, *m_fe = nullptr;   // masks of the unordered pairs (first, second element)
+    const uint2 *m = nullptr;                          // masks of the unordered pairs (first, second element)
     const double *det = nullptr;                       // |det J| per element
     double c = 0.0;
     double mo[kMaxRule][3] = {};                       // w_p phi_a(x_p), outer rule
@@ -252,7 +252,8 @@ __device__ __forceinline__ uint32_t whole_nibble(uint32_t m, int n)
 __device__ __forceinline__ void entry_masks(const MomArgs &m, int64_t u, int32_t e, int32_t f, uint32_t &me,
                                             uint32_t &mf)
 {
-    const uint32_t x0 = m.m_ef[u], x1 = m.m_fe[u];
+    const uint2 x = m.m[u];
+    const uint32_t x0 = x.x, x1 = x.y;
     me = f >= e ? x0 : x1;
     mf = f > e ? x1 : x0;
 }
@@ -726,7 +727,8 @@ template <int KER, typename T, int PM, bool POLY>
 __device__ __forceinline__ void far_item(const FarArgs &a, const RoleArgs &r1, const RoleArgs &r2, int64_t idx)
 {
     const int32_t e = a.ue[idx], f = a.uf[idx];
-    const uint32_t ms = a.m_ef[idx], mt = a.m_fe[idx];   // mt == 0 for the self pair
+    const uint2 mm = a.m[idx];
+    const uint32_t ms = mm.x, mt = mm.y;   // mt == 0 for the self pair
     FarAcc<KER, T> acc;
     far_whole<KER, T, PM>(a, r1, r2, e, f, ms, mt, acc);
     if (POLY) {
@@ -766,8 +768,9 @@ __device__ __forceinline__ void far_wave_poly(const FarArgs &a, const RoleArgs &
     if (active) {
         e = a.ue[idx];
         f = a.uf[idx];
-        ms = a.m_ef[idx];
-        mt = a.m_fe[idx];
+        const uint2 mm = a.m[idx];
+        ms = mm.x;
+        mt = mm.y;
         far_whole<KER, T, PM>(a, r1, r2, e, f, ms, mt, acc);
     }
     const uint32_t b0 = active ? straddle_bits(ms, a.P) : 0u;

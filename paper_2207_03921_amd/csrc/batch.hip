@@ -128,7 +128,8 @@ __global__ void __launch_bounds__(256) kb_far(QueueArgs q, const FarArgs *__rest
                         const int64_t idx = it - base;
                         const int32_t e = a.ue[idx], f = a.uf[idx];
                         self = e == f;
-                        far_whole<KER, T, PM>(a, r1[r.p], r2[r.p], e, f, a.m_ef[idx], a.m_fe[idx], acc);
+                        const uint2 mm = a.m[idx];
+                        far_whole<KER, T, PM>(a, r1[r.p], r2[r.p], e, f, mm.x, mm.y, acc);
                     }
                     far_store_wave<KER, T>(a, it - lane + r.lane0 - base, __popcll(r.mask), self, acc,
                                            slots + (threadIdx.x >> 6) * 64 * NV, r.lane0);

@@ -38,7 +38,7 @@ struct ListArgs {
     const int64_t *ne_ptr;     // node -> element incidence
     const int32_t *ne_list;
     int32_t *ue, *uf;
-    uint32_t *um_ef, *um_fe;
+    uint2 *um;
     int32_t *te, *tf;
     int32_t *err;
     SpecGate gate;
@@ -158,8 +158,7 @@ __global__ void __launch_bounds__(64) k_sort_lists(ListArgs a)
                 const int64_t u = oF + __popcll(bF & lt);
                 a.ue[u] = (int32_t)e;
                 a.uf[u] = f;
-                a.um_ef[u] = m.x;
-                a.um_fe[u] = f == e ? 0u : m.y;
+                a.um[u] = make_uint2(m.x, f == e ? 0u : m.y);
                 rec = (int32_t)u;
             }
             if (isI || isE || isV) {
@@ -206,8 +205,7 @@ ListArgs list_args(nlfem_pairs *h)
     a.ne_list = h->ne_list;
     a.ue = h->ue;
     a.uf = h->uf;
-    a.um_ef = h->um_ef;
-    a.um_fe = h->um_fe;
+    a.um = h->um;
     a.te = h->te;
     a.tf = h->tf;
     a.err = h->err;

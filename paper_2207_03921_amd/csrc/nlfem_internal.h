@@ -288,7 +288,7 @@ struct nlfem_pairs {
     uint2 *smask_tmp = nullptr;
     // unordered non-touching pairs e <= f (far work list)
     int32_t *ue = nullptr, *uf = nullptr;     // [nUF]
-    uint32_t *um_ef = nullptr, *um_fe = nullptr;
+    uint2 *um = nullptr;
     // unordered touching pairs e <= f: [ident | edge | vertex]
     int32_t *te = nullptr, *tf = nullptr;     // [nUT]
     // degree-of-freedom nodes (the rows of the matrix) in the Morton order of

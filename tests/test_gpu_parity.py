@@ -51,6 +51,14 @@ def _cases():
         "const_outer_ne_inner": _w("constant", square_mesh(10, delta=0.2, jitter=0.15, seed=7), 0.2,
                                    rule=gauss7(), inner=paper7()),
         "invdist_neumann": _w("inv_dist", square_mesh(12, delta=0.2, jitter=0.2, seed=8, neumann=True), 0.2),
+        # constant kernel, barycentre ball: far blocks from the status masks
+        # with 1 and 4 outer points (one nibble), and with 9 outer points
+        # (more than the mask form takes: far records)
+        "const_outer1_inner7": _w("constant", square_mesh(10, delta=0.2, jitter=0.15, seed=60), 0.2,
+                                  rule=centroid1(), inner=gauss7()),
+        "const_outer4_inner7": _w("constant", square_mesh(10, delta=0.2, jitter=0.15, seed=61), 0.2,
+                                  rule=collapsed(2), inner=paper7()),
+        "const_rule9": _w("constant", square_mesh(10, delta=0.2, jitter=0.15, seed=62), 0.2, rule=collapsed(3)),
         "const_duffy": _w("constant", square_mesh(12, delta=0.15, jitter=0.2, seed=9), 0.15, singular_n=4),
         # inscribed 32-gon: straddling points are clipped and fan-triangulated
         "const_poly_h16": _w("constant", square_mesh(16, delta=0.1), 0.1, approach="poly"),
