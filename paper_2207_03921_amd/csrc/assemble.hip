@@ -308,6 +308,68 @@ AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_co
 
 }  // namespace items
 
+namespace items {
+
+void launch_phase(const AssemblePlan &p, int phase, hipStream_t s)
+{
+    switch (phase) {
+    case 0:   // non-touching pairs
+        if (p.far.n == 0 || p.mom) return;
+        switch (p.kernel) {
+        case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(p, s); break;
+        case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(p, s); break;
+        case NLFEM_K_FRAC_HALF: far_dispatch<NLFEM_K_FRAC_HALF>(p, s); break;
+        case NLFEM_K_INV_DIST | kKerNoZeroDiv: far_dispatch<NLFEM_K_INV_DIST | kKerNoZeroDiv>(p, s); break;
+        case NLFEM_K_PERIDYNAMIC | kKerNoZeroDiv:
+            far_dispatch<NLFEM_K_PERIDYNAMIC | kKerNoZeroDiv>(p, s);
+            break;
+        default: far_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
+        }
+        return;
+    case 1:   // touching pairs (all classes present in the plan)
+        switch (p.kernel) {
+        case NLFEM_K_CONSTANT: touch_dispatch<NLFEM_K_CONSTANT>(p, s); break;
+        case NLFEM_K_INV_DIST: touch_dispatch<NLFEM_K_INV_DIST>(p, s); break;
+        case NLFEM_K_FRAC_HALF: touch_dispatch<NLFEM_K_FRAC_HALF>(p, s); break;
+        default: touch_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
+        }
+        return;
+    case 2: {   // element-diagonal sums
+        if (p.rows.nrows == 0) return;
+        const int per = 256 / (p.mom ? diag_group<true>() : diag_group<false>());
+        const unsigned dg = xcd_grid((p.diag.K + per - 1) / per, INT32_MAX);
+        if (p.nc == 1 && p.mom) {
+            if (p.fp32) hipLaunchKernelGGL((k_elem_diag<1, float, true>), dim3(dg), dim3(256), 0, s, p.diag);
+            else hipLaunchKernelGGL((k_elem_diag<1, double, true>), dim3(dg), dim3(256), 0, s, p.diag);
+        } else if (p.nc == 1) {
+            if (p.fp32) hipLaunchKernelGGL((k_elem_diag<1, float>), dim3(dg), dim3(256), 0, s, p.diag);
+            else hipLaunchKernelGGL((k_elem_diag<1, double>), dim3(dg), dim3(256), 0, s, p.diag);
+        } else {
+            if (p.fp32) hipLaunchKernelGGL((k_elem_diag<3, float>), dim3(dg), dim3(256), 0, s, p.diag);
+            else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, p.diag);
+        }
+        return;
+    }
+    default: {   // row gather (continuous ansatz)
+        if (p.rows.nrows == 0) return;
+        const size_t lds = row_lds_bytes(p.rows.maxlen, p.nc, p.rows.hcap);
+        const unsigned grid = xcd_grid(p.rows.nrows);
+        if (p.nc == 1 && p.mom) {
+            if (p.fp32) hipLaunchKernelGGL((k_rows<1, float, true>), dim3(grid), dim3(64), lds, s, p.rows);
+            else hipLaunchKernelGGL((k_rows<1, double, true>), dim3(grid), dim3(64), lds, s, p.rows);
+        } else if (p.nc == 1) {
+            if (p.fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(64), lds, s, p.rows);
+            else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(64), lds, s, p.rows);
+        } else {
+            if (p.fp32) hipLaunchKernelGGL((k_rows<2, float>), dim3(grid), dim3(64), lds, s, p.rows);
+            else hipLaunchKernelGGL((k_rows<2, double>), dim3(grid), dim3(64), lds, s, p.rows);
+        }
+    }
+    }
+}
+
+}  // namespace items
+
 int far_record_stride(int ncomp) { return ncomp == 1 ? Rec<1>::kValues : Rec<3>::kValues; }
 // packed symmetric local matrices over the union of the pair's unknowns:
 // at most 5 nodes (continuous) or 6 unknowns (discontinuous) per component
@@ -334,59 +396,21 @@ int launch_assemble(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_confi
     // two cross-queue waits than their overlap with the far records gains
     if (has_touch) {
         timing_begin(kPhTouch, s);
-        switch (p.kernel) {
-        case NLFEM_K_CONSTANT: touch_dispatch<NLFEM_K_CONSTANT>(p, s); break;
-        case NLFEM_K_INV_DIST: touch_dispatch<NLFEM_K_INV_DIST>(p, s); break;
-        case NLFEM_K_FRAC_HALF: touch_dispatch<NLFEM_K_FRAC_HALF>(p, s); break;
-        default: touch_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
-        }
+        items::launch_phase(p, 1, s);
         timing_end(kPhTouch, s);
     }
     if (p.far.n > 0 && !p.mom) {
         timing_begin(kPhFar, s);
-        switch (p.kernel) {
-        case NLFEM_K_CONSTANT: far_dispatch<NLFEM_K_CONSTANT>(p, s); break;
-        case NLFEM_K_INV_DIST: far_dispatch<NLFEM_K_INV_DIST>(p, s); break;
-        case NLFEM_K_FRAC_HALF: far_dispatch<NLFEM_K_FRAC_HALF>(p, s); break;
-        case NLFEM_K_INV_DIST | kKerNoZeroDiv: far_dispatch<NLFEM_K_INV_DIST | kKerNoZeroDiv>(p, s); break;
-        case NLFEM_K_PERIDYNAMIC | kKerNoZeroDiv:
-            far_dispatch<NLFEM_K_PERIDYNAMIC | kKerNoZeroDiv>(p, s);
-            break;
-        default: far_dispatch<NLFEM_K_PERIDYNAMIC>(p, s); break;
-        }
+        items::launch_phase(p, 0, s);
         timing_end(kPhFar, s);
     }
     if (p.rows.nrows > 0) {
-        const int nc = p.nc;
-        const bool fp32 = p.fp32;
         timing_begin(kPhDiag, s);
-        const int per = 256 / (p.mom ? diag_group<true>() : diag_group<false>());
-        const unsigned dg = xcd_grid((h->K + per - 1) / per, INT32_MAX);
-        if (nc == 1 && p.mom) {
-            if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float, true>), dim3(dg), dim3(256), 0, s, p.diag);
-            else hipLaunchKernelGGL((k_elem_diag<1, double, true>), dim3(dg), dim3(256), 0, s, p.diag);
-        } else if (nc == 1) {
-            if (fp32) hipLaunchKernelGGL((k_elem_diag<1, float>), dim3(dg), dim3(256), 0, s, p.diag);
-            else hipLaunchKernelGGL((k_elem_diag<1, double>), dim3(dg), dim3(256), 0, s, p.diag);
-        } else {
-            if (fp32) hipLaunchKernelGGL((k_elem_diag<3, float>), dim3(dg), dim3(256), 0, s, p.diag);
-            else hipLaunchKernelGGL((k_elem_diag<3, double>), dim3(dg), dim3(256), 0, s, p.diag);
-        }
+        items::launch_phase(p, 2, s);
         timing_end(kPhDiag, s);
         if (h->dg) return launch_dg_rows(h, m, cfg, val, s);
-        const size_t lds = row_lds_bytes(p.rows.maxlen, nc, p.rows.hcap);
-        const unsigned grid = xcd_grid(p.rows.nrows);
         timing_begin(kPhRows, s);
-        if (nc == 1 && p.mom) {
-            if (fp32) hipLaunchKernelGGL((k_rows<1, float, true>), dim3(grid), dim3(64), lds, s, p.rows);
-            else hipLaunchKernelGGL((k_rows<1, double, true>), dim3(grid), dim3(64), lds, s, p.rows);
-        } else if (nc == 1) {
-            if (fp32) hipLaunchKernelGGL((k_rows<1, float>), dim3(grid), dim3(64), lds, s, p.rows);
-            else hipLaunchKernelGGL((k_rows<1, double>), dim3(grid), dim3(64), lds, s, p.rows);
-        } else {
-            if (fp32) hipLaunchKernelGGL((k_rows<2, float>), dim3(grid), dim3(64), lds, s, p.rows);
-            else hipLaunchKernelGGL((k_rows<2, double>), dim3(grid), dim3(64), lds, s, p.rows);
-        }
+        items::launch_phase(p, 3, s);
         timing_end(kPhRows, s);
     }
     NLFEM_HIP(hipGetLastError());

@@ -1715,6 +1715,9 @@ struct AssemblePlan {
 
 RoleArgs roles(const RuleArgs &r, bool a_outer, bool b_outer);
 MomArgs moment_args(const nlfem_pairs *h, const nlfem_config *cfg);
+// the single-problem launches of one phase of a plan (0 non-touching pairs,
+// 1 touching pairs, 2 element diagonals, 3 rows; continuous ansatz), on s
+void launch_phase(const AssemblePlan &p, int phase, hipStream_t s);
 AssemblePlan make_plan(const nlfem_pairs *h, const nlfem_mesh *m, const nlfem_config *cfg, const GaussArgs &g,
                        double *val);
 

@@ -378,8 +378,16 @@ void launch_group(const nlfem_batch *b, const Group &g, const Shape &sh, hipStre
     }
 }
 
+// Shape {0, 0}: the phase as the single-problem launches of each problem
+// in turn (the same per-item functions, so the same values); the tuner
+// takes it where it is faster than the shared queue.
 int run_phase(const nlfem_batch *b, Phase ph, const Shape &sh, hipStream_t s)
 {
+    if (sh.chunk == 0) {
+        for (const AssemblePlan &p : b->plans) launch_phase(p, (int)ph, s);
+        NLFEM_HIP(hipGetLastError());
+        return NLFEM_OK;
+    }
     for (const Group &g : b->groups)
         if (g.phase == ph) launch_group(b, g, sh, s);
     NLFEM_HIP(hipGetLastError());
@@ -444,12 +452,12 @@ void make_groups(nlfem_batch *b)
                     g.kernel = p.kernel;
                     g.cls = cls;
                 } else if (ph == kRows) {
-                    // rows grouped by the power of two of their LDS need: each
+                    // rows grouped by their LDS need in steps of 1.2x: each
                     // launch reserves its own problems' size (the largest of a
                     // single group would cap the resident waves of the others)
                     const size_t need = row_lds_bytes(p.rows.maxlen, p.nc, p.rows.hcap);
                     int c2 = 0;
-                    while (((size_t)1024 << c2) < need) ++c2;
+                    for (double lim = 1024.0; lim < (double)need; lim *= 1.2) ++c2;
                     g.cls = c2;
                     g.mom = p.mom;
                 } else if (ph == kDiag) {
@@ -594,7 +602,8 @@ bool cache_read(const char *path, const std::string &key, Shape *out)
                                 &s[1].per_cu, &s[2].chunk, &s[2].per_cu, &s[3].chunk, &s[3].per_cu);
         if (nread == 2 * kPhases) {
             bool ok = true;
-            for (int p = 0; p < kPhases; ++p) ok &= s[p].chunk > 0 && s[p].per_cu > 0 && s[p].per_cu <= 64;
+            for (int p = 0; p < kPhases; ++p)
+                ok &= (s[p].chunk == 0 && s[p].per_cu == 0) || (s[p].chunk > 0 && s[p].per_cu > 0 && s[p].per_cu <= 64);
             if (ok) {
                 std::memcpy(out, s, sizeof s);
                 found = true;
@@ -628,13 +637,14 @@ int tune(nlfem_batch *b, hipStream_t s)
         bool any = false;
         for (const Group &g : b->groups) any |= g.phase == ph;
         if (!any) continue;
-        if (ph == kRows) {   // static mapping: nothing to choose
-            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, b->counters, (int)b->groups.size());
-            rc = run_phase(b, (Phase)ph, b->shape[ph], s);
-            continue;
-        }
+        // the queue shapes (rows: the static mapping only), then the
+        // per-problem launches
+        std::vector<Shape> cands;
+        if (ph == kRows) cands.push_back(b->shape[ph]);
+        else cands.assign(kCandidates[ph], kCandidates[ph] + 6);
+        cands.push_back(Shape{0, 0});
         float best = 1e30f;
-        for (const Shape &cand : kCandidates[ph]) {
+        for (const Shape &cand : cands) {
             float total = 0.f;
             for (int rep = 0; rep < 3 && rc == NLFEM_OK; ++rep) {
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, b->counters, (int)b->groups.size());
@@ -673,6 +683,9 @@ int batch_create(const std::vector<AssemblePlan> &plans, const std::vector<nlfem
     if (!b) return set_error(NLFEM_E_NOMEM, "host allocation failed");
     b->n = (int)plans.size();
     b->plans = plans;
+    // the queue kernels take no speculative-rebuild gate (the handles are
+    // checked on the host at each run); the per-problem launches alike
+    for (AssemblePlan &p : b->plans) p.far.gate = p.diag.gate = p.rows.gate = SpecGate{};
     b->handles = handles;
     for (const nlfem_pairs *h : handles) b->generation.push_back(h->generation);
     int dev = 0;
