@@ -371,7 +371,8 @@ typedef struct nlfem_batch nlfem_batch;   /* opaque, library-owned */
    used; the handles' workspaces are used by the batch.
    tune: 0 = default launch shapes; 1 = shapes from `tune_cache` (a text
    file, one line per device and batch structure) or, when absent, chosen by
-   timing candidate shapes on this stream and appended to the file
+   timing candidate shapes on this stream (per phase: queue shapes and one
+   launch per problem) and appended to the file
    (tune_cache may be NULL: nothing is read or written); 2 = always timed.
    Tuning runs the assembly, so vals hold a valid result afterwards.
    Allocates device tables; synchronises.
@@ -396,7 +397,9 @@ int nlfem_batch_launch_graph(nlfem_batch *batch, void *stream);
 
 /* Number of launch groups and the launch shape of the four phases
    (non-touching, touching, element diagonals, rows) as
-   shape[8] = {chunk, workgroups per CU} x 4.  Errors: E_INVALID. */
+   shape[8] = {chunk, workgroups per CU} x 4; {0, 0}: the phase runs as the
+   single-problem launches of each problem in turn (the tuner's other
+   candidate; same values).  Errors: E_INVALID. */
 int nlfem_batch_info(const nlfem_batch *batch, int32_t *groups, int32_t *shape);
 
 /* Releases a batch (synchronises the device).  NULL is ignored. */
