@@ -126,6 +126,31 @@ def test_batch_tuning_and_cache(tmp_path):
     _assert_same(probs)
 
 
+def test_batch_per_problem_shapes(tmp_path):
+    """Every phase as one launch per problem (shape {0, 0}, forced through
+    the tune cache): the values are those of the single-problem path."""
+    import paper_2207_03921_amd as nl
+    probs = _build(_mixed_set()[:5])
+    cache = str(tmp_path / "tune.txt")
+    args = ([p["dm"] for p in probs], [p["cfg"] for p in probs], [p["pairs"] for p in probs],
+            [p["val"] for p in probs])
+    nl.nlfem_batch_free(nl.nlfem_batch_create(*args, tune_cache=cache, tune=1))
+    key = open(cache).read().splitlines()[0].rsplit(" ", 8)[0]   # the line without its 8 shape numbers
+    open(cache, "w").write(key + " 0 0 0 0 0 0 0 0\n")
+    b = nl.nlfem_batch_create(*args, tune_cache=cache, tune=1)
+    shape = nl.nlfem_batch_info(b)["shape"]
+    assert all(v == {"chunk": 0, "per_cu": 0} for v in shape.values()), shape
+    for p in probs:
+        p["val"].fill_(float("nan"))
+    nl.nlfem_batch_assemble(b)
+    _assert_same(probs)
+    for p in probs:
+        p["val"].fill_(float("nan"))
+    nl.nlfem_batch_launch_graph(b)
+    _assert_same(probs)
+    nl.nlfem_batch_free(b)
+
+
 def test_batch_rejects_bad_input():
     import paper_2207_03921_amd as nl
     probs = _build(_mixed_set()[:2])
