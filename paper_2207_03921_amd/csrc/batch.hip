@@ -275,6 +275,10 @@ struct nlfem_batch {
     unsigned long long *counters = nullptr;
     Shape shape[kPhases] = {{1024, 4}, {256, 4}, {64, 4}, {4, 16}};
     hipStream_t capture = nullptr;
+    // per-problem phases: launches spread round-robin over the caller's
+    // stream and these (forked and joined by events, also under capture)
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<nlfem_pairs *> handles;
@@ -384,7 +388,21 @@ void launch_group(const nlfem_batch *b, const Group &g, const Shape &sh, hipStre
 int run_phase(const nlfem_batch *b, Phase ph, const Shape &sh, hipStream_t s)
 {
     if (sh.chunk == 0) {
-        for (const AssemblePlan &p : b->plans) launch_phase(p, (int)ph, s);
+        constexpr int NS = 4;   // the caller's stream and the three side streams
+        const bool fan = b->side[0] != nullptr;
+        if (fan) {
+            NLFEM_HIP(hipEventRecord(b->fork, s));
+            for (int k = 0; k < NS - 1; ++k) NLFEM_HIP(hipStreamWaitEvent(b->side[k], b->fork, 0));
+        }
+        for (size_t i = 0; i < b->plans.size(); ++i) {
+            const int k = fan ? (int)(i % NS) : 0;
+            launch_phase(b->plans[i], (int)ph, k == 0 ? s : b->side[k - 1]);
+        }
+        if (fan)
+            for (int k = 0; k < NS - 1; ++k) {
+                NLFEM_HIP(hipEventRecord(b->join[k], b->side[k]));
+                NLFEM_HIP(hipStreamWaitEvent(s, b->join[k], 0));
+            }
         NLFEM_HIP(hipGetLastError());
         return NLFEM_OK;
     }
@@ -697,6 +715,12 @@ int batch_create(const std::vector<AssemblePlan> &plans, const std::vector<nlfem
         make_groups(b);
         rc = upload_tables(b, s);
     }
+    for (int k = 0; k < 3 && rc == NLFEM_OK; ++k)
+        if (hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) != hipSuccess)
+            rc = set_error(NLFEM_E_HIP, "cannot create the batch's side streams");
+    if (rc == NLFEM_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+        rc = set_error(NLFEM_E_HIP, "cannot create the batch's events");
     if (rc == NLFEM_OK && tune_mode != 0) {
         const std::string key = tune_key(b);
         if (tune_mode == 2 || !cache_read(tune_cache, key, b->shape)) {
@@ -764,6 +788,11 @@ void batch_free(nlfem_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (int k = 0; k < 3; ++k) {
+        if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+        if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     dev_release(b->mem);
     delete b;
 }
