@@ -229,10 +229,10 @@ struct MomArgs {
     const uint2 *m = nullptr;                          // masks of the unordered pairs (first, second element)
     const double *det = nullptr;                       // |det J| per element
     double c = 0.0;
-    double mo[kMaxRule][3] = {};                       // w_p phi_a(x_p), outer rule
+    double mo[kMomP][3] = {};                          // w_p phi_a(x_p), outer rule
     double mi[3] = {};                                 // M_I
-    double wo[kMaxRule] = {};                          // w_p, outer rule
-    double qo[kMaxRule][6] = {};                       // w_p phi_a phi_b (a <= b, packed), outer rule
+    double wo[kMomP] = {};                             // w_p, outer rule
+    double qo[kMomP][6] = {};                          // w_p phi_a phi_b (a <= b, packed), outer rule
     double qi[6] = {};                                 // Q_I
     double wi = 0.0;                                   // W_I
 };
