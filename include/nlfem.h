@@ -426,7 +426,7 @@ int nlfem_assemble_batched(int32_t n, const nlfem_mesh *meshes, const nlfem_conf
    Handles with an unchecked rebuild are rejected (E_INVALID; call
    nlfem_pairs_info first), since finishing one may need a plain build.
    Errors: those of nlfem_assemble_batched, and E_OVERFLOW when the batch's
-   tables (about 5 KB per problem) exceed the array. */
+   tables (about 7 KB per problem) exceed the array. */
 #define NLFEM_NOALLOC_SCRATCH_BYTES (8u << 20)
 int nlfem_assemble_batched_noalloc(int32_t n, const nlfem_mesh *meshes, const nlfem_config *cfgs,
                                    nlfem_pairs *const *pairs, double *const *vals, void *stream);
