@@ -108,7 +108,12 @@ enum {
     NLFEM_P_FP64 = 0,   /* everything in FP64 */
     NLFEM_P_MIXED = 1   /* non-touching pairs in FP32 with FP32 accumulation per
                            pair; inclusion tests, polygon clipping, touching pairs
-                           and the global sums stay FP64 */
+                           and the global sums stay FP64.  The constant kernel
+                           under NLFEM_A_NOCAPS_BARY (outer rules of up to 8
+                           points, continuous ansatz) has no quadrature loop:
+                           its non-touching blocks factor into one-element rule
+                           sums over the points' status bits (Sec. 2.3, 2.4.1)
+                           and are formed in FP64 in either precision */
 };
 
 /* ansatz spaces (Sec. 1, 2.3) */
